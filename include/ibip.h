@@ -1,0 +1,152 @@
+/*
+ * ibip.h -- C ABI of the MI355X (gfx950) image-based invasion percolation
+ * library: exact squared Euclidean distance transform, volume-controlled
+ * invasion of a non-wetting fluid, defender trapping and pressure-based
+ * morphological-opening drainage on binary voxel images, after Gostick, Yang
+ * & Boek, "Simulating volume-controlled invasion of a non-wetting fluid in
+ * volumetric images using basic image processing tools" (arXiv 2101.03240).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Grid: dims {X, Y, Z}, C order, voxel v = (x*Y + y)*Z + z, x slowest.
+ *    2D images are X = 1. N = X*Y*Z must be below 2^31.
+ *  - image: uint8, nonzero = pore (void), zero = solid.
+ *  - Every N-sized array is a caller-owned DEVICE buffer on the context's
+ *    device (e.g. a torch tensor's data pointer), contiguous in C order.
+ *    Inputs are never written. Outputs are fully overwritten.
+ *  - Calls are ordered on the context's stream (ibip_ctx_set_stream); calls
+ *    that return a host-side count (n_steps, n_steps_after) synchronise that
+ *    stream before returning, the others do not.
+ *  - A context is used by one host thread at a time. The library owns only
+ *    the context and its scratch arena, which grows on demand and is freed by
+ *    ibip_ctx_destroy.
+ *  - Every call returns an ibip_status; on error the outputs are unspecified
+ *    and ibip_last_error() describes the failure. No C++ exception crosses
+ *    this ABI.
+ *  - Connectivity is 6 (face neighbours; 4 in 2D) everywhere.
+ */
+#ifndef IBIP_H
+#define IBIP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    IBIP_OK = 0,
+    IBIP_EINVAL = -1,     /* null pointer, bad dims, bad option or threshold list */
+    IBIP_ENOMEM = -2,     /* device or pinned host allocation failed */
+    IBIP_ENOSOLID = -3,   /* image holds no solid voxel: the distance transform is undefined */
+    IBIP_EDEVICE = -4,    /* a HIP runtime call or kernel launch failed */
+    IBIP_ECAPACITY = -5,  /* caller array too short, or an internal limit exceeded */
+    IBIP_ECANCELLED = -6  /* a job was cancelled before it ran */
+} ibip_status;
+
+typedef struct { int32_t X, Y, Z; } ibip_dims;
+
+/* Options of ibip_invade. Zero-initialise, then set what you need; a NULL
+   options pointer means all defaults. */
+typedef struct {
+    int64_t max_steps;   /* stop after this many steps; 0 = run until no candidate is left */
+    double sigma;        /* interfacial tension for the Washburn pressure (0 -> 1.0) */
+    double theta_rad;    /* contact angle through the defending phase, radians (default 0) */
+    double voxel_size;   /* length of one voxel (0 -> 1.0) */
+} ibip_invade_opts;
+
+typedef struct ibip_ctx ibip_ctx;
+
+/* Create a context on HIP device `device`, ordered on `stream` (a hipStream_t;
+   NULL = the null stream). */
+ibip_status ibip_ctx_create(ibip_ctx** out, int32_t device, void* stream);
+ibip_status ibip_ctx_destroy(ibip_ctx* ctx);
+ibip_status ibip_ctx_set_stream(ibip_ctx* ctx, void* stream);
+/* Text of the last error on this context ("" if none). Owned by the context. */
+const char* ibip_last_error(const ibip_ctx* ctx);
+/* Bytes of device scratch the context currently holds. */
+int64_t ibip_ctx_scratch_bytes(const ibip_ctx* ctx);
+
+/*
+ * ibip_edt -- distance transform of the pore space (Section 2.1, Figure 2(b)).
+ * dt2[v] = min over solid voxels s of |v - s|^2 (exact, integer), 0 on solid.
+ * Only voxels inside the image count as solid; the border is not solid.
+ * Errors: EINVAL, ENOSOLID (checked on device, reported after a sync).
+ */
+ibip_status ibip_edt(ibip_ctx* ctx, const uint8_t* image, ibip_dims dims, uint32_t* dt2);
+
+/*
+ * ibip_invade -- the invasion loop of Section 2.1 (Figure 2(e)-(l)).
+ * Step k takes the candidates (inlets, plus the face neighbours of the inlets
+ * and of every earlier centre, pore only, not yet a centre), finds the
+ * largest distance-transform value M_k among them, makes every candidate
+ * holding M_k a centre of step k, and inserts at each centre c the sphere
+ * B(c, M_k) = {v : |v - c|^2 < M_k} (which lies in pore space), writing k only
+ * where nothing was written before (first write wins). The loop stops when no
+ * candidate is left or after max_steps steps.
+ *
+ * inlets: uint8 mask, nonzero = inlet voxel (anywhere in the image; inlet
+ *         voxels on solid still contribute their neighbours).
+ * seq:    int32 out. -1 solid, 0 uninvaded pore, k >= 1 = step of invasion.
+ * rad2:   uint32 out or NULL. M_{seq[v]} for invaded voxels (the squared
+ *         radius of the sphere that invaded v), 0 elsewhere.
+ * centre_step: int32 out or NULL. The step at which v was a centre, 0 if never.
+ * n_steps: host out, the number of steps K.
+ * The per-step arrays of this call stay in the context until the next
+ * ibip_invade on it; read them with ibip_get_steps.
+ * Errors: EINVAL, ENOSOLID, ENOMEM, EDEVICE, ECAPACITY (more than 8192
+ * distinct distance values in the pore space).
+ */
+ibip_status ibip_invade(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlets, ibip_dims dims,
+                        const ibip_invade_opts* opts, int32_t* seq, uint32_t* rad2,
+                        int32_t* centre_step, int64_t* n_steps);
+
+/*
+ * ibip_get_steps -- per-step arrays of the last ibip_invade (Sections 2.2.1,
+ * 2.2.2). For k = 1..K, entry k-1 holds:
+ *   M      uint32  squared radius inserted at step k
+ *   n_new  int64   voxels first invaded at step k
+ *   sat    double  saturation after step k = (voxels invaded at steps <= k) / (pore voxels)
+ *   pc     double  Washburn capillary pressure 2 sigma cos(theta) / (sqrt(M_k) voxel_size)
+ * Each pointer is a DEVICE buffer of at least `capacity` entries, or NULL to
+ * skip it. Errors: EINVAL (no invade yet), ECAPACITY (capacity < K).
+ */
+ibip_status ibip_get_steps(ibip_ctx* ctx, uint32_t* M, int64_t* n_new, double* sat, double* pc,
+                           int64_t capacity);
+
+/*
+ * ibip_trap -- defender trapping and re-ranking (Section 2.2.3, Figure 7).
+ * A voxel invaded at step k (seq[v] = k > 0) is trapped when the defender
+ * region just before step k, {pore u : seq[u] == 0 or seq[u] >= k}, holds no
+ * path of face neighbours from v to a pore voxel with outlets[u] != 0.
+ * seq:          int32 in, as written by ibip_invade (-1 solid, 0 uninvaded).
+ * outlets:      uint8 mask in.
+ * trapped:      uint8 out, 1 for trapped invaded voxels, else 0.
+ * seq_trapped:  int32 out or NULL. -1 solid, 0 uninvaded or trapped, else the
+ *               dense rank (1..K') of seq[v] among the surviving step values.
+ * n_steps_after: host out or NULL, K'.
+ * Errors: EINVAL, ENOMEM, EDEVICE.
+ */
+ibip_status ibip_trap(ibip_ctx* ctx, const int32_t* seq, const uint8_t* outlets, ibip_dims dims,
+                      uint8_t* trapped, int32_t* seq_trapped, int64_t* n_steps_after);
+
+/*
+ * ibip_opening_drainage -- pressure-based drainage by morphological image
+ * opening (Section 2.4.1), the comparison of Section 3.1.1.
+ * For each squared radius T_i (HOST array, strictly decreasing, >= 1): erode
+ * the pore space by B(., T_i) (the centres c with dt2[c] >= T_i), keep the
+ * eroded components that touch the inlet candidates (inlets and their face
+ * neighbours, pore only), and dilate the kept centres by B(., T_i).
+ * mio_r2:  uint32 DEVICE out. The first (largest) T_i whose opening holds v, 0 if none.
+ * mio_sat: double HOST out or NULL, n entries: |{v : mio_r2[v] >= T_i}| / (pore voxels).
+ * Errors: EINVAL, ENOSOLID, ENOMEM, EDEVICE.
+ */
+ibip_status ibip_opening_drainage(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlets,
+                                  ibip_dims dims, const uint32_t* r2_thresholds, int32_t n,
+                                  uint32_t* mio_r2, double* mio_sat);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IBIP_H */

@@ -1,0 +1,224 @@
+"""MI355X-native image-based invasion percolation (IBIP).
+
+Thin Python binding over the C ABI of ``libibip_hip.so`` (``include/ibip.h``).
+PyTorch supplies device memory and the stream; every step of the computation
+runs in the library's HIP kernels. There is no CPU fallback: if the library is
+missing or no GPU is present, the calls raise.
+
+    import paper_2101_03240_amd as ibip
+    dt2 = ibip.edt(image)                         # exact squared EDT
+    r = ibip.invade(image, inlets)                # step / radius / saturation / Pc
+    t = ibip.trap(r["seq"], outlets)              # trapped defender, re-ranked steps
+    m = ibip.opening_drainage(image, inlets, T)   # pressure-based MIO drainage
+
+Image tensors are ``torch.uint8`` on a ROCm device with shape (X, Y, Z) or
+(Y, Z) (a 2D image, X = 1); nonzero = pore. uint32 outputs are returned in
+``torch.int32`` tensors holding the same bits (every value fits below 2^31 for
+the supported sizes).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+__all__ = ["edt", "invade", "trap", "opening_drainage", "IbipError", "library_path", "load_library"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libibip_hip.so")
+_lib = None
+_lock = threading.Lock()
+_ctx = {}
+
+_STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "ENOSOLID", -4: "EDEVICE", -5: "ECAPACITY",
+           -6: "ECANCELLED"}
+
+
+class IbipError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _Dims(ctypes.Structure):
+    _fields_ = [("X", ctypes.c_int32), ("Y", ctypes.c_int32), ("Z", ctypes.c_int32)]
+
+
+class _InvadeOpts(ctypes.Structure):
+    _fields_ = [("max_steps", ctypes.c_int64), ("sigma", ctypes.c_double),
+                ("theta_rad", ctypes.c_double), ("voxel_size", ctypes.c_double)]
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def load_library():
+    """Load ``libibip_hip.so`` (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(_LIB_PATH):
+            raise IbipError(-4, f"{_LIB_PATH} is missing; build it with paper_2101_03240_amd.build.build()")
+        lib = ctypes.CDLL(_LIB_PATH)
+        P, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        lib.ibip_ctx_create.argtypes = [ctypes.POINTER(P), i32, P]
+        lib.ibip_ctx_destroy.argtypes = [P]
+        lib.ibip_ctx_set_stream.argtypes = [P, P]
+        lib.ibip_last_error.argtypes = [P]
+        lib.ibip_last_error.restype = ctypes.c_char_p
+        lib.ibip_ctx_scratch_bytes.argtypes = [P]
+        lib.ibip_ctx_scratch_bytes.restype = i64
+        lib.ibip_edt.argtypes = [P, P, _Dims, P]
+        lib.ibip_invade.argtypes = [P, P, P, _Dims, ctypes.POINTER(_InvadeOpts), P, P, P, ctypes.POINTER(i64)]
+        lib.ibip_get_steps.argtypes = [P, P, P, P, P, i64]
+        lib.ibip_trap.argtypes = [P, P, P, _Dims, P, P, ctypes.POINTER(i64)]
+        lib.ibip_opening_drainage.argtypes = [P, P, P, _Dims, P, i32, P, P]
+        for fn in (lib.ibip_ctx_create, lib.ibip_ctx_destroy, lib.ibip_ctx_set_stream, lib.ibip_edt,
+                   lib.ibip_invade, lib.ibip_get_steps, lib.ibip_trap, lib.ibip_opening_drainage):
+            fn.restype = i32
+        _lib = lib
+    return _lib
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _context(device) -> ctypes.c_void_p:
+    torch = _torch()
+    lib = load_library()
+    idx = device.index if device.index is not None else torch.cuda.current_device()
+    ctx = _ctx.get(idx)
+    if ctx is None:
+        ctx = ctypes.c_void_p()
+        st = lib.ibip_ctx_create(ctypes.byref(ctx), idx, None)
+        if st != 0:
+            raise IbipError(st, f"cannot create a context on device {idx}")
+        _ctx[idx] = ctx
+    stream = torch.cuda.current_stream(idx).cuda_stream
+    lib.ibip_ctx_set_stream(ctx, ctypes.c_void_p(stream))
+    return ctx
+
+
+def _check(st: int, ctx):
+    if st != 0:
+        msg = load_library().ibip_last_error(ctx)
+        raise IbipError(st, msg.decode() if msg else "")
+
+
+def _dims_of(t) -> tuple[_Dims, tuple]:
+    if t.dim() == 2:
+        shape = (1,) + tuple(t.shape)
+    elif t.dim() == 3:
+        shape = tuple(t.shape)
+    else:
+        raise ValueError("expected a 2D or 3D tensor")
+    return _Dims(*shape), shape
+
+
+def _dev_u8(t, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a torch tensor on a GPU device")
+    if t.dtype != torch.uint8:
+        t = (t != 0).to(torch.uint8)
+    return t.contiguous()
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def edt(image):
+    """Exact squared distance from every voxel to the nearest solid voxel
+    (Section 2.1, Figure 2(b)); 0 on solid. Returns int32 bits of uint32."""
+    torch = _torch()
+    image = _dev_u8(image, "image")
+    dims, shape = _dims_of(image)
+    ctx = _context(image.device)
+    out = torch.empty(image.shape, dtype=torch.int32, device=image.device)
+    _check(load_library().ibip_edt(ctx, _ptr(image), dims, _ptr(out)), ctx)
+    return out
+
+
+def invade(image, inlets, max_steps: int = 0, sigma: float = 1.0, theta_rad: float = 0.0,
+           voxel_size: float = 1.0, rad2: bool = True, centre_step: bool = True, steps: bool = True):
+    """The invasion loop of Section 2.1 with the per-step arrays of Sections
+    2.2.1-2.2.2. Returns a dict with ``seq`` (int32: -1 solid, 0 uninvaded,
+    k = step), ``rad2``, ``centre_step``, ``K`` and, when ``steps``, the
+    per-step ``M``, ``n_new``, ``sat`` and ``pc`` (device tensors)."""
+    torch = _torch()
+    image = _dev_u8(image, "image")
+    inlets = _dev_u8(inlets, "inlets")
+    if inlets.shape != image.shape:
+        raise ValueError("inlets must have the image's shape")
+    dims, shape = _dims_of(image)
+    dev = image.device
+    ctx = _context(dev)
+    lib = load_library()
+    seq = torch.empty(image.shape, dtype=torch.int32, device=dev)
+    r2 = torch.empty(image.shape, dtype=torch.int32, device=dev) if rad2 else None
+    cs = torch.empty(image.shape, dtype=torch.int32, device=dev) if centre_step else None
+    opts = _InvadeOpts(int(max_steps), float(sigma), float(theta_rad), float(voxel_size))
+    K = ctypes.c_int64(0)
+    _check(lib.ibip_invade(ctx, _ptr(image), _ptr(inlets), dims, ctypes.byref(opts), _ptr(seq),
+                           _ptr(r2) if r2 is not None else None, _ptr(cs) if cs is not None else None,
+                           ctypes.byref(K)), ctx)
+    out = {"seq": seq, "rad2": r2, "centre_step": cs, "K": int(K.value)}
+    if steps:
+        k = max(int(K.value), 1)
+        M = torch.empty(k, dtype=torch.int32, device=dev)
+        n_new = torch.empty(k, dtype=torch.int64, device=dev)
+        sat = torch.empty(k, dtype=torch.float64, device=dev)
+        pc = torch.empty(k, dtype=torch.float64, device=dev)
+        _check(lib.ibip_get_steps(ctx, _ptr(M), _ptr(n_new), _ptr(sat), _ptr(pc), k), ctx)
+        kk = int(K.value)
+        out.update(M=M[:kk], n_new=n_new[:kk], sat=sat[:kk], pc=pc[:kk])
+    return out
+
+
+def trap(seq, outlets, seq_trapped: bool = True):
+    """Defender trapping and re-ranking (Section 2.2.3). Returns a dict with
+    ``trapped`` (uint8), ``seq_trapped`` (int32) and ``K_after``."""
+    torch = _torch()
+    if not isinstance(seq, torch.Tensor) or not seq.is_cuda or seq.dtype != torch.int32:
+        raise ValueError("seq must be an int32 torch tensor on a GPU device")
+    seq = seq.contiguous()
+    outlets = _dev_u8(outlets, "outlets")
+    if outlets.shape != seq.shape:
+        raise ValueError("outlets must have the shape of seq")
+    dims, shape = _dims_of(seq)
+    dev = seq.device
+    ctx = _context(dev)
+    tr = torch.empty(seq.shape, dtype=torch.uint8, device=dev)
+    st = torch.empty(seq.shape, dtype=torch.int32, device=dev) if seq_trapped else None
+    K = ctypes.c_int64(0)
+    _check(load_library().ibip_trap(ctx, _ptr(seq), _ptr(outlets), dims, _ptr(tr),
+                                    _ptr(st) if st is not None else None, ctypes.byref(K)), ctx)
+    return {"trapped": tr, "seq_trapped": st, "K_after": int(K.value)}
+
+
+def opening_drainage(image, inlets, thresholds):
+    """Pressure-based drainage by morphological image opening (Section 2.4.1)
+    at the squared radii ``thresholds`` (strictly decreasing, >= 1). Returns a
+    dict with ``mio_r2`` (int32 bits of uint32) and ``mio_sat`` (list)."""
+    torch = _torch()
+    image = _dev_u8(image, "image")
+    inlets = _dev_u8(inlets, "inlets")
+    if inlets.shape != image.shape:
+        raise ValueError("inlets must have the image's shape")
+    dims, shape = _dims_of(image)
+    dev = image.device
+    ctx = _context(dev)
+    T = [int(t) for t in thresholds]
+    arr = (ctypes.c_uint32 * max(len(T), 1))(*T)
+    sat = (ctypes.c_double * max(len(T), 1))()
+    out = torch.empty(image.shape, dtype=torch.int32, device=dev)
+    _check(load_library().ibip_opening_drainage(ctx, _ptr(image), _ptr(inlets), dims, ctypes.cast(arr, ctypes.c_void_p),
+                                                len(T), _ptr(out), ctypes.cast(sat, ctypes.c_void_p)), ctx)
+    return {"mio_r2": out, "mio_sat": [sat[i] for i in range(len(T))]}

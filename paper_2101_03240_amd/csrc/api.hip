@@ -1,0 +1,214 @@
+// C ABI of the library (declared in include/ibip.h): context, scratch arena,
+// argument checks and error plumbing around the kernels of edt.hip,
+// invade.hip, trap.hip and mio.hip.
+#include <cstring>
+#include <new>
+
+#include "ibip_internal.h"
+
+namespace ibip {
+
+ibip_status fail(ibip_ctx* ctx, ibip_status st, const std::string& what) {
+    if (ctx) ctx->err = what;
+    return st;
+}
+
+ibip_status hip_check(ibip_ctx* ctx, hipError_t e, const char* what) {
+    if (e == hipSuccess) return IBIP_OK;
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    return fail(ctx, e == hipErrorOutOfMemory ? IBIP_ENOMEM : IBIP_EDEVICE, m);
+}
+
+void* ensure(ibip_ctx* ctx, BufId id, size_t bytes) {
+    Buf& b = ctx->buf[id];
+    if (bytes == 0) bytes = 16;
+    if (b.bytes >= bytes) return b.p;
+    if (b.p) {
+        // the old buffer may still be in use by queued work on our stream
+        if (hipStreamSynchronize(ctx->stream) != hipSuccess) return nullptr;
+        (void)hipFree(b.p);
+        b.p = nullptr;
+        b.bytes = 0;
+    }
+    size_t want = bytes + bytes / 8;  // some headroom for slightly larger calls
+    void* p = nullptr;
+    if (hipMalloc(&p, want) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    b.p = p;
+    b.bytes = want;
+    return p;
+}
+
+void* pinned(ibip_ctx* ctx, size_t bytes) {
+    if (ctx->host_pinned_bytes >= bytes) return ctx->host_pinned;
+    if (ctx->host_pinned) {
+        if (hipStreamSynchronize(ctx->stream) != hipSuccess) return nullptr;
+        (void)hipHostFree(ctx->host_pinned);
+        ctx->host_pinned = nullptr;
+        ctx->host_pinned_bytes = 0;
+    }
+    void* p = nullptr;
+    if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    std::memset(p, 0, bytes);
+    ctx->host_pinned = p;
+    ctx->host_pinned_bytes = bytes;
+    return p;
+}
+
+bool dims_ok(ibip_dims d) {
+    if (d.X <= 0 || d.Y <= 0 || d.Z <= 0) return false;
+    if (d.X > 65535 || d.Y > 65535 || d.Z > 65535) return false;
+    return nvox(d) < ((int64_t)1 << 31);
+}
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+}  // namespace
+
+}  // namespace ibip
+
+using namespace ibip;
+
+extern "C" {
+
+ibip_status ibip_ctx_create(ibip_ctx** out, int32_t device, void* stream) {
+    if (!out) return IBIP_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return IBIP_EDEVICE;
+    ibip_ctx* ctx = new (std::nothrow) ibip_ctx();
+    if (!ctx) return IBIP_ENOMEM;
+    ctx->device = device;
+    ctx->stream = (hipStream_t)stream;
+    *out = ctx;
+    return IBIP_OK;
+}
+
+ibip_status ibip_ctx_destroy(ibip_ctx* ctx) {
+    if (!ctx) return IBIP_EINVAL;
+    DeviceGuard g(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    for (auto& b : ctx->buf)
+        if (b.p) (void)hipFree(b.p);
+    if (ctx->host_pinned) (void)hipHostFree(ctx->host_pinned);
+    delete ctx;
+    return IBIP_OK;
+}
+
+ibip_status ibip_ctx_set_stream(ibip_ctx* ctx, void* stream) {
+    if (!ctx) return IBIP_EINVAL;
+    ctx->stream = (hipStream_t)stream;
+    return IBIP_OK;
+}
+
+const char* ibip_last_error(const ibip_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int64_t ibip_ctx_scratch_bytes(const ibip_ctx* ctx) {
+    if (!ctx) return -1;
+    int64_t t = 0;
+    for (const auto& b : ctx->buf) t += (int64_t)b.bytes;
+    return t;
+}
+
+ibip_status ibip_edt(ibip_ctx* ctx, const uint8_t* image, ibip_dims dims, uint32_t* dt2) {
+    if (!ctx) return IBIP_EINVAL;
+    if (!image || !dt2) return fail(ctx, IBIP_EINVAL, "edt: null pointer");
+    if (!dims_ok(dims)) return fail(ctx, IBIP_EINVAL, "edt: bad dims");
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(ctx, IBIP_EDEVICE, "edt: cannot select device");
+    const int64_t n = nvox(dims);
+    uint16_t* g16 = (uint16_t*)ensure(ctx, B_TMP0, sizeof(uint16_t) * n);
+    uint32_t* tmp = (uint32_t*)ensure(ctx, B_TMP1, sizeof(uint32_t) * n);
+    uint8_t* misc = (uint8_t*)ensure(ctx, B_MISC, 4096);
+    uint32_t* h = (uint32_t*)pinned(ctx, 4096);
+    if (!g16 || !tmp || !misc || !h) return fail(ctx, IBIP_ENOMEM, "edt: allocation failed");
+    uint32_t* flag = (uint32_t*)(misc + 3600);
+    ibip_status rc;
+    if ((rc = hip_check(ctx, hipMemsetAsync(flag, 0, 4, ctx->stream), "memset")) != IBIP_OK) return rc;
+    if ((rc = hip_check(ctx, launch_edt(image, nullptr, 0, dims, g16, tmp, dt2, flag, ctx->stream), "edt launch")) !=
+        IBIP_OK)
+        return rc;
+    if ((rc = hip_check(ctx, hipMemcpyAsync(h, flag, 4, hipMemcpyDeviceToHost, ctx->stream), "copy")) != IBIP_OK)
+        return rc;
+    if ((rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "sync")) != IBIP_OK) return rc;
+    if (!h[0]) return fail(ctx, IBIP_ENOSOLID, "edt: image holds no solid voxel");
+    return IBIP_OK;
+}
+
+ibip_status ibip_invade(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlets, ibip_dims dims,
+                        const ibip_invade_opts* opts, int32_t* seq, uint32_t* rad2, int32_t* centre_step,
+                        int64_t* n_steps) {
+    if (!ctx) return IBIP_EINVAL;
+    if (!image || !inlets || !seq) return fail(ctx, IBIP_EINVAL, "invade: null pointer");
+    if (!dims_ok(dims)) return fail(ctx, IBIP_EINVAL, "invade: bad dims");
+    if (opts && opts->max_steps < 0) return fail(ctx, IBIP_EINVAL, "invade: max_steps < 0");
+    if (opts && (opts->voxel_size < 0.0)) return fail(ctx, IBIP_EINVAL, "invade: voxel_size < 0");
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(ctx, IBIP_EDEVICE, "invade: cannot select device");
+    return run_invade(ctx, image, inlets, dims, opts, seq, rad2, centre_step, n_steps);
+}
+
+ibip_status ibip_get_steps(ibip_ctx* ctx, uint32_t* M, int64_t* n_new, double* sat, double* pc, int64_t capacity) {
+    if (!ctx) return IBIP_EINVAL;
+    if (!ctx->have_steps) return fail(ctx, IBIP_EINVAL, "get_steps: no completed invade on this context");
+    const int64_t K = ctx->last_K;
+    if (capacity < K) return fail(ctx, IBIP_ECAPACITY, "get_steps: capacity below the number of steps");
+    if (K == 0) return IBIP_OK;
+    DeviceGuard g(ctx->device);
+    hipStream_t s = ctx->stream;
+    ibip_status rc;
+    struct { void* dst; BufId id; size_t sz; } items[4] = {
+        {M, B_M, sizeof(uint32_t)}, {n_new, B_NNEW, sizeof(int64_t)}, {sat, B_SAT, sizeof(double)},
+        {pc, B_PC, sizeof(double)}};
+    for (auto& it : items) {
+        if (!it.dst) continue;
+        if ((rc = hip_check(ctx, hipMemcpyAsync(it.dst, ctx->buf[it.id].p, it.sz * K, hipMemcpyDeviceToDevice, s),
+                            "get_steps copy")) != IBIP_OK)
+            return rc;
+    }
+    return IBIP_OK;
+}
+
+ibip_status ibip_trap(ibip_ctx* ctx, const int32_t* seq, const uint8_t* outlets, ibip_dims dims, uint8_t* trapped,
+                      int32_t* seq_trapped, int64_t* n_steps_after) {
+    if (!ctx) return IBIP_EINVAL;
+    if (!seq || !outlets || !trapped) return fail(ctx, IBIP_EINVAL, "trap: null pointer");
+    if (!dims_ok(dims)) return fail(ctx, IBIP_EINVAL, "trap: bad dims");
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(ctx, IBIP_EDEVICE, "trap: cannot select device");
+    return run_trap(ctx, seq, outlets, dims, trapped, seq_trapped, n_steps_after);
+}
+
+ibip_status ibip_opening_drainage(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlets, ibip_dims dims,
+                                  const uint32_t* r2_thresholds, int32_t n, uint32_t* mio_r2, double* mio_sat) {
+    if (!ctx) return IBIP_EINVAL;
+    if (!image || !inlets || !mio_r2 || (n > 0 && !r2_thresholds))
+        return fail(ctx, IBIP_EINVAL, "opening_drainage: null pointer");
+    if (n < 0) return fail(ctx, IBIP_EINVAL, "opening_drainage: n < 0");
+    if (!dims_ok(dims)) return fail(ctx, IBIP_EINVAL, "opening_drainage: bad dims");
+    for (int32_t i = 0; i < n; i++)
+        if (r2_thresholds[i] == 0 || (i > 0 && r2_thresholds[i] >= r2_thresholds[i - 1]))
+            return fail(ctx, IBIP_EINVAL, "opening_drainage: thresholds must be >= 1 and strictly decreasing");
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(ctx, IBIP_EDEVICE, "opening_drainage: cannot select device");
+    return run_mio(ctx, image, inlets, dims, r2_thresholds, n, mio_r2, mio_sat);
+}
+
+}  // extern "C"

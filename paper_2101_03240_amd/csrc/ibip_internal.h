@@ -1,0 +1,125 @@
+// Internal declarations of the HIP library: context, scratch arena, error
+// plumbing and the host-side launchers each .hip file provides.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <string>
+
+#include "../../include/ibip.h"
+
+namespace ibip {
+
+// Distinct distance values the invasion loop keeps in LDS (bucket heads and
+// tails of 4 bytes each, plus a two-level occupancy bitmap).
+constexpr int kMaxRanks = 8192;
+// A step with more centres than this is handed to the whole-GPU kernel.
+constexpr uint32_t kWideRound = 8192;
+constexpr uint32_t kInf32 = 0xFFFFFFFFu;
+
+// One grow-only device allocation.
+struct Buf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+enum BufId {
+    B_KEY = 0,     // uint32[N]   dt2, then the rank of dt2 (0 = solid)
+    B_STATE,       // int32[N]    -2 solid, 0 unseen, -1 candidate, k > 0 centre of step k
+    B_BUCKET,      // uint32[N]   candidate voxel indices grouped by rank
+    B_HIST,        // uint32[V]   histogram of dt2 values, then value -> rank
+    B_OFF,         // uint32[R+2] bucket offsets by rank
+    B_HEAD,        // uint32[R+1]
+    B_TAIL,        // uint32[R+1]
+    B_VAL,         // uint32[R+1] rank -> dt2 value
+    B_M,           // uint32[K]   squared radius per step
+    B_NNEW,        // int64[K]
+    B_SAT,         // double[K]
+    B_PC,          // double[K]
+    B_FULL,        // uint32[N]   centres that need a full ball
+    B_MISC,        // small control block (LoopState and counters)
+    B_TMP0,        // generic N-sized scratch
+    B_TMP1,
+    B_TMP2,
+    B_SCAN,        // scan partials
+    B_NUM
+};
+
+// Device-side control block of the invasion loop (lives in B_MISC).
+struct LoopState {
+    uint32_t k;        // next step number
+    uint32_t status;   // LoopStatus
+    uint32_t R;        // number of ranks
+    uint32_t big_r;    // pending wide step: rank, bucket range [big_h, big_t)
+    uint32_t big_h;
+    uint32_t big_t;
+    uint32_t n_pore;
+    uint32_t maxval;   // largest dt2 value
+    uint32_t solid_seen;
+    uint32_t n_full;   // centres that need a full ball
+    uint32_t err;
+    uint32_t big_k;    // step number of the pending wide step
+    int64_t max_steps;
+};
+
+enum LoopStatus : uint32_t { LS_RUN = 0, LS_DONE = 1, LS_WIDE = 2, LS_MAXSTEPS = 3 };
+
+}  // namespace ibip
+
+struct ibip_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    ibip::Buf buf[ibip::B_NUM];
+    void* host_pinned = nullptr;   // pinned mirror of LoopState and small results
+    size_t host_pinned_bytes = 0;
+    // results of the last invade
+    int64_t last_K = -1;
+    int64_t last_n_pore = 0;
+    bool have_steps = false;
+};
+
+namespace ibip {
+
+// Set ctx->err and return `st`.
+ibip_status fail(ibip_ctx* ctx, ibip_status st, const std::string& what);
+// Map a HIP error to IBIP_EDEVICE with a message; IBIP_OK if e == hipSuccess.
+ibip_status hip_check(ibip_ctx* ctx, hipError_t e, const char* what);
+// Ensure buffer `id` holds at least `bytes`; returns its pointer or nullptr.
+void* ensure(ibip_ctx* ctx, BufId id, size_t bytes);
+void* pinned(ibip_ctx* ctx, size_t bytes);
+bool dims_ok(ibip_dims d);
+inline int64_t nvox(ibip_dims d) { return (int64_t)d.X * d.Y * d.Z; }
+
+// ---- launchers (each returns hipSuccess or the first launch error) ----
+// EDT: dt2 = squared distance to the nearest voxel with feature != 0, where
+// feature(v) = (image[v] == 0) when `image` is given, else (w[v] >= thr).
+// Sets *solid_flag (device) to 1 if any feature voxel exists.
+hipError_t launch_edt(const uint8_t* image, const uint32_t* w, uint32_t thr, ibip_dims d,
+                      uint16_t* g16, uint32_t* tmp32, uint32_t* out, uint32_t* solid_flag,
+                      hipStream_t s);
+
+// Exclusive scan of n uint32 values in place; returns the total in *total (device).
+hipError_t launch_scan_u32(uint32_t* data, int64_t n, uint32_t* partials, uint32_t* total,
+                           hipStream_t s);
+
+// Maximin reconstruction: w[v] = max over face-connected paths from the seeds
+// to v of the smallest cap along the path. On entry w holds the seed values
+// (w <= cap) and 0 elsewhere. cap(v) is cap32[v] when cap32 is given, else it
+// is derived from a step image: 0 on solid (seq < 0), 0xFFFFFFFF on uninvaded
+// pore (seq == 0), seq[v] on invaded voxels. Iterates to the fixed point;
+// *n_iter receives the number of sweeps.
+ibip_status reconstruct(ibip_ctx* ctx, const int32_t* seq, const uint32_t* cap32, ibip_dims d,
+                        uint32_t* w, int* n_iter);
+
+ibip_status run_invade(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlets, ibip_dims d,
+                       const ibip_invade_opts* opts, int32_t* seq, uint32_t* rad2, int32_t* centre_step,
+                       int64_t* n_steps);
+ibip_status run_trap(ibip_ctx* ctx, const int32_t* seq, const uint8_t* outlets, ibip_dims d,
+                     uint8_t* trapped, int32_t* seq_trapped, int64_t* n_steps_after);
+ibip_status run_mio(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlets, ibip_dims d,
+                    const uint32_t* T, int32_t n, uint32_t* mio_r2, double* mio_sat);
+
+}  // namespace ibip

@@ -1,0 +1,692 @@
+// The invasion loop of Section 2.1 (Figure 2(e)-(l)) and its per-step
+// post-processing (Sections 2.2.1-2.2.2).
+//
+// Data layout in HBM (N voxels, N_pore pore voxels, R distinct dt2 values):
+//   key[N]      uint32  rank of dt2 among the distinct pore values (1..R), 0 on solid
+//   state[N]    int32   -2 solid, 0 unseen pore, -1 candidate, k > 0 centre of step k
+//   bucket[N_pore] uint32  candidates grouped by rank; rank r owns the slice
+//               [off[r], off[r+1]) whose length is the number of pore voxels
+//               of that rank, so every pore voxel fits exactly once
+//   head/tail[R+1]  the live part of each slice
+//
+// One step (a "round") pops the whole live part of the highest non-empty
+// slice (every candidate holding the maximum -- the all-maxima rule), marks
+// those voxels as centres of the step and appends their unseen pore face
+// neighbours to the slices of their ranks. Entries appended during a step are
+// popped from the next step on, which reproduces the rescan of the dilated
+// inlets image step by step.
+//
+// Steps are a chain of dependent rounds, mostly tiny, so the loop runs inside
+// ONE workgroup with the slice heads, tails and a two-level occupancy bitmap
+// in LDS: a round costs one workgroup barrier and a few L2 round trips. A
+// step with more than kWideRound centres exits to the host, which runs that
+// step with the whole GPU and resumes the loop.
+//
+// Sphere insertion is decoupled from selection (selection never reads what
+// was painted): after the loop, seq[v] = min over centres c whose ball
+// B(c, M) = {|v - c|^2 < M} holds v of step(c), as an atomicMin per stamp --
+// this equals first-write-wins in step order. A centre c with a face
+// neighbour p that was a centre of an earlier step with a ball at least as
+// large stamps only the part of its ball outside B(p): the one-voxel cap
+// S = {o : |o|^2 < M <= |o - n|^2} (n = p - c), filtered by every other such
+// neighbour. This is exact: the smallest step covering a voxel always stamps
+// it, since a ball it skipped is covered by an earlier ball.
+#include <climits>
+
+#include "ibip_internal.h"
+
+namespace ibip {
+
+namespace {
+
+// largest q with q * q <= a (64-bit products: no overflow for any a)
+__device__ inline uint32_t isqrt_u32(uint32_t a) {
+    uint64_t q = (uint64_t)sqrtf((float)a);
+    while (q * q > a) q--;
+    while ((q + 1) * (q + 1) <= a) q++;
+    return (uint32_t)q;
+}
+
+__device__ inline uint64_t lanemask_lt() {
+    const int lane = threadIdx.x & 63;
+    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// ---------------------------------------------------------------------------
+// Setup
+// ---------------------------------------------------------------------------
+
+// Histogram of dt2 over pore voxels, pore count, largest value.
+constexpr int kHistLds = 2048;
+// Values >= vlimit (the no-solid sentinel) are skipped; the host rejects such
+// images before anything reads the tables.
+__global__ __launch_bounds__(256) void k_hist(const uint8_t* __restrict__ img, const uint32_t* __restrict__ dt2,
+                                              int64_t n, uint32_t vlimit, uint32_t* hist, LoopState* st) {
+    __shared__ uint32_t h[kHistLds];
+    __shared__ uint32_t s_pore, s_max;
+    for (int i = threadIdx.x; i < kHistLds; i += 256) h[i] = 0;
+    if (threadIdx.x == 0) { s_pore = 0; s_max = 0; }
+    __syncthreads();
+    uint32_t pore = 0, mx = 0;
+    for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < n; v += (int64_t)gridDim.x * 256) {
+        if (!img[v]) continue;
+        uint32_t d = dt2[v];
+        if (d >= vlimit) continue;
+        pore++;
+        mx = d > mx ? d : mx;
+        if (d < kHistLds) atomicAdd(&h[d], 1u);
+        else atomicAdd(&hist[d], 1u);
+    }
+    atomicAdd(&s_pore, pore);
+    atomicMax(&s_max, mx);
+    __syncthreads();
+    for (int i = threadIdx.x; i < kHistLds; i += 256)
+        if (h[i]) atomicAdd(&hist[i], h[i]);
+    if (threadIdx.x == 0) {
+        atomicAdd(&st->n_pore, s_pore);
+        atomicMax(&st->maxval, s_max);
+    }
+}
+
+// present[v] = 1 if some pore voxel has dt2 == v (v >= 1)
+__global__ void k_present(const uint32_t* hist, uint32_t* present, int64_t V) {
+    int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (v < V) present[v] = (v >= 1 && hist[v] > 0) ? 1u : 0u;
+}
+
+// After the scans: offv[v] = bucket offset of value v, rk[v] = rank - 1 of v.
+__global__ void k_rank_tables(const uint32_t* cnt_scanned, const uint32_t* present_scanned,
+                              const uint32_t* hist_raw_flag, int64_t V, uint32_t* val, uint32_t* off,
+                              uint32_t* head, uint32_t* tail) {
+    int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (v >= V || v == 0 || !hist_raw_flag[v]) return;
+    uint32_t r = present_scanned[v] + 1;
+    val[r] = (uint32_t)v;
+    off[r] = cnt_scanned[v];
+    head[r] = cnt_scanned[v];
+    tail[r] = cnt_scanned[v];
+}
+
+// key = rank (0 on solid); state; seq = INT_MAX on pore, -1 on solid.
+__global__ __launch_bounds__(256) void k_convert(const uint8_t* __restrict__ img, uint32_t* key,
+                                                 const uint32_t* __restrict__ present_scanned, int64_t n,
+                                                 int32_t* state, int32_t* seq) {
+    int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (v >= n) return;
+    if (img[v]) {
+        key[v] = present_scanned[key[v]] + 1;
+        state[v] = 0;
+        seq[v] = INT_MAX;
+    } else {
+        key[v] = 0;
+        state[v] = -2;
+        seq[v] = -1;
+    }
+}
+
+// Append u to the slice of rank rr with one atomic per distinct rank in the
+// wave (lanes with active == false do nothing).
+__device__ inline void push_global(bool active, uint32_t u, uint32_t rr, uint32_t* tail, uint32_t* bucket) {
+    uint64_t pending = __ballot(active);
+    while (pending) {
+        const int leader = __ffsll((unsigned long long)pending) - 1;
+        const uint32_t lr = __shfl(rr, leader, 64);
+        const uint64_t same = __ballot(active && rr == lr) & pending;
+        uint32_t base = 0;
+        if ((threadIdx.x & 63) == leader) base = atomicAdd(&tail[lr], (uint32_t)__popcll(same));
+        base = __shfl(base, leader, 64);
+        if (active && rr == lr) bucket[base + __popcll(same & lanemask_lt())] = u;
+        pending &= ~same;
+    }
+}
+
+// Seeds: Q0 = (inlets U their face neighbours) restricted to pore.
+__global__ __launch_bounds__(256) void k_seed(const uint8_t* __restrict__ inlets, const uint32_t* __restrict__ key,
+                                              int X, int Y, int Z, int32_t* state, uint32_t* tail,
+                                              uint32_t* bucket) {
+    const int64_t n = (int64_t)X * Y * Z;
+    const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const bool inl = v < n && inlets[v] != 0;
+    if (!__any(inl)) return;
+    const int64_t yz = (int64_t)Y * Z;
+    int z = 0, y = 0, x = 0;
+    if (inl) { z = (int)(v % Z); y = (int)((v / Z) % Y); x = (int)(v / yz); }
+#pragma unroll
+    for (int j = 0; j < 7; j++) {
+        bool ok = inl;
+        int64_t u = v;
+        if (j == 1) { ok &= x > 0; u = v - yz; }
+        if (j == 2) { ok &= x < X - 1; u = v + yz; }
+        if (j == 3) { ok &= y > 0; u = v - Z; }
+        if (j == 4) { ok &= y < Y - 1; u = v + Z; }
+        if (j == 5) { ok &= z > 0; u = v - 1; }
+        if (j == 6) { ok &= z < Z - 1; u = v + 1; }
+        bool won = false;
+        uint32_t rr = 0;
+        if (ok && state[u] == 0) {
+            won = atomicCAS(&state[u], 0, -1) == 0;
+            if (won) rr = key[u];
+        }
+        push_global(won, (uint32_t)u, rr, tail, bucket);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The round loop: one workgroup.
+// ---------------------------------------------------------------------------
+struct LoopArgs {
+    LoopState* st;
+    uint32_t* head;
+    uint32_t* tail;
+    const uint32_t* val;
+    uint32_t* bucket;
+    int32_t* state;
+    const uint32_t* key;
+    uint32_t* M;
+    int X, Y, Z;
+    uint32_t wide;
+};
+
+constexpr int kLoopThreads = 1024;
+constexpr int kBitWords = (kMaxRanks >> 5) + 2;
+constexpr int kSumWords = (kBitWords >> 5) + 1;
+
+struct LoopShared {
+    uint32_t head[kMaxRanks + 1];
+    uint32_t tail[kMaxRanks + 1];
+    uint32_t bits[kBitWords];
+    uint32_t sum[kSumWords];
+    uint32_t r, h, cnt, k, pushmax, exit;
+};
+
+__device__ inline void lds_set(LoopShared& s, uint32_t r) {
+    atomicOr(&s.bits[r >> 5], 1u << (r & 31));
+    atomicOr(&s.sum[r >> 10], 1u << ((r >> 5) & 31));
+}
+
+__device__ inline void lds_push(LoopShared& s, bool active, uint32_t u, uint32_t rr, uint32_t* bucket) {
+    uint64_t pending = __ballot(active);
+    while (pending) {
+        const int leader = __ffsll((unsigned long long)pending) - 1;
+        const uint32_t lr = __shfl(rr, leader, 64);
+        const uint64_t same = __ballot(active && rr == lr) & pending;
+        uint32_t base = 0;
+        if ((threadIdx.x & 63) == leader) {
+            base = atomicAdd(&s.tail[lr], (uint32_t)__popcll(same));
+            lds_set(s, lr);
+            atomicMax(&s.pushmax, lr);
+        }
+        base = __shfl(base, leader, 64);
+        if (active && rr == lr) bucket[base + __popcll(same & lanemask_lt())] = u;
+        pending &= ~same;
+    }
+}
+
+// Make centre c a centre of step k and try to claim its unseen pore face
+// neighbours; calls push(active, u, rank) once per direction for the wave.
+template <class Push>
+__device__ inline void expand(bool have, uint32_t c, uint32_t k, const LoopArgs& a, Push push) {
+    const int64_t yz = (int64_t)a.Y * a.Z;
+    int z = 0, y = 0, x = 0;
+    if (have) {
+        a.state[c] = (int32_t)k;
+        z = (int)(c % (uint32_t)a.Z);
+        uint32_t t = c / (uint32_t)a.Z;
+        y = (int)(t % (uint32_t)a.Y);
+        x = (int)(t / (uint32_t)a.Y);
+    }
+    int32_t* state = a.state;
+    // issue the six claims back to back, then push per direction
+    bool won[6];
+    int64_t uu[6] = {(int64_t)c - yz, (int64_t)c + yz, (int64_t)c - a.Z, (int64_t)c + a.Z,
+                     (int64_t)c - 1, (int64_t)c + 1};
+    bool okd[6] = {have && x > 0, have && x < a.X - 1, have && y > 0, have && y < a.Y - 1,
+                   have && z > 0, have && z < a.Z - 1};
+#pragma unroll
+    for (int j = 0; j < 6; j++) won[j] = okd[j] && atomicCAS(&state[uu[j]], 0, -1) == 0;
+#pragma unroll
+    for (int j = 0; j < 6; j++) {
+        uint32_t rr = won[j] ? a.key[uu[j]] : 0u;
+        push(won[j], (uint32_t)uu[j], rr);
+    }
+}
+
+__device__ inline uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+
+// highest set rank strictly below r (0 = none), with every loaded word made
+// wave-uniform so the search runs on scalar branches
+__device__ inline uint32_t lds_highest_below_uni(const LoopShared& s, uint32_t r) {
+    uint32_t w = r >> 5, b = r & 31;
+    uint32_t m = uni(s.bits[w]) & ((1u << b) - 1u);
+    if (m) return (w << 5) + 31 - __clz(m);
+    uint32_t sw = w >> 5, sb = w & 31;
+    uint32_t ms = uni(s.sum[sw]) & ((1u << sb) - 1u);
+    for (;;) {
+        if (ms) {
+            uint32_t ww = (sw << 5) + 31 - __clz(ms);
+            return (ww << 5) + 31 - __clz(uni(s.bits[ww]));
+        }
+        if (sw == 0) return 0;
+        sw--;
+        ms = uni(s.sum[sw]);
+    }
+}
+
+// Control flow: the per-step decisions run in all 64 lanes of wave 0 under a
+// wave-uniform branch, on values made uniform with readfirstlane (duplicate
+// stores of one value from several lanes are harmless). No lane-divergent
+// region sits in the control path of the barrier loop, so the compiler keeps
+// both barriers in uniform control flow; a `tid == 0` region there can be
+// restructured so that lanes 1..63 of wave 0 loop back to a barrier while
+// lane 0 waits outside the loop.
+__global__ __launch_bounds__(kLoopThreads) void k_loop(LoopArgs a) {
+    __shared__ LoopShared s;
+    const int tid = threadIdx.x;
+    const bool wave0 = uni((uint32_t)tid >> 6) == 0;
+    const uint32_t R = a.st->R;
+    for (uint32_t r = tid; r <= R; r += kLoopThreads) {
+        s.head[r] = a.head[r];
+        s.tail[r] = a.tail[r];
+    }
+    for (int w = tid; w < kBitWords; w += kLoopThreads) s.bits[w] = 0;
+    for (int w = tid; w < kSumWords; w += kLoopThreads) s.sum[w] = 0;
+    __syncthreads();
+    for (uint32_t r = 1 + tid; r <= R; r += kLoopThreads)
+        if (s.tail[r] > s.head[r]) lds_set(s, r);
+    __syncthreads();
+    const int64_t max_steps = a.st->max_steps;
+    const uint32_t n_pore = a.st->n_pore;
+    // loop control, live in wave 0 only
+    uint32_t r = 0, k = 0;
+    bool first = true;
+    if (wave0) {
+        r = lds_highest_below_uni(s, R + 1);
+        k = uni(a.st->k);
+    }
+    for (;;) {
+        if (wave0) {
+            if (!first) {
+                // close the previous step: pick the next maximum
+                uint32_t cand;
+                if (uni(s.tail[r]) > uni(s.head[r])) {
+                    cand = r;
+                } else {
+                    const uint32_t wv = uni(s.bits[r >> 5]) & ~(1u << (r & 31));
+                    s.bits[r >> 5] = wv;
+                    if (wv == 0) s.sum[r >> 10] = uni(s.sum[r >> 10]) & ~(1u << ((r >> 5) & 31));
+                    cand = lds_highest_below_uni(s, r);
+                }
+                const uint32_t pm = uni(s.pushmax);
+                r = cand > pm ? cand : pm;
+                k = k + 1;
+            }
+            uint32_t ex = 0, hh = 0, cn = 0;
+            if (r == 0) {
+                a.st->status = LS_DONE;
+                ex = 1;
+            } else if (k > n_pore) {
+                // every step takes at least one new pore voxel: more steps than
+                // pore voxels means corrupted state; stop instead of looping
+                a.st->err = 1;
+                a.st->status = LS_DONE;
+                ex = 1;
+            } else if (max_steps > 0 && (int64_t)k > max_steps) {
+                a.st->status = LS_MAXSTEPS;
+                ex = 1;
+            } else {
+                const uint32_t h = uni(s.head[r]), t = uni(s.tail[r]);
+                s.head[r] = t;
+                a.M[k - 1] = uni(a.val[r]);
+                if (t - h > a.wide) {
+                    a.st->big_r = r;
+                    a.st->big_h = h;
+                    a.st->big_t = t;
+                    a.st->big_k = k;
+                    a.st->status = LS_WIDE;
+                    k = k + 1;
+                    ex = 1;
+                } else {
+                    hh = h;
+                    cn = t - h;
+                    s.pushmax = 0;
+                }
+            }
+            s.exit = ex;
+            s.h = hh;
+            s.cnt = cn;
+            s.k = k;
+        }
+        first = false;
+        __syncthreads();
+        if (uni(s.exit)) break;
+        const uint32_t h = uni(s.h);
+        const uint32_t cnt = uni(s.cnt);
+        const uint32_t kk = uni(s.k);
+        const uint32_t ntrip = (cnt + kLoopThreads - 1) / kLoopThreads;
+        for (uint32_t it = 0; it < ntrip; it++) {
+            const uint32_t i = it * kLoopThreads + tid;
+            const bool have = i < cnt;
+            const uint32_t c = have ? a.bucket[h + i] : 0u;
+            expand(have, c, kk, a, [&](bool act, uint32_t u, uint32_t rr) { lds_push(s, act, u, rr, a.bucket); });
+        }
+        __syncthreads();
+    }
+    if (wave0) a.st->k = k;
+    for (uint32_t q = tid; q <= R; q += kLoopThreads) {
+        a.head[q] = s.head[q];
+        a.tail[q] = s.tail[q];
+    }
+}
+
+// One step with many centres, spread over the whole GPU.
+__global__ __launch_bounds__(256) void k_wide(LoopArgs a) {
+    const uint32_t h = a.st->big_h, t = a.st->big_t, k = a.st->big_k;
+    const uint32_t cnt = t - h;
+    const uint32_t stride = gridDim.x * 256;
+    const uint32_t ntrip = (cnt + stride - 1) / stride;
+    for (uint32_t it = 0; it < ntrip; it++) {
+        const uint32_t i = it * stride + blockIdx.x * 256 + threadIdx.x;
+        const bool have = i < cnt;
+        const uint32_t c = have ? a.bucket[h + i] : 0u;
+        expand(have, c, k, a, [&](bool act, uint32_t u, uint32_t rr) { push_global(act, u, rr, a.tail, a.bucket); });
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Sphere insertion
+// ---------------------------------------------------------------------------
+struct PaintArgs {
+    const int32_t* state;
+    const uint32_t* key;
+    const uint32_t* val;
+    int32_t* seq;
+    uint32_t* full;
+    uint32_t* n_full;
+    int X, Y, Z;
+};
+
+__device__ inline void stamp(int32_t* seq, int64_t v, int32_t k) {
+    if (seq[v] > k) atomicMin(&seq[v], k);
+}
+
+// One thread per voxel: centres with an earlier, at-least-as-large face
+// neighbour stamp their cap; the others are listed for the full-ball pass.
+__global__ __launch_bounds__(256) void k_paint_shell(PaintArgs a) {
+    const int64_t yz = (int64_t)a.Y * a.Z;
+    const int64_t n = (int64_t)a.X * yz;
+    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (c >= n) return;
+    const int32_t k = a.state[c];
+    if (k <= 0) return;
+    const uint32_t rc = a.key[c];
+    const uint32_t m = a.val[rc];
+    const int z = (int)(c % a.Z), y = (int)((c / a.Z) % a.Y), x = (int)(c / yz);
+    // neighbour j sits at c + n_j: axis j >> 1, sign (j & 1) ? +1 : -1
+    const bool inb[6] = {x > 0, x < a.X - 1, y > 0, y < a.Y - 1, z > 0, z < a.Z - 1};
+    const int64_t off[6] = {-yz, yz, -(int64_t)a.Z, (int64_t)a.Z, -1, 1};
+    uint32_t qmask = 0;
+    uint32_t mp[6];
+#pragma unroll
+    for (int j = 0; j < 6; j++) {
+        mp[j] = 0;
+        if (!inb[j]) continue;
+        const int32_t kp = a.state[c + off[j]];
+        if (kp > 0 && kp < k) {
+            const uint32_t rp = a.key[c + off[j]];
+            if (rp >= rc) { qmask |= 1u << j; mp[j] = a.val[rp]; }
+        }
+    }
+    if (!qmask) {
+        const uint32_t slot = atomicAdd(a.n_full, 1u);
+        a.full[slot] = (uint32_t)c;
+        return;
+    }
+    const int j0 = __ffs(qmask) - 1;
+    const int A = j0 >> 1;                  // axis of the cap
+    const int sgn = (j0 & 1) ? -1 : 1;      // cap on the side away from the neighbour
+    const int B = (A + 1) % 3, C = (A + 2) % 3;
+    const int pos[3] = {x, y, z};
+    const int dim[3] = {a.X, a.Y, a.Z};
+    const int64_t stride[3] = {yz, (int64_t)a.Z, 1};
+    const int Rb = (int)isqrt_u32(m - 1);
+    for (int p = -Rb; p <= Rb; p++) {
+        const int pb = pos[B] + p;
+        if (pb < 0 || pb >= dim[B]) continue;
+        const uint32_t rem = m - 1 - (uint32_t)(p * p);
+        const int U = (int)isqrt_u32(rem);
+        for (int q = -U; q <= U; q++) {
+            const int pc = pos[C] + q;
+            if (pc < 0 || pc >= dim[C]) continue;
+            const int w = (int)isqrt_u32(rem - (uint32_t)(q * q));
+            const int oa = sgn * w;
+            const int pa = pos[A] + oa;
+            if (pa < 0 || pa >= dim[A]) continue;
+            int o[3];
+            o[A] = oa; o[B] = p; o[C] = q;
+            const uint32_t oo = (uint32_t)(w * w + p * p + q * q);
+            bool covered = false;
+            uint32_t rest = qmask & ~(1u << j0);
+            while (rest) {
+                const int j = __ffs(rest) - 1;
+                rest &= rest - 1;
+                const int sj = (j & 1) ? 1 : -1;      // n_j component
+                const uint32_t d = oo - 2 * sj * o[j >> 1] + 1;  // |o - n_j|^2
+                if (d < mp[j]) { covered = true; break; }
+            }
+            if (covered) continue;
+            stamp(a.seq, c + (int64_t)oa * stride[A] + (int64_t)p * stride[B] + (int64_t)q * stride[C], k);
+        }
+    }
+}
+
+// One wave per listed centre: the whole ball, lanes over (x, y) columns,
+// each lane writing a contiguous run along z.
+__global__ __launch_bounds__(256) void k_paint_full(PaintArgs a) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t nf = *a.n_full;
+    const int64_t yz = (int64_t)a.Y * a.Z;
+    for (uint32_t i = blockIdx.x * 4 + (threadIdx.x >> 6); i < nf; i += gridDim.x * 4) {
+        const int64_t c = a.full[i];
+        const int32_t k = a.state[c];
+        const uint32_t m = a.val[a.key[c]];
+        const int z = (int)(c % a.Z), y = (int)((c / a.Z) % a.Y), x = (int)(c / yz);
+        const int Rb = (int)isqrt_u32(m - 1);
+        for (int dx = -Rb; dx <= Rb; dx++) {
+            const int xx = x + dx;
+            if (xx < 0 || xx >= a.X) continue;
+            const uint32_t rem = m - 1 - (uint32_t)(dx * dx);
+            const int U = (int)isqrt_u32(rem);
+            for (int dy = -U + lane; dy <= U; dy += 64) {
+                const int yy = y + dy;
+                if (yy < 0 || yy >= a.Y) continue;
+                const int W = (int)isqrt_u32(rem - (uint32_t)(dy * dy));
+                const int z0 = max(z - W, 0), z1 = min(z + W, a.Z - 1);
+                const int64_t rowv = ((int64_t)xx * a.Y + yy) * a.Z;
+                for (int zz = z0; zz <= z1; zz++) stamp(a.seq, rowv + zz, k);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Finalise and per-step accounting
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_finalise(int32_t* seq, int32_t* state_io, bool map_state, int64_t n,
+                                                  const uint32_t* M, uint32_t* rad2, uint32_t* count) {
+    const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    bool have = v < n;
+    int32_t s = 0;
+    if (have) {
+        s = seq[v];
+        if (s == INT_MAX) { s = 0; seq[v] = 0; }
+        if (rad2) rad2[v] = s > 0 ? M[s - 1] : 0u;
+        if (map_state) {
+            int32_t t = state_io[v];
+            if (t < 0) state_io[v] = 0;
+        }
+    }
+    // per-step counts, one atomic per distinct step in the wave
+    bool act = have && s > 0;
+    uint64_t pending = __ballot(act);
+    while (pending) {
+        const int leader = __ffsll((unsigned long long)pending) - 1;
+        const int32_t ls = __shfl(s, leader, 64);
+        const uint64_t same = __ballot(act && s == ls) & pending;
+        if ((threadIdx.x & 63) == leader) atomicAdd(&count[ls - 1], (uint32_t)__popcll(same));
+        pending &= ~same;
+    }
+}
+
+__global__ void k_copy_u32(const uint32_t* src, uint32_t* dst, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+// count_excl: exclusive scan of counts; counts: raw counts.
+__global__ void k_steps(const uint32_t* counts, const uint32_t* count_excl, const uint32_t* M, int64_t K,
+                        const LoopState* st, double c0, int64_t* n_new, double* sat, double* pc) {
+    int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k >= K) return;
+    const uint32_t c = counts[k];
+    n_new[k] = c;
+    const double np = (double)st->n_pore;
+    sat[k] = (double)(count_excl[k] + c) / np;
+    pc[k] = c0 / sqrt((double)M[k]);
+}
+
+inline unsigned blocks(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Host driver
+// ---------------------------------------------------------------------------
+ibip_status run_invade(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlets, ibip_dims d,
+                       const ibip_invade_opts* opts, int32_t* seq, uint32_t* rad2, int32_t* centre_step,
+                       int64_t* n_steps) {
+    hipStream_t s = ctx->stream;
+    const int64_t n = nvox(d);
+    const int64_t V = (int64_t)(d.X - 1) * (d.X - 1) + (int64_t)(d.Y - 1) * (d.Y - 1) +
+                      (int64_t)(d.Z - 1) * (d.Z - 1) + 2;
+    ctx->have_steps = false;
+    uint32_t* key = (uint32_t*)ensure(ctx, B_KEY, sizeof(uint32_t) * n);
+    int32_t* state = centre_step ? centre_step : (int32_t*)ensure(ctx, B_STATE, sizeof(int32_t) * n);
+    uint32_t* bucket = (uint32_t*)ensure(ctx, B_BUCKET, sizeof(uint32_t) * n);
+    uint32_t* hist = (uint32_t*)ensure(ctx, B_HIST, sizeof(uint32_t) * 3 * V);
+    uint16_t* g16 = (uint16_t*)ensure(ctx, B_TMP0, sizeof(uint16_t) * n);
+    uint32_t* tmp32 = (uint32_t*)ensure(ctx, B_TMP1, sizeof(uint32_t) * n);
+    uint32_t* partials = (uint32_t*)ensure(ctx, B_SCAN, sizeof(uint32_t) * (V / 1000 + n / 1000 + 64));
+    uint8_t* misc = (uint8_t*)ensure(ctx, B_MISC, 4096);
+    LoopState* h_st = (LoopState*)pinned(ctx, 4096);
+    if (!key || !state || !bucket || !hist || !g16 || !tmp32 || !partials || !misc || !h_st)
+        return fail(ctx, IBIP_ENOMEM, "invade: scratch allocation failed");
+    LoopState* st = (LoopState*)misc;
+    uint32_t* solid_flag = &st->solid_seen;
+    uint32_t* dummy_total = (uint32_t*)(misc + 1024);
+    uint32_t* present = hist + V;
+    uint32_t* flags = hist + 2 * V;  // raw presence (kept unscanned)
+
+    ibip_status rc;
+    if ((rc = hip_check(ctx, hipMemsetAsync(misc, 0, 4096, s), "memset")) != IBIP_OK) return rc;
+    if ((rc = hip_check(ctx, hipMemsetAsync(hist, 0, sizeof(uint32_t) * V, s), "memset")) != IBIP_OK) return rc;
+    // a1: distance transform into key[]
+    if ((rc = hip_check(ctx, launch_edt(image, nullptr, 0, d, g16, tmp32, key, solid_flag, s), "edt")) != IBIP_OK)
+        return rc;
+    // a2: histogram -> ranks and bucket slices
+    hipLaunchKernelGGL(k_hist, dim3(std::min<int64_t>(blocks(n), 4096)), dim3(256), 0, s, image, key, n,
+                       (uint32_t)(V - 1), hist, st);
+    hipLaunchKernelGGL(k_present, dim3(blocks(V)), dim3(256), 0, s, hist, present, V);
+    hipLaunchKernelGGL(k_copy_u32, dim3(blocks(V)), dim3(256), 0, s, present, flags, V);
+    if ((rc = hip_check(ctx, launch_scan_u32(hist, V, partials, dummy_total, s), "scan")) != IBIP_OK) return rc;
+    if ((rc = hip_check(ctx, launch_scan_u32(present, V, partials, &st->R, s), "scan")) != IBIP_OK) return rc;
+    // sync once: the rank count sizes the per-rank arrays and picks the loop variant
+    if ((rc = hip_check(ctx, hipMemcpyAsync(h_st, st, sizeof(LoopState), hipMemcpyDeviceToHost, s), "copy")) != IBIP_OK)
+        return rc;
+    if ((rc = hip_check(ctx, hipStreamSynchronize(s), "sync")) != IBIP_OK) return rc;
+    if (!h_st->solid_seen) return fail(ctx, IBIP_ENOSOLID, "invade: image holds no solid voxel");
+    const uint32_t R = h_st->R;
+    if (R > (uint32_t)kMaxRanks)
+        return fail(ctx, IBIP_ECAPACITY, "invade: more than 8192 distinct distance values in the pore space");
+    const int64_t n_pore = h_st->n_pore;
+    uint32_t* val = (uint32_t*)ensure(ctx, B_VAL, sizeof(uint32_t) * (R + 2));
+    uint32_t* off = (uint32_t*)ensure(ctx, B_OFF, sizeof(uint32_t) * (R + 2));
+    uint32_t* head = (uint32_t*)ensure(ctx, B_HEAD, sizeof(uint32_t) * (R + 2));
+    uint32_t* tail = (uint32_t*)ensure(ctx, B_TAIL, sizeof(uint32_t) * (R + 2));
+    uint32_t* M = (uint32_t*)ensure(ctx, B_M, sizeof(uint32_t) * (n_pore + 1));
+    uint32_t* full = (uint32_t*)ensure(ctx, B_FULL, sizeof(uint32_t) * (n_pore + 1));
+    if (!val || !off || !head || !tail || !M || !full)
+        return fail(ctx, IBIP_ENOMEM, "invade: scratch allocation failed");
+    if ((rc = hip_check(ctx, hipMemsetAsync(head, 0, sizeof(uint32_t) * (R + 2), s), "memset")) != IBIP_OK) return rc;
+    if ((rc = hip_check(ctx, hipMemsetAsync(tail, 0, sizeof(uint32_t) * (R + 2), s), "memset")) != IBIP_OK) return rc;
+    hipLaunchKernelGGL(k_rank_tables, dim3(blocks(V)), dim3(256), 0, s, hist, present, flags, V, val, off, head, tail);
+    hipLaunchKernelGGL(k_convert, dim3(blocks(n)), dim3(256), 0, s, image, key, present, n, state, seq);
+    hipLaunchKernelGGL(k_seed, dim3(blocks(n)), dim3(256), 0, s, inlets, key, d.X, d.Y, d.Z, state, tail, bucket);
+    // loop control
+    h_st->k = 1;
+    h_st->status = LS_RUN;
+    h_st->max_steps = opts ? opts->max_steps : 0;
+    {
+        // k, status and max_steps only; the rest stays as computed on the device
+        LoopState init = *h_st;
+        if ((rc = hip_check(ctx, hipMemcpyAsync(&st->k, &init.k, sizeof(uint32_t) * 2, hipMemcpyHostToDevice, s),
+                            "copy")) != IBIP_OK)
+            return rc;
+        if ((rc = hip_check(ctx, hipMemcpyAsync(&st->max_steps, &init.max_steps, sizeof(int64_t),
+                                                hipMemcpyHostToDevice, s), "copy")) != IBIP_OK)
+            return rc;
+        if ((rc = hip_check(ctx, hipStreamSynchronize(s), "sync")) != IBIP_OK) return rc;
+    }
+    LoopArgs la{st, head, tail, val, bucket, state, key, M, d.X, d.Y, d.Z, kWideRound};
+    int64_t segments = 0;
+    for (;;) {
+        hipLaunchKernelGGL(k_loop, dim3(1), dim3(kLoopThreads), 0, s, la);
+        if ((rc = hip_check(ctx, hipGetLastError(), "loop launch")) != IBIP_OK) return rc;
+        if ((rc = hip_check(ctx, hipMemcpyAsync(h_st, st, sizeof(LoopState), hipMemcpyDeviceToHost, s), "copy")) !=
+            IBIP_OK)
+            return rc;
+        if ((rc = hip_check(ctx, hipStreamSynchronize(s), "sync")) != IBIP_OK) return rc;
+        if (++segments > n_pore + 2) return fail(ctx, IBIP_EDEVICE, "invade: too many loop segments");
+        if (h_st->status == LS_WIDE) {
+            const uint32_t cnt = h_st->big_t - h_st->big_h;
+            const unsigned g = (unsigned)std::min<int64_t>((cnt + 255) / 256, 4096);
+            hipLaunchKernelGGL(k_wide, dim3(g), dim3(256), 0, s, la);
+            if ((rc = hip_check(ctx, hipGetLastError(), "wide launch")) != IBIP_OK) return rc;
+            continue;
+        }
+        break;
+    }
+    if (h_st->err) return fail(ctx, IBIP_EDEVICE, "invade: step loop exceeded the pore count");
+    const int64_t K = (int64_t)h_st->k - 1;
+    // a5: sphere insertion
+    PaintArgs pa{state, key, val, seq, full, &st->n_full, d.X, d.Y, d.Z};
+    hipLaunchKernelGGL(k_paint_shell, dim3(blocks(n)), dim3(256), 0, s, pa);
+    hipLaunchKernelGGL(k_paint_full, dim3(2048), dim3(256), 0, s, pa);
+    // a6: finalise and per-step arrays
+    int64_t* n_new = (int64_t*)ensure(ctx, B_NNEW, sizeof(int64_t) * (K + 1));
+    double* sat = (double*)ensure(ctx, B_SAT, sizeof(double) * (K + 1));
+    double* pc = (double*)ensure(ctx, B_PC, sizeof(double) * (K + 1));
+    uint32_t* counts = (uint32_t*)ensure(ctx, B_TMP2, sizeof(uint32_t) * 2 * (K + 1));
+    partials = (uint32_t*)ensure(ctx, B_SCAN, sizeof(uint32_t) * (V / 1000 + n / 1000 + 64));
+    if (!n_new || !sat || !pc || !counts || !partials) return fail(ctx, IBIP_ENOMEM, "invade: scratch allocation failed");
+    if ((rc = hip_check(ctx, hipMemsetAsync(counts, 0, sizeof(uint32_t) * (K + 1), s), "memset")) != IBIP_OK) return rc;
+    hipLaunchKernelGGL(k_finalise, dim3(blocks(n)), dim3(256), 0, s, seq, state, true, n, M, rad2, counts);
+    if (K > 0) {
+        uint32_t* excl = counts + (K + 1);
+        hipLaunchKernelGGL(k_copy_u32, dim3(blocks(K)), dim3(256), 0, s, counts, excl, K);
+        if ((rc = hip_check(ctx, launch_scan_u32(excl, K, partials, dummy_total, s), "scan")) != IBIP_OK) return rc;
+        const double sigma = (opts && opts->sigma != 0.0) ? opts->sigma : 1.0;
+        const double theta = opts ? opts->theta_rad : 0.0;
+        const double vs = (opts && opts->voxel_size != 0.0) ? opts->voxel_size : 1.0;
+        const double c0 = 2.0 * sigma * cos(theta) / vs;
+        hipLaunchKernelGGL(k_steps, dim3(blocks(K)), dim3(256), 0, s, counts, excl, M, K, st, c0, n_new, sat, pc);
+    }
+    if ((rc = hip_check(ctx, hipGetLastError(), "post launch")) != IBIP_OK) return rc;
+    if ((rc = hip_check(ctx, hipStreamSynchronize(s), "sync")) != IBIP_OK) return rc;
+    ctx->last_K = K;
+    ctx->last_n_pore = n_pore;
+    ctx->have_steps = true;
+    if (n_steps) *n_steps = K;
+    return IBIP_OK;
+}
+
+}  // namespace ibip

@@ -1,0 +1,110 @@
+// Pressure-based drainage by morphological image opening (Section 2.4.1),
+// used for the equal-saturation comparison of Section 3.1.1.
+//
+// For a squared radius T: eroding the pore space by B(., T) leaves the
+// centres c with dt2[c] >= T (a ball around c is free of solid exactly when
+// the nearest solid is at squared distance >= T); trimming keeps the eroded
+// components that touch the inlet candidates Q0 (inlets and their face
+// neighbours, pore only); dilating by B(., T) gives
+//   D_T = {v : some kept c has |v - c|^2 < T}.
+// The kept sets are nested in T, and c is kept at T exactly when
+// K(c) >= T, where K(c) is the maximin of dt2 over paths from Q0 to c. So one
+// maximin reconstruction gives every trim at once, and each dilation is a
+// distance transform of {K >= T} thresholded at T.
+#include "ibip_internal.h"
+
+namespace ibip {
+
+namespace {
+
+// K0(v) = dt2(v) on Q0, 0 elsewhere; also counts pore voxels.
+__global__ __launch_bounds__(256) void k_mio_seed(const uint8_t* img, const uint8_t* inlets, const uint32_t* dt2,
+                                                  int X, int Y, int Z, uint32_t* k0, uint32_t* n_pore) {
+    const int64_t yz = (int64_t)Y * Z;
+    const int64_t n = (int64_t)X * yz;
+    const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    bool pore = false;
+    if (v < n) {
+        pore = img[v] != 0;
+        bool seed = false;
+        if (pore) {
+            seed = inlets[v] != 0;
+            const int z = (int)(v % Z), y = (int)((v / Z) % Y), x = (int)(v / yz);
+            if (!seed && x > 0) seed = inlets[v - yz] != 0;
+            if (!seed && x < X - 1) seed = inlets[v + yz] != 0;
+            if (!seed && y > 0) seed = inlets[v - Z] != 0;
+            if (!seed && y < Y - 1) seed = inlets[v + Z] != 0;
+            if (!seed && z > 0) seed = inlets[v - 1] != 0;
+            if (!seed && z < Z - 1) seed = inlets[v + 1] != 0;
+        }
+        k0[v] = seed ? dt2[v] : 0u;
+    }
+    const uint64_t b = __ballot(pore);
+    if ((threadIdx.x & 63) == 0 && b) atomicAdd(n_pore, (uint32_t)__popcll(b));
+}
+
+// First write in decreasing T; count voxels with mio_r2 >= T.
+__global__ __launch_bounds__(256) void k_mio_update(const uint32_t* d2, uint32_t T, int64_t n, uint32_t* mio_r2,
+                                                    uint32_t* count) {
+    const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    bool hit = false;
+    if (v < n) {
+        uint32_t r = mio_r2[v];
+        if (r == 0 && d2[v] < T) { r = T; mio_r2[v] = T; }
+        hit = r >= T;
+    }
+    const uint64_t b = __ballot(hit);
+    if ((threadIdx.x & 63) == 0 && b) atomicAdd(count, (uint32_t)__popcll(b));
+}
+
+inline unsigned blocks(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace
+
+ibip_status run_mio(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlets, ibip_dims d, const uint32_t* T,
+                    int32_t nT, uint32_t* mio_r2, double* mio_sat) {
+    hipStream_t s = ctx->stream;
+    const int64_t n = nvox(d);
+    uint32_t* dt2 = (uint32_t*)ensure(ctx, B_KEY, sizeof(uint32_t) * n);
+    uint32_t* kmap = (uint32_t*)ensure(ctx, B_STATE, sizeof(uint32_t) * n);
+    uint16_t* g16 = (uint16_t*)ensure(ctx, B_TMP0, sizeof(uint16_t) * n);
+    uint32_t* tmp32 = (uint32_t*)ensure(ctx, B_TMP1, sizeof(uint32_t) * n);
+    uint32_t* d2 = (uint32_t*)ensure(ctx, B_TMP2, sizeof(uint32_t) * n);
+    uint32_t* counts = (uint32_t*)ensure(ctx, B_M, sizeof(uint32_t) * (nT + 8));
+    uint8_t* misc = (uint8_t*)ensure(ctx, B_MISC, 4096);
+    uint32_t* h = (uint32_t*)pinned(ctx, 4096 + sizeof(uint32_t) * (nT + 8));
+    if (!dt2 || !kmap || !g16 || !tmp32 || !d2 || !counts || !misc || !h)
+        return fail(ctx, IBIP_ENOMEM, "opening_drainage: allocation failed");
+    uint32_t* flags = (uint32_t*)(misc + 3584);  // [0] solid seen, [1] n_pore, [2] scratch flag
+    ibip_status rc;
+    if ((rc = hip_check(ctx, hipMemsetAsync(flags, 0, 16, s), "memset")) != IBIP_OK) return rc;
+    if ((rc = hip_check(ctx, hipMemsetAsync(counts, 0, sizeof(uint32_t) * (nT + 8), s), "memset")) != IBIP_OK)
+        return rc;
+    if ((rc = hip_check(ctx, hipMemsetAsync(mio_r2, 0, sizeof(uint32_t) * n, s), "memset")) != IBIP_OK) return rc;
+    if ((rc = hip_check(ctx, launch_edt(image, nullptr, 0, d, g16, tmp32, dt2, &flags[0], s), "edt")) != IBIP_OK)
+        return rc;
+    hipLaunchKernelGGL(k_mio_seed, dim3(blocks(n)), dim3(256), 0, s, image, inlets, dt2, d.X, d.Y, d.Z, kmap,
+                       &flags[1]);
+    if ((rc = hip_check(ctx, hipMemcpyAsync(h, flags, 8, hipMemcpyDeviceToHost, s), "copy")) != IBIP_OK) return rc;
+    if ((rc = hip_check(ctx, hipStreamSynchronize(s), "sync")) != IBIP_OK) return rc;
+    if (!h[0]) return fail(ctx, IBIP_ENOSOLID, "opening_drainage: image holds no solid voxel");
+    const uint32_t n_pore = h[1];
+    int iters = 0;
+    if ((rc = reconstruct(ctx, nullptr, dt2, d, kmap, &iters)) != IBIP_OK) return rc;
+    for (int32_t i = 0; i < nT; i++) {
+        if ((rc = hip_check(ctx, launch_edt(nullptr, kmap, T[i], d, g16, tmp32, d2, &flags[2], s), "edt")) != IBIP_OK)
+            return rc;
+        hipLaunchKernelGGL(k_mio_update, dim3(blocks(n)), dim3(256), 0, s, d2, T[i], n, mio_r2, &counts[i]);
+    }
+    if ((rc = hip_check(ctx, hipGetLastError(), "mio launch")) != IBIP_OK) return rc;
+    uint32_t* hc = h + 1024;
+    if ((rc = hip_check(ctx, hipMemcpyAsync(hc, counts, sizeof(uint32_t) * nT, hipMemcpyDeviceToHost, s), "copy")) !=
+        IBIP_OK)
+        return rc;
+    if ((rc = hip_check(ctx, hipStreamSynchronize(s), "sync")) != IBIP_OK) return rc;
+    if (mio_sat)
+        for (int32_t i = 0; i < nT; i++) mio_sat[i] = n_pore ? (double)hc[i] / (double)n_pore : 0.0;
+    return IBIP_OK;
+}
+
+}  // namespace ibip

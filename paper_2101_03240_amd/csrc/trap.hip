@@ -1,0 +1,219 @@
+// Defender trapping and re-ranking (Section 2.2.3, Figure 7), and the
+// maximin reconstruction it shares with the opening drainage.
+//
+// A voxel v invaded at step k is trapped when the defender region D_k =
+// {pore u : seq[u] == 0 or seq[u] >= k} holds no path from v to an outlet.
+// With node capacities cap(u) = infinity for uninvaded pore and seq[u] for
+// invaded voxels, a path lies in D_k exactly when its smallest capacity is
+// >= k. So with W(v) = max over paths from the outlets to v of the smallest
+// capacity on the path (a maximin, or widest-path, value), v is free iff
+// W(v) >= seq[v]. The paper's reverse sweep over thresholds computes the same
+// predicate one level at a time; W gives it for every level at once and is
+// computed here by data-parallel relaxation to the fixed point
+//   W(v) = max(W0(v), min(cap(v), max over face neighbours u of W(u))).
+//
+// Relaxation runs per 4 x 8 x 32 tile: the tile and a one-voxel halo sit in
+// LDS and are swept until nothing changes; sweeps over all tiles repeat until
+// no tile changed (W only grows and is bounded, so this terminates at the
+// unique fixed point).
+#include <climits>
+
+#include "ibip_internal.h"
+
+namespace ibip {
+
+namespace {
+
+constexpr int TX = 4, TY = 8, TZ = 32;
+constexpr int HX = TX + 2, HY = TY + 2, HZ = TZ + 2;
+
+struct CapSeq {
+    const int32_t* seq;
+    __device__ uint32_t operator()(int64_t v) const {
+        int32_t s = seq[v];
+        return s < 0 ? 0u : (s == 0 ? kInf32 : (uint32_t)s);
+    }
+};
+struct CapU32 {
+    const uint32_t* cap;
+    __device__ uint32_t operator()(int64_t v) const { return cap[v]; }
+};
+
+template <class Cap>
+__global__ __launch_bounds__(256) void k_relax_tiles(Cap cap, int X, int Y, int Z, int ntx, int nty, int ntz,
+                                                     uint32_t* w, uint32_t* changed) {
+    __shared__ uint32_t hw[HX * HY * HZ];
+    const int tid = threadIdx.x;
+    const int64_t tile = blockIdx.x;
+    const int tz = (int)(tile % ntz);
+    const int ty = (int)((tile / ntz) % nty);
+    const int tx = (int)(tile / ((int64_t)ntz * nty));
+    const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
+    const int64_t yz = (int64_t)Y * Z;
+    for (int i = tid; i < HX * HY * HZ; i += 256) {
+        const int hz = i % HZ, hy = (i / HZ) % HY, hx = i / (HZ * HY);
+        const int gx = x0 + hx - 1, gy = y0 + hy - 1, gz = z0 + hz - 1;
+        uint32_t val = 0;
+        if (gx >= 0 && gx < X && gy >= 0 && gy < Y && gz >= 0 && gz < Z) val = w[gx * yz + (int64_t)gy * Z + gz];
+        hw[i] = val;
+    }
+    const int lz = tid & 31, ly = tid >> 5;
+    uint32_t c[TX], orig[TX];
+    const int gy = y0 + ly, gz = z0 + lz;
+#pragma unroll
+    for (int j = 0; j < TX; j++) {
+        const int gx = x0 + j;
+        const bool in = gx < X && gy < Y && gz < Z;
+        c[j] = in ? cap(gx * yz + (int64_t)gy * Z + gz) : 0u;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < TX; j++) orig[j] = hw[((j + 1) * HY + (ly + 1)) * HZ + (lz + 1)];
+    bool any_change = false;
+    for (;;) {
+        bool ch = false;
+#pragma unroll
+        for (int j = 0; j < TX; j++) {
+            if (c[j] == 0) continue;
+            const int idx = ((j + 1) * HY + (ly + 1)) * HZ + (lz + 1);
+            const uint32_t cur = hw[idx];
+            uint32_t nb = max(max(hw[idx - 1], hw[idx + 1]), max(hw[idx - HZ], hw[idx + HZ]));
+            nb = max(nb, max(hw[idx - HY * HZ], hw[idx + HY * HZ]));
+            const uint32_t cand = min(c[j], nb);
+            if (cand > cur) { hw[idx] = cand; ch = true; }
+        }
+        // wave-uniform exit (see the note on loop control in invade.hip)
+        if (!__builtin_amdgcn_readfirstlane(__syncthreads_or(ch))) break;
+        any_change = true;
+    }
+    if (!any_change) return;
+    bool wrote = false;
+#pragma unroll
+    for (int j = 0; j < TX; j++) {
+        const int gx = x0 + j;
+        if (gx >= X || gy >= Y || gz >= Z) continue;
+        const uint32_t nv = hw[((j + 1) * HY + (ly + 1)) * HZ + (lz + 1)];
+        if (nv != orig[j]) { w[gx * yz + (int64_t)gy * Z + gz] = nv; wrote = true; }
+    }
+    if (__builtin_amdgcn_readfirstlane(__syncthreads_or(wrote)) && tid == 0) atomicAdd(changed, 1u);
+}
+
+// ---- trapping ----
+__global__ __launch_bounds__(256) void k_max_seq(const int32_t* seq, int64_t n, int32_t* out) {
+    int32_t m = 0;
+    for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < n; v += (int64_t)gridDim.x * 256)
+        m = max(m, seq[v]);
+    for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(out, m);
+}
+
+__global__ __launch_bounds__(256) void k_trap_init(const int32_t* seq, const uint8_t* outlets, int64_t n,
+                                                   uint32_t* w) {
+    int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (v >= n) return;
+    const int32_t s = seq[v];
+    uint32_t val = 0;
+    if (s >= 0 && outlets[v]) val = s == 0 ? kInf32 : (uint32_t)s;
+    w[v] = val;
+}
+
+__global__ __launch_bounds__(256) void k_trap_mark(const int32_t* seq, const uint32_t* w, int64_t n,
+                                                   uint8_t* trapped, uint32_t* present) {
+    int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (v >= n) return;
+    const int32_t s = seq[v];
+    const bool t = s > 0 && w[v] < (uint32_t)s;
+    trapped[v] = t ? 1 : 0;
+    if (s > 0 && !t) present[s - 1] = 1u;
+}
+
+__global__ __launch_bounds__(256) void k_trap_rank(const int32_t* seq, const uint8_t* trapped,
+                                                   const uint32_t* rank_excl, int64_t n, int32_t* out) {
+    int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (v >= n) return;
+    const int32_t s = seq[v];
+    int32_t r;
+    if (s < 0) r = -1;
+    else if (s == 0 || trapped[v]) r = 0;
+    else r = (int32_t)rank_excl[s - 1] + 1;
+    out[v] = r;
+}
+
+inline unsigned blocks(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace
+
+ibip_status reconstruct(ibip_ctx* ctx, const int32_t* seq, const uint32_t* cap32, ibip_dims d, uint32_t* w,
+                        int* n_iter) {
+    hipStream_t s = ctx->stream;
+    uint8_t* misc = (uint8_t*)ensure(ctx, B_MISC, 4096);
+    uint32_t* h = (uint32_t*)pinned(ctx, 4096);
+    if (!misc || !h) return fail(ctx, IBIP_ENOMEM, "reconstruct: allocation failed");
+    uint32_t* changed = (uint32_t*)(misc + 2048);
+    uint32_t* h_changed = h + 512;
+    const int ntx = (d.X + TX - 1) / TX, nty = (d.Y + TY - 1) / TY, ntz = (d.Z + TZ - 1) / TZ;
+    const int64_t ntiles = (int64_t)ntx * nty * ntz;
+    ibip_status rc;
+    int it = 0;
+    for (;; it++) {
+        if ((rc = hip_check(ctx, hipMemsetAsync(changed, 0, sizeof(uint32_t), s), "memset")) != IBIP_OK) return rc;
+        if (cap32)
+            hipLaunchKernelGGL(k_relax_tiles<CapU32>, dim3((unsigned)ntiles), dim3(256), 0, s, CapU32{cap32}, d.X,
+                               d.Y, d.Z, ntx, nty, ntz, w, changed);
+        else
+            hipLaunchKernelGGL(k_relax_tiles<CapSeq>, dim3((unsigned)ntiles), dim3(256), 0, s, CapSeq{seq}, d.X,
+                               d.Y, d.Z, ntx, nty, ntz, w, changed);
+        if ((rc = hip_check(ctx, hipGetLastError(), "relax launch")) != IBIP_OK) return rc;
+        if ((rc = hip_check(ctx, hipMemcpyAsync(h_changed, changed, sizeof(uint32_t), hipMemcpyDeviceToHost, s),
+                            "copy")) != IBIP_OK)
+            return rc;
+        if ((rc = hip_check(ctx, hipStreamSynchronize(s), "sync")) != IBIP_OK) return rc;
+        if (*h_changed == 0) break;
+        if (it > 4 * (d.X + d.Y + d.Z) + 100000)
+            return fail(ctx, IBIP_EDEVICE, "reconstruct: no fixed point after the iteration limit");
+    }
+    if (n_iter) *n_iter = it + 1;
+    return IBIP_OK;
+}
+
+ibip_status run_trap(ibip_ctx* ctx, const int32_t* seq, const uint8_t* outlets, ibip_dims d, uint8_t* trapped,
+                     int32_t* seq_trapped, int64_t* n_steps_after) {
+    hipStream_t s = ctx->stream;
+    const int64_t n = nvox(d);
+    uint32_t* w = (uint32_t*)ensure(ctx, B_KEY, sizeof(uint32_t) * n);
+    uint8_t* misc = (uint8_t*)ensure(ctx, B_MISC, 4096);
+    uint32_t* h = (uint32_t*)pinned(ctx, 4096);
+    if (!w || !misc || !h) return fail(ctx, IBIP_ENOMEM, "trap: allocation failed");
+    int32_t* dmax = (int32_t*)(misc + 3072);
+    uint32_t* dtotal = (uint32_t*)(misc + 3076);
+    ibip_status rc;
+    if ((rc = hip_check(ctx, hipMemsetAsync(dmax, 0, 8, s), "memset")) != IBIP_OK) return rc;
+    hipLaunchKernelGGL(k_max_seq, dim3(std::min<int64_t>(blocks(n), 2048)), dim3(256), 0, s, seq, n, dmax);
+    hipLaunchKernelGGL(k_trap_init, dim3(blocks(n)), dim3(256), 0, s, seq, outlets, n, w);
+    if ((rc = hip_check(ctx, hipMemcpyAsync(h, dmax, sizeof(int32_t), hipMemcpyDeviceToHost, s), "copy")) != IBIP_OK)
+        return rc;
+    if ((rc = hip_check(ctx, hipStreamSynchronize(s), "sync")) != IBIP_OK) return rc;
+    const int64_t K = (int32_t)h[0];
+    int iters = 0;
+    if ((rc = reconstruct(ctx, seq, nullptr, d, w, &iters)) != IBIP_OK) return rc;
+    uint32_t* present = (uint32_t*)ensure(ctx, B_TMP2, sizeof(uint32_t) * (K + 1));
+    uint32_t* partials = (uint32_t*)ensure(ctx, B_SCAN, sizeof(uint32_t) * (K / 1000 + n / 1000 + 64));
+    if (!present || !partials) return fail(ctx, IBIP_ENOMEM, "trap: allocation failed");
+    if ((rc = hip_check(ctx, hipMemsetAsync(present, 0, sizeof(uint32_t) * (K + 1), s), "memset")) != IBIP_OK)
+        return rc;
+    hipLaunchKernelGGL(k_trap_mark, dim3(blocks(n)), dim3(256), 0, s, seq, w, n, trapped, present);
+    if (K > 0) {
+        if ((rc = hip_check(ctx, launch_scan_u32(present, K, partials, dtotal, s), "scan")) != IBIP_OK) return rc;
+    }
+    if (seq_trapped) hipLaunchKernelGGL(k_trap_rank, dim3(blocks(n)), dim3(256), 0, s, seq, trapped, present, n,
+                                        seq_trapped);
+    if ((rc = hip_check(ctx, hipGetLastError(), "trap launch")) != IBIP_OK) return rc;
+    if ((rc = hip_check(ctx, hipMemcpyAsync(h + 1, dtotal, sizeof(uint32_t), hipMemcpyDeviceToHost, s), "copy")) !=
+        IBIP_OK)
+        return rc;
+    if ((rc = hip_check(ctx, hipStreamSynchronize(s), "sync")) != IBIP_OK) return rc;
+    if (n_steps_after) *n_steps_after = K > 0 ? (int64_t)h[1] : 0;
+    return IBIP_OK;
+}
+
+}  // namespace ibip
