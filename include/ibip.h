@@ -67,6 +67,30 @@ const char* ibip_last_error(const ibip_ctx* ctx);
 /* Bytes of device scratch the context currently holds. */
 int64_t ibip_ctx_scratch_bytes(const ibip_ctx* ctx);
 
+/* Phase timing, for measurement. When enabled, the calls record HIP events
+   on the context's stream around each phase and each launch of the step
+   loop, and add the elapsed times (milliseconds) to the counters below. */
+typedef struct {
+    double edt_ms;          /* distance transform inside ibip_invade */
+    double setup_ms;        /* histogram, ranks, buckets, seeding */
+    double loop_ms;         /* the whole step loop, host round trips included */
+    double loop_kernel_ms;  /* sum of the single-workgroup loop kernel durations */
+    double wide_kernel_ms;  /* sum of the whole-GPU step kernel durations */
+    double paint_ms;        /* sphere insertion */
+    double steps_ms;        /* finalisation and per-step arrays */
+    double trap_ms;         /* ibip_trap */
+    double mio_ms;          /* ibip_opening_drainage */
+    int64_t loop_launches;  /* launches of the loop kernel */
+    int64_t wide_launches;  /* launches of the whole-GPU step kernel */
+    int64_t steps;          /* steps K summed over ibip_invade calls */
+    int64_t popped;         /* centres summed over ibip_invade calls */
+    int64_t relax_sweeps;   /* reconstruction sweeps (trapping and MIO) */
+} ibip_timing;
+
+ibip_status ibip_ctx_enable_timing(ibip_ctx* ctx, int32_t enable);
+ibip_status ibip_ctx_get_timing(const ibip_ctx* ctx, ibip_timing* out);
+ibip_status ibip_ctx_reset_timing(ibip_ctx* ctx);
+
 /*
  * ibip_edt -- distance transform of the pore space (Section 2.1, Figure 2(b)).
  * dt2[v] = min over solid voxels s of |v - s|^2 (exact, integer), 0 on solid.

@@ -22,7 +22,8 @@ import ctypes
 import os
 import threading
 
-__all__ = ["edt", "invade", "trap", "opening_drainage", "IbipError", "library_path", "load_library"]
+__all__ = ["edt", "invade", "trap", "opening_drainage", "IbipError", "library_path", "load_library",
+           "enable_timing", "get_timing", "reset_timing"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libibip_hip.so")
@@ -42,6 +43,12 @@ class IbipError(RuntimeError):
 
 class _Dims(ctypes.Structure):
     _fields_ = [("X", ctypes.c_int32), ("Y", ctypes.c_int32), ("Z", ctypes.c_int32)]
+
+
+class _Timing(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in ("edt_ms", "setup_ms", "loop_ms", "loop_kernel_ms", "wide_kernel_ms",
+                                                "paint_ms", "steps_ms", "trap_ms", "mio_ms")] + \
+               [(n, ctypes.c_int64) for n in ("loop_launches", "wide_launches", "steps", "popped", "relax_sweeps")]
 
 
 class _InvadeOpts(ctypes.Structure):
@@ -77,6 +84,11 @@ def load_library():
         lib.ibip_get_steps.argtypes = [P, P, P, P, P, i64]
         lib.ibip_trap.argtypes = [P, P, P, _Dims, P, P, ctypes.POINTER(i64)]
         lib.ibip_opening_drainage.argtypes = [P, P, P, _Dims, P, i32, P, P]
+        lib.ibip_ctx_enable_timing.argtypes = [P, i32]
+        lib.ibip_ctx_get_timing.argtypes = [P, ctypes.POINTER(_Timing)]
+        lib.ibip_ctx_reset_timing.argtypes = [P]
+        for fn in (lib.ibip_ctx_enable_timing, lib.ibip_ctx_get_timing, lib.ibip_ctx_reset_timing):
+            fn.restype = i32
         for fn in (lib.ibip_ctx_create, lib.ibip_ctx_destroy, lib.ibip_ctx_set_stream, lib.ibip_edt,
                    lib.ibip_invade, lib.ibip_get_steps, lib.ibip_trap, lib.ibip_opening_drainage):
             fn.restype = i32
@@ -222,3 +234,25 @@ def opening_drainage(image, inlets, thresholds):
     _check(load_library().ibip_opening_drainage(ctx, _ptr(image), _ptr(inlets), dims, ctypes.cast(arr, ctypes.c_void_p),
                                                 len(T), _ptr(out), ctypes.cast(sat, ctypes.c_void_p)), ctx)
     return {"mio_r2": out, "mio_sat": [sat[i] for i in range(len(T))]}
+
+
+def enable_timing(enable: bool = True, device=None):
+    """Turn the library's per-phase HIP-event timing on or off (see ibip_timing)."""
+    torch = _torch()
+    ctx = _context(torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device()))
+    _check(load_library().ibip_ctx_enable_timing(ctx, 1 if enable else 0), ctx)
+
+
+def reset_timing(device=None):
+    torch = _torch()
+    ctx = _context(torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device()))
+    _check(load_library().ibip_ctx_reset_timing(ctx), ctx)
+
+
+def get_timing(device=None) -> dict:
+    """Accumulated phase times (ms) and counters since the last reset."""
+    torch = _torch()
+    ctx = _context(torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device()))
+    t = _Timing()
+    _check(load_library().ibip_ctx_get_timing(ctx, ctypes.byref(t)), ctx)
+    return {name: getattr(t, name) for name, _ in _Timing._fields_}

@@ -101,10 +101,30 @@ ibip_status ibip_ctx_create(ibip_ctx** out, int32_t device, void* stream) {
     return IBIP_OK;
 }
 
+ibip_status ibip_ctx_enable_timing(ibip_ctx* ctx, int32_t enable) {
+    if (!ctx) return IBIP_EINVAL;
+    ctx->timer.on = enable != 0;
+    return IBIP_OK;
+}
+
+ibip_status ibip_ctx_get_timing(const ibip_ctx* ctx, ibip_timing* out) {
+    if (!ctx || !out) return IBIP_EINVAL;
+    *out = ctx->timing;
+    return IBIP_OK;
+}
+
+ibip_status ibip_ctx_reset_timing(ibip_ctx* ctx) {
+    if (!ctx) return IBIP_EINVAL;
+    ctx->timing = ibip_timing{};
+    return IBIP_OK;
+}
+
 ibip_status ibip_ctx_destroy(ibip_ctx* ctx) {
     if (!ctx) return IBIP_EINVAL;
     DeviceGuard g(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->timer.made)
+        for (auto& e : ctx->timer.ev) (void)hipEventDestroy(e);
     for (auto& b : ctx->buf)
         if (b.p) (void)hipFree(b.p);
     if (ctx->host_pinned) (void)hipHostFree(ctx->host_pinned);

@@ -61,6 +61,8 @@ struct LoopState {
     uint32_t n_full;   // centres that need a full ball
     uint32_t err;
     uint32_t big_k;    // step number of the pending wide step
+    uint32_t popped;   // centres (voxels with state > 0) after the loop
+    uint32_t pad2;
     int64_t max_steps;
 };
 
@@ -68,7 +70,34 @@ enum LoopStatus : uint32_t { LS_RUN = 0, LS_DONE = 1, LS_WIDE = 2, LS_MAXSTEPS =
 
 }  // namespace ibip
 
+namespace ibip {
+// Optional event-based phase timer (see ibip_timing).
+struct Timer {
+    bool on = false;
+    hipEvent_t ev[12] = {};
+    bool made = false;
+    // record event i on stream s (no-op when off)
+    void mark(int i, hipStream_t s) {
+        if (!on) return;
+        if (!made) {
+            for (auto& e : ev) (void)hipEventCreate(&e);
+            made = true;
+        }
+        (void)hipEventRecord(ev[i], s);
+    }
+    // elapsed ms between events a and b (both recorded and complete)
+    double ms(int a, int b) const {
+        float t = 0.f;
+        if (!on || !made) return 0.0;
+        if (hipEventElapsedTime(&t, ev[a], ev[b]) != hipSuccess) return 0.0;
+        return (double)t;
+    }
+};
+}  // namespace ibip
+
 struct ibip_ctx {
+    ibip::Timer timer;
+    ibip_timing timing = {};
     int device = 0;
     hipStream_t stream = nullptr;
     std::string err;

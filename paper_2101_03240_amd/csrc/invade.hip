@@ -512,19 +512,22 @@ __global__ __launch_bounds__(256) void k_paint_full(PaintArgs a) {
 // Finalise and per-step accounting
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_finalise(int32_t* seq, int32_t* state_io, bool map_state, int64_t n,
-                                                  const uint32_t* M, uint32_t* rad2, uint32_t* count) {
+                                                  const uint32_t* M, uint32_t* rad2, uint32_t* count,
+                                                  uint32_t* popped) {
     const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
     bool have = v < n;
     int32_t s = 0;
+    bool centre = false;
     if (have) {
         s = seq[v];
         if (s == INT_MAX) { s = 0; seq[v] = 0; }
         if (rad2) rad2[v] = s > 0 ? M[s - 1] : 0u;
-        if (map_state) {
-            int32_t t = state_io[v];
-            if (t < 0) state_io[v] = 0;
-        }
+        const int32_t t = state_io[v];
+        centre = t > 0;
+        if (map_state && t < 0) state_io[v] = 0;
     }
+    const uint64_t cb = __ballot(centre);
+    if ((threadIdx.x & 63) == 0 && cb) atomicAdd(popped, (uint32_t)__popcll(cb));
     // per-step counts, one atomic per distinct step in the wave
     bool act = have && s > 0;
     uint64_t pending = __ballot(act);
@@ -587,11 +590,14 @@ ibip_status run_invade(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlet
     uint32_t* flags = hist + 2 * V;  // raw presence (kept unscanned)
 
     ibip_status rc;
+    Timer& tm = ctx->timer;
+    tm.mark(0, s);
     if ((rc = hip_check(ctx, hipMemsetAsync(misc, 0, 4096, s), "memset")) != IBIP_OK) return rc;
     if ((rc = hip_check(ctx, hipMemsetAsync(hist, 0, sizeof(uint32_t) * V, s), "memset")) != IBIP_OK) return rc;
     // a1: distance transform into key[]
     if ((rc = hip_check(ctx, launch_edt(image, nullptr, 0, d, g16, tmp32, key, solid_flag, s), "edt")) != IBIP_OK)
         return rc;
+    tm.mark(1, s);
     // a2: histogram -> ranks and bucket slices
     hipLaunchKernelGGL(k_hist, dim3(std::min<int64_t>(blocks(n), 4096)), dim3(256), 0, s, image, key, n,
                        (uint32_t)(V - 1), hist, st);
@@ -621,6 +627,7 @@ ibip_status run_invade(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlet
     hipLaunchKernelGGL(k_rank_tables, dim3(blocks(V)), dim3(256), 0, s, hist, present, flags, V, val, off, head, tail);
     hipLaunchKernelGGL(k_convert, dim3(blocks(n)), dim3(256), 0, s, image, key, present, n, state, seq);
     hipLaunchKernelGGL(k_seed, dim3(blocks(n)), dim3(256), 0, s, inlets, key, d.X, d.Y, d.Z, state, tail, bucket);
+    tm.mark(2, s);
     // loop control
     h_st->k = 1;
     h_st->status = LS_RUN;
@@ -638,18 +645,33 @@ ibip_status run_invade(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlet
     }
     LoopArgs la{st, head, tail, val, bucket, state, key, M, d.X, d.Y, d.Z, kWideRound};
     int64_t segments = 0;
+    bool wide_pending_timing = false;
     for (;;) {
+        tm.mark(3, s);
         hipLaunchKernelGGL(k_loop, dim3(1), dim3(kLoopThreads), 0, s, la);
+        tm.mark(4, s);
         if ((rc = hip_check(ctx, hipGetLastError(), "loop launch")) != IBIP_OK) return rc;
         if ((rc = hip_check(ctx, hipMemcpyAsync(h_st, st, sizeof(LoopState), hipMemcpyDeviceToHost, s), "copy")) !=
             IBIP_OK)
             return rc;
         if ((rc = hip_check(ctx, hipStreamSynchronize(s), "sync")) != IBIP_OK) return rc;
+        if (tm.on) {
+            ctx->timing.loop_kernel_ms += tm.ms(3, 4);
+            ctx->timing.loop_launches++;
+            if (wide_pending_timing) {
+                ctx->timing.wide_kernel_ms += tm.ms(5, 6);
+                ctx->timing.wide_launches++;
+                wide_pending_timing = false;
+            }
+        }
         if (++segments > n_pore + 2) return fail(ctx, IBIP_EDEVICE, "invade: too many loop segments");
         if (h_st->status == LS_WIDE) {
             const uint32_t cnt = h_st->big_t - h_st->big_h;
             const unsigned g = (unsigned)std::min<int64_t>((cnt + 255) / 256, 4096);
+            tm.mark(5, s);
             hipLaunchKernelGGL(k_wide, dim3(g), dim3(256), 0, s, la);
+            tm.mark(6, s);
+            wide_pending_timing = true;
             if ((rc = hip_check(ctx, hipGetLastError(), "wide launch")) != IBIP_OK) return rc;
             continue;
         }
@@ -657,10 +679,12 @@ ibip_status run_invade(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlet
     }
     if (h_st->err) return fail(ctx, IBIP_EDEVICE, "invade: step loop exceeded the pore count");
     const int64_t K = (int64_t)h_st->k - 1;
+    tm.mark(7, s);
     // a5: sphere insertion
     PaintArgs pa{state, key, val, seq, full, &st->n_full, d.X, d.Y, d.Z};
     hipLaunchKernelGGL(k_paint_shell, dim3(blocks(n)), dim3(256), 0, s, pa);
     hipLaunchKernelGGL(k_paint_full, dim3(2048), dim3(256), 0, s, pa);
+    tm.mark(8, s);
     // a6: finalise and per-step arrays
     int64_t* n_new = (int64_t*)ensure(ctx, B_NNEW, sizeof(int64_t) * (K + 1));
     double* sat = (double*)ensure(ctx, B_SAT, sizeof(double) * (K + 1));
@@ -669,7 +693,8 @@ ibip_status run_invade(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlet
     partials = (uint32_t*)ensure(ctx, B_SCAN, sizeof(uint32_t) * (V / 1000 + n / 1000 + 64));
     if (!n_new || !sat || !pc || !counts || !partials) return fail(ctx, IBIP_ENOMEM, "invade: scratch allocation failed");
     if ((rc = hip_check(ctx, hipMemsetAsync(counts, 0, sizeof(uint32_t) * (K + 1), s), "memset")) != IBIP_OK) return rc;
-    hipLaunchKernelGGL(k_finalise, dim3(blocks(n)), dim3(256), 0, s, seq, state, true, n, M, rad2, counts);
+    hipLaunchKernelGGL(k_finalise, dim3(blocks(n)), dim3(256), 0, s, seq, state, true, n, M, rad2, counts,
+                       &st->popped);
     if (K > 0) {
         uint32_t* excl = counts + (K + 1);
         hipLaunchKernelGGL(k_copy_u32, dim3(blocks(K)), dim3(256), 0, s, counts, excl, K);
@@ -681,7 +706,20 @@ ibip_status run_invade(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlet
         hipLaunchKernelGGL(k_steps, dim3(blocks(K)), dim3(256), 0, s, counts, excl, M, K, st, c0, n_new, sat, pc);
     }
     if ((rc = hip_check(ctx, hipGetLastError(), "post launch")) != IBIP_OK) return rc;
+    tm.mark(9, s);
+    if ((rc = hip_check(ctx, hipMemcpyAsync(h_st, st, sizeof(LoopState), hipMemcpyDeviceToHost, s), "copy")) != IBIP_OK)
+        return rc;
     if ((rc = hip_check(ctx, hipStreamSynchronize(s), "sync")) != IBIP_OK) return rc;
+    if (tm.on) {
+        ibip_timing& T = ctx->timing;
+        T.edt_ms += tm.ms(0, 1);
+        T.setup_ms += tm.ms(1, 2);
+        T.loop_ms += tm.ms(2, 7);
+        T.paint_ms += tm.ms(7, 8);
+        T.steps_ms += tm.ms(8, 9);
+        T.steps += K;
+        T.popped += h_st->popped;
+    }
     ctx->last_K = K;
     ctx->last_n_pore = n_pore;
     ctx->have_steps = true;

@@ -77,6 +77,7 @@ ibip_status run_mio(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlets, 
         return fail(ctx, IBIP_ENOMEM, "opening_drainage: allocation failed");
     uint32_t* flags = (uint32_t*)(misc + 3584);  // [0] solid seen, [1] n_pore, [2] scratch flag
     ibip_status rc;
+    ctx->timer.mark(10, s);
     if ((rc = hip_check(ctx, hipMemsetAsync(flags, 0, 16, s), "memset")) != IBIP_OK) return rc;
     if ((rc = hip_check(ctx, hipMemsetAsync(counts, 0, sizeof(uint32_t) * (nT + 8), s), "memset")) != IBIP_OK)
         return rc;
@@ -101,7 +102,12 @@ ibip_status run_mio(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlets, 
     if ((rc = hip_check(ctx, hipMemcpyAsync(hc, counts, sizeof(uint32_t) * nT, hipMemcpyDeviceToHost, s), "copy")) !=
         IBIP_OK)
         return rc;
+    ctx->timer.mark(11, s);
     if ((rc = hip_check(ctx, hipStreamSynchronize(s), "sync")) != IBIP_OK) return rc;
+    if (ctx->timer.on) {
+        ctx->timing.mio_ms += ctx->timer.ms(10, 11);
+        ctx->timing.relax_sweeps += iters;
+    }
     if (mio_sat)
         for (int32_t i = 0; i < nT; i++) mio_sat[i] = n_pore ? (double)hc[i] / (double)n_pore : 0.0;
     return IBIP_OK;

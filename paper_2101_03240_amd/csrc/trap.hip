@@ -187,6 +187,7 @@ ibip_status run_trap(ibip_ctx* ctx, const int32_t* seq, const uint8_t* outlets, 
     int32_t* dmax = (int32_t*)(misc + 3072);
     uint32_t* dtotal = (uint32_t*)(misc + 3076);
     ibip_status rc;
+    ctx->timer.mark(10, s);
     if ((rc = hip_check(ctx, hipMemsetAsync(dmax, 0, 8, s), "memset")) != IBIP_OK) return rc;
     hipLaunchKernelGGL(k_max_seq, dim3(std::min<int64_t>(blocks(n), 2048)), dim3(256), 0, s, seq, n, dmax);
     hipLaunchKernelGGL(k_trap_init, dim3(blocks(n)), dim3(256), 0, s, seq, outlets, n, w);
@@ -211,7 +212,12 @@ ibip_status run_trap(ibip_ctx* ctx, const int32_t* seq, const uint8_t* outlets, 
     if ((rc = hip_check(ctx, hipMemcpyAsync(h + 1, dtotal, sizeof(uint32_t), hipMemcpyDeviceToHost, s), "copy")) !=
         IBIP_OK)
         return rc;
+    ctx->timer.mark(11, s);
     if ((rc = hip_check(ctx, hipStreamSynchronize(s), "sync")) != IBIP_OK) return rc;
+    if (ctx->timer.on) {
+        ctx->timing.trap_ms += ctx->timer.ms(10, 11);
+        ctx->timing.relax_sweeps += iters;
+    }
     if (n_steps_after) *n_steps_after = K > 0 ? (int64_t)h[1] : 0;
     return IBIP_OK;
 }
