@@ -35,7 +35,7 @@ constexpr int kPer = 8;
 constexpr int kSeg = 64 * kPer;
 
 template <class Feat>
-__global__ __launch_bounds__(256) void edt_pass_z(Feat feat, int64_t rows, int Z, uint16_t* g,
+__global__ __launch_bounds__(256) void edt_pass_z(Feat feat, int64_t rows, int Z, uint64_t cap, uint16_t* g,
                                                   uint32_t* solid_flag) {
     const int lane = threadIdx.x & 63;
     const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -69,7 +69,8 @@ __global__ __launch_bounds__(256) void edt_pass_z(Feat feat, int64_t rows, int Z
             int z = z0 + j;
             if (z >= Z) break;
             if (fbits & (1u << j)) prev = z;
-            g[base + z] = prev < 0 ? kInf16 : (uint16_t)(z - prev);
+            const uint64_t dz = (uint64_t)(z - prev);
+            g[base + z] = (prev < 0 || dz * dz >= cap) ? kInf16 : (uint16_t)dz;
         }
         carry = max(carry, __shfl(incl, 63, 64));
     }
@@ -101,9 +102,9 @@ __global__ __launch_bounds__(256) void edt_pass_z(Feat feat, int64_t rows, int Z
             if (z >= Z) continue;
             if (fbits & (1u << j)) next = z;
             if (next != 0x7FFFFFFF) {
-                uint32_t d = (uint32_t)(next - z);
-                uint16_t f = g[base + z];
-                if (d < f) g[base + z] = (uint16_t)d;
+                const uint32_t d = (uint32_t)(next - z);
+                const uint16_t f = g[base + z];
+                if (d < f && (uint64_t)d * d < cap) g[base + z] = (uint16_t)d;
             }
         }
         carryn = min(carryn, __shfl(incl, 0, 64));
@@ -112,7 +113,7 @@ __global__ __launch_bounds__(256) void edt_pass_z(Feat feat, int64_t rows, int Z
 }
 
 // pass y: lines along y at fixed (x, z). One thread per voxel.
-__global__ __launch_bounds__(256) void edt_pass_y(const uint16_t* __restrict__ g, int X, int Y, int Z,
+__global__ __launch_bounds__(256) void edt_pass_y(const uint16_t* __restrict__ g, int X, int Y, int Z, uint64_t cap,
                                                   uint32_t* __restrict__ h) {
     const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int64_t n = (int64_t)X * Y * Z;
@@ -121,7 +122,7 @@ __global__ __launch_bounds__(256) void edt_pass_y(const uint16_t* __restrict__ g
     uint64_t best;
     {
         uint16_t f = g[v];
-        best = f == kInf16 ? ~0ull : (uint64_t)f * f;
+        best = f == kInf16 ? cap : (uint64_t)f * f;
     }
     const int far = max(y, Y - 1 - y);
     for (int o = 1; o <= far; o++) {
@@ -136,11 +137,11 @@ __global__ __launch_bounds__(256) void edt_pass_y(const uint16_t* __restrict__ g
             if (f != kInf16) { uint64_t c = (uint64_t)f * f + oo; best = c < best ? c : best; }
         }
     }
-    h[v] = best >= 0xFFFFFFFFull ? kInf32 : (uint32_t)best;
+    h[v] = best >= cap ? kInf32 : (uint32_t)best;
 }
 
 // pass x: lines along x at fixed (y, z).
-__global__ __launch_bounds__(256) void edt_pass_x(const uint32_t* __restrict__ h, int X, int Y, int Z,
+__global__ __launch_bounds__(256) void edt_pass_x(const uint32_t* __restrict__ h, int X, int Y, int Z, uint64_t cap,
                                                   uint32_t* __restrict__ out) {
     const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int64_t yz = (int64_t)Y * Z;
@@ -150,7 +151,7 @@ __global__ __launch_bounds__(256) void edt_pass_x(const uint32_t* __restrict__ h
     uint64_t best;
     {
         uint32_t f = h[v];
-        best = f == kInf32 ? ~0ull : (uint64_t)f;
+        best = f == kInf32 ? cap : (uint64_t)f;
     }
     const int far = max(x, X - 1 - x);
     for (int o = 1; o <= far; o++) {
@@ -165,26 +166,28 @@ __global__ __launch_bounds__(256) void edt_pass_x(const uint32_t* __restrict__ h
             if (f != kInf32) { uint64_t c = (uint64_t)f + oo; best = c < best ? c : best; }
         }
     }
-    out[v] = best >= 0xFFFFFFFFull ? kInf32 : (uint32_t)best;
+    out[v] = best >= cap ? kInf32 : (uint32_t)best;
 }
 
 }  // namespace
 
-hipError_t launch_edt(const uint8_t* image, const uint32_t* w, uint32_t thr, ibip_dims d,
+hipError_t launch_edt(const uint8_t* image, const uint32_t* w, uint32_t thr, uint32_t cap, ibip_dims d,
                       uint16_t* g16, uint32_t* tmp32, uint32_t* out, uint32_t* solid_flag,
                       hipStream_t s) {
+    // cap == 0: exact everywhere; else exact where dt2 < cap, 0xFFFFFFFF elsewhere
+    const uint64_t c64 = cap ? (uint64_t)cap : 0xFFFFFFFFull;
     const int64_t n = nvox(d);
     const int64_t rows = (int64_t)d.X * d.Y;
     const unsigned gz = (unsigned)((rows + 3) / 4);
     if (image)
         hipLaunchKernelGGL(edt_pass_z<FeatImage>, dim3(gz), dim3(256), 0, s, FeatImage{image}, rows, d.Z,
-                           g16, solid_flag);
+                           c64, g16, solid_flag);
     else
         hipLaunchKernelGGL(edt_pass_z<FeatThreshold>, dim3(gz), dim3(256), 0, s, FeatThreshold{w, thr},
-                           rows, d.Z, g16, solid_flag);
+                           rows, d.Z, c64, g16, solid_flag);
     const unsigned gv = (unsigned)((n + 255) / 256);
-    hipLaunchKernelGGL(edt_pass_y, dim3(gv), dim3(256), 0, s, g16, d.X, d.Y, d.Z, tmp32);
-    hipLaunchKernelGGL(edt_pass_x, dim3(gv), dim3(256), 0, s, tmp32, d.X, d.Y, d.Z, out);
+    hipLaunchKernelGGL(edt_pass_y, dim3(gv), dim3(256), 0, s, g16, d.X, d.Y, d.Z, c64, tmp32);
+    hipLaunchKernelGGL(edt_pass_x, dim3(gv), dim3(256), 0, s, tmp32, d.X, d.Y, d.Z, c64, out);
     return hipGetLastError();
 }
 

@@ -17,6 +17,8 @@ namespace ibip {
 constexpr int kMaxRanks = 8192;
 // A step with more centres than this is handed to the whole-GPU kernel.
 constexpr uint32_t kWideRound = 8192;
+// A step with at most this many centres runs in one wave, without barriers.
+constexpr uint32_t kSmallRound = 128;
 constexpr uint32_t kInf32 = 0xFFFFFFFFu;
 
 // One grow-only device allocation.
@@ -27,7 +29,7 @@ struct Buf {
 
 enum BufId {
     B_KEY = 0,     // uint32[N]   dt2, then the rank of dt2 (0 = solid)
-    B_STATE,       // int32[N]    -2 solid, 0 unseen, -1 candidate, k > 0 centre of step k
+    B_STATE,       // int32[N]    k > 0 centre of step k, else 0
     B_BUCKET,      // uint32[N]   candidate voxel indices grouped by rank
     B_HIST,        // uint32[V]   histogram of dt2 values, then value -> rank
     B_OFF,         // uint32[R+2] bucket offsets by rank
@@ -44,6 +46,8 @@ enum BufId {
     B_TMP1,
     B_TMP2,
     B_SCAN,        // scan partials
+    B_ACT,         // uint8[2 * tiles] active-tile flags of the reconstruction
+    B_CNT,         // uint32 per-sweep change counters
     B_NUM
 };
 
@@ -125,8 +129,10 @@ inline int64_t nvox(ibip_dims d) { return (int64_t)d.X * d.Y * d.Z; }
 // ---- launchers (each returns hipSuccess or the first launch error) ----
 // EDT: dt2 = squared distance to the nearest voxel with feature != 0, where
 // feature(v) = (image[v] == 0) when `image` is given, else (w[v] >= thr).
-// Sets *solid_flag (device) to 1 if any feature voxel exists.
-hipError_t launch_edt(const uint8_t* image, const uint32_t* w, uint32_t thr, ibip_dims d,
+// With cap > 0 the result is exact where it is below cap and 0xFFFFFFFF
+// elsewhere (the searches stop at cap). Sets *solid_flag (device) to 1 if any
+// feature voxel exists.
+hipError_t launch_edt(const uint8_t* image, const uint32_t* w, uint32_t thr, uint32_t cap, ibip_dims d,
                       uint16_t* g16, uint32_t* tmp32, uint32_t* out, uint32_t* solid_flag,
                       hipStream_t s);
 

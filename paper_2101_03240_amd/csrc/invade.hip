@@ -3,7 +3,9 @@
 //
 // Data layout in HBM (N voxels, N_pore pore voxels, R distinct dt2 values):
 //   key[N]      uint32  rank of dt2 among the distinct pore values (1..R), 0 on solid
-//   state[N]    int32   -2 solid, 0 unseen pore, -1 candidate, k > 0 centre of step k
+//   key[N] bit 31 marks a voxel claimed as a candidate (one atomicOr claims
+//               a neighbour and returns its rank)
+//   state[N]    int32   k > 0: centre of step k; 0 otherwise
 //   bucket[N_pore] uint32  candidates grouped by rank; rank r owns the slice
 //               [off[r], off[r+1]) whose length is the number of pore voxels
 //               of that rank, so every pore voxel fits exactly once
@@ -46,6 +48,11 @@ __device__ inline uint32_t isqrt_u32(uint32_t a) {
     while ((q + 1) * (q + 1) <= a) q++;
     return (uint32_t)q;
 }
+
+// Key words: bits 0..30 hold the rank of dt2 among the distinct pore values
+// (0 on solid); bit 31 marks a voxel claimed as a candidate.
+constexpr uint32_t kClaim = 0x80000000u;
+constexpr uint32_t kRankMask = 0x7FFFFFFFu;
 
 __device__ inline uint64_t lanemask_lt() {
     const int lane = threadIdx.x & 63;
@@ -107,19 +114,18 @@ __global__ void k_rank_tables(const uint32_t* cnt_scanned, const uint32_t* prese
     tail[r] = cnt_scanned[v];
 }
 
-// key = rank (0 on solid); state; seq = INT_MAX on pore, -1 on solid.
+// key = rank (0 on solid); state = 0; seq = INT_MAX on pore, -1 on solid.
 __global__ __launch_bounds__(256) void k_convert(const uint8_t* __restrict__ img, uint32_t* key,
                                                  const uint32_t* __restrict__ present_scanned, int64_t n,
                                                  int32_t* state, int32_t* seq) {
     int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (v >= n) return;
+    state[v] = 0;
     if (img[v]) {
         key[v] = present_scanned[key[v]] + 1;
-        state[v] = 0;
         seq[v] = INT_MAX;
     } else {
         key[v] = 0;
-        state[v] = -2;
         seq[v] = -1;
     }
 }
@@ -141,9 +147,8 @@ __device__ inline void push_global(bool active, uint32_t u, uint32_t rr, uint32_
 }
 
 // Seeds: Q0 = (inlets U their face neighbours) restricted to pore.
-__global__ __launch_bounds__(256) void k_seed(const uint8_t* __restrict__ inlets, const uint32_t* __restrict__ key,
-                                              int X, int Y, int Z, int32_t* state, uint32_t* tail,
-                                              uint32_t* bucket) {
+__global__ __launch_bounds__(256) void k_seed(const uint8_t* __restrict__ inlets, uint32_t* key, int X, int Y,
+                                              int Z, uint32_t* tail, uint32_t* bucket) {
     const int64_t n = (int64_t)X * Y * Z;
     const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const bool inl = v < n && inlets[v] != 0;
@@ -163,16 +168,17 @@ __global__ __launch_bounds__(256) void k_seed(const uint8_t* __restrict__ inlets
         if (j == 6) { ok &= z < Z - 1; u = v + 1; }
         bool won = false;
         uint32_t rr = 0;
-        if (ok && state[u] == 0) {
-            won = atomicCAS(&state[u], 0, -1) == 0;
-            if (won) rr = key[u];
+        if (ok && key[u] < kClaim) {
+            const uint32_t old = atomicOr(&key[u], kClaim);
+            rr = old & kRankMask;
+            won = !(old & kClaim) && rr != 0;
         }
         push_global(won, (uint32_t)u, rr, tail, bucket);
     }
 }
 
 // ---------------------------------------------------------------------------
-// The round loop: one workgroup.
+// The step loop: one workgroup.
 // ---------------------------------------------------------------------------
 struct LoopArgs {
     LoopState* st;
@@ -181,77 +187,38 @@ struct LoopArgs {
     const uint32_t* val;
     uint32_t* bucket;
     int32_t* state;
-    const uint32_t* key;
+    uint32_t* key;
     uint32_t* M;
     int X, Y, Z;
-    uint32_t wide;
+    uint32_t wide;    // steps with more centres go to the whole-GPU kernel
+    uint32_t small;   // steps with at most this many centres run in wave 0 alone
 };
 
 constexpr int kLoopThreads = 1024;
 constexpr int kBitWords = (kMaxRanks >> 5) + 2;
 constexpr int kSumWords = (kBitWords >> 5) + 1;
+constexpr uint32_t kLog = 2048;  // entries of the per-step push log
 
 struct LoopShared {
     uint32_t head[kMaxRanks + 1];
     uint32_t tail[kMaxRanks + 1];
-    uint32_t bits[kBitWords];
-    uint32_t sum[kSumWords];
-    uint32_t r, h, cnt, k, pushmax, exit;
+    uint32_t bits[kBitWords];   // rank r non-empty
+    uint32_t sum[kSumWords];    // bits word w non-zero
+    // pushes of the last two steps (voxel, rank), double-buffered
+    uint32_t logu[2][kLog];
+    uint32_t logr[2][kLog];
+    uint32_t logn[2];           // pushes counted (more than kLog = log incomplete)
+    uint32_t pushmax;
+    // descriptor of a step run by all waves
+    uint32_t d_exit, d_h, d_cnt, d_k, d_r, d_fromlog, d_sel;
 };
+
+__device__ inline uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 
 __device__ inline void lds_set(LoopShared& s, uint32_t r) {
     atomicOr(&s.bits[r >> 5], 1u << (r & 31));
     atomicOr(&s.sum[r >> 10], 1u << ((r >> 5) & 31));
 }
-
-__device__ inline void lds_push(LoopShared& s, bool active, uint32_t u, uint32_t rr, uint32_t* bucket) {
-    uint64_t pending = __ballot(active);
-    while (pending) {
-        const int leader = __ffsll((unsigned long long)pending) - 1;
-        const uint32_t lr = __shfl(rr, leader, 64);
-        const uint64_t same = __ballot(active && rr == lr) & pending;
-        uint32_t base = 0;
-        if ((threadIdx.x & 63) == leader) {
-            base = atomicAdd(&s.tail[lr], (uint32_t)__popcll(same));
-            lds_set(s, lr);
-            atomicMax(&s.pushmax, lr);
-        }
-        base = __shfl(base, leader, 64);
-        if (active && rr == lr) bucket[base + __popcll(same & lanemask_lt())] = u;
-        pending &= ~same;
-    }
-}
-
-// Make centre c a centre of step k and try to claim its unseen pore face
-// neighbours; calls push(active, u, rank) once per direction for the wave.
-template <class Push>
-__device__ inline void expand(bool have, uint32_t c, uint32_t k, const LoopArgs& a, Push push) {
-    const int64_t yz = (int64_t)a.Y * a.Z;
-    int z = 0, y = 0, x = 0;
-    if (have) {
-        a.state[c] = (int32_t)k;
-        z = (int)(c % (uint32_t)a.Z);
-        uint32_t t = c / (uint32_t)a.Z;
-        y = (int)(t % (uint32_t)a.Y);
-        x = (int)(t / (uint32_t)a.Y);
-    }
-    int32_t* state = a.state;
-    // issue the six claims back to back, then push per direction
-    bool won[6];
-    int64_t uu[6] = {(int64_t)c - yz, (int64_t)c + yz, (int64_t)c - a.Z, (int64_t)c + a.Z,
-                     (int64_t)c - 1, (int64_t)c + 1};
-    bool okd[6] = {have && x > 0, have && x < a.X - 1, have && y > 0, have && y < a.Y - 1,
-                   have && z > 0, have && z < a.Z - 1};
-#pragma unroll
-    for (int j = 0; j < 6; j++) won[j] = okd[j] && atomicCAS(&state[uu[j]], 0, -1) == 0;
-#pragma unroll
-    for (int j = 0; j < 6; j++) {
-        uint32_t rr = won[j] ? a.key[uu[j]] : 0u;
-        push(won[j], (uint32_t)uu[j], rr);
-    }
-}
-
-__device__ inline uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 
 // highest set rank strictly below r (0 = none), with every loaded word made
 // wave-uniform so the search runs on scalar branches
@@ -272,109 +239,289 @@ __device__ inline uint32_t lds_highest_below_uni(const LoopShared& s, uint32_t r
     }
 }
 
-// Control flow: the per-step decisions run in all 64 lanes of wave 0 under a
-// wave-uniform branch, on values made uniform with readfirstlane (duplicate
-// stores of one value from several lanes are harmless). No lane-divergent
-// region sits in the control path of the barrier loop, so the compiler keeps
-// both barriers in uniform control flow; a `tid == 0` region there can be
-// restructured so that lanes 1..63 of wave 0 loop back to a barrier while
-// lane 0 waits outside the loop.
+// After step r: the next maximum is r itself if its slice refilled, else the
+// highest non-empty rank below it, or anything larger pushed during the step.
+__device__ inline uint32_t next_top(LoopShared& s, uint32_t r, uint32_t pushmax) {
+    uint32_t cand;
+    if (uni(s.tail[r]) > uni(s.head[r])) {
+        cand = r;
+    } else {
+        const uint32_t wv = uni(s.bits[r >> 5]) & ~(1u << (r & 31));
+        s.bits[r >> 5] = wv;
+        if (wv == 0) s.sum[r >> 10] = uni(s.sum[r >> 10]) & ~(1u << ((r >> 5) & 31));
+        cand = lds_highest_below_uni(s, r);
+    }
+    return cand > pushmax ? cand : pushmax;
+}
+
+// wave-wide maximum of a lane value (result uniform)
+__device__ inline uint32_t wave_max(uint32_t x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint32_t t = __shfl_xor(x, o, 64);
+        x = t > x ? t : x;
+    }
+    return uni(x);
+}
+
+// Make c a centre of step k and claim its unseen pore face neighbours: one
+// atomicOr per neighbour sets the claim bit and returns the rank, so a claim
+// costs one round trip; the six claims are in flight together. The claimed
+// voxels are then appended to the slices of their ranks in LDS: one
+// independent atomicAdd per push on the slice tail (no serial per-rank loop),
+// one wave-level atomicAdd reserving the push-log entries, and return-less ORs
+// into the occupancy bitmap. Returns the largest rank pushed by the wave
+// (wave-uniform, 0 if none).
+__device__ inline uint32_t expand_lds(bool have, uint32_t c, uint32_t k, const LoopArgs& a, LoopShared& s,
+                                      uint32_t sel) {
+    const int64_t yz = (int64_t)a.Y * a.Z;
+    int z = 0, y = 0, x = 0;
+    if (have) {
+        a.state[c] = (int32_t)k;
+        z = (int)(c % (uint32_t)a.Z);
+        const uint32_t t = c / (uint32_t)a.Z;
+        y = (int)(t % (uint32_t)a.Y);
+        x = (int)(t / (uint32_t)a.Y);
+    }
+    const int64_t uu[6] = {(int64_t)c - yz, (int64_t)c + yz, (int64_t)c - a.Z, (int64_t)c + a.Z,
+                           (int64_t)c - 1, (int64_t)c + 1};
+    const bool okd[6] = {have && x > 0, have && x < a.X - 1, have && y > 0, have && y < a.Y - 1,
+                         have && z > 0, have && z < a.Z - 1};
+    uint32_t old[6];
+#pragma unroll
+    for (int j = 0; j < 6; j++) old[j] = okd[j] ? atomicOr(&a.key[uu[j]], kClaim) : kClaim;
+    bool won[6];
+    uint32_t rr[6], pos[6];
+    uint32_t mymax = 0;
+#pragma unroll
+    for (int j = 0; j < 6; j++) {
+        rr[j] = old[j] & kRankMask;
+        won[j] = !(old[j] & kClaim) && rr[j] != 0;
+        mymax = won[j] && rr[j] > mymax ? rr[j] : mymax;
+    }
+    // slice positions: independent LDS atomics, all in flight together
+#pragma unroll
+    for (int j = 0; j < 6; j++) pos[j] = won[j] ? atomicAdd(&s.tail[rr[j]], 1u) : 0u;
+    // push-log entries: one reservation per wave
+    uint64_t m[6];
+    uint32_t before[6], total = 0;
+#pragma unroll
+    for (int j = 0; j < 6; j++) {
+        m[j] = __ballot(won[j]);
+        before[j] = total;
+        total += (uint32_t)__popcll(m[j]);
+    }
+    uint32_t lbase = 0;
+    if (total) {
+        uint32_t b = 0;
+        if ((threadIdx.x & 63) == 0) b = atomicAdd(&s.logn[sel], total);
+        lbase = uni(__shfl(b, 0, 64));
+    }
+    const uint64_t lt = lanemask_lt();
+#pragma unroll
+    for (int j = 0; j < 6; j++) {
+        if (!won[j]) continue;
+        a.bucket[pos[j]] = (uint32_t)uu[j];
+        lds_set(s, rr[j]);
+        const uint32_t li = lbase + before[j] + (uint32_t)__popcll(m[j] & lt);
+        if (li < kLog) {
+            s.logu[sel][li] = (uint32_t)uu[j];
+            s.logr[sel][li] = rr[j];
+        }
+    }
+    return wave_max(mymax);
+}
+
+// Control flow: the step decisions run in all 64 lanes of wave 0 on values
+// made uniform with readfirstlane (duplicate stores of one value from several
+// lanes are harmless). Wave 0 runs steps of up to `small` centres alone, with
+// no barrier; larger steps are run by all waves between two barriers, and the
+// barriers stay in wave-uniform control flow. (A lane-divergent `tid == 0`
+// region in a barrier loop can be restructured so that lanes 1..63 of wave 0
+// loop back to a barrier while lane 0 waits outside the loop.)
+//
+// When the new maximum rank is at least the previous step's, its live entries
+// are exactly the previous step's pushes of that rank (the slice was either
+// popped empty by that step or empty before it), so they are read from the
+// LDS push log instead of global memory, if the log did not overflow.
 __global__ __launch_bounds__(kLoopThreads) void k_loop(LoopArgs a) {
     __shared__ LoopShared s;
     const int tid = threadIdx.x;
+    const int lane = tid & 63;
     const bool wave0 = uni((uint32_t)tid >> 6) == 0;
     const uint32_t R = a.st->R;
-    for (uint32_t r = tid; r <= R; r += kLoopThreads) {
-        s.head[r] = a.head[r];
-        s.tail[r] = a.tail[r];
+    for (uint32_t q = tid; q <= R; q += kLoopThreads) {
+        s.head[q] = a.head[q];
+        s.tail[q] = a.tail[q];
     }
     for (int w = tid; w < kBitWords; w += kLoopThreads) s.bits[w] = 0;
     for (int w = tid; w < kSumWords; w += kLoopThreads) s.sum[w] = 0;
+    if (tid < 2) s.logn[tid] = 0;
     __syncthreads();
-    for (uint32_t r = 1 + tid; r <= R; r += kLoopThreads)
-        if (s.tail[r] > s.head[r]) lds_set(s, r);
+    for (uint32_t q = 1 + tid; q <= R; q += kLoopThreads)
+        if (s.tail[q] > s.head[q]) lds_set(s, q);
     __syncthreads();
     const int64_t max_steps = a.st->max_steps;
     const uint32_t n_pore = a.st->n_pore;
-    // loop control, live in wave 0 only
-    uint32_t r = 0, k = 0;
-    bool first = true;
+    // driver state, live in wave 0
+    uint32_t r = 0, k = 0, prev_r = 0, sel = 0;
+    bool log_ok = false;
     if (wave0) {
         r = lds_highest_below_uni(s, R + 1);
         k = uni(a.st->k);
     }
     for (;;) {
         if (wave0) {
-            if (!first) {
-                // close the previous step: pick the next maximum
-                uint32_t cand;
-                if (uni(s.tail[r]) > uni(s.head[r])) {
-                    cand = r;
-                } else {
-                    const uint32_t wv = uni(s.bits[r >> 5]) & ~(1u << (r & 31));
-                    s.bits[r >> 5] = wv;
-                    if (wv == 0) s.sum[r >> 10] = uni(s.sum[r >> 10]) & ~(1u << ((r >> 5) & 31));
-                    cand = lds_highest_below_uni(s, r);
+            for (;;) {
+                uint32_t ex = 0;
+                if (r == 0) {
+                    a.st->status = LS_DONE;
+                    ex = 1;
+                } else if (k > n_pore) {
+                    // every step takes at least one new pore voxel: more steps than
+                    // pore voxels means corrupted state; stop instead of looping
+                    a.st->err = 1;
+                    a.st->status = LS_DONE;
+                    ex = 1;
+                } else if (max_steps > 0 && (int64_t)k > max_steps) {
+                    a.st->status = LS_MAXSTEPS;
+                    ex = 1;
                 }
-                const uint32_t pm = uni(s.pushmax);
-                r = cand > pm ? cand : pm;
-                k = k + 1;
-            }
-            uint32_t ex = 0, hh = 0, cn = 0;
-            if (r == 0) {
-                a.st->status = LS_DONE;
-                ex = 1;
-            } else if (k > n_pore) {
-                // every step takes at least one new pore voxel: more steps than
-                // pore voxels means corrupted state; stop instead of looping
-                a.st->err = 1;
-                a.st->status = LS_DONE;
-                ex = 1;
-            } else if (max_steps > 0 && (int64_t)k > max_steps) {
-                a.st->status = LS_MAXSTEPS;
-                ex = 1;
-            } else {
+                if (ex) {
+                    s.d_exit = 1;
+                    break;
+                }
                 const uint32_t h = uni(s.head[r]), t = uni(s.tail[r]);
+                const uint32_t cnt = t - h;
                 s.head[r] = t;
-                a.M[k - 1] = uni(a.val[r]);
-                if (t - h > a.wide) {
+                a.M[k - 1] = r;  // rank; k_rank_to_value turns it into dt2 after the loop
+                const bool fromlog = log_ok && r >= prev_r;
+                if (cnt > a.wide) {
                     a.st->big_r = r;
                     a.st->big_h = h;
                     a.st->big_t = t;
                     a.st->big_k = k;
                     a.st->status = LS_WIDE;
                     k = k + 1;
-                    ex = 1;
-                } else {
-                    hh = h;
-                    cn = t - h;
+                    s.d_exit = 1;
+                    break;
+                }
+                const uint32_t nsel = sel ^ 1u;
+                s.logn[nsel] = 0;
+                if (cnt > a.small) {
                     s.pushmax = 0;
+                    s.d_exit = 0;
+                    s.d_h = h;
+                    s.d_cnt = cnt;
+                    s.d_k = k;
+                    s.d_r = r;
+                    s.d_fromlog = fromlog ? 1u : 0u;
+                    s.d_sel = sel;
+                    break;
+                }
+                // a small step, wave 0 alone
+                uint32_t pm = 0;
+                if (fromlog) {
+                    const uint32_t n = uni(s.logn[sel]);
+                    for (uint32_t b0 = 0; b0 < n; b0 += 64) {
+                        const uint32_t i = b0 + lane;
+                        bool have = false;
+                        uint32_t c = 0;
+                        if (i < n) {
+                            have = s.logr[sel][i] == r;
+                            c = s.logu[sel][i];
+                        }
+                        const uint32_t m = expand_lds(have, c, k, a, s, nsel);
+                        pm = m > pm ? m : pm;
+                    }
+                } else {
+                    for (uint32_t b0 = 0; b0 < cnt; b0 += 64) {
+                        const uint32_t i = b0 + lane;
+                        const bool have = i < cnt;
+                        const uint32_t c = have ? a.bucket[h + i] : 0u;
+                        const uint32_t m = expand_lds(have, c, k, a, s, nsel);
+                        pm = m > pm ? m : pm;
+                    }
+                }
+                const uint32_t r_done = r;
+                r = next_top(s, r, uni(pm));
+                prev_r = r_done;
+                k = k + 1;
+                sel = nsel;
+                log_ok = uni(s.logn[nsel]) <= kLog;
+            }
+        }
+        __syncthreads();
+        if (uni(s.d_exit)) break;
+        {
+            // a step with many centres, all waves
+            const uint32_t h = uni(s.d_h), cnt = uni(s.d_cnt), kk = uni(s.d_k), rr0 = uni(s.d_r);
+            const uint32_t osel = uni(s.d_sel), nsel = osel ^ 1u;
+            uint32_t pm = 0;
+            if (uni(s.d_fromlog)) {
+                const uint32_t n = uni(s.logn[osel]);
+                for (uint32_t b0 = 0; b0 < n; b0 += kLoopThreads) {
+                    const uint32_t i = b0 + tid;
+                    bool have = false;
+                    uint32_t c = 0;
+                    if (i < n) {
+                        have = s.logr[osel][i] == rr0;
+                        c = s.logu[osel][i];
+                    }
+                    const uint32_t m = expand_lds(have, c, kk, a, s, nsel);
+                    pm = m > pm ? m : pm;
+                }
+            } else {
+                for (uint32_t b0 = 0; b0 < cnt; b0 += kLoopThreads) {
+                    const uint32_t i = b0 + tid;
+                    const bool have = i < cnt;
+                    const uint32_t c = have ? a.bucket[h + i] : 0u;
+                    const uint32_t m = expand_lds(have, c, kk, a, s, nsel);
+                    pm = m > pm ? m : pm;
                 }
             }
-            s.exit = ex;
-            s.h = hh;
-            s.cnt = cn;
-            s.k = k;
-        }
-        first = false;
-        __syncthreads();
-        if (uni(s.exit)) break;
-        const uint32_t h = uni(s.h);
-        const uint32_t cnt = uni(s.cnt);
-        const uint32_t kk = uni(s.k);
-        const uint32_t ntrip = (cnt + kLoopThreads - 1) / kLoopThreads;
-        for (uint32_t it = 0; it < ntrip; it++) {
-            const uint32_t i = it * kLoopThreads + tid;
-            const bool have = i < cnt;
-            const uint32_t c = have ? a.bucket[h + i] : 0u;
-            expand(have, c, kk, a, [&](bool act, uint32_t u, uint32_t rr) { lds_push(s, act, u, rr, a.bucket); });
+            if (lane == 0 && pm) atomicMax(&s.pushmax, pm);
         }
         __syncthreads();
+        if (wave0) {
+            const uint32_t r_done = r;
+            r = next_top(s, r, uni(s.pushmax));
+            prev_r = r_done;
+            k = k + 1;
+            sel ^= 1u;
+            log_ok = uni(s.logn[sel]) <= kLog;
+        }
     }
     if (wave0) a.st->k = k;
     for (uint32_t q = tid; q <= R; q += kLoopThreads) {
         a.head[q] = s.head[q];
         a.tail[q] = s.tail[q];
+    }
+}
+
+// expand() for the whole-GPU kernel: the same claims, pushed to the global
+// slice tails with one atomic per distinct rank in the wave.
+__device__ inline void expand_global(bool have, uint32_t c, uint32_t k, const LoopArgs& a) {
+    const int64_t yz = (int64_t)a.Y * a.Z;
+    int z = 0, y = 0, x = 0;
+    if (have) {
+        a.state[c] = (int32_t)k;
+        z = (int)(c % (uint32_t)a.Z);
+        const uint32_t t = c / (uint32_t)a.Z;
+        y = (int)(t % (uint32_t)a.Y);
+        x = (int)(t / (uint32_t)a.Y);
+    }
+    const int64_t uu[6] = {(int64_t)c - yz, (int64_t)c + yz, (int64_t)c - a.Z, (int64_t)c + a.Z,
+                           (int64_t)c - 1, (int64_t)c + 1};
+    const bool okd[6] = {have && x > 0, have && x < a.X - 1, have && y > 0, have && y < a.Y - 1,
+                         have && z > 0, have && z < a.Z - 1};
+    uint32_t old[6];
+#pragma unroll
+    for (int j = 0; j < 6; j++) old[j] = okd[j] ? atomicOr(&a.key[uu[j]], kClaim) : kClaim;
+#pragma unroll
+    for (int j = 0; j < 6; j++) {
+        const uint32_t rr = old[j] & kRankMask;
+        push_global(!(old[j] & kClaim) && rr != 0, (uint32_t)uu[j], rr, a.tail, a.bucket);
     }
 }
 
@@ -388,7 +535,7 @@ __global__ __launch_bounds__(256) void k_wide(LoopArgs a) {
         const uint32_t i = it * stride + blockIdx.x * 256 + threadIdx.x;
         const bool have = i < cnt;
         const uint32_t c = have ? a.bucket[h + i] : 0u;
-        expand(have, c, k, a, [&](bool act, uint32_t u, uint32_t rr) { push_global(act, u, rr, a.tail, a.bucket); });
+        expand_global(have, c, k, a);
     }
 }
 
@@ -418,7 +565,7 @@ __global__ __launch_bounds__(256) void k_paint_shell(PaintArgs a) {
     if (c >= n) return;
     const int32_t k = a.state[c];
     if (k <= 0) return;
-    const uint32_t rc = a.key[c];
+    const uint32_t rc = a.key[c] & kRankMask;
     const uint32_t m = a.val[rc];
     const int z = (int)(c % a.Z), y = (int)((c / a.Z) % a.Y), x = (int)(c / yz);
     // neighbour j sits at c + n_j: axis j >> 1, sign (j & 1) ? +1 : -1
@@ -432,7 +579,7 @@ __global__ __launch_bounds__(256) void k_paint_shell(PaintArgs a) {
         if (!inb[j]) continue;
         const int32_t kp = a.state[c + off[j]];
         if (kp > 0 && kp < k) {
-            const uint32_t rp = a.key[c + off[j]];
+            const uint32_t rp = a.key[c + off[j]] & kRankMask;
             if (rp >= rc) { qmask |= 1u << j; mp[j] = a.val[rp]; }
         }
     }
@@ -488,7 +635,7 @@ __global__ __launch_bounds__(256) void k_paint_full(PaintArgs a) {
     for (uint32_t i = blockIdx.x * 4 + (threadIdx.x >> 6); i < nf; i += gridDim.x * 4) {
         const int64_t c = a.full[i];
         const int32_t k = a.state[c];
-        const uint32_t m = a.val[a.key[c]];
+        const uint32_t m = a.val[a.key[c] & kRankMask];
         const int z = (int)(c % a.Z), y = (int)((c / a.Z) % a.Y), x = (int)(c / yz);
         const int Rb = (int)isqrt_u32(m - 1);
         for (int dx = -Rb; dx <= Rb; dx++) {
@@ -511,6 +658,12 @@ __global__ __launch_bounds__(256) void k_paint_full(PaintArgs a) {
 // ---------------------------------------------------------------------------
 // Finalise and per-step accounting
 // ---------------------------------------------------------------------------
+// M held ranks during the loop; turn them into squared radii.
+__global__ void k_rank_to_value(uint32_t* M, int64_t K, const uint32_t* val) {
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k < K) M[k] = val[M[k]];
+}
+
 __global__ __launch_bounds__(256) void k_finalise(int32_t* seq, int32_t* state_io, bool map_state, int64_t n,
                                                   const uint32_t* M, uint32_t* rad2, uint32_t* count,
                                                   uint32_t* popped) {
@@ -595,7 +748,7 @@ ibip_status run_invade(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlet
     if ((rc = hip_check(ctx, hipMemsetAsync(misc, 0, 4096, s), "memset")) != IBIP_OK) return rc;
     if ((rc = hip_check(ctx, hipMemsetAsync(hist, 0, sizeof(uint32_t) * V, s), "memset")) != IBIP_OK) return rc;
     // a1: distance transform into key[]
-    if ((rc = hip_check(ctx, launch_edt(image, nullptr, 0, d, g16, tmp32, key, solid_flag, s), "edt")) != IBIP_OK)
+    if ((rc = hip_check(ctx, launch_edt(image, nullptr, 0, 0, d, g16, tmp32, key, solid_flag, s), "edt")) != IBIP_OK)
         return rc;
     tm.mark(1, s);
     // a2: histogram -> ranks and bucket slices
@@ -626,7 +779,7 @@ ibip_status run_invade(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlet
     if ((rc = hip_check(ctx, hipMemsetAsync(tail, 0, sizeof(uint32_t) * (R + 2), s), "memset")) != IBIP_OK) return rc;
     hipLaunchKernelGGL(k_rank_tables, dim3(blocks(V)), dim3(256), 0, s, hist, present, flags, V, val, off, head, tail);
     hipLaunchKernelGGL(k_convert, dim3(blocks(n)), dim3(256), 0, s, image, key, present, n, state, seq);
-    hipLaunchKernelGGL(k_seed, dim3(blocks(n)), dim3(256), 0, s, inlets, key, d.X, d.Y, d.Z, state, tail, bucket);
+    hipLaunchKernelGGL(k_seed, dim3(blocks(n)), dim3(256), 0, s, inlets, key, d.X, d.Y, d.Z, tail, bucket);
     tm.mark(2, s);
     // loop control
     h_st->k = 1;
@@ -643,7 +796,7 @@ ibip_status run_invade(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlet
             return rc;
         if ((rc = hip_check(ctx, hipStreamSynchronize(s), "sync")) != IBIP_OK) return rc;
     }
-    LoopArgs la{st, head, tail, val, bucket, state, key, M, d.X, d.Y, d.Z, kWideRound};
+    LoopArgs la{st, head, tail, val, bucket, state, key, M, d.X, d.Y, d.Z, kWideRound, kSmallRound};
     int64_t segments = 0;
     bool wide_pending_timing = false;
     for (;;) {
@@ -680,6 +833,7 @@ ibip_status run_invade(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlet
     if (h_st->err) return fail(ctx, IBIP_EDEVICE, "invade: step loop exceeded the pore count");
     const int64_t K = (int64_t)h_st->k - 1;
     tm.mark(7, s);
+    if (K > 0) hipLaunchKernelGGL(k_rank_to_value, dim3(blocks(K)), dim3(256), 0, s, M, K, val);
     // a5: sphere insertion
     PaintArgs pa{state, key, val, seq, full, &st->n_full, d.X, d.Y, d.Z};
     hipLaunchKernelGGL(k_paint_shell, dim3(blocks(n)), dim3(256), 0, s, pa);

@@ -82,7 +82,7 @@ ibip_status run_mio(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlets, 
     if ((rc = hip_check(ctx, hipMemsetAsync(counts, 0, sizeof(uint32_t) * (nT + 8), s), "memset")) != IBIP_OK)
         return rc;
     if ((rc = hip_check(ctx, hipMemsetAsync(mio_r2, 0, sizeof(uint32_t) * n, s), "memset")) != IBIP_OK) return rc;
-    if ((rc = hip_check(ctx, launch_edt(image, nullptr, 0, d, g16, tmp32, dt2, &flags[0], s), "edt")) != IBIP_OK)
+    if ((rc = hip_check(ctx, launch_edt(image, nullptr, 0, 0, d, g16, tmp32, dt2, &flags[0], s), "edt")) != IBIP_OK)
         return rc;
     hipLaunchKernelGGL(k_mio_seed, dim3(blocks(n)), dim3(256), 0, s, image, inlets, dt2, d.X, d.Y, d.Z, kmap,
                        &flags[1]);
@@ -93,7 +93,7 @@ ibip_status run_mio(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlets, 
     int iters = 0;
     if ((rc = reconstruct(ctx, nullptr, dt2, d, kmap, &iters)) != IBIP_OK) return rc;
     for (int32_t i = 0; i < nT; i++) {
-        if ((rc = hip_check(ctx, launch_edt(nullptr, kmap, T[i], d, g16, tmp32, d2, &flags[2], s), "edt")) != IBIP_OK)
+        if ((rc = hip_check(ctx, launch_edt(nullptr, kmap, T[i], T[i], d, g16, tmp32, d2, &flags[2], s), "edt")) != IBIP_OK)
             return rc;
         hipLaunchKernelGGL(k_mio_update, dim3(blocks(n)), dim3(256), 0, s, d2, T[i], n, mio_r2, &counts[i]);
     }

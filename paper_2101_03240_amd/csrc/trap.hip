@@ -12,10 +12,11 @@
 // computed here by data-parallel relaxation to the fixed point
 //   W(v) = max(W0(v), min(cap(v), max over face neighbours u of W(u))).
 //
-// Relaxation runs per 4 x 8 x 32 tile: the tile and a one-voxel halo sit in
-// LDS and are swept until nothing changes; sweeps over all tiles repeat until
-// no tile changed (W only grows and is bounded, so this terminates at the
-// unique fixed point).
+// Relaxation runs per 8 x 16 x 32 tile: the tile and a one-voxel halo sit in
+// LDS and are swept until nothing changes. Sweeps repeat over the active
+// tiles (all at first, then those whose face-neighbour changed its boundary
+// layer) until no tile changes. W only grows and is bounded, so this ends at
+// the unique fixed point.
 #include <climits>
 
 #include "ibip_internal.h"
@@ -24,7 +25,7 @@ namespace ibip {
 
 namespace {
 
-constexpr int TX = 4, TY = 8, TZ = 32;
+constexpr int TX = 8, TY = 16, TZ = 32;  // 4096 voxels per tile, 16 per thread
 constexpr int HX = TX + 2, HY = TY + 2, HZ = TZ + 2;
 
 struct CapSeq {
@@ -39,17 +40,24 @@ struct CapU32 {
     __device__ uint32_t operator()(int64_t v) const { return cap[v]; }
 };
 
+// One sweep over the active tiles. A tile whose boundary layer changed
+// activates the face-neighbour tiles across the changed faces for the next
+// sweep (act_out); *changed counts tiles that changed anything.
 template <class Cap>
 __global__ __launch_bounds__(256) void k_relax_tiles(Cap cap, int X, int Y, int Z, int ntx, int nty, int ntz,
-                                                     uint32_t* w, uint32_t* changed) {
+                                                     uint32_t* w, const uint8_t* act_in, uint8_t* act_out,
+                                                     uint32_t* changed) {
     __shared__ uint32_t hw[HX * HY * HZ];
+    __shared__ uint32_t face[6];
     const int tid = threadIdx.x;
     const int64_t tile = blockIdx.x;
+    if (!act_in[tile]) return;
     const int tz = (int)(tile % ntz);
     const int ty = (int)((tile / ntz) % nty);
     const int tx = (int)(tile / ((int64_t)ntz * nty));
     const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
     const int64_t yz = (int64_t)Y * Z;
+    if (tid < 6) face[tid] = 0;
     for (int i = tid; i < HX * HY * HZ; i += 256) {
         const int hz = i % HZ, hy = (i / HZ) % HY, hx = i / (HZ * HY);
         const int gx = x0 + hx - 1, gy = y0 + hy - 1, gz = z0 + hz - 1;
@@ -57,26 +65,28 @@ __global__ __launch_bounds__(256) void k_relax_tiles(Cap cap, int X, int Y, int 
         if (gx >= 0 && gx < X && gy >= 0 && gy < Y && gz >= 0 && gz < Z) val = w[gx * yz + (int64_t)gy * Z + gz];
         hw[i] = val;
     }
-    const int lz = tid & 31, ly = tid >> 5;
-    uint32_t c[TX], orig[TX];
-    const int gy = y0 + ly, gz = z0 + lz;
+    const int lz = tid & 31, ly = tid >> 5;  // ly in [0, 8): rows ly and ly + 8
+    constexpr int NV = TX * 2;
+    uint32_t c[NV], orig[NV];
+    const int gz = z0 + lz;
 #pragma unroll
-    for (int j = 0; j < TX; j++) {
-        const int gx = x0 + j;
+    for (int j = 0; j < NV; j++) {
+        const int gx = x0 + (j >> 1), gy = y0 + ly + 8 * (j & 1);
         const bool in = gx < X && gy < Y && gz < Z;
         c[j] = in ? cap(gx * yz + (int64_t)gy * Z + gz) : 0u;
     }
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < TX; j++) orig[j] = hw[((j + 1) * HY + (ly + 1)) * HZ + (lz + 1)];
+    for (int j = 0; j < NV; j++) orig[j] = hw[(((j >> 1) + 1) * HY + (ly + 8 * (j & 1) + 1)) * HZ + (lz + 1)];
     bool any_change = false;
     for (;;) {
         bool ch = false;
 #pragma unroll
-        for (int j = 0; j < TX; j++) {
+        for (int j = 0; j < NV; j++) {
             if (c[j] == 0) continue;
-            const int idx = ((j + 1) * HY + (ly + 1)) * HZ + (lz + 1);
+            const int idx = (((j >> 1) + 1) * HY + (ly + 8 * (j & 1) + 1)) * HZ + (lz + 1);
             const uint32_t cur = hw[idx];
+            if (cur >= c[j]) continue;
             uint32_t nb = max(max(hw[idx - 1], hw[idx + 1]), max(hw[idx - HZ], hw[idx + HZ]));
             nb = max(nb, max(hw[idx - HY * HZ], hw[idx + HY * HZ]));
             const uint32_t cand = min(c[j], nb);
@@ -89,13 +99,36 @@ __global__ __launch_bounds__(256) void k_relax_tiles(Cap cap, int X, int Y, int 
     if (!any_change) return;
     bool wrote = false;
 #pragma unroll
-    for (int j = 0; j < TX; j++) {
-        const int gx = x0 + j;
+    for (int j = 0; j < NV; j++) {
+        const int lx = j >> 1, lyy = ly + 8 * (j & 1);
+        const int gx = x0 + lx, gy = y0 + lyy;
         if (gx >= X || gy >= Y || gz >= Z) continue;
-        const uint32_t nv = hw[((j + 1) * HY + (ly + 1)) * HZ + (lz + 1)];
-        if (nv != orig[j]) { w[gx * yz + (int64_t)gy * Z + gz] = nv; wrote = true; }
+        const uint32_t nv = hw[((lx + 1) * HY + (lyy + 1)) * HZ + (lz + 1)];
+        if (nv != orig[j]) {
+            w[gx * yz + (int64_t)gy * Z + gz] = nv;
+            wrote = true;
+            if (lx == 0) face[0] = 1;
+            if (lx == TX - 1) face[1] = 1;
+            if (lyy == 0) face[2] = 1;
+            if (lyy == TY - 1) face[3] = 1;
+            if (lz == 0) face[4] = 1;
+            if (lz == TZ - 1) face[5] = 1;
+        }
     }
-    if (__builtin_amdgcn_readfirstlane(__syncthreads_or(wrote)) && tid == 0) atomicAdd(changed, 1u);
+    if (__builtin_amdgcn_readfirstlane(__syncthreads_or(wrote))) {
+        if (tid == 0) atomicAdd(changed, 1u);
+        if (tid < 6 && face[tid]) {
+            int nx = tx, ny = ty, nz = tz;
+            if (tid == 0) nx--;
+            if (tid == 1) nx++;
+            if (tid == 2) ny--;
+            if (tid == 3) ny++;
+            if (tid == 4) nz--;
+            if (tid == 5) nz++;
+            if (nx >= 0 && nx < ntx && ny >= 0 && ny < nty && nz >= 0 && nz < ntz)
+                act_out[((int64_t)nx * nty + ny) * ntz + nz] = 1;
+        }
+    }
 }
 
 // ---- trapping ----
@@ -146,33 +179,43 @@ inline unsigned blocks(int64_t n) { return (unsigned)((n + 255) / 256); }
 ibip_status reconstruct(ibip_ctx* ctx, const int32_t* seq, const uint32_t* cap32, ibip_dims d, uint32_t* w,
                         int* n_iter) {
     hipStream_t s = ctx->stream;
-    uint8_t* misc = (uint8_t*)ensure(ctx, B_MISC, 4096);
-    uint32_t* h = (uint32_t*)pinned(ctx, 4096);
-    if (!misc || !h) return fail(ctx, IBIP_ENOMEM, "reconstruct: allocation failed");
-    uint32_t* changed = (uint32_t*)(misc + 2048);
-    uint32_t* h_changed = h + 512;
     const int ntx = (d.X + TX - 1) / TX, nty = (d.Y + TY - 1) / TY, ntz = (d.Z + TZ - 1) / TZ;
     const int64_t ntiles = (int64_t)ntx * nty * ntz;
+    constexpr int kBatch = 8;  // sweeps per host check
+    uint8_t* misc = (uint8_t*)ensure(ctx, B_MISC, 4096);
+    uint8_t* act = (uint8_t*)ensure(ctx, B_ACT, 2 * (size_t)ntiles + 64);
+    uint32_t* cnt = (uint32_t*)ensure(ctx, B_CNT, sizeof(uint32_t) * kBatch);
+    uint32_t* h = (uint32_t*)pinned(ctx, 4096);
+    if (!misc || !act || !cnt || !h) return fail(ctx, IBIP_ENOMEM, "reconstruct: allocation failed");
+    uint8_t* a0 = act;
+    uint8_t* a1 = act + ntiles;
+    uint32_t* h_changed = h + 512;
     ibip_status rc;
+    if ((rc = hip_check(ctx, hipMemsetAsync(a0, 1, ntiles, s), "memset")) != IBIP_OK) return rc;
     int it = 0;
-    for (;; it++) {
-        if ((rc = hip_check(ctx, hipMemsetAsync(changed, 0, sizeof(uint32_t), s), "memset")) != IBIP_OK) return rc;
-        if (cap32)
-            hipLaunchKernelGGL(k_relax_tiles<CapU32>, dim3((unsigned)ntiles), dim3(256), 0, s, CapU32{cap32}, d.X,
-                               d.Y, d.Z, ntx, nty, ntz, w, changed);
-        else
-            hipLaunchKernelGGL(k_relax_tiles<CapSeq>, dim3((unsigned)ntiles), dim3(256), 0, s, CapSeq{seq}, d.X,
-                               d.Y, d.Z, ntx, nty, ntz, w, changed);
+    const int limit = 4 * (d.X + d.Y + d.Z) + 100000;
+    for (;;) {
+        if ((rc = hip_check(ctx, hipMemsetAsync(cnt, 0, sizeof(uint32_t) * kBatch, s), "memset")) != IBIP_OK) return rc;
+        for (int b = 0; b < kBatch; b++, it++) {
+            uint8_t* in = (it & 1) ? a1 : a0;
+            uint8_t* out = (it & 1) ? a0 : a1;
+            if ((rc = hip_check(ctx, hipMemsetAsync(out, 0, ntiles, s), "memset")) != IBIP_OK) return rc;
+            if (cap32)
+                hipLaunchKernelGGL(k_relax_tiles<CapU32>, dim3((unsigned)ntiles), dim3(256), 0, s, CapU32{cap32}, d.X,
+                                   d.Y, d.Z, ntx, nty, ntz, w, in, out, cnt + b);
+            else
+                hipLaunchKernelGGL(k_relax_tiles<CapSeq>, dim3((unsigned)ntiles), dim3(256), 0, s, CapSeq{seq}, d.X,
+                                   d.Y, d.Z, ntx, nty, ntz, w, in, out, cnt + b);
+        }
         if ((rc = hip_check(ctx, hipGetLastError(), "relax launch")) != IBIP_OK) return rc;
-        if ((rc = hip_check(ctx, hipMemcpyAsync(h_changed, changed, sizeof(uint32_t), hipMemcpyDeviceToHost, s),
-                            "copy")) != IBIP_OK)
+        if ((rc = hip_check(ctx, hipMemcpyAsync(h_changed, cnt + kBatch - 1, sizeof(uint32_t), hipMemcpyDeviceToHost,
+                                                s), "copy")) != IBIP_OK)
             return rc;
         if ((rc = hip_check(ctx, hipStreamSynchronize(s), "sync")) != IBIP_OK) return rc;
         if (*h_changed == 0) break;
-        if (it > 4 * (d.X + d.Y + d.Z) + 100000)
-            return fail(ctx, IBIP_EDEVICE, "reconstruct: no fixed point after the iteration limit");
+        if (it > limit) return fail(ctx, IBIP_EDEVICE, "reconstruct: no fixed point after the iteration limit");
     }
-    if (n_iter) *n_iter = it + 1;
+    if (n_iter) *n_iter = it;
     return IBIP_OK;
 }
 
