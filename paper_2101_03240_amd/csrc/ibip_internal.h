@@ -21,6 +21,23 @@ constexpr uint32_t kWideRound = 8192;
 constexpr uint32_t kSmallRound = 128;
 constexpr uint32_t kInf32 = 0xFFFFFFFFu;
 
+// Division of 32-bit values by a fixed divisor with a precomputed multiplier
+// (Granlund & Montgomery, "Division by invariant integers using
+// multiplication", 1994): q = (t + ((n - t) >> s1)) >> s2, t = mulhi(m, n).
+struct FastDiv {
+    uint32_t d, m, s1, s2;
+};
+inline FastDiv make_fastdiv(uint32_t d) {
+    uint32_t l = 0;
+    while (((uint64_t)1 << l) < d) l++;
+    const uint64_t m = (((uint64_t)1 << 32) * (((uint64_t)1 << l) - d)) / d + 1;
+    return FastDiv{d, (uint32_t)m, l < 1 ? l : 1u, l > 1 ? l - 1 : 0u};
+}
+__device__ inline uint32_t fdiv(uint32_t n, const FastDiv& f) {
+    const uint32_t t = __umulhi(f.m, n);
+    return (t + ((n - t) >> f.s1)) >> f.s2;
+}
+
 // One grow-only device allocation.
 struct Buf {
     void* p = nullptr;

@@ -192,6 +192,7 @@ struct LoopArgs {
     int X, Y, Z;
     uint32_t wide;    // steps with more centres go to the whole-GPU kernel
     uint32_t small;   // steps with at most this many centres run in wave 0 alone
+    FastDiv divZ, divY;
 };
 
 constexpr int kLoopThreads = 1024;
@@ -208,9 +209,9 @@ struct LoopShared {
     uint32_t logu[2][kLog];
     uint32_t logr[2][kLog];
     uint32_t logn[2];           // pushes counted (more than kLog = log incomplete)
-    uint32_t pushmax;
+    uint32_t cl[kSmallRound];   // centres of a small step gathered from the log
     // descriptor of a step run by all waves
-    uint32_t d_exit, d_h, d_cnt, d_k, d_r, d_fromlog, d_sel;
+    uint32_t d_exit, d_h, d_cnt, d_k, d_r, d_fromlog, d_sel, d_up;
 };
 
 __device__ inline uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
@@ -239,97 +240,108 @@ __device__ inline uint32_t lds_highest_below_uni(const LoopShared& s, uint32_t r
     }
 }
 
-// After step r: the next maximum is r itself if its slice refilled, else the
-// highest non-empty rank below it, or anything larger pushed during the step.
-__device__ inline uint32_t next_top(LoopShared& s, uint32_t r, uint32_t pushmax) {
-    uint32_t cand;
-    if (uni(s.tail[r]) > uni(s.head[r])) {
-        cand = r;
-    } else {
+// After step r: clear the occupancy bit of r if its slice stayed empty. If a
+// rank above r was pushed (`up`), the new maximum is the highest set bit,
+// since every rank above r was empty when the step began; otherwise it is r
+// itself if its slice refilled, else the highest non-empty rank below it.
+__device__ inline uint32_t next_top(LoopShared& s, uint32_t r, bool up, uint32_t R) {
+    const bool refilled = uni(s.tail[r]) > uni(s.head[r]);
+    if (!refilled) {
         const uint32_t wv = uni(s.bits[r >> 5]) & ~(1u << (r & 31));
         s.bits[r >> 5] = wv;
         if (wv == 0) s.sum[r >> 10] = uni(s.sum[r >> 10]) & ~(1u << ((r >> 5) & 31));
-        cand = lds_highest_below_uni(s, r);
     }
-    return cand > pushmax ? cand : pushmax;
-}
-
-// wave-wide maximum of a lane value (result uniform)
-__device__ inline uint32_t wave_max(uint32_t x) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        const uint32_t t = __shfl_xor(x, o, 64);
-        x = t > x ? t : x;
-    }
-    return uni(x);
+    if (up) return lds_highest_below_uni(s, R + 1);
+    return refilled ? r : lds_highest_below_uni(s, r);
 }
 
 // Make c a centre of step k and claim its unseen pore face neighbours: one
 // atomicOr per neighbour sets the claim bit and returns the rank, so a claim
 // costs one round trip; the six claims are in flight together. The claimed
-// voxels are then appended to the slices of their ranks in LDS: one
-// independent atomicAdd per push on the slice tail (no serial per-rank loop),
-// one wave-level atomicAdd reserving the push-log entries, and return-less ORs
-// into the occupancy bitmap. Returns the largest rank pushed by the wave
-// (wave-uniform, 0 if none).
-__device__ inline uint32_t expand_lds(bool have, uint32_t c, uint32_t k, const LoopArgs& a, LoopShared& s,
-                                      uint32_t sel) {
+// voxels are then appended to the slices of their ranks in LDS with one
+// independent atomicAdd per push on the slice tail (no serial per-rank loop).
+// Only the push that finds its slice empty (position == head) sets the
+// occupancy bit, so the bitmap sees no same-address atomics. Push-log entries
+// are reserved per wave: from the scalar running count `logn` when wave 0
+// runs the step alone (kSingle), else with one LDS atomic per wave. Returns
+// the largest rank this lane pushed (0 if none).
+template <bool kSingle, int NC>
+__device__ inline uint32_t expand_lds(const bool (&have)[NC], const uint32_t (&c)[NC], uint32_t k, const LoopArgs& a,
+                                      LoopShared& s, uint32_t sel, uint32_t& logn) {
+    constexpr int ND = 6 * NC;
     const int64_t yz = (int64_t)a.Y * a.Z;
-    int z = 0, y = 0, x = 0;
-    if (have) {
-        a.state[c] = (int32_t)k;
-        z = (int)(c % (uint32_t)a.Z);
-        const uint32_t t = c / (uint32_t)a.Z;
-        y = (int)(t % (uint32_t)a.Y);
-        x = (int)(t / (uint32_t)a.Y);
-    }
-    const int64_t uu[6] = {(int64_t)c - yz, (int64_t)c + yz, (int64_t)c - a.Z, (int64_t)c + a.Z,
-                           (int64_t)c - 1, (int64_t)c + 1};
-    const bool okd[6] = {have && x > 0, have && x < a.X - 1, have && y > 0, have && y < a.Y - 1,
-                         have && z > 0, have && z < a.Z - 1};
-    uint32_t old[6];
+    int64_t uu[ND];
+    bool okd[ND];
 #pragma unroll
-    for (int j = 0; j < 6; j++) old[j] = okd[j] ? atomicOr(&a.key[uu[j]], kClaim) : kClaim;
-    bool won[6];
-    uint32_t rr[6], pos[6];
+    for (int q = 0; q < NC; q++) {
+        int z = 0, y = 0, x = 0;
+        if (have[q]) {
+            a.state[c[q]] = (int32_t)k;
+            const uint32_t t = fdiv(c[q], a.divZ);
+            z = (int)(c[q] - t * (uint32_t)a.Z);
+            x = (int)fdiv(t, a.divY);
+            y = (int)(t - (uint32_t)x * (uint32_t)a.Y);
+        }
+        const int64_t cc = (int64_t)c[q];
+        uu[6 * q + 0] = cc - yz; okd[6 * q + 0] = have[q] && x > 0;
+        uu[6 * q + 1] = cc + yz; okd[6 * q + 1] = have[q] && x < a.X - 1;
+        uu[6 * q + 2] = cc - a.Z; okd[6 * q + 2] = have[q] && y > 0;
+        uu[6 * q + 3] = cc + a.Z; okd[6 * q + 3] = have[q] && y < a.Y - 1;
+        uu[6 * q + 4] = cc - 1; okd[6 * q + 4] = have[q] && z > 0;
+        uu[6 * q + 5] = cc + 1; okd[6 * q + 5] = have[q] && z < a.Z - 1;
+    }
+    uint32_t old[ND];
+#pragma unroll
+    for (int j = 0; j < ND; j++) old[j] = okd[j] ? atomicOr(&a.key[uu[j]], kClaim) : kClaim;
+    bool won[ND];
+    uint32_t rr[ND], pos[ND], hd[ND];
     uint32_t mymax = 0;
 #pragma unroll
-    for (int j = 0; j < 6; j++) {
+    for (int j = 0; j < ND; j++) {
         rr[j] = old[j] & kRankMask;
         won[j] = !(old[j] & kClaim) && rr[j] != 0;
         mymax = won[j] && rr[j] > mymax ? rr[j] : mymax;
     }
-    // slice positions: independent LDS atomics, all in flight together
+    // slice positions: independent LDS atomics, all in flight together, with
+    // the slice heads read alongside
 #pragma unroll
-    for (int j = 0; j < 6; j++) pos[j] = won[j] ? atomicAdd(&s.tail[rr[j]], 1u) : 0u;
-    // push-log entries: one reservation per wave
-    uint64_t m[6];
-    uint32_t before[6], total = 0;
+    for (int j = 0; j < ND; j++) {
+        pos[j] = won[j] ? atomicAdd(&s.tail[rr[j]], 1u) : 0u;
+        hd[j] = won[j] ? s.head[rr[j]] : 1u;
+    }
+    // push-log entries
+    uint64_t m[ND];
+    uint32_t before[ND], total = 0;
 #pragma unroll
-    for (int j = 0; j < 6; j++) {
+    for (int j = 0; j < ND; j++) {
         m[j] = __ballot(won[j]);
         before[j] = total;
         total += (uint32_t)__popcll(m[j]);
     }
     uint32_t lbase = 0;
     if (total) {
-        uint32_t b = 0;
-        if ((threadIdx.x & 63) == 0) b = atomicAdd(&s.logn[sel], total);
-        lbase = uni(__shfl(b, 0, 64));
+        if (kSingle) {
+            lbase = logn;
+            logn += total;
+        } else {
+            uint32_t b = 0;
+            if ((threadIdx.x & 63) == 0) b = atomicAdd(&s.logn[sel], total);
+            lbase = __builtin_amdgcn_readlane(b, 0);
+        }
     }
     const uint64_t lt = lanemask_lt();
 #pragma unroll
-    for (int j = 0; j < 6; j++) {
+    for (int j = 0; j < ND; j++) {
         if (!won[j]) continue;
         a.bucket[pos[j]] = (uint32_t)uu[j];
-        lds_set(s, rr[j]);
+        if (pos[j] == hd[j]) lds_set(s, rr[j]);
         const uint32_t li = lbase + before[j] + (uint32_t)__popcll(m[j] & lt);
         if (li < kLog) {
             s.logu[sel][li] = (uint32_t)uu[j];
             s.logr[sel][li] = rr[j];
         }
     }
-    return wave_max(mymax);
+    return mymax;
 }
 
 // Control flow: the step decisions run in all 64 lanes of wave 0 on values
@@ -409,7 +421,7 @@ __global__ __launch_bounds__(kLoopThreads) void k_loop(LoopArgs a) {
                 const uint32_t nsel = sel ^ 1u;
                 s.logn[nsel] = 0;
                 if (cnt > a.small) {
-                    s.pushmax = 0;
+                    s.d_up = 0;
                     s.d_exit = 0;
                     s.d_h = h;
                     s.d_cnt = cnt;
@@ -419,36 +431,48 @@ __global__ __launch_bounds__(kLoopThreads) void k_loop(LoopArgs a) {
                     s.d_sel = sel;
                     break;
                 }
-                // a small step, wave 0 alone
-                uint32_t pm = 0;
+                // a small step, wave 0 alone: each lane takes up to two centres,
+                // so the step waits for one round of claims
+                uint32_t ln = 0;  // entries in the new push log
+                bool hv[2];
+                uint32_t cv[2];
                 if (fromlog) {
+                    // compact the log entries of rank r into s.cl
                     const uint32_t n = uni(s.logn[sel]);
+                    uint32_t got = 0;
                     for (uint32_t b0 = 0; b0 < n; b0 += 64) {
                         const uint32_t i = b0 + lane;
-                        bool have = false;
-                        uint32_t c = 0;
-                        if (i < n) {
-                            have = s.logr[sel][i] == r;
-                            c = s.logu[sel][i];
-                        }
-                        const uint32_t m = expand_lds(have, c, k, a, s, nsel);
-                        pm = m > pm ? m : pm;
+                        const bool match = i < n && s.logr[sel][i] == r;
+                        const uint64_t mm = __ballot(match);
+                        const uint32_t slot = got + (uint32_t)__popcll(mm & lanemask_lt());
+                        if (match && slot < kSmallRound) s.cl[slot] = s.logu[sel][i];
+                        got += (uint32_t)__popcll(mm);
                     }
+                    hv[0] = lane < cnt;
+                    hv[1] = lane + 64 < cnt;
+                    cv[0] = hv[0] ? s.cl[lane] : 0u;
+                    cv[1] = hv[1] ? s.cl[lane + 64] : 0u;
                 } else {
-                    for (uint32_t b0 = 0; b0 < cnt; b0 += 64) {
-                        const uint32_t i = b0 + lane;
-                        const bool have = i < cnt;
-                        const uint32_t c = have ? a.bucket[h + i] : 0u;
-                        const uint32_t m = expand_lds(have, c, k, a, s, nsel);
-                        pm = m > pm ? m : pm;
-                    }
+                    hv[0] = lane < cnt;
+                    hv[1] = lane + 64 < cnt;
+                    cv[0] = hv[0] ? a.bucket[h + lane] : 0u;
+                    cv[1] = hv[1] ? a.bucket[h + 64 + lane] : 0u;
                 }
+                uint32_t lm;
+                if (cnt <= 64) {
+                    const bool h1[1] = {hv[0]};
+                    const uint32_t c1[1] = {cv[0]};
+                    lm = expand_lds<true, 1>(h1, c1, k, a, s, nsel, ln);
+                } else {
+                    lm = expand_lds<true, 2>(hv, cv, k, a, s, nsel, ln);
+                }
+                s.logn[nsel] = ln;
                 const uint32_t r_done = r;
-                r = next_top(s, r, uni(pm));
+                r = next_top(s, r, __ballot(lm > r) != 0, R);
                 prev_r = r_done;
                 k = k + 1;
                 sel = nsel;
-                log_ok = uni(s.logn[nsel]) <= kLog;
+                log_ok = ln <= kLog;
             }
         }
         __syncthreads();
@@ -457,7 +481,7 @@ __global__ __launch_bounds__(kLoopThreads) void k_loop(LoopArgs a) {
             // a step with many centres, all waves
             const uint32_t h = uni(s.d_h), cnt = uni(s.d_cnt), kk = uni(s.d_k), rr0 = uni(s.d_r);
             const uint32_t osel = uni(s.d_sel), nsel = osel ^ 1u;
-            uint32_t pm = 0;
+            uint32_t unused = 0, lm = 0;
             if (uni(s.d_fromlog)) {
                 const uint32_t n = uni(s.logn[osel]);
                 for (uint32_t b0 = 0; b0 < n; b0 += kLoopThreads) {
@@ -468,24 +492,27 @@ __global__ __launch_bounds__(kLoopThreads) void k_loop(LoopArgs a) {
                         have = s.logr[osel][i] == rr0;
                         c = s.logu[osel][i];
                     }
-                    const uint32_t m = expand_lds(have, c, kk, a, s, nsel);
-                    pm = m > pm ? m : pm;
+                    const bool hv[1] = {have};
+                    const uint32_t cv[1] = {c};
+                    const uint32_t m = expand_lds<false, 1>(hv, cv, kk, a, s, nsel, unused);
+                    lm = m > lm ? m : lm;
                 }
             } else {
                 for (uint32_t b0 = 0; b0 < cnt; b0 += kLoopThreads) {
                     const uint32_t i = b0 + tid;
                     const bool have = i < cnt;
-                    const uint32_t c = have ? a.bucket[h + i] : 0u;
-                    const uint32_t m = expand_lds(have, c, kk, a, s, nsel);
-                    pm = m > pm ? m : pm;
+                    const bool hv[1] = {have};
+                    const uint32_t cv[1] = {have ? a.bucket[h + i] : 0u};
+                    const uint32_t m = expand_lds<false, 1>(hv, cv, kk, a, s, nsel, unused);
+                    lm = m > lm ? m : lm;
                 }
             }
-            if (lane == 0 && pm) atomicMax(&s.pushmax, pm);
+            if (__ballot(lm > rr0) != 0 && lane == 0) s.d_up = 1;
         }
         __syncthreads();
         if (wave0) {
             const uint32_t r_done = r;
-            r = next_top(s, r, uni(s.pushmax));
+            r = next_top(s, r, uni(s.d_up) != 0, R);
             prev_r = r_done;
             k = k + 1;
             sel ^= 1u;
@@ -506,10 +533,10 @@ __device__ inline void expand_global(bool have, uint32_t c, uint32_t k, const Lo
     int z = 0, y = 0, x = 0;
     if (have) {
         a.state[c] = (int32_t)k;
-        z = (int)(c % (uint32_t)a.Z);
-        const uint32_t t = c / (uint32_t)a.Z;
-        y = (int)(t % (uint32_t)a.Y);
-        x = (int)(t / (uint32_t)a.Y);
+        const uint32_t t = fdiv(c, a.divZ);
+        z = (int)(c - t * (uint32_t)a.Z);
+        x = (int)fdiv(t, a.divY);
+        y = (int)(t - (uint32_t)x * (uint32_t)a.Y);
     }
     const int64_t uu[6] = {(int64_t)c - yz, (int64_t)c + yz, (int64_t)c - a.Z, (int64_t)c + a.Z,
                            (int64_t)c - 1, (int64_t)c + 1};
@@ -796,7 +823,8 @@ ibip_status run_invade(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlet
             return rc;
         if ((rc = hip_check(ctx, hipStreamSynchronize(s), "sync")) != IBIP_OK) return rc;
     }
-    LoopArgs la{st, head, tail, val, bucket, state, key, M, d.X, d.Y, d.Z, kWideRound, kSmallRound};
+    LoopArgs la{st,     head, tail, val, bucket, state, key, M, d.X, d.Y, d.Z, kWideRound, kSmallRound,
+                make_fastdiv((uint32_t)d.Z), make_fastdiv((uint32_t)d.Y)};
     int64_t segments = 0;
     bool wide_pending_timing = false;
     for (;;) {
