@@ -344,6 +344,78 @@ __device__ inline uint32_t expand_lds(const bool (&have)[NC], const uint32_t (&c
     return mymax;
 }
 
+// A step with at most kSmallRound centres, run by wave 0 alone. The centres
+// sit in s.cl; each lane takes one (centre, direction) pair per pass, so a
+// step with few centres is a single short pass, and the claims of all passes
+// are issued before the wave waits for any of them. Returns the largest rank
+// this lane pushed (0 if none); *logn receives the push-log length.
+__device__ inline uint32_t small_step(uint32_t cnt, uint32_t k, const LoopArgs& a, LoopShared& s, uint32_t sel,
+                                      uint32_t& logn) {
+    constexpr int kMaxPass = (6 * kSmallRound + 63) / 64;
+    const int lane = threadIdx.x & 63;
+    const uint32_t np = 6 * cnt;
+    const uint32_t passes = (np + 63) / 64;
+    const int64_t yz = (int64_t)a.Y * a.Z;
+    uint32_t old[kMaxPass], uv[kMaxPass];
+#pragma unroll
+    for (int p = 0; p < kMaxPass; p++) {
+        old[p] = kClaim;
+        uv[p] = 0;
+        if ((uint32_t)p < passes) {
+            const uint32_t i = (uint32_t)p * 64 + lane;
+            const bool act = i < np;
+            const uint32_t ci = i / 6u;
+            const uint32_t dir = i - ci * 6u;
+            const uint32_t c = act ? s.cl[ci < kSmallRound ? ci : kSmallRound - 1] : 0u;
+            const uint32_t t = fdiv(c, a.divZ);
+            const int z = (int)(c - t * (uint32_t)a.Z);
+            const int x = (int)fdiv(t, a.divY);
+            const int y = (int)(t - (uint32_t)x * (uint32_t)a.Y);
+            if (act && dir == 0) a.state[c] = (int32_t)k;
+            int64_t off;
+            bool ok;
+            switch (dir) {
+                case 0: off = -yz; ok = x > 0; break;
+                case 1: off = yz; ok = x < a.X - 1; break;
+                case 2: off = -(int64_t)a.Z; ok = y > 0; break;
+                case 3: off = a.Z; ok = y < a.Y - 1; break;
+                case 4: off = -1; ok = z > 0; break;
+                default: off = 1; ok = z < a.Z - 1; break;
+            }
+            ok = ok && act;
+            const uint32_t u = (uint32_t)((int64_t)c + off);
+            uv[p] = u;
+            if (ok) old[p] = atomicOr(&a.key[u], kClaim);
+        }
+    }
+    uint32_t mymax = 0;
+    const uint64_t lt = lanemask_lt();
+#pragma unroll
+    for (int p = 0; p < kMaxPass; p++) {
+        if ((uint32_t)p >= passes) break;
+        const uint32_t rr = old[p] & kRankMask;
+        const bool won = !(old[p] & kClaim) && rr != 0;
+        mymax = won && rr > mymax ? rr : mymax;
+        uint32_t pos = 0, hd = 1;
+        if (won) {
+            pos = atomicAdd(&s.tail[rr], 1u);
+            hd = s.head[rr];
+        }
+        const uint64_t m = __ballot(won);
+        const uint32_t li = logn + (uint32_t)__popcll(m & lt);
+        logn += (uint32_t)__popcll(m);
+        if (won) {
+            a.bucket[pos] = uv[p];
+            if (pos == hd) lds_set(s, rr);
+            if (li < kLog) {
+                s.logu[sel][li] = uv[p];
+                s.logr[sel][li] = rr;
+            }
+        }
+    }
+    return mymax;
+}
+
 // Control flow: the step decisions run in all 64 lanes of wave 0 on values
 // made uniform with readfirstlane (duplicate stores of one value from several
 // lanes are harmless). Wave 0 runs steps of up to `small` centres alone, with
@@ -431,13 +503,9 @@ __global__ __launch_bounds__(kLoopThreads) void k_loop(LoopArgs a) {
                     s.d_sel = sel;
                     break;
                 }
-                // a small step, wave 0 alone: each lane takes up to two centres,
-                // so the step waits for one round of claims
+                // a small step, wave 0 alone: gather its centres into s.cl
                 uint32_t ln = 0;  // entries in the new push log
-                bool hv[2];
-                uint32_t cv[2];
                 if (fromlog) {
-                    // compact the log entries of rank r into s.cl
                     const uint32_t n = uni(s.logn[sel]);
                     uint32_t got = 0;
                     for (uint32_t b0 = 0; b0 < n; b0 += 64) {
@@ -448,24 +516,13 @@ __global__ __launch_bounds__(kLoopThreads) void k_loop(LoopArgs a) {
                         if (match && slot < kSmallRound) s.cl[slot] = s.logu[sel][i];
                         got += (uint32_t)__popcll(mm);
                     }
-                    hv[0] = lane < cnt;
-                    hv[1] = lane + 64 < cnt;
-                    cv[0] = hv[0] ? s.cl[lane] : 0u;
-                    cv[1] = hv[1] ? s.cl[lane + 64] : 0u;
                 } else {
-                    hv[0] = lane < cnt;
-                    hv[1] = lane + 64 < cnt;
-                    cv[0] = hv[0] ? a.bucket[h + lane] : 0u;
-                    cv[1] = hv[1] ? a.bucket[h + 64 + lane] : 0u;
+                    const uint32_t c0 = lane < cnt ? a.bucket[h + lane] : 0u;
+                    const uint32_t c1 = lane + 64 < cnt ? a.bucket[h + 64 + lane] : 0u;
+                    if (lane < cnt) s.cl[lane] = c0;
+                    if (lane + 64 < cnt) s.cl[lane + 64] = c1;
                 }
-                uint32_t lm;
-                if (cnt <= 64) {
-                    const bool h1[1] = {hv[0]};
-                    const uint32_t c1[1] = {cv[0]};
-                    lm = expand_lds<true, 1>(h1, c1, k, a, s, nsel, ln);
-                } else {
-                    lm = expand_lds<true, 2>(hv, cv, k, a, s, nsel, ln);
-                }
+                const uint32_t lm = small_step(cnt, k, a, s, nsel, ln);
                 s.logn[nsel] = ln;
                 const uint32_t r_done = r;
                 r = next_top(s, r, __ballot(lm > r) != 0, R);
