@@ -109,7 +109,9 @@ __global__ __launch_bounds__(256) void edt_pass_z(Feat feat, int64_t rows, int Z
         }
         carryn = min(carryn, __shfl(incl, 0, 64));
     }
-    if (lane == 0 && any) atomicOr(solid_flag, 1u);
+    // the flag only needs setting once: read before writing
+    if (lane == 0 && any && __hip_atomic_load(solid_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
+        atomicOr(solid_flag, 1u);
 }
 
 // pass y: lines along y at fixed (x, z). One thread per voxel.
@@ -169,11 +171,146 @@ __global__ __launch_bounds__(256) void edt_pass_x(const uint32_t* __restrict__ h
     out[v] = best >= cap ? kInf32 : (uint32_t)best;
 }
 
+// LDS-tiled passes. A workgroup owns consecutive z columns of one plane:
+// pass y loads the whole (Y x 64) tile of g, pass x the whole (X x 32) tile of
+// h, in 128-byte row segments, and evaluates the envelope for every voxel
+// of the tile by the same bounded outward search, reading LDS instead of
+// global memory. Used when a whole line fits in LDS (L <= kMaxTileLine).
+constexpr int kW = 64;             // pass y: 64 uint16 columns = 128 B row segments
+constexpr int kWx = 32;            // pass x: 32 uint32 columns = 128 B row segments
+constexpr int kMaxTileLine = 512;  // at most 64 KB of LDS per tile
+
+__global__ __launch_bounds__(256) void edt_pass_y_tile(const uint16_t* __restrict__ g, int X, int Y, int Z,
+                                                       uint64_t cap, uint32_t* __restrict__ h) {
+    extern __shared__ uint16_t tile16[];  // [Y][kW]
+    const int nzc = (Z + kW - 1) / kW;
+    const int x = blockIdx.x / nzc;
+    const int z0 = (blockIdx.x - x * nzc) * kW;
+    const int lz = threadIdx.x & (kW - 1);
+    const int r0 = threadIdx.x / kW;          // 0..3
+    const int z = z0 + lz;
+    const bool zin = z < Z;
+    const int64_t plane = (int64_t)x * Y * Z;
+    for (int y = r0; y < Y; y += 256 / kW) tile16[y * kW + lz] = zin ? g[plane + (int64_t)y * Z + z] : kInf16;
+    __syncthreads();
+    if (!zin) return;
+    for (int y = r0; y < Y; y += 256 / kW) {
+        const uint16_t f0 = tile16[y * kW + lz];
+        uint64_t best = f0 == kInf16 ? cap : (uint64_t)f0 * f0;
+        const int far = max(y, Y - 1 - y);
+        for (int o = 1; o <= far; o++) {
+            const uint64_t oo = (uint64_t)o * o;
+            if (oo >= best) break;
+            if (y - o >= 0) {
+                const uint16_t f = tile16[(y - o) * kW + lz];
+                if (f != kInf16) { const uint64_t c = (uint64_t)f * f + oo; best = c < best ? c : best; }
+            }
+            if (y + o < Y) {
+                const uint16_t f = tile16[(y + o) * kW + lz];
+                if (f != kInf16) { const uint64_t c = (uint64_t)f * f + oo; best = c < best ? c : best; }
+            }
+        }
+        h[plane + (int64_t)y * Z + z] = best >= cap ? kInf32 : (uint32_t)best;
+    }
+}
+
+// Epilogue of pass x: write dt2, or (opening) first-write T into mio_r2 where
+// dt2 < T and count the voxels with mio_r2 >= T.
+struct OutPlain {
+    uint32_t* out;
+    __device__ void put(int64_t v, uint64_t best, uint64_t cap) const {
+        out[v] = best >= cap ? kInf32 : (uint32_t)best;
+    }
+    __device__ uint32_t hit(int64_t, uint64_t) const { return 0; }
+};
+struct OutOpening {
+    uint32_t* mio_r2;
+    uint32_t T;
+    __device__ void put(int64_t, uint64_t, uint64_t) const {}
+    __device__ uint32_t hit(int64_t v, uint64_t best) const {
+        uint32_t r = mio_r2[v];
+        if (r == 0 && best < T) {
+            r = T;
+            mio_r2[v] = T;
+        }
+        return r >= T ? 1u : 0u;
+    }
+};
+
+template <class Out>
+__global__ __launch_bounds__(256) void edt_pass_x_tile(const uint32_t* __restrict__ hin, int X, int Y, int Z,
+                                                       uint64_t cap, Out outp, uint32_t* count) {
+    extern __shared__ uint32_t tile32[];  // [X][kWx]
+    const int nzc = (Z + kWx - 1) / kWx;
+    const int y = blockIdx.x / nzc;
+    const int z0 = (blockIdx.x - y * nzc) * kWx;
+    const int lz = threadIdx.x & (kWx - 1);
+    const int r0 = threadIdx.x / kWx;
+    const int z = z0 + lz;
+    const bool zin = z < Z;
+    const int64_t yz = (int64_t)Y * Z;
+    const int64_t col = (int64_t)y * Z + z;
+    for (int x = r0; x < X; x += 256 / kWx) tile32[x * kWx + lz] = zin ? hin[x * yz + col] : kInf32;
+    __syncthreads();
+    uint32_t hits = 0;
+    if (zin) {
+        for (int x = r0; x < X; x += 256 / kWx) {
+            const uint32_t f0 = tile32[x * kWx + lz];
+            uint64_t best = f0 == kInf32 ? cap : (uint64_t)f0;
+            const int far = max(x, X - 1 - x);
+            for (int o = 1; o <= far; o++) {
+                const uint64_t oo = (uint64_t)o * o;
+                if (oo >= best) break;
+                if (x - o >= 0) {
+                    const uint32_t f = tile32[(x - o) * kWx + lz];
+                    if (f != kInf32) { const uint64_t c = (uint64_t)f + oo; best = c < best ? c : best; }
+                }
+                if (x + o < X) {
+                    const uint32_t f = tile32[(x + o) * kWx + lz];
+                    if (f != kInf32) { const uint64_t c = (uint64_t)f + oo; best = c < best ? c : best; }
+                }
+            }
+            outp.put(x * yz + col, best, cap);
+            hits += outp.hit(x * yz + col, best);
+        }
+    }
+    if (count) block_add_u32(count, hits);
+}
+
+// Non-tiled pass x with the opening epilogue (lines longer than the tile).
+__global__ __launch_bounds__(256) void edt_pass_x_opening(const uint32_t* __restrict__ h, int X, int Y, int Z,
+                                                          uint64_t cap, OutOpening outp, uint32_t* count) {
+    const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t yz = (int64_t)Y * Z;
+    const int64_t n = (int64_t)X * yz;
+    uint32_t hits = 0;
+    if (v < n) {
+        const int x = (int)(v / yz);
+        const uint32_t f0 = h[v];
+        uint64_t best = f0 == kInf32 ? cap : (uint64_t)f0;
+        const int far = max(x, X - 1 - x);
+        for (int o = 1; o <= far; o++) {
+            const uint64_t oo = (uint64_t)o * o;
+            if (oo >= best) break;
+            if (x - o >= 0) {
+                const uint32_t f = h[v - (int64_t)o * yz];
+                if (f != kInf32) { const uint64_t c = (uint64_t)f + oo; best = c < best ? c : best; }
+            }
+            if (x + o < X) {
+                const uint32_t f = h[v + (int64_t)o * yz];
+                if (f != kInf32) { const uint64_t c = (uint64_t)f + oo; best = c < best ? c : best; }
+            }
+        }
+        hits = outp.hit(v, best);
+    }
+    block_add_u32(count, hits);
+}
+
 }  // namespace
 
 hipError_t launch_edt(const uint8_t* image, const uint32_t* w, uint32_t thr, uint32_t cap, ibip_dims d,
-                      uint16_t* g16, uint32_t* tmp32, uint32_t* out, uint32_t* solid_flag,
-                      hipStream_t s) {
+                      uint16_t* g16, uint32_t* tmp32, uint32_t* out, uint32_t* solid_flag, hipStream_t s,
+                      uint32_t* mio_r2, uint32_t* mio_count) {
     // cap == 0: exact everywhere; else exact where dt2 < cap, 0xFFFFFFFF elsewhere
     const uint64_t c64 = cap ? (uint64_t)cap : 0xFFFFFFFFull;
     const int64_t n = nvox(d);
@@ -186,8 +323,29 @@ hipError_t launch_edt(const uint8_t* image, const uint32_t* w, uint32_t thr, uin
         hipLaunchKernelGGL(edt_pass_z<FeatThreshold>, dim3(gz), dim3(256), 0, s, FeatThreshold{w, thr},
                            rows, d.Z, c64, g16, solid_flag);
     const unsigned gv = (unsigned)((n + 255) / 256);
-    hipLaunchKernelGGL(edt_pass_y, dim3(gv), dim3(256), 0, s, g16, d.X, d.Y, d.Z, c64, tmp32);
-    hipLaunchKernelGGL(edt_pass_x, dim3(gv), dim3(256), 0, s, tmp32, d.X, d.Y, d.Z, c64, out);
+    const int nzc = (d.Z + kW - 1) / kW;
+    const int nzcx = (d.Z + kWx - 1) / kWx;
+    if (d.Y <= kMaxTileLine)
+        hipLaunchKernelGGL(edt_pass_y_tile, dim3((unsigned)(d.X * nzc)), dim3(256), sizeof(uint16_t) * kW * d.Y, s,
+                           g16, d.X, d.Y, d.Z, c64, tmp32);
+    else
+        hipLaunchKernelGGL(edt_pass_y, dim3(gv), dim3(256), 0, s, g16, d.X, d.Y, d.Z, c64, tmp32);
+    const bool tile_x = d.X <= kMaxTileLine;
+    if (mio_r2) {
+        OutOpening o{mio_r2, cap};
+        if (tile_x)
+            hipLaunchKernelGGL(edt_pass_x_tile<OutOpening>, dim3((unsigned)(d.Y * nzcx)), dim3(256),
+                               sizeof(uint32_t) * kWx * d.X, s, tmp32, d.X, d.Y, d.Z, c64, o, mio_count);
+        else
+            hipLaunchKernelGGL(edt_pass_x_opening, dim3(gv), dim3(256), 0, s, tmp32, d.X, d.Y, d.Z, c64, o,
+                               mio_count);
+    } else if (tile_x) {
+        hipLaunchKernelGGL(edt_pass_x_tile<OutPlain>, dim3((unsigned)(d.Y * nzcx)), dim3(256),
+                           sizeof(uint32_t) * kWx * d.X, s, tmp32, d.X, d.Y, d.Z, c64, OutPlain{out},
+                           (uint32_t*)nullptr);
+    } else {
+        hipLaunchKernelGGL(edt_pass_x, dim3(gv), dim3(256), 0, s, tmp32, d.X, d.Y, d.Z, c64, out);
+    }
     return hipGetLastError();
 }
 

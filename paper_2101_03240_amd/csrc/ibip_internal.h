@@ -38,6 +38,23 @@ __device__ inline uint32_t fdiv(uint32_t n, const FastDiv& f) {
     return (t + ((n - t) >> f.s1)) >> f.s2;
 }
 
+// Adds each thread's `v` into *dst with one global atomic per block (a
+// single counter hit by every wave serialises at L2). Every thread of the
+// block must call it; blockDim.x must be a multiple of 64 and <= 1024.
+__device__ inline void block_add_u32(uint32_t* dst, uint32_t v) {
+    __shared__ uint32_t part[16];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (lane == 0) part[wid] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); w++) t += part[w];
+        if (t) atomicAdd(dst, t);
+    }
+}
+
 // One grow-only device allocation.
 struct Buf {
     void* p = nullptr;
@@ -149,9 +166,12 @@ inline int64_t nvox(ibip_dims d) { return (int64_t)d.X * d.Y * d.Z; }
 // With cap > 0 the result is exact where it is below cap and 0xFFFFFFFF
 // elsewhere (the searches stop at cap). Sets *solid_flag (device) to 1 if any
 // feature voxel exists.
+// With mio_r2 given (opening drainage), the last pass writes no distances:
+// it sets mio_r2[v] = cap where mio_r2[v] == 0 and dt2 < cap, and adds the
+// number of voxels with mio_r2 >= cap to *mio_count.
 hipError_t launch_edt(const uint8_t* image, const uint32_t* w, uint32_t thr, uint32_t cap, ibip_dims d,
                       uint16_t* g16, uint32_t* tmp32, uint32_t* out, uint32_t* solid_flag,
-                      hipStream_t s);
+                      hipStream_t s, uint32_t* mio_r2 = nullptr, uint32_t* mio_count = nullptr);
 
 // Exclusive scan of n uint32 values in place; returns the total in *total (device).
 hipError_t launch_scan_u32(uint32_t* data, int64_t n, uint32_t* partials, uint32_t* total,

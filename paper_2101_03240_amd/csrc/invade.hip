@@ -763,8 +763,7 @@ __global__ __launch_bounds__(256) void k_finalise(int32_t* seq, int32_t* state_i
         centre = t > 0;
         if (map_state && t < 0) state_io[v] = 0;
     }
-    const uint64_t cb = __ballot(centre);
-    if ((threadIdx.x & 63) == 0 && cb) atomicAdd(popped, (uint32_t)__popcll(cb));
+    block_add_u32(popped, centre ? 1u : 0u);
     // per-step counts, one atomic per distinct step in the wave
     bool act = have && s > 0;
     uint64_t pending = __ballot(act);

@@ -39,8 +39,7 @@ __global__ __launch_bounds__(256) void k_mio_seed(const uint8_t* img, const uint
         }
         k0[v] = seed ? dt2[v] : 0u;
     }
-    const uint64_t b = __ballot(pore);
-    if ((threadIdx.x & 63) == 0 && b) atomicAdd(n_pore, (uint32_t)__popcll(b));
+    block_add_u32(n_pore, pore ? 1u : 0u);
 }
 
 // First write in decreasing T; count voxels with mio_r2 >= T.
@@ -53,8 +52,7 @@ __global__ __launch_bounds__(256) void k_mio_update(const uint32_t* d2, uint32_t
         if (r == 0 && d2[v] < T) { r = T; mio_r2[v] = T; }
         hit = r >= T;
     }
-    const uint64_t b = __ballot(hit);
-    if ((threadIdx.x & 63) == 0 && b) atomicAdd(count, (uint32_t)__popcll(b));
+    block_add_u32(count, hit ? 1u : 0u);
 }
 
 inline unsigned blocks(int64_t n) { return (unsigned)((n + 255) / 256); }
@@ -93,9 +91,11 @@ ibip_status run_mio(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlets, 
     int iters = 0;
     if ((rc = reconstruct(ctx, nullptr, dt2, d, kmap, &iters)) != IBIP_OK) return rc;
     for (int32_t i = 0; i < nT; i++) {
-        if ((rc = hip_check(ctx, launch_edt(nullptr, kmap, T[i], T[i], d, g16, tmp32, d2, &flags[2], s), "edt")) != IBIP_OK)
+        // distance to the kept centres, capped at T; the last pass writes T
+        // into mio_r2 where it is still 0 and the distance is below T
+        if ((rc = hip_check(ctx, launch_edt(nullptr, kmap, T[i], T[i], d, g16, tmp32, nullptr, &flags[2], s, mio_r2,
+                                            &counts[i]), "edt")) != IBIP_OK)
             return rc;
-        hipLaunchKernelGGL(k_mio_update, dim3(blocks(n)), dim3(256), 0, s, d2, T[i], n, mio_r2, &counts[i]);
     }
     if ((rc = hip_check(ctx, hipGetLastError(), "mio launch")) != IBIP_OK) return rc;
     uint32_t* hc = h + 1024;

@@ -71,6 +71,27 @@ def test_edt_random_shapes(dev, seed):
     np.testing.assert_array_equal(_u32(ibip.edt(_d(img, dev))), oracle.edt(img))
 
 
+@pytest.mark.parametrize("shape", [(600, 3, 5), (2, 700, 9), (1, 900, 40), (520, 1, 70)])
+def test_edt_long_lines(dev, shape):
+    """Lines longer than an LDS tile take the untiled passes."""
+    rng = np.random.default_rng(sum(shape))
+    img = (rng.random(shape) < 0.97).astype(np.uint8)
+    img.flat[int(rng.integers(img.size))] = 0
+    np.testing.assert_array_equal(_u32(ibip.edt(_d(img, dev))), oracle.edt(img))
+
+
+def test_mio_long_lines(dev):
+    rng = np.random.default_rng(5)
+    img = (rng.random((530, 6, 7)) < 0.85).astype(np.uint8)
+    img[0, 0, 0] = 0
+    inl = synth.face_mask(img.shape, 0, 0)
+    T = [4, 2, 1]
+    m = ibip.opening_drainage(_d(img, dev), _d(inl, dev), T)
+    r = oracle.mio(img, inl, np.array(T, np.uint32))
+    np.testing.assert_array_equal(_u32(m["mio_r2"]), r["mio_r2"])
+    np.testing.assert_array_equal(np.array(m["mio_sat"]), r["mio_sat"])
+
+
 def test_edt_no_solid_is_an_error(dev):
     img = np.ones((5, 6, 7), np.uint8)
     with pytest.raises(ibip.IbipError) as e:
