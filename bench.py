@@ -77,6 +77,24 @@ def cpu_baseline(img, seconds_hint: float = 20.0) -> dict:
                       f"outlets x={L - 1}: invade + trap + MIO at {len(T)} radii in {dt:.1f} s"}
 
 
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None when there is none for this workload or the kernel's
+    source changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("kernel") != kernel:
+        return None
+    with open(os.path.join(ROOT, t["source"]), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != t["source_sha256"]:
+            return None
+    return float(t["traffic_bytes_per_launch"])
+
+
 def make_image(name: str):
     from paper_2101_03240_amd import synth
     return synth.config_image(name, seed=0)
@@ -89,6 +107,9 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="packing200", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="run one device-to-device copy of this many MiB before the workload, as a reference "
+                         "for hardware traffic counters")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -106,6 +127,12 @@ def main() -> int:
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
     dev = torch.device("cuda:0")
+    if args.copy_probe_mb > 0:
+        src = torch.ones(args.copy_probe_mb << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     img = make_image(args.workload)
     inl = synth.face_mask(img.shape, 0, 0)
     out = synth.face_mask(img.shape, 0, img.shape[0] - 1)
@@ -176,7 +203,8 @@ def main() -> int:
                    "shape": list(img.shape), "pore_voxels": n_pore, "invaded_voxels": invaded,
                    "invasion_steps": K, "mio_radii": len(T), "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBPS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
+                     "traffic": measured_traffic(dom, args.workload),
                      "avg_launch_ms": d_ms, "launches": int(d_launches)},
         "edt_gbps_algorithmic": edt_gbps,
         "phases_ms_per_step": {
