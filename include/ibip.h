@@ -126,6 +126,35 @@ ibip_status ibip_invade(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inle
                         int32_t* centre_step, int64_t* n_steps);
 
 /*
+ * ibip_invade_batch -- ibip_invade (Section 2.1) over many images of uneven
+ * size in one call, with the same results as one ibip_invade per image.
+ * Each job names its own device buffers, dims and step limit; per-job setup
+ * runs concurrently, the step loops of all jobs run in ONE launch (one
+ * workgroup per job, largest first) and the call synchronises once between
+ * the loops and the post-processing.
+ * Per job: status receives the job's ibip_status (OK, ENOSOLID, ECAPACITY,
+ * EDEVICE) and n_steps its K. M (uint32) and sat (double) are optional DEVICE
+ * outputs of the per-step squared radius and saturation, each with capacity
+ * for at least as many entries as the image has pore voxels.
+ * Returns IBIP_OK when every job succeeded, else the first failing job's code.
+ */
+typedef struct {
+    const uint8_t* image;   /* device, image mask as in ibip_invade */
+    const uint8_t* inlets;  /* device */
+    ibip_dims dims;
+    int64_t max_steps;      /* 0 = run until no candidate is left */
+    int32_t* seq;           /* device out */
+    uint32_t* rad2;         /* device out or NULL */
+    int32_t* centre_step;   /* device out or NULL */
+    uint32_t* M;            /* device out or NULL */
+    double* sat;            /* device out or NULL */
+    int64_t n_steps;        /* out */
+    int32_t status;         /* out */
+} ibip_job;
+
+ibip_status ibip_invade_batch(ibip_ctx* ctx, ibip_job* jobs, int32_t n);
+
+/*
  * ibip_get_steps -- per-step arrays of the last ibip_invade (Sections 2.2.1,
  * 2.2.2). For k = 1..K, entry k-1 holds:
  *   M      uint32  squared radius inserted at step k

@@ -22,7 +22,7 @@ import ctypes
 import os
 import threading
 
-__all__ = ["edt", "invade", "trap", "opening_drainage", "IbipError", "library_path", "load_library",
+__all__ = ["edt", "invade", "invade_batch", "trap", "opening_drainage", "IbipError", "library_path", "load_library",
            "enable_timing", "get_timing", "reset_timing"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -49,6 +49,13 @@ class _Timing(ctypes.Structure):
     _fields_ = [(n, ctypes.c_double) for n in ("edt_ms", "setup_ms", "loop_ms", "loop_kernel_ms", "wide_kernel_ms",
                                                 "paint_ms", "steps_ms", "trap_ms", "mio_ms")] + \
                [(n, ctypes.c_int64) for n in ("loop_launches", "wide_launches", "steps", "popped", "relax_sweeps")]
+
+
+class _Job(ctypes.Structure):
+    _fields_ = [("image", ctypes.c_void_p), ("inlets", ctypes.c_void_p), ("dims", _Dims),
+                ("max_steps", ctypes.c_int64), ("seq", ctypes.c_void_p), ("rad2", ctypes.c_void_p),
+                ("centre_step", ctypes.c_void_p), ("M", ctypes.c_void_p), ("sat", ctypes.c_void_p),
+                ("n_steps", ctypes.c_int64), ("status", ctypes.c_int32)]
 
 
 class _InvadeOpts(ctypes.Structure):
@@ -84,6 +91,8 @@ def load_library():
         lib.ibip_get_steps.argtypes = [P, P, P, P, P, i64]
         lib.ibip_trap.argtypes = [P, P, P, _Dims, P, P, ctypes.POINTER(i64)]
         lib.ibip_opening_drainage.argtypes = [P, P, P, _Dims, P, i32, P, P]
+        lib.ibip_invade_batch.argtypes = [P, ctypes.POINTER(_Job), i32]
+        lib.ibip_invade_batch.restype = i32
         lib.ibip_ctx_enable_timing.argtypes = [P, i32]
         lib.ibip_ctx_get_timing.argtypes = [P, ctypes.POINTER(_Timing)]
         lib.ibip_ctx_reset_timing.argtypes = [P]
@@ -192,6 +201,56 @@ def invade(image, inlets, max_steps: int = 0, sigma: float = 1.0, theta_rad: flo
         kk = int(K.value)
         out.update(M=M[:kk], n_new=n_new[:kk], sat=sat[:kk], pc=pc[:kk])
     return out
+
+
+def invade_batch(images, inlets, max_steps=0, rad2: bool = True, centre_step: bool = True, M: bool = True,
+                 sat: bool = False, raise_on_error: bool = True):
+    """ibip_invade over a list of images of uneven size in one call (the step
+    loops of all jobs run in one launch). ``inlets`` is a list of masks of
+    matching shapes; ``max_steps`` an int or a list. Returns a list of dicts
+    like ``invade`` (``seq``, ``rad2``, ``centre_step``, ``K``, ``M``, ``sat``)
+    plus each job's ``status``."""
+    torch = _torch()
+    n = len(images)
+    if len(inlets) != n:
+        raise ValueError("one inlets mask per image")
+    ms = list(max_steps) if isinstance(max_steps, (list, tuple)) else [int(max_steps)] * n
+    imgs = [_dev_u8(t, "image") for t in images]
+    inls = [_dev_u8(t, "inlets") for t in inlets]
+    if n == 0:
+        return []
+    dev = imgs[0].device
+    ctx = _context(dev)
+    jobs = (_Job * n)()
+    outs = []
+    for i, (im, il) in enumerate(zip(imgs, inls)):
+        if il.shape != im.shape:
+            raise ValueError("inlets must have the image's shape")
+        dims, _ = _dims_of(im)
+        o = {"seq": torch.empty(im.shape, dtype=torch.int32, device=dev),
+             "rad2": torch.empty(im.shape, dtype=torch.int32, device=dev) if rad2 else None,
+             "centre_step": torch.empty(im.shape, dtype=torch.int32, device=dev) if centre_step else None,
+             "M": torch.empty(max(im.numel(), 1), dtype=torch.int32, device=dev) if M else None,
+             "sat": torch.empty(max(im.numel(), 1), dtype=torch.float64, device=dev) if sat else None}
+        outs.append(o)
+        jobs[i].image = im.data_ptr()
+        jobs[i].inlets = il.data_ptr()
+        jobs[i].dims = dims
+        jobs[i].max_steps = int(ms[i])
+        for f in ("seq", "rad2", "centre_step", "M", "sat"):
+            setattr(jobs[i], f, o[f].data_ptr() if o[f] is not None else None)
+    st = load_library().ibip_invade_batch(ctx, jobs, n)
+    if st != 0 and raise_on_error:
+        _check(st, ctx)
+    for i, o in enumerate(outs):
+        k = int(jobs[i].n_steps)
+        o["K"] = k
+        o["status"] = int(jobs[i].status)
+        if o["M"] is not None:
+            o["M"] = o["M"][:k]
+        if o["sat"] is not None:
+            o["sat"] = o["sat"][:k]
+    return outs
 
 
 def trap(seq, outlets, seq_trapped: bool = True):

@@ -60,6 +60,18 @@ void* pinned(ibip_ctx* ctx, size_t bytes) {
     return p;
 }
 
+ibip_status batch_streams(ibip_ctx* ctx) {
+    if (ctx->have_bstreams) return IBIP_OK;
+    for (auto& st : ctx->bstream)
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess)
+            return fail(ctx, IBIP_EDEVICE, "cannot create batch streams");
+    for (auto& e : ctx->bev)
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+            return fail(ctx, IBIP_EDEVICE, "cannot create batch events");
+    ctx->have_bstreams = true;
+    return IBIP_OK;
+}
+
 bool dims_ok(ibip_dims d) {
     if (d.X <= 0 || d.Y <= 0 || d.Z <= 0) return false;
     if (d.X > 65535 || d.Y > 65535 || d.Z > 65535) return false;
@@ -123,6 +135,10 @@ ibip_status ibip_ctx_destroy(ibip_ctx* ctx) {
     if (!ctx) return IBIP_EINVAL;
     DeviceGuard g(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->have_bstreams) {
+        for (auto& st : ctx->bstream) (void)hipStreamDestroy(st);
+        for (auto& e : ctx->bev) (void)hipEventDestroy(e);
+    }
     if (ctx->timer.made)
         for (auto& e : ctx->timer.ev) (void)hipEventDestroy(e);
     for (auto& b : ctx->buf)
@@ -183,6 +199,21 @@ ibip_status ibip_invade(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inle
     DeviceGuard g(ctx->device);
     if (!g.ok) return fail(ctx, IBIP_EDEVICE, "invade: cannot select device");
     return run_invade(ctx, image, inlets, dims, opts, seq, rad2, centre_step, n_steps);
+}
+
+ibip_status ibip_invade_batch(ibip_ctx* ctx, ibip_job* jobs, int32_t n) {
+    if (!ctx) return IBIP_EINVAL;
+    if (n < 0 || (n > 0 && !jobs)) return fail(ctx, IBIP_EINVAL, "invade_batch: bad job list");
+    for (int32_t i = 0; i < n; i++) {
+        const ibip_job& j = jobs[i];
+        if (!j.image || !j.inlets || !j.seq) return fail(ctx, IBIP_EINVAL, "invade_batch: null pointer in a job");
+        if (!dims_ok(j.dims)) return fail(ctx, IBIP_EINVAL, "invade_batch: bad dims in a job");
+        if (j.max_steps < 0) return fail(ctx, IBIP_EINVAL, "invade_batch: max_steps < 0");
+    }
+    if (n == 0) return IBIP_OK;
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(ctx, IBIP_EDEVICE, "invade_batch: cannot select device");
+    return run_invade_batch(ctx, jobs, n);
 }
 
 ibip_status ibip_get_steps(ibip_ctx* ctx, uint32_t* M, int64_t* n_new, double* sat, double* pc, int64_t capacity) {

@@ -20,6 +20,8 @@ constexpr uint32_t kWideRound = 8192;
 // A step with at most this many centres runs in one wave, without barriers.
 constexpr uint32_t kSmallRound = 128;
 constexpr uint32_t kInf32 = 0xFFFFFFFFu;
+// Streams a batch spreads its per-job setup and post-processing over.
+constexpr int kBatchStreams = 8;
 
 // Division of 32-bit values by a fixed divisor with a precomputed multiplier
 // (Granlund & Montgomery, "Division by invariant integers using
@@ -82,6 +84,7 @@ enum BufId {
     B_SCAN,        // scan partials
     B_ACT,         // uint8[2 * tiles] active-tile flags of the reconstruction
     B_CNT,         // uint32 per-sweep change counters
+    B_BATCH,       // arena of a batch of jobs
     B_NUM
 };
 
@@ -135,6 +138,9 @@ struct Timer {
 
 struct ibip_ctx {
     ibip::Timer timer;
+    hipStream_t bstream[ibip::kBatchStreams] = {};
+    hipEvent_t bev[ibip::kBatchStreams + 1] = {};
+    bool have_bstreams = false;
     ibip_timing timing = {};
     int device = 0;
     hipStream_t stream = nullptr;
@@ -189,6 +195,9 @@ ibip_status reconstruct(ibip_ctx* ctx, const int32_t* seq, const uint32_t* cap32
 ibip_status run_invade(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlets, ibip_dims d,
                        const ibip_invade_opts* opts, int32_t* seq, uint32_t* rad2, int32_t* centre_step,
                        int64_t* n_steps);
+ibip_status run_invade_batch(ibip_ctx* ctx, ibip_job* jobs, int32_t n);
+// create the batch streams and events once per context
+ibip_status batch_streams(ibip_ctx* ctx);
 ibip_status run_trap(ibip_ctx* ctx, const int32_t* seq, const uint8_t* outlets, ibip_dims d,
                      uint8_t* trapped, int32_t* seq_trapped, int64_t* n_steps_after);
 ibip_status run_mio(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlets, ibip_dims d,

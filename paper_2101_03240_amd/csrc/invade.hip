@@ -34,6 +34,7 @@
 // neighbour. This is exact: the smallest step covering a voxel always stamps
 // it, since a ball it skipped is covered by an earlier ball.
 #include <climits>
+#include <vector>
 
 #include "ibip_internal.h"
 
@@ -108,6 +109,7 @@ __global__ void k_rank_tables(const uint32_t* cnt_scanned, const uint32_t* prese
     int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (v >= V || v == 0 || !hist_raw_flag[v]) return;
     uint32_t r = present_scanned[v] + 1;
+    if (r > (uint32_t)kMaxRanks + 1) return;  // too many ranks: the loop rejects the image
     val[r] = (uint32_t)v;
     off[r] = cnt_scanned[v];
     head[r] = cnt_scanned[v];
@@ -117,12 +119,15 @@ __global__ void k_rank_tables(const uint32_t* cnt_scanned, const uint32_t* prese
 // key = rank (0 on solid); state = 0; seq = INT_MAX on pore, -1 on solid.
 __global__ __launch_bounds__(256) void k_convert(const uint8_t* __restrict__ img, uint32_t* key,
                                                  const uint32_t* __restrict__ present_scanned, int64_t n,
-                                                 int32_t* state, int32_t* seq) {
+                                                 uint32_t vlimit, int32_t* state, int32_t* seq) {
     int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (v >= n) return;
     state[v] = 0;
     if (img[v]) {
-        key[v] = present_scanned[key[v]] + 1;
+        const uint32_t d = key[v];
+        // d >= vlimit only without any solid voxel; such images are rejected
+        const uint32_t rk = d < vlimit ? present_scanned[d] + 1 : 0u;
+        key[v] = rk > (uint32_t)kMaxRanks ? 0u : rk;
         seq[v] = INT_MAX;
     } else {
         key[v] = 0;
@@ -171,7 +176,7 @@ __global__ __launch_bounds__(256) void k_seed(const uint8_t* __restrict__ inlets
         if (ok && key[u] < kClaim) {
             const uint32_t old = atomicOr(&key[u], kClaim);
             rr = old & kRankMask;
-            won = !(old & kClaim) && rr != 0;
+            won = !(old & kClaim) && rr != 0 && rr <= (uint32_t)kMaxRanks;
         }
         push_global(won, (uint32_t)u, rr, tail, bucket);
     }
@@ -428,12 +433,21 @@ __device__ inline uint32_t small_step(uint32_t cnt, uint32_t k, const LoopArgs& 
 // are exactly the previous step's pushes of that rank (the slice was either
 // popped empty by that step or empty before it), so they are read from the
 // LDS push log instead of global memory, if the log did not overflow.
-__global__ __launch_bounds__(kLoopThreads) void k_loop(LoopArgs a) {
-    __shared__ LoopShared s;
+__device__ inline void loop_body(const LoopArgs& a, LoopShared& s) {
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const bool wave0 = uni((uint32_t)tid >> 6) == 0;
     const uint32_t R = a.st->R;
+    // an image without solid, or with more distinct distances than the LDS
+    // tables hold, is rejected before anything is read (its setup kernels
+    // skipped the offending values)
+    if (!a.st->solid_seen || R > (uint32_t)kMaxRanks) {
+        if (tid == 0) {
+            a.st->err = !a.st->solid_seen ? 2u : 3u;
+            a.st->status = LS_DONE;
+        }
+        return;
+    }
     for (uint32_t q = tid; q <= R; q += kLoopThreads) {
         s.head[q] = a.head[q];
         s.tail[q] = a.tail[q];
@@ -581,6 +595,19 @@ __global__ __launch_bounds__(kLoopThreads) void k_loop(LoopArgs a) {
         a.head[q] = s.head[q];
         a.tail[q] = s.tail[q];
     }
+}
+
+__global__ __launch_bounds__(kLoopThreads) void k_loop(LoopArgs a) {
+    __shared__ LoopShared s;
+    loop_body(a, s);
+}
+
+// Many images in one launch: workgroup j runs the whole step loop of job j
+// (jobs are ordered largest first, so the longest loops start first).
+__global__ __launch_bounds__(kLoopThreads) void k_loop_batch(const LoopArgs* __restrict__ all) {
+    __shared__ LoopShared s;
+    const LoopArgs a = all[blockIdx.x];
+    loop_body(a, s);
 }
 
 // expand() for the whole-GPU kernel: the same claims, pushed to the global
@@ -764,8 +791,8 @@ __global__ __launch_bounds__(256) void k_finalise(int32_t* seq, int32_t* state_i
         if (map_state && t < 0) state_io[v] = 0;
     }
     block_add_u32(popped, centre ? 1u : 0u);
-    // per-step counts, one atomic per distinct step in the wave
-    bool act = have && s > 0;
+    // per-step counts (when requested), one atomic per distinct step in the wave
+    bool act = count != nullptr && have && s > 0;
     uint64_t pending = __ballot(act);
     while (pending) {
         const int leader = __ffsll((unsigned long long)pending) - 1;
@@ -861,7 +888,8 @@ ibip_status run_invade(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlet
     if ((rc = hip_check(ctx, hipMemsetAsync(head, 0, sizeof(uint32_t) * (R + 2), s), "memset")) != IBIP_OK) return rc;
     if ((rc = hip_check(ctx, hipMemsetAsync(tail, 0, sizeof(uint32_t) * (R + 2), s), "memset")) != IBIP_OK) return rc;
     hipLaunchKernelGGL(k_rank_tables, dim3(blocks(V)), dim3(256), 0, s, hist, present, flags, V, val, off, head, tail);
-    hipLaunchKernelGGL(k_convert, dim3(blocks(n)), dim3(256), 0, s, image, key, present, n, state, seq);
+    hipLaunchKernelGGL(k_convert, dim3(blocks(n)), dim3(256), 0, s, image, key, present, n, (uint32_t)(V - 1), state,
+                       seq);
     hipLaunchKernelGGL(k_seed, dim3(blocks(n)), dim3(256), 0, s, inlets, key, d.X, d.Y, d.Z, tail, bucket);
     tm.mark(2, s);
     // loop control
@@ -962,6 +990,244 @@ ibip_status run_invade(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlet
     ctx->last_n_pore = n_pore;
     ctx->have_steps = true;
     if (n_steps) *n_steps = K;
+    return IBIP_OK;
+}
+
+
+// ---------------------------------------------------------------------------
+// Batches: many images of uneven size in one call.
+// ---------------------------------------------------------------------------
+namespace {
+
+// Per-job scratch carved from one arena. Everything a job needs lives here,
+// so jobs run their setup concurrently on different streams.
+struct JobBufs {
+    uint32_t* key;
+    int32_t* state;
+    uint32_t* bucket;
+    uint32_t* hist;
+    uint16_t* g16;
+    uint32_t* tmp32;
+    uint32_t* partials;
+    uint32_t* val;
+    uint32_t* off;
+    uint32_t* head;
+    uint32_t* tail;
+    uint32_t* M;
+    uint32_t* full;
+    uint32_t* counts;  // 2 (N + 1) entries, only when saturation is requested
+    uint32_t* scan_total;
+};
+
+inline int64_t value_range(ibip_dims d) {
+    return (int64_t)(d.X - 1) * (d.X - 1) + (int64_t)(d.Y - 1) * (d.Y - 1) + (int64_t)(d.Z - 1) * (d.Z - 1) + 2;
+}
+
+inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// bytes of one job's scratch; carve() lays the same regions out in order
+size_t job_bytes(ibip_dims d, bool own_state, bool want_sat) {
+    const size_t n = (size_t)nvox(d), V = (size_t)value_range(d);
+    size_t b = 0;
+    b += align256(4 * n);                                 // key
+    if (own_state) b += align256(4 * n);                  // state
+    b += align256(4 * n);                                 // bucket
+    b += align256(4 * 3 * V);                             // hist
+    b += align256(2 * n);                                 // g16
+    b += align256(4 * n);                                 // tmp32
+    b += align256(4 * (V / 1000 + n / 1000 + 64));        // partials
+    b += 4 * align256(4 * ((size_t)kMaxRanks + 2));       // val, off, head, tail
+    b += align256(4 * (n + 1));                           // M
+    b += align256(4 * (n + 1));                           // full
+    if (want_sat) b += align256(4 * 2 * (n + 1));         // counts
+    b += 256;                                             // scan total
+    return b;
+}
+
+JobBufs carve(uint8_t* base, ibip_dims d, int32_t* caller_state, bool want_sat) {
+    const size_t n = (size_t)nvox(d), V = (size_t)value_range(d);
+    JobBufs j{};
+    auto take = [&](size_t bytes) {
+        uint8_t* p = base;
+        base += align256(bytes);
+        return p;
+    };
+    j.key = (uint32_t*)take(4 * n);
+    j.state = caller_state ? caller_state : (int32_t*)take(4 * n);
+    j.bucket = (uint32_t*)take(4 * n);
+    j.hist = (uint32_t*)take(4 * 3 * V);
+    j.g16 = (uint16_t*)take(2 * n);
+    j.tmp32 = (uint32_t*)take(4 * n);
+    j.partials = (uint32_t*)take(4 * (V / 1000 + n / 1000 + 64));
+    j.val = (uint32_t*)take(4 * ((size_t)kMaxRanks + 2));
+    j.off = (uint32_t*)take(4 * ((size_t)kMaxRanks + 2));
+    j.head = (uint32_t*)take(4 * ((size_t)kMaxRanks + 2));
+    j.tail = (uint32_t*)take(4 * ((size_t)kMaxRanks + 2));
+    j.M = (uint32_t*)take(4 * (n + 1));
+    j.full = (uint32_t*)take(4 * (n + 1));
+    j.counts = want_sat ? (uint32_t*)take(4 * 2 * (n + 1)) : nullptr;
+    j.scan_total = (uint32_t*)take(256);
+    return j;
+}
+
+__global__ void k_loopstate_init(LoopState* st, int64_t max_steps) {
+    st->k = 1;
+    st->status = LS_RUN;
+    st->max_steps = max_steps;
+}
+
+// saturation after each step: (counts up to k) / n_pore
+__global__ void k_sat(const uint32_t* counts, const uint32_t* count_excl, int64_t K, const LoopState* st,
+                      double* sat) {
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k < K) sat[k] = (double)(count_excl[k] + counts[k]) / (double)st->n_pore;
+}
+
+hipError_t job_setup(const JobBufs& j, LoopState* st, const uint8_t* image, const uint8_t* inlets, ibip_dims d,
+                     int64_t max_steps, int32_t* seq, hipStream_t s) {
+    const int64_t n = nvox(d), V = value_range(d);
+    hipError_t e;
+    if ((e = hipMemsetAsync(st, 0, sizeof(LoopState), s)) != hipSuccess) return e;
+    if ((e = hipMemsetAsync(j.hist, 0, sizeof(uint32_t) * V, s)) != hipSuccess) return e;
+    if ((e = hipMemsetAsync(j.head, 0, sizeof(uint32_t) * (kMaxRanks + 2), s)) != hipSuccess) return e;
+    if ((e = hipMemsetAsync(j.tail, 0, sizeof(uint32_t) * (kMaxRanks + 2), s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_loopstate_init, dim3(1), dim3(1), 0, s, st, max_steps);
+    if ((e = launch_edt(image, nullptr, 0, 0, d, j.g16, j.tmp32, j.key, &st->solid_seen, s)) != hipSuccess) return e;
+    uint32_t* present = j.hist + V;
+    uint32_t* flags = j.hist + 2 * V;
+    hipLaunchKernelGGL(k_hist, dim3(std::min<int64_t>(blocks(n), 4096)), dim3(256), 0, s, image, j.key, n,
+                       (uint32_t)(V - 1), j.hist, st);
+    hipLaunchKernelGGL(k_present, dim3(blocks(V)), dim3(256), 0, s, j.hist, present, V);
+    hipLaunchKernelGGL(k_copy_u32, dim3(blocks(V)), dim3(256), 0, s, present, flags, V);
+    if ((e = launch_scan_u32(j.hist, V, j.partials, j.scan_total, s)) != hipSuccess) return e;
+    if ((e = launch_scan_u32(present, V, j.partials, &st->R, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_rank_tables, dim3(blocks(V)), dim3(256), 0, s, j.hist, present, flags, V, j.val, j.off,
+                       j.head, j.tail);
+    hipLaunchKernelGGL(k_convert, dim3(blocks(n)), dim3(256), 0, s, image, j.key, present, n, (uint32_t)(V - 1),
+                       j.state, seq);
+    hipLaunchKernelGGL(k_seed, dim3(blocks(n)), dim3(256), 0, s, inlets, j.key, d.X, d.Y, d.Z, j.tail, j.bucket);
+    return hipGetLastError();
+}
+
+hipError_t job_post(const JobBufs& j, LoopState* st, ibip_dims d, int64_t K, int32_t* seq, uint32_t* rad2,
+                    uint32_t* M_out, double* sat_out, hipStream_t s) {
+    const int64_t n = nvox(d);
+    hipError_t e;
+    if (K > 0) hipLaunchKernelGGL(k_rank_to_value, dim3(blocks(K)), dim3(256), 0, s, j.M, K, j.val);
+    PaintArgs pa{j.state, j.key, j.val, seq, j.full, &st->n_full, d.X, d.Y, d.Z};
+    hipLaunchKernelGGL(k_paint_shell, dim3(blocks(n)), dim3(256), 0, s, pa);
+    hipLaunchKernelGGL(k_paint_full, dim3(std::min<int64_t>(blocks(n), 2048)), dim3(256), 0, s, pa);
+    uint32_t* counts = j.counts;
+    if (counts && (e = hipMemsetAsync(counts, 0, sizeof(uint32_t) * (K + 1), s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_finalise, dim3(blocks(n)), dim3(256), 0, s, seq, j.state, true, n, j.M, rad2, counts,
+                       &st->popped);
+    if (K > 0 && M_out)
+        if ((e = hipMemcpyAsync(M_out, j.M, sizeof(uint32_t) * K, hipMemcpyDeviceToDevice, s)) != hipSuccess) return e;
+    if (K > 0 && sat_out && counts) {
+        uint32_t* excl = counts + (K + 1);
+        hipLaunchKernelGGL(k_copy_u32, dim3(blocks(K)), dim3(256), 0, s, counts, excl, K);
+        if ((e = launch_scan_u32(excl, K, j.partials, j.scan_total, s)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_sat, dim3(blocks(K)), dim3(256), 0, s, counts, excl, K, st, sat_out);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+ibip_status run_invade_batch(ibip_ctx* ctx, ibip_job* jobs, int32_t nj) {
+    hipStream_t s0 = ctx->stream;
+    // largest jobs first: their loops are the longest
+    std::vector<int32_t> order(nj);
+    for (int32_t i = 0; i < nj; i++) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t a, int32_t b) { return nvox(jobs[a].dims) > nvox(jobs[b].dims); });
+    std::vector<size_t> offs(nj);
+    size_t total = 0;
+    for (int32_t q = 0; q < nj; q++) {
+        const ibip_job& jb = jobs[order[q]];
+        offs[q] = total;
+        total += job_bytes(jb.dims, jb.centre_step == nullptr, jb.sat != nullptr);
+    }
+    const size_t st_off = total;
+    total += align256(sizeof(LoopState) * (size_t)nj);
+    const size_t la_off = total;
+    total += align256(sizeof(LoopArgs) * (size_t)nj);
+    uint8_t* arena = (uint8_t*)ensure(ctx, B_BATCH, total);
+    LoopState* h_st = (LoopState*)pinned(ctx, std::max<size_t>(4096, sizeof(LoopState) * nj + sizeof(LoopArgs) * nj));
+    if (!arena || !h_st) return fail(ctx, IBIP_ENOMEM, "invade_batch: scratch allocation failed");
+    LoopState* states = (LoopState*)(arena + st_off);
+    LoopArgs* d_args = (LoopArgs*)(arena + la_off);
+    LoopArgs* h_args = (LoopArgs*)(h_st + nj);
+    ibip_status rc;
+    if ((rc = batch_streams(ctx)) != IBIP_OK) return rc;
+    const int S = kBatchStreams;
+    std::vector<JobBufs> bufs(nj);
+    // fork: every stream waits for the caller's stream (inputs ready)
+    if ((rc = hip_check(ctx, hipEventRecord(ctx->bev[S], s0), "event")) != IBIP_OK) return rc;
+    for (int i = 0; i < S; i++)
+        if ((rc = hip_check(ctx, hipStreamWaitEvent(ctx->bstream[i], ctx->bev[S], 0), "wait")) != IBIP_OK) return rc;
+    for (int32_t q = 0; q < nj; q++) {
+        ibip_job& jb = jobs[order[q]];
+        bufs[q] = carve(arena + offs[q], jb.dims, jb.centre_step, jb.sat != nullptr);
+        hipStream_t s = ctx->bstream[q % S];
+        if ((rc = hip_check(ctx, job_setup(bufs[q], states + q, jb.image, jb.inlets, jb.dims, jb.max_steps, jb.seq, s),
+                            "setup")) != IBIP_OK)
+            return rc;
+        const JobBufs& j = bufs[q];
+        h_args[q] = LoopArgs{states + q, j.head, j.tail, j.val, j.bucket, j.state, j.key, j.M,
+                             jb.dims.X, jb.dims.Y, jb.dims.Z, 0xFFFFFFFFu, kSmallRound,
+                             make_fastdiv((uint32_t)jb.dims.Z), make_fastdiv((uint32_t)jb.dims.Y)};
+    }
+    // join, then one launch runs every job's step loop
+    for (int i = 0; i < S; i++) {
+        if ((rc = hip_check(ctx, hipEventRecord(ctx->bev[i], ctx->bstream[i]), "event")) != IBIP_OK) return rc;
+        if ((rc = hip_check(ctx, hipStreamWaitEvent(s0, ctx->bev[i], 0), "wait")) != IBIP_OK) return rc;
+    }
+    Timer& tm = ctx->timer;
+    if ((rc = hip_check(ctx, hipMemcpyAsync(d_args, h_args, sizeof(LoopArgs) * nj, hipMemcpyHostToDevice, s0),
+                        "copy")) != IBIP_OK)
+        return rc;
+    tm.mark(3, s0);
+    hipLaunchKernelGGL(k_loop_batch, dim3((unsigned)nj), dim3(kLoopThreads), 0, s0, d_args);
+    tm.mark(4, s0);
+    if ((rc = hip_check(ctx, hipGetLastError(), "batch loop launch")) != IBIP_OK) return rc;
+    if ((rc = hip_check(ctx, hipMemcpyAsync(h_st, states, sizeof(LoopState) * nj, hipMemcpyDeviceToHost, s0),
+                        "copy")) != IBIP_OK)
+        return rc;
+    if ((rc = hip_check(ctx, hipStreamSynchronize(s0), "sync")) != IBIP_OK) return rc;
+    if (tm.on) {
+        ctx->timing.loop_kernel_ms += tm.ms(3, 4);
+        ctx->timing.loop_launches++;
+    }
+    // post-processing, again spread over the streams
+    if ((rc = hip_check(ctx, hipEventRecord(ctx->bev[S], s0), "event")) != IBIP_OK) return rc;
+    for (int i = 0; i < S; i++)
+        if ((rc = hip_check(ctx, hipStreamWaitEvent(ctx->bstream[i], ctx->bev[S], 0), "wait")) != IBIP_OK) return rc;
+    ibip_status first = IBIP_OK;
+    for (int32_t q = 0; q < nj; q++) {
+        ibip_job& jb = jobs[order[q]];
+        const LoopState& hs = h_st[q];
+        jb.status = IBIP_OK;
+        jb.n_steps = 0;
+        if (hs.err == 2) jb.status = IBIP_ENOSOLID;
+        else if (hs.err == 3) jb.status = IBIP_ECAPACITY;
+        else if (hs.err) jb.status = IBIP_EDEVICE;
+        if (jb.status != IBIP_OK) {
+            if (first == IBIP_OK) first = (ibip_status)jb.status;
+            continue;
+        }
+        const int64_t K = (int64_t)hs.k - 1;
+        jb.n_steps = K;
+        if ((rc = hip_check(ctx, job_post(bufs[q], states + q, jb.dims, K, jb.seq, jb.rad2, jb.M, jb.sat,
+                                          ctx->bstream[q % S]), "post")) != IBIP_OK)
+            return rc;
+    }
+    for (int i = 0; i < S; i++) {
+        if ((rc = hip_check(ctx, hipEventRecord(ctx->bev[i], ctx->bstream[i]), "event")) != IBIP_OK) return rc;
+        if ((rc = hip_check(ctx, hipStreamWaitEvent(s0, ctx->bev[i], 0), "wait")) != IBIP_OK) return rc;
+    }
+    if ((rc = hip_check(ctx, hipStreamSynchronize(s0), "sync")) != IBIP_OK) return rc;
+    if (first != IBIP_OK) return fail(ctx, first, "invade_batch: at least one job failed (see its status)");
     return IBIP_OK;
 }
 
