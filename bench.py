@@ -36,6 +36,9 @@ WORKLOADS = {
                   "inlets x=0, outlets x=199; invade + trap + MIO at 25 radii",
     "noise512": "512^3 Gaussian-blurred noise (sigma 6, porosity 0.55, seed 0); inlets x=0, outlets x=511; "
                 "invade + trap + MIO at 25 radii",
+    "batch96": "96 images of uneven size, sides uniform in 32..192 (even: sphere packings with radii scaled to "
+               "the side, odd: blurred noise), porosity uniform in 0.35..0.70, seeds 0..95; inlets x=0; "
+               "invade of every image in one batched call vs one call per image",
 }
 
 # Algorithmic bytes per unit of work for each phase.
@@ -95,6 +98,72 @@ def measured_traffic(kernel: str, workload: str):
     return float(t["traffic_bytes_per_launch"])
 
 
+def _spec_image(i):
+    from paper_2101_03240_amd import synth
+    sp = synth.batch_specs(96)[i]
+    return synth.image_for_spec(sp)
+
+
+def batch_images(n: int = 96):
+    """The uneven-size batch, generated in a process pool."""
+    import concurrent.futures as cf
+    workers = max(1, min(16, os.cpu_count() or 1))
+    with cf.ProcessPoolExecutor(max_workers=workers) as ex:
+        return list(ex.map(_spec_image, range(n)))
+
+
+def run_batch(args) -> int:
+    import numpy as np
+    import torch
+
+    import paper_2101_03240_amd as ibip
+    from paper_2101_03240_amd import synth
+
+    dev = torch.device("cuda:0")
+    imgs = batch_images(96)
+    d_imgs = [torch.from_numpy(a).to(dev) for a in imgs]
+    d_inls = [torch.from_numpy(synth.face_mask(a.shape, 0, 0)).to(dev) for a in imgs]
+    n_vox = int(sum(a.size for a in imgs))
+
+    def batched():
+        return ibip.invade_batch(d_imgs, d_inls)
+
+    def plain():
+        return [ibip.invade(a, b) for a, b in zip(d_imgs, d_inls)]
+
+    for _ in range(args.warmup):
+        batched()
+        plain()
+    b = batched()
+    p = plain()
+    exact = all(torch.equal(x["seq"], y["seq"]) and torch.equal(x["rad2"], y["rad2"]) and x["K"] == y["K"]
+                and torch.equal(x["M"], y["M"]) for x, y in zip(b, p))
+    invaded = int(sum(int((x["seq"] > 0).sum().item()) for x in b))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        batched()
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t0) / args.steps
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plain()
+    torch.cuda.synchronize()
+    tp = (time.perf_counter() - t0) / args.steps
+    res = {
+        "metric": METRIC, "value": invaded / tb, "unit": "invaded voxels/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * tb, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "batch96", "description": WORKLOADS["batch96"], "images": len(imgs),
+                   "voxels": n_vox, "invaded_voxels": invaded, "parallelism": "single GPU"},
+        "batched_vs_plain": {"batched_ms": 1e3 * tb, "plain_ms": 1e3 * tp, "speedup": tp / tb,
+                             "bit_exact": bool(exact), "plain_value": invaded / tp},
+    }
+    print(json.dumps(res), flush=True)
+    del np
+    return 0
+
+
 def make_image(name: str):
     from paper_2101_03240_amd import synth
     return synth.config_image(name, seed=0)
@@ -126,6 +195,8 @@ def main() -> int:
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
+    if args.workload == "batch96":
+        return run_batch(args)
     dev = torch.device("cuda:0")
     if args.copy_probe_mb > 0:
         src = torch.ones(args.copy_probe_mb << 20, dtype=torch.uint8, device=dev)
