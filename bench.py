@@ -36,6 +36,9 @@ WORKLOADS = {
                   "inlets x=0, outlets x=199; invade + trap + MIO at 25 radii",
     "noise512": "512^3 Gaussian-blurred noise (sigma 6, porosity 0.55, seed 0); inlets x=0, outlets x=511; "
                 "invade + trap + MIO at 25 radii",
+    "serve": "continuous-batching server: blurred-noise requests (sigma 6, porosity U[0.45, 0.65], side "
+             "log-uniform in 64..768, seeds 1000+j), inlets x=0; a closed loop at fixed depth gives the "
+             "sustained capacity, then Poisson arrivals at 0.7x that rate give the latency from arrival to result",
     "batch96": "96 images of uneven size, sides uniform in 32..192 (even: sphere packings with radii scaled to "
                "the side, odd: blurred noise), porosity uniform in 0.35..0.70, seeds 0..95; inlets x=0; "
                "invade of every image in one batched call vs one call per image",
@@ -164,6 +167,108 @@ def run_batch(args) -> int:
     return 0
 
 
+def run_serve(args) -> int:
+    import queue
+    import threading
+
+    import numpy as np
+    import torch
+
+    import paper_2101_03240_amd as ibip
+    from paper_2101_03240_amd import synth
+
+    dev = torch.device("cuda:0")
+    specs = synth.serve_specs(args.requests)
+    imgs, inls = [], []
+    for sp in specs:
+        L = sp.L
+        imgs.append(synth.blurred_noise_device((L, L, L), sp.sigma, sp.porosity, sp.seed, dev))
+        m = torch.zeros((L, L, L), dtype=torch.uint8, device=dev)
+        m[0] = 1
+        inls.append(m)
+    torch.cuda.synchronize()
+    vox = np.array([x.numel() for x in imgs], dtype=np.float64)
+    print(f"serve: {len(imgs)} requests generated, {vox.sum() / 1e9:.2f} G voxels", file=sys.stderr, flush=True)
+    srv = ibip.Server(dev, hbm_budget_bytes=int(args.serve_budget_gb * (1 << 30)), max_inflight=args.inflight,
+                      lookahead=args.lookahead)
+    small = np.argsort(vox)[:min(8, len(imgs))]
+    for i in small[: args.warmup * 4]:
+        srv.wait(srv.submit(imgs[i], inls[i]))
+
+    def collect(q, out):
+        while True:
+            item = q.get()
+            if item is None:
+                return
+            i, t = item
+            r = srv.wait(t)
+            out[i] = (r["status"], r["latency_ms"], r["K"], int((r["seq"] > 0).sum().item()))
+
+    def run(arrivals):
+        q, out = queue.Queue(), {}
+        th = threading.Thread(target=collect, args=(q, out))
+        th.start()
+        t0 = time.perf_counter()
+        depth = args.depth
+        inflight = []
+        for i in range(len(imgs)):
+            if arrivals is None:
+                # closed loop: keep `depth` requests outstanding
+                while len(inflight) >= depth:
+                    inflight = [j for j in inflight if j not in out]
+                    if len(inflight) >= depth:
+                        time.sleep(0.0002)
+            else:
+                dt = t0 + arrivals[i] - time.perf_counter()
+                if dt > 0:
+                    time.sleep(dt)
+            q.put((i, srv.submit(imgs[i], inls[i])))
+            inflight.append(i)
+        q.put(None)
+        th.join()
+        return time.perf_counter() - t0, out
+
+    wall_c, res_c = run(None)
+    print(f"serve: closed loop {wall_c:.2f} s", file=sys.stderr, flush=True)
+    rate = 0.7 * len(imgs) / wall_c
+    arr = np.cumsum(np.random.default_rng(7).exponential(1.0 / rate, size=len(imgs)))
+    arr -= arr[0]
+    wall_p, res_p = run(arr)
+    print(f"serve: poisson {wall_p:.2f} s", file=sys.stderr, flush=True)
+    st = srv.stats()
+    # a few requests again, alone, must give the same result
+    exact = True
+    for i in list(small[:3]) + [int(np.argmax(vox))][: args.check_large]:
+        t = srv.submit(imgs[i], inls[i])
+        r = srv.wait(t)
+        a = ibip.invade(imgs[i], inls[i])
+        exact &= r["K"] == a["K"] and torch.equal(r["seq"], a["seq"]) and torch.equal(r["M"], a["M"])
+    srv.close()
+    ok = all(v[0] == 0 for v in list(res_c.values()) + list(res_p.values()))
+    lat_c = np.array([res_c[i][1] for i in range(len(imgs))])
+    lat_p = np.array([res_p[i][1] for i in range(len(imgs))])
+    invaded = float(sum(res_c[i][3] for i in range(len(imgs))))
+    res = {
+        "metric": METRIC, "value": invaded / wall_c, "unit": "invaded voxels/s", "n_gpus": 1,
+        "steps": 1, "warmup": args.warmup, "ms_per_step": 1e3 * wall_c, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "serve", "description": WORKLOADS["serve"], "requests": len(imgs),
+                   "voxels": float(vox.sum()), "max_inflight": args.inflight, "hbm_budget_gb": args.serve_budget_gb,
+                   "closed_loop_depth": args.depth, "parallelism": "single GPU"},
+        "serve": {"capacity_jobs_per_s": len(imgs) / wall_c, "capacity_voxels_per_s": vox.sum() / wall_c,
+                  "closed_loop_p50_ms": float(np.percentile(lat_c, 50)),
+                  "closed_loop_p99_ms": float(np.percentile(lat_c, 99)),
+                  "poisson_rate_jobs_per_s": rate, "poisson_jobs_per_s": len(imgs) / wall_p,
+                  "poisson_voxels_per_s": vox.sum() / wall_p,
+                  "poisson_p50_ms": float(np.percentile(lat_p, 50)),
+                  "poisson_p99_ms": float(np.percentile(lat_p, 99)),
+                  "peak_running": int(st["peak_running"]), "peak_pool_gb": st["peak_bytes"] / 2 ** 30,
+                  "all_ok": bool(ok), "alone_equals_mix": bool(exact)},
+    }
+    print(json.dumps(res), flush=True)
+    return 0
+
+
 def make_image(name: str):
     from paper_2101_03240_amd import synth
     return synth.config_image(name, seed=0)
@@ -179,7 +284,17 @@ def main() -> int:
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="run one device-to-device copy of this many MiB before the workload, as a reference "
                          "for hardware traffic counters")
+    ap.add_argument("--requests", type=int, default=64, help="serve: number of requests")
+    ap.add_argument("--inflight", type=int, default=16, help="serve: execution slots")
+    ap.add_argument("--lookahead", type=int, default=8, help="serve: admission window")
+    ap.add_argument("--depth", type=int, default=32, help="serve: outstanding requests in the closed loop")
+    ap.add_argument("--serve-budget-gb", type=float, default=96.0, help="serve: HBM pool for job scratch")
+    ap.add_argument("--check-large", type=int, default=0, help="serve: also rerun the largest request alone")
+    ap.add_argument("--hw-queues", type=int, default=0,
+                    help="hardware queues per process for the HIP runtime (0: its default)")
     args = ap.parse_args()
+    if args.hw_queues:
+        os.environ["GPU_MAX_HW_QUEUES"] = str(min(args.hw_queues, 32))
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -197,6 +312,8 @@ def main() -> int:
         return 1
     if args.workload == "batch96":
         return run_batch(args)
+    if args.workload == "serve":
+        return run_serve(args)
     dev = torch.device("cuda:0")
     if args.copy_probe_mb > 0:
         src = torch.ones(args.copy_probe_mb << 20, dtype=torch.uint8, device=dev)

@@ -155,6 +155,52 @@ typedef struct {
 ibip_status ibip_invade_batch(ibip_ctx* ctx, ibip_job* jobs, int32_t n);
 
 /*
+ * Continuous-batching server for invasion jobs (the serving pattern of the
+ * invasion loop of Section 2.1). Jobs are submitted at any time; a worker
+ * thread admits a pending job as soon as an execution slot is free and the
+ * job's scratch (about 26 bytes per voxel) fits in the server's HBM pool, and
+ * runs it on its slot's stream: setup, the step loop in one workgroup, sphere
+ * insertion and finalisation, without host synchronisation, so admitted jobs
+ * overlap on the device. A job behind one that does not fit yet may start
+ * first (within `lookahead` places), so a huge job does not block the queue.
+ * A job's results are those of ibip_invade on the same inputs.
+ * The job's input buffers must hold their data when it is submitted, and its
+ * output buffers must stay valid until ibip_server_wait returns for it.
+ * ibip_job.M, when given, receives the per-step squared radii; sat is not
+ * produced by the server. Latency = submission to completion.
+ */
+typedef struct ibip_server ibip_server;
+
+typedef struct {
+    int64_t hbm_budget_bytes;  /* device pool for job scratch (0 -> 8 GiB) */
+    int32_t max_inflight;      /* execution slots (0 -> 16) */
+    int32_t lookahead;         /* pending jobs scanned for one that fits (0 -> 8) */
+} ibip_server_opts;
+
+typedef struct {
+    int64_t submitted, completed, cancelled, pending, running;
+    int64_t bytes_in_use, peak_bytes, peak_running;
+} ibip_server_stats;
+
+ibip_status ibip_server_create(ibip_server** out, int32_t device, const ibip_server_opts* opts);
+/* Queue a job (copied); *ticket identifies it. ECAPACITY if its scratch
+   exceeds the whole pool, EINVAL for a bad job. */
+ibip_status ibip_server_submit(ibip_server* s, const ibip_job* job, int64_t* ticket);
+/* *done = 1 once the job completed (or was cancelled). */
+ibip_status ibip_server_poll(ibip_server* s, int64_t ticket, int32_t* done);
+/* Block until the job completes; copy it (status, n_steps) into *result and
+   its latency into *latency_ms (either may be NULL), then forget the ticket.
+   Returns the job's status. */
+ibip_status ibip_server_wait(ibip_server* s, int64_t ticket, ibip_job* result, double* latency_ms);
+/* Cancel a job that has not started (its status becomes ECANCELLED); EINVAL
+   if it is running, done or unknown. */
+ibip_status ibip_server_cancel(ibip_server* s, int64_t ticket);
+ibip_status ibip_server_stats_get(ibip_server* s, ibip_server_stats* out);
+const char* ibip_server_last_error(const ibip_server* s);
+/* Cancel pending jobs, let running ones finish, free everything. */
+ibip_status ibip_server_destroy(ibip_server* s);
+
+/*
  * ibip_get_steps -- per-step arrays of the last ibip_invade (Sections 2.2.1,
  * 2.2.2). For k = 1..K, entry k-1 holds:
  *   M      uint32  squared radius inserted at step k

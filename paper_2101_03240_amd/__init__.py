@@ -22,7 +22,7 @@ import ctypes
 import os
 import threading
 
-__all__ = ["edt", "invade", "invade_batch", "trap", "opening_drainage", "IbipError", "library_path", "load_library",
+__all__ = ["edt", "invade", "invade_batch", "Server", "trap", "opening_drainage", "IbipError", "library_path", "load_library",
            "enable_timing", "get_timing", "reset_timing"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -56,6 +56,15 @@ class _Job(ctypes.Structure):
                 ("max_steps", ctypes.c_int64), ("seq", ctypes.c_void_p), ("rad2", ctypes.c_void_p),
                 ("centre_step", ctypes.c_void_p), ("M", ctypes.c_void_p), ("sat", ctypes.c_void_p),
                 ("n_steps", ctypes.c_int64), ("status", ctypes.c_int32)]
+
+
+class _ServerOpts(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("max_inflight", ctypes.c_int32), ("lookahead", ctypes.c_int32)]
+
+
+class _ServerStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in ("submitted", "completed", "cancelled", "pending", "running",
+                                                "bytes_in_use", "peak_bytes", "peak_running")]
 
 
 class _InvadeOpts(ctypes.Structure):
@@ -93,6 +102,18 @@ def load_library():
         lib.ibip_opening_drainage.argtypes = [P, P, P, _Dims, P, i32, P, P]
         lib.ibip_invade_batch.argtypes = [P, ctypes.POINTER(_Job), i32]
         lib.ibip_invade_batch.restype = i32
+        lib.ibip_server_create.argtypes = [ctypes.POINTER(P), i32, ctypes.POINTER(_ServerOpts)]
+        lib.ibip_server_submit.argtypes = [P, ctypes.POINTER(_Job), ctypes.POINTER(i64)]
+        lib.ibip_server_poll.argtypes = [P, i64, ctypes.POINTER(i32)]
+        lib.ibip_server_wait.argtypes = [P, i64, ctypes.POINTER(_Job), ctypes.POINTER(ctypes.c_double)]
+        lib.ibip_server_cancel.argtypes = [P, i64]
+        lib.ibip_server_stats_get.argtypes = [P, ctypes.POINTER(_ServerStats)]
+        lib.ibip_server_last_error.argtypes = [P]
+        lib.ibip_server_last_error.restype = ctypes.c_char_p
+        lib.ibip_server_destroy.argtypes = [P]
+        for fn in (lib.ibip_server_create, lib.ibip_server_submit, lib.ibip_server_poll, lib.ibip_server_wait,
+                   lib.ibip_server_cancel, lib.ibip_server_stats_get, lib.ibip_server_destroy):
+            fn.restype = i32
         lib.ibip_ctx_enable_timing.argtypes = [P, i32]
         lib.ibip_ctx_get_timing.argtypes = [P, ctypes.POINTER(_Timing)]
         lib.ibip_ctx_reset_timing.argtypes = [P]
@@ -251,6 +272,92 @@ def invade_batch(images, inlets, max_steps=0, rad2: bool = True, centre_step: bo
         if o["sat"] is not None:
             o["sat"] = o["sat"][:k]
     return outs
+
+
+class Server:
+    """Continuous-batching invasion server (``ibip_server_*``). ``submit``
+    queues one image and returns a ticket at once; ``wait`` returns the
+    ``invade``-style result dict with ``status``, ``K`` and ``latency_ms``."""
+
+    def __init__(self, device=0, hbm_budget_bytes: int = 8 << 30, max_inflight: int = 16, lookahead: int = 8):
+        torch = _torch()
+        self._lib = load_library()
+        self._dev = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        idx = self._dev.index if self._dev.index is not None else torch.cuda.current_device()
+        self._h = ctypes.c_void_p()
+        opts = _ServerOpts(int(hbm_budget_bytes), int(max_inflight), int(lookahead))
+        st = self._lib.ibip_server_create(ctypes.byref(self._h), idx, ctypes.byref(opts))
+        if st != 0:
+            raise IbipError(st, "cannot create the server")
+        self._live = {}
+
+    def submit(self, image, inlets, max_steps: int = 0, rad2: bool = True, centre_step: bool = True,
+               M: bool = True) -> int:
+        torch = _torch()
+        image = _dev_u8(image, "image")
+        inlets = _dev_u8(inlets, "inlets")
+        if inlets.shape != image.shape:
+            raise ValueError("inlets must have the image's shape")
+        dims, _ = _dims_of(image)
+        dev = image.device
+        o = {"image": image, "inlets": inlets,
+             "seq": torch.empty(image.shape, dtype=torch.int32, device=dev),
+             "rad2": torch.empty(image.shape, dtype=torch.int32, device=dev) if rad2 else None,
+             "centre_step": torch.empty(image.shape, dtype=torch.int32, device=dev) if centre_step else None,
+             "M": torch.empty(max(image.numel(), 1), dtype=torch.int32, device=dev) if M else None}
+        # inputs must be in place before the server's streams read them
+        torch.cuda.current_stream(dev).synchronize()
+        job = _Job()
+        job.image = image.data_ptr()
+        job.inlets = inlets.data_ptr()
+        job.dims = dims
+        job.max_steps = int(max_steps)
+        for f in ("seq", "rad2", "centre_step", "M"):
+            setattr(job, f, o[f].data_ptr() if o[f] is not None else None)
+        job.sat = None
+        t = ctypes.c_int64(0)
+        st = self._lib.ibip_server_submit(self._h, ctypes.byref(job), ctypes.byref(t))
+        if st != 0:
+            raise IbipError(st, (self._lib.ibip_server_last_error(self._h) or b"").decode())
+        self._live[int(t.value)] = o
+        return int(t.value)
+
+    def done(self, ticket: int) -> bool:
+        d = ctypes.c_int32(0)
+        st = self._lib.ibip_server_poll(self._h, int(ticket), ctypes.byref(d))
+        if st != 0:
+            raise IbipError(st, "unknown ticket")
+        return bool(d.value)
+
+    def wait(self, ticket: int) -> dict:
+        job = _Job()
+        lat = ctypes.c_double(0.0)
+        self._lib.ibip_server_wait(self._h, int(ticket), ctypes.byref(job), ctypes.byref(lat))
+        o = self._live.pop(int(ticket))
+        k = int(job.n_steps)
+        res = {"seq": o["seq"], "rad2": o["rad2"], "centre_step": o["centre_step"],
+               "M": o["M"][:k] if o["M"] is not None else None, "K": k, "status": int(job.status),
+               "latency_ms": float(lat.value)}
+        return res
+
+    def cancel(self, ticket: int) -> bool:
+        return self._lib.ibip_server_cancel(self._h, int(ticket)) == 0
+
+    def stats(self) -> dict:
+        s = _ServerStats()
+        self._lib.ibip_server_stats_get(self._h, ctypes.byref(s))
+        return {n: getattr(s, n) for n, _ in _ServerStats._fields_}
+
+    def close(self):
+        if self._h:
+            self._lib.ibip_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
 
 
 def trap(seq, outlets, seq_trapped: bool = True):

@@ -196,6 +196,42 @@ ibip_status run_invade(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlet
                        const ibip_invade_opts* opts, int32_t* seq, uint32_t* rad2, int32_t* centre_step,
                        int64_t* n_steps);
 ibip_status run_invade_batch(ibip_ctx* ctx, ibip_job* jobs, int32_t n);
+
+// ---- one job of the batch / server paths (invade.hip) ----
+// Per-job scratch carved from one region, so jobs run concurrently.
+struct JobBufs {
+    uint32_t* key;
+    int32_t* state;
+    uint32_t* bucket;
+    uint32_t* hist;
+    uint16_t* g16;
+    uint32_t* tmp32;
+    uint32_t* partials;
+    uint32_t* val;
+    uint32_t* off;
+    uint32_t* head;
+    uint32_t* tail;
+    uint32_t* M;
+    uint32_t* full;
+    uint32_t* counts;  // 2 (N + 1) entries, only when saturation is requested
+    uint32_t* scan_total;
+};
+inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+int64_t value_range(ibip_dims d);
+// bytes of one job's scratch (own_state: no caller centre_step buffer)
+size_t job_bytes(ibip_dims d, bool own_state, bool want_sat);
+JobBufs carve(uint8_t* base, ibip_dims d, int32_t* caller_state, bool want_sat);
+// EDT, ranks, slices and seeds; loop state initialised on the device
+hipError_t job_setup(const JobBufs& j, LoopState* st, const uint8_t* image, const uint8_t* inlets, ibip_dims d,
+                     int64_t max_steps, int32_t* seq, hipStream_t s);
+// post-processing with K read on the device (no host sync)
+hipError_t job_post_devk(const JobBufs& j, LoopState* st, ibip_dims d, int32_t* seq, uint32_t* rad2,
+                         uint32_t* M_out, hipStream_t s);
+size_t loop_args_bytes();
+// fills `out` (loop_args_bytes() of host memory) with the loop arguments of a job
+void fill_loop_args(void* out, const JobBufs& j, LoopState* st, ibip_dims d);
+// one workgroup per job, every step loop to completion
+hipError_t launch_loop_jobs(const void* d_args, int32_t n, hipStream_t s);
 // create the batch streams and events once per context
 ibip_status batch_streams(ibip_ctx* ctx);
 ibip_status run_trap(ibip_ctx* ctx, const int32_t* seq, const uint8_t* outlets, ibip_dims d,

@@ -997,33 +997,10 @@ ibip_status run_invade(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlet
 // ---------------------------------------------------------------------------
 // Batches: many images of uneven size in one call.
 // ---------------------------------------------------------------------------
-namespace {
-
-// Per-job scratch carved from one arena. Everything a job needs lives here,
-// so jobs run their setup concurrently on different streams.
-struct JobBufs {
-    uint32_t* key;
-    int32_t* state;
-    uint32_t* bucket;
-    uint32_t* hist;
-    uint16_t* g16;
-    uint32_t* tmp32;
-    uint32_t* partials;
-    uint32_t* val;
-    uint32_t* off;
-    uint32_t* head;
-    uint32_t* tail;
-    uint32_t* M;
-    uint32_t* full;
-    uint32_t* counts;  // 2 (N + 1) entries, only when saturation is requested
-    uint32_t* scan_total;
-};
-
-inline int64_t value_range(ibip_dims d) {
+int64_t value_range(ibip_dims d) {
     return (int64_t)(d.X - 1) * (d.X - 1) + (int64_t)(d.Y - 1) * (d.Y - 1) + (int64_t)(d.Z - 1) * (d.Z - 1) + 2;
 }
 
-inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 // bytes of one job's scratch; carve() lays the same regions out in order
 size_t job_bytes(ibip_dims d, bool own_state, bool want_sat) {
@@ -1070,14 +1047,14 @@ JobBufs carve(uint8_t* base, ibip_dims d, int32_t* caller_state, bool want_sat) 
     return j;
 }
 
-__global__ void k_loopstate_init(LoopState* st, int64_t max_steps) {
+static __global__ void k_loopstate_init(LoopState* st, int64_t max_steps) {
     st->k = 1;
     st->status = LS_RUN;
     st->max_steps = max_steps;
 }
 
 // saturation after each step: (counts up to k) / n_pore
-__global__ void k_sat(const uint32_t* counts, const uint32_t* count_excl, int64_t K, const LoopState* st,
+static __global__ void k_sat(const uint32_t* counts, const uint32_t* count_excl, int64_t K, const LoopState* st,
                       double* sat) {
     const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (k < K) sat[k] = (double)(count_excl[k] + counts[k]) / (double)st->n_pore;
@@ -1132,7 +1109,46 @@ hipError_t job_post(const JobBufs& j, LoopState* st, ibip_dims d, int64_t K, int
     return hipGetLastError();
 }
 
-}  // namespace
+// Post-processing when K is only known on the device (the server path):
+// grid-stride kernels read K from the loop state.
+static __global__ void k_rank_to_value_dev(uint32_t* M, const LoopState* st, const uint32_t* val, uint32_t* M_out) {
+    const int64_t K = (int64_t)st->k - 1;
+    if (st->err) return;
+    for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < K; k += (int64_t)gridDim.x * 256) {
+        const uint32_t v = val[M[k]];
+        M[k] = v;
+        if (M_out) M_out[k] = v;
+    }
+}
+
+hipError_t job_post_devk(const JobBufs& j, LoopState* st, ibip_dims d, int32_t* seq, uint32_t* rad2,
+                         uint32_t* M_out, hipStream_t s) {
+    const int64_t n = nvox(d);
+    hipLaunchKernelGGL(k_rank_to_value_dev, dim3((unsigned)std::min<int64_t>(blocks(n), 1024)), dim3(256), 0, s,
+                       j.M, st, j.val, M_out);
+    PaintArgs pa{j.state, j.key, j.val, seq, j.full, &st->n_full, d.X, d.Y, d.Z};
+    hipLaunchKernelGGL(k_paint_shell, dim3(blocks(n)), dim3(256), 0, s, pa);
+    hipLaunchKernelGGL(k_paint_full, dim3(std::min<int64_t>(blocks(n), 2048)), dim3(256), 0, s, pa);
+    hipLaunchKernelGGL(k_finalise, dim3(blocks(n)), dim3(256), 0, s, seq, j.state, true, n, j.M, rad2,
+                       (uint32_t*)nullptr, &st->popped);
+    return hipGetLastError();
+}
+
+hipError_t launch_loop_jobs(const void* d_args, int32_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_loop_batch, dim3((unsigned)n), dim3(kLoopThreads), 0, s, (const LoopArgs*)d_args);
+    return hipGetLastError();
+}
+
+LoopArgs job_loop_args(const JobBufs& j, LoopState* st, ibip_dims d) {
+    return LoopArgs{st,  j.head, j.tail, j.val, j.bucket, j.state, j.key, j.M, d.X, d.Y, d.Z, 0xFFFFFFFFu,
+                    kSmallRound, make_fastdiv((uint32_t)d.Z), make_fastdiv((uint32_t)d.Y)};
+}
+
+size_t loop_args_bytes() { return sizeof(LoopArgs); }
+
+void fill_loop_args(void* out, const JobBufs& j, LoopState* st, ibip_dims d) {
+    *(LoopArgs*)out = job_loop_args(j, st, d);
+}
 
 ibip_status run_invade_batch(ibip_ctx* ctx, ibip_job* jobs, int32_t nj) {
     hipStream_t s0 = ctx->stream;
@@ -1174,9 +1190,7 @@ ibip_status run_invade_batch(ibip_ctx* ctx, ibip_job* jobs, int32_t nj) {
                             "setup")) != IBIP_OK)
             return rc;
         const JobBufs& j = bufs[q];
-        h_args[q] = LoopArgs{states + q, j.head, j.tail, j.val, j.bucket, j.state, j.key, j.M,
-                             jb.dims.X, jb.dims.Y, jb.dims.Z, 0xFFFFFFFFu, kSmallRound,
-                             make_fastdiv((uint32_t)jb.dims.Z), make_fastdiv((uint32_t)jb.dims.Y)};
+        h_args[q] = job_loop_args(j, states + q, jb.dims);
     }
     // join, then one launch runs every job's step loop
     for (int i = 0; i < S; i++) {

@@ -263,3 +263,48 @@ def batch_specs(n: int = 96, lo: int = 32, hi: int = 192) -> list[ImageSpec]:
             sg = 2.0 + 4.0 * (L - lo) / float(hi - lo)
             out.append(ImageSpec("noise", L, phi, i, sigma=sg))
     return out
+
+
+# ---------------------------------------------------------------------------
+# Serving stream: many blurred-noise requests up to 768^3, generated on the
+# device (the host FFT of a 768^3 volume takes seconds per image).
+# ---------------------------------------------------------------------------
+def serve_specs(n: int = 256, lo: int = 64, hi: int = 768, seed0: int = 1000) -> list[ImageSpec]:
+    """Request j has seed seed0 + j, side round(exp(U[ln lo, ln hi])) (log-
+    uniform), porosity U[0.45, 0.65], blurred noise of sigma 6."""
+    out = []
+    for j in range(n):
+        rng = _rng(seed0 + j)
+        L = int(round(math.exp(rng.uniform(math.log(lo), math.log(hi)))))
+        phi = float(rng.uniform(0.45, 0.65))
+        out.append(ImageSpec("noise", L, phi, seed0 + j, sigma=6.0))
+    return out
+
+
+def blurred_noise_device(shape, sigma: float, porosity: float, seed: int, device):
+    """The blurred-noise recipe of ``blurred_noise`` computed with torch on a
+    device: N(0, 1) float32 noise from torch's generator seeded with ``seed``,
+    periodic Gaussian blur in Fourier space, pore = values at or below the
+    ``porosity`` quantile of 2^21 sampled values. Returns a uint8 device
+    tensor (1 = pore). Not bit-identical to ``blurred_noise`` (another
+    generator); used where the host generator is too slow."""
+    import torch
+
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    a = torch.randn(tuple(shape), generator=g, device=device, dtype=torch.float32)
+    F = torch.fft.rfftn(a)
+    del a
+    c = -2.0 * math.pi ** 2 * sigma ** 2
+    fz = torch.fft.fftfreq(shape[0], device=device)
+    fy = torch.fft.fftfreq(shape[1], device=device)
+    fx = torch.fft.rfftfreq(shape[2], device=device)
+    F *= torch.exp(c * fz * fz)[:, None, None]
+    F *= torch.exp(c * fy * fy)[None, :, None]
+    F *= torch.exp(c * fx * fx)[None, None, :]
+    b = torch.fft.irfftn(F, s=tuple(shape))
+    del F
+    n = b.numel()
+    idx = torch.randint(0, n, (1 << 21,), generator=g, device=device)
+    t = torch.quantile(b.reshape(-1)[idx], porosity)
+    return (b <= t).to(torch.uint8)
