@@ -306,6 +306,269 @@ __global__ __launch_bounds__(256) void edt_pass_x_opening(const uint32_t* __rest
     block_add_u32(count, hits);
 }
 
+// ---------------------------------------------------------------------------
+// Vectorised passes (rows of Z % 8 == 0 voxels, lines of at most 512 voxels):
+// every global access is an 8- or 16-byte vector per lane and each row or
+// tile is read once. Other shapes take the passes above.
+// ---------------------------------------------------------------------------
+struct FeatImage8 {
+    const uint8_t* img;
+    // feature bits of voxels v..v+7 (v % 8 == 0): bit j set iff voxel v+j is solid
+    __device__ uint32_t bits8(int64_t v) const {
+        const uint2 w = *reinterpret_cast<const uint2*>(img + v);
+        uint32_t b = 0;
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            b |= (((w.x >> (8 * j)) & 0xFFu) == 0u ? 1u : 0u) << j;
+            b |= (((w.y >> (8 * j)) & 0xFFu) == 0u ? 1u : 0u) << (j + 4);
+        }
+        return b;
+    }
+};
+struct FeatThreshold8 {
+    const uint32_t* w;
+    uint32_t thr;
+    __device__ uint32_t bits8(int64_t v) const {
+        const uint4 a = *reinterpret_cast<const uint4*>(w + v);
+        const uint4 c = *reinterpret_cast<const uint4*>(w + v + 4);
+        return (a.x >= thr ? 1u : 0u) | (a.y >= thr ? 2u : 0u) | (a.z >= thr ? 4u : 0u) | (a.w >= thr ? 8u : 0u) |
+               (c.x >= thr ? 16u : 0u) | (c.y >= thr ? 32u : 0u) | (c.z >= thr ? 64u : 0u) |
+               (c.w >= thr ? 128u : 0u);
+    }
+};
+
+// Pass z with the whole row in registers: a lane owns 8 consecutive voxels, a
+// row spans lpr = Z / 8 lanes, a wave holds 64 / lpr rows. The nearest
+// feature before / after each lane's voxels comes from a max / min scan over
+// the row's lanes.
+constexpr int kZGroups = 2;  // row groups per wave, their loads issued together
+
+// pass z of one row group: lane li of lpr holds feature bits fb of voxels
+// v0..v0+7 of its row; writes their distances along z
+__device__ inline void pass_z_rows(uint32_t fb, bool act, int64_t v0, int li, int lpr, uint64_t cap, uint16_t* g) {
+    const int zb = li * 8;
+    // nearest feature at or before the end of this lane's voxels
+    int incl = fb ? zb + 31 - __clz(fb) : -1;
+    // nearest feature at or after the start of this lane's voxels
+    int incr = fb ? zb + __ffs(fb) - 1 : 0x7FFFFFFF;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int a = __shfl_up(incl, o, 64);
+        const int b = __shfl_down(incr, o, 64);
+        if (o < lpr) {
+            if (li >= o) incl = max(incl, a);
+            if (li + o < lpr) incr = min(incr, b);
+        }
+    }
+    int prev = __shfl_up(incl, 1, 64);
+    int next = __shfl_down(incr, 1, 64);
+    if (li == 0) prev = -1;
+    if (li == lpr - 1) next = 0x7FFFFFFF;
+    uint32_t d[8];
+#pragma unroll
+    for (int j = 0; j < 8; j++) {
+        if (fb & (1u << j)) prev = zb + j;
+        d[j] = prev < 0 ? 0xFFFFFFFFu : (uint32_t)(zb + j - prev);
+    }
+#pragma unroll
+    for (int j = 7; j >= 0; j--) {
+        if (fb & (1u << j)) next = zb + j;
+        if (next != 0x7FFFFFFF) d[j] = min(d[j], (uint32_t)(next - zb - j));
+    }
+    uint32_t pk[4];
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        const uint32_t lo = (d[2 * j] == 0xFFFFFFFFu || (uint64_t)d[2 * j] * d[2 * j] >= cap) ? kInf16 : d[2 * j];
+        const uint32_t hi =
+            (d[2 * j + 1] == 0xFFFFFFFFu || (uint64_t)d[2 * j + 1] * d[2 * j + 1] >= cap) ? kInf16 : d[2 * j + 1];
+        pk[j] = lo | (hi << 16);
+    }
+    if (act) *reinterpret_cast<uint4*>(g + v0) = make_uint4(pk[0], pk[1], pk[2], pk[3]);
+}
+
+template <class Feat>
+__global__ __launch_bounds__(256) void edt_pass_z_vec(Feat feat, int64_t rows, int Z, uint64_t cap, uint16_t* g,
+                                                      uint32_t* solid_flag) {
+    const int lane = threadIdx.x & 63;
+    const int lpr = Z >> 3;
+    const int rpw = 64 / lpr;
+    const int r = lane / lpr;
+    const int li = lane - r * lpr;
+    const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    uint32_t fb[kZGroups];
+    bool act[kZGroups];
+    int64_t v0[kZGroups];
+#pragma unroll
+    for (int q = 0; q < kZGroups; q++) {
+        const int64_t row = (wave * kZGroups + q) * rpw + r;
+        act[q] = r < rpw && row < rows;
+        v0[q] = row * Z + li * 8;
+        fb[q] = act[q] ? feat.bits8(v0[q]) : 0u;
+    }
+    bool any = false;
+#pragma unroll
+    for (int q = 0; q < kZGroups; q++) {
+        pass_z_rows(fb[q], act[q], v0[q], li, lpr, cap, g);
+        any |= __ballot(fb[q] != 0) != 0;
+    }
+    if (lane == 0 && any && __hip_atomic_load(solid_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
+        atomicOr(solid_flag, 1u);
+}
+
+// Tiled passes y and x: a workgroup loads a whole tile of lines (every line
+// of one plane, 32 z columns wide) into LDS with 16-byte vectors, then
+// evaluates the envelope min over i of f(i) + (u - i)^2 at every voxel by the
+// outward search, four offsets per side at a time, stopping once o^2 >= best
+// (every farther i adds at least o^2; reading a whole group before the test
+// only adds candidates, so the result is exact). The tile carries kPad rows
+// of a sentinel above and below the line, and a side that has run past its
+// end reads the sentinel rows, so a group is eight unconditional LDS reads at
+// fixed offsets. The sentinel stands for "no feature": it is larger than any
+// real value and small enough that sentinel + o^2 cannot overflow, so each
+// candidate costs one multiply-add (or add) and one min. Lines are at most
+// 512 voxels, so every real sum stays below 3 * 511^2.
+constexpr int kPad = 4;
+constexpr int kTW = 32;                              // z columns per tile
+constexpr uint32_t kSent16 = 0x7FFFu;                // pass y: sentinel distance
+constexpr uint32_t kSentSq = kSent16 * kSent16;      // its square (+ o^2 < 2^31)
+constexpr uint32_t kSent32 = 0x40000000u;            // pass x: sentinel value
+constexpr int kThreadsY = 512, kThreadsX = 1024;
+
+__global__ __launch_bounds__(kThreadsY) void edt_pass_y_vec(const uint16_t* __restrict__ g, int X, int Y, int Z,
+                                                           uint64_t cap, uint32_t* __restrict__ h) {
+    extern __shared__ uint16_t t16[];  // [kPad + Y + kPad][kTW]
+    constexpr int kSegs = kTW / 8, kRows = kThreadsY / kSegs;
+    const int nzc = (Z + kTW - 1) / kTW;
+    const int x = blockIdx.x / nzc;
+    const int z0 = (blockIdx.x - x * nzc) * kTW;
+    const int64_t plane = (int64_t)x * Y * Z;
+    {
+        const int seg = threadIdx.x % kSegs;
+        const int zc = z0 + seg * 8;
+        for (int y = threadIdx.x / kSegs; y < Y; y += kRows) {
+            uint4 w = make_uint4(0x7FFF7FFFu, 0x7FFF7FFFu, 0x7FFF7FFFu, 0x7FFF7FFFu);
+            if (zc < Z) {
+                // 0xFFFF (no feature) becomes the sentinel 0x7FFF; distances are < 512
+                w = *reinterpret_cast<const uint4*>(g + plane + (int64_t)y * Z + zc);
+                w.x &= 0x7FFF7FFFu;
+                w.y &= 0x7FFF7FFFu;
+                w.z &= 0x7FFF7FFFu;
+                w.w &= 0x7FFF7FFFu;
+            }
+            *reinterpret_cast<uint4*>(t16 + (y + kPad) * kTW + seg * 8) = w;
+        }
+        for (int i = threadIdx.x; i < 2 * kPad * kTW; i += kThreadsY) {
+            const int r = i / kTW;
+            t16[(r < kPad ? r : Y + r) * kTW + (i - r * kTW)] = (uint16_t)kSent16;
+        }
+    }
+    __syncthreads();
+    const int lz = threadIdx.x % kTW;
+    const int z = z0 + lz;
+    if (z >= Z) return;
+    const uint32_t capv = (uint32_t)cap;
+    const uint32_t lim = min(capv, kSentSq);
+    const uint16_t* col = t16 + kPad * kTW + lz;  // row i at col[i * kTW]
+    for (int y = threadIdx.x / kTW; y < Y; y += kThreadsY / kTW) {
+        const uint32_t f0 = col[y * kTW];
+        uint32_t best = f0 == kSent16 ? capv : f0 * f0;
+        if (best) {
+            const int far = max(y, Y - 1 - y);
+            for (int o = 1; o <= far; o += 4) {
+                if ((uint32_t)(o * o) >= best) break;
+                const uint16_t* lp = col + (y - o >= 0 ? y - o : -1) * kTW;
+                const uint16_t* rp = col + (y + o < Y ? y + o : Y) * kTW;
+#pragma unroll
+                for (int j = 0; j < 4; j++) {
+                    const uint32_t oo = (uint32_t)((o + j) * (o + j));
+                    const uint32_t fl = lp[-j * kTW], fr = rp[j * kTW];
+                    best = min(best, fl * fl + oo);
+                    best = min(best, fr * fr + oo);
+                }
+            }
+        }
+        h[plane + (int64_t)y * Z + z] = best >= lim ? kInf32 : best;
+    }
+}
+
+template <class Out>
+__global__ __launch_bounds__(kThreadsX) void edt_pass_x_vec(const uint32_t* __restrict__ hin, int X, int Y, int Z,
+                                                           uint64_t cap, Out outp, uint32_t* count) {
+    extern __shared__ uint32_t t32[];  // [kPad + X + kPad][kTW]
+    constexpr int kSegs = kTW / 4, kRows = kThreadsX / kSegs;
+    const int nzc = (Z + kTW - 1) / kTW;
+    const int y = blockIdx.x / nzc;
+    const int z0 = (blockIdx.x - y * nzc) * kTW;
+    const int64_t yz = (int64_t)Y * Z;
+    const int64_t col0 = (int64_t)y * Z + z0;
+    {
+        const int seg = threadIdx.x % kSegs;
+        const int zc = z0 + seg * 4;
+        for (int x = threadIdx.x / kSegs; x < X; x += kRows) {
+            uint4 w = make_uint4(kSent32, kSent32, kSent32, kSent32);
+            if (zc < Z) {
+                w = *reinterpret_cast<const uint4*>(hin + x * yz + col0 + seg * 4);
+                w.x = w.x == kInf32 ? kSent32 : w.x;
+                w.y = w.y == kInf32 ? kSent32 : w.y;
+                w.z = w.z == kInf32 ? kSent32 : w.z;
+                w.w = w.w == kInf32 ? kSent32 : w.w;
+            }
+            *reinterpret_cast<uint4*>(t32 + (x + kPad) * kTW + seg * 4) = w;
+        }
+        for (int i = threadIdx.x; i < 2 * kPad * kTW; i += kThreadsX) {
+            const int r = i / kTW;
+            t32[(r < kPad ? r : X + r) * kTW + (i - r * kTW)] = kSent32;
+        }
+    }
+    __syncthreads();
+    const int lz = threadIdx.x % kTW;
+    const int z = z0 + lz;
+    uint32_t hits = 0;
+    if (z < Z) {
+        const uint32_t capv = (uint32_t)cap;
+        const uint32_t lim = min(capv, kSent32);
+        const uint32_t* col = t32 + kPad * kTW + lz;
+        for (int x = threadIdx.x / kTW; x < X; x += kThreadsX / kTW) {
+            const uint32_t f0 = col[x * kTW];
+            uint32_t best = f0 == kSent32 ? capv : f0;
+            if (best) {
+                const int far = max(x, X - 1 - x);
+                for (int o = 1; o <= far; o += 4) {
+                    if ((uint32_t)(o * o) >= best) break;
+                    const uint32_t* lp = col + (x - o >= 0 ? x - o : -1) * kTW;
+                    const uint32_t* rp = col + (x + o < X ? x + o : X) * kTW;
+#pragma unroll
+                    for (int j = 0; j < 4; j++) {
+                        const uint32_t oo = (uint32_t)((o + j) * (o + j));
+                        best = min(best, lp[-j * kTW] + oo);
+                        best = min(best, rp[j * kTW] + oo);
+                    }
+                }
+            }
+            const int64_t v = x * yz + col0 + lz;
+            const uint64_t b = best >= lim ? (uint64_t)cap : (uint64_t)best;
+            outp.put(v, b, cap);
+            hits += outp.hit(v, b);
+        }
+    }
+    if (count) block_add_u32(count, hits);
+}
+
+// LDS a workgroup may use on the current device (the pass-x tile of a
+// 512-voxel line takes 66.5 KB).
+size_t max_lds_per_block() {
+    static size_t cached[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 65536;
+    if (!cached[dev]) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+            v = 65536;
+        cached[dev] = (size_t)v;
+    }
+    return cached[dev];
+}
+
 }  // namespace
 
 hipError_t launch_edt(const uint8_t* image, const uint32_t* w, uint32_t thr, uint32_t cap, ibip_dims d,
@@ -314,6 +577,33 @@ hipError_t launch_edt(const uint8_t* image, const uint32_t* w, uint32_t thr, uin
     // cap == 0: exact everywhere; else exact where dt2 < cap, 0xFFFFFFFF elsewhere
     const uint64_t c64 = cap ? (uint64_t)cap : 0xFFFFFFFFull;
     const int64_t n = nvox(d);
+    // vector path: rows of Z % 8 == 0 voxels, lines of at most 512 voxels,
+    // aligned inputs; 32-bit sums when they cannot reach 2^31
+    const size_t ly = sizeof(uint16_t) * kTW * (d.Y + 2 * kPad), lx = sizeof(uint32_t) * kTW * (d.X + 2 * kPad);
+    const bool vec = d.Z % 8 == 0 && d.Z <= 512 && d.X <= kMaxTileLine && d.Y <= kMaxTileLine &&
+                     (image ? ((uintptr_t)image & 7) == 0 : ((uintptr_t)w & 15) == 0) &&
+                     std::max(ly, lx) <= max_lds_per_block();
+    if (vec) {
+        const int64_t rows = (int64_t)d.X * d.Y;
+        const int64_t rows_per_block = 4LL * (64 / (d.Z / 8)) * kZGroups;
+        const unsigned gz = (unsigned)((rows + rows_per_block - 1) / rows_per_block);
+        if (image)
+            hipLaunchKernelGGL(edt_pass_z_vec<FeatImage8>, dim3(gz), dim3(256), 0, s, FeatImage8{image}, rows, d.Z,
+                               c64, g16, solid_flag);
+        else
+            hipLaunchKernelGGL(edt_pass_z_vec<FeatThreshold8>, dim3(gz), dim3(256), 0, s, FeatThreshold8{w, thr},
+                               rows, d.Z, c64, g16, solid_flag);
+        const unsigned nzc = (unsigned)((d.Z + kTW - 1) / kTW);
+        hipLaunchKernelGGL(edt_pass_y_vec, dim3((unsigned)d.X * nzc), dim3(kThreadsY), ly, s, g16, d.X, d.Y, d.Z, c64,
+                           tmp32);
+        if (mio_r2)
+            hipLaunchKernelGGL(edt_pass_x_vec<OutOpening>, dim3((unsigned)d.Y * nzc), dim3(kThreadsX), lx, s, tmp32,
+                               d.X, d.Y, d.Z, c64, OutOpening{mio_r2, cap}, mio_count);
+        else
+            hipLaunchKernelGGL(edt_pass_x_vec<OutPlain>, dim3((unsigned)d.Y * nzc), dim3(kThreadsX), lx, s, tmp32,
+                               d.X, d.Y, d.Z, c64, OutPlain{out}, (uint32_t*)nullptr);
+        return hipGetLastError();
+    }
     const int64_t rows = (int64_t)d.X * d.Y;
     const unsigned gz = (unsigned)((rows + 3) / 4);
     if (image)

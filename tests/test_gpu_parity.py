@@ -80,6 +80,28 @@ def test_edt_long_lines(dev, shape):
     np.testing.assert_array_equal(_u32(ibip.edt(_d(img, dev))), oracle.edt(img))
 
 
+@pytest.mark.parametrize("shape", [(3, 5, 8), (1, 40, 64), (17, 33, 200), (512, 2, 16), (2, 512, 24), (9, 7, 512),
+                                   (5, 3, 96), (1, 1, 8)])
+@pytest.mark.parametrize("p", [0.6, 0.995])
+def test_edt_vector_path(dev, shape, p):
+    """Rows of a multiple of 8 voxels and lines of at most 512 take the
+    vectorised passes (several rows per wave when Z < 512)."""
+    rng = np.random.default_rng(sum(shape) + int(1000 * p))
+    img = (rng.random(shape) < p).astype(np.uint8)
+    img.flat[int(rng.integers(img.size))] = 0
+    np.testing.assert_array_equal(_u32(ibip.edt(_d(img, dev))), oracle.edt(img))
+
+
+def test_edt_unaligned_input(dev):
+    rng = np.random.default_rng(3)
+    img = (rng.random((16, 24, 64)) < 0.9).astype(np.uint8)
+    img[0, 0, 0] = 0
+    buf = torch.zeros(img.size + 16, dtype=torch.uint8, device=dev)
+    t = buf[3:3 + img.size].view(img.shape)
+    t.copy_(torch.from_numpy(img))
+    np.testing.assert_array_equal(_u32(ibip.edt(t)), oracle.edt(img))
+
+
 def test_mio_long_lines(dev):
     rng = np.random.default_rng(5)
     img = (rng.random((530, 6, 7)) < 0.85).astype(np.uint8)
