@@ -135,20 +135,38 @@ __global__ __launch_bounds__(256) void k_convert(const uint8_t* __restrict__ img
     }
 }
 
-// Append u to the slice of rank rr with one atomic per distinct rank in the
-// wave (lanes with active == false do nothing).
-__device__ inline void push_global(bool active, uint32_t u, uint32_t rr, uint32_t* tail, uint32_t* bucket) {
+// Groups the active lanes of a wave by rank with ballots only (no memory
+// access): `lead` = the group's first lane, `off` = the lane's place in its
+// group, `cnt` = the group's size on the first lane, 0 elsewhere.
+struct RankGroup {
+    uint32_t lead = 0, off = 0, cnt = 0;
+};
+__device__ inline RankGroup group_by_rank(bool active, uint32_t rr) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t lt = lanemask_lt();
+    RankGroup g;
     uint64_t pending = __ballot(active);
     while (pending) {
         const int leader = __ffsll((unsigned long long)pending) - 1;
-        const uint32_t lr = __shfl(rr, leader, 64);
+        const uint32_t lr = __builtin_amdgcn_readlane(rr, leader);
         const uint64_t same = __ballot(active && rr == lr) & pending;
-        uint32_t base = 0;
-        if ((threadIdx.x & 63) == leader) base = atomicAdd(&tail[lr], (uint32_t)__popcll(same));
-        base = __shfl(base, leader, 64);
-        if (active && rr == lr) bucket[base + __popcll(same & lanemask_lt())] = u;
+        if ((same >> lane) & 1) {
+            g.lead = (uint32_t)leader;
+            g.off = (uint32_t)__popcll(same & lt);
+        }
+        if (lane == leader) g.cnt = (uint32_t)__popcll(same);
         pending &= ~same;
     }
+    return g;
+}
+
+// Append u to the slice of rank rr with one atomic per distinct rank in the
+// wave (many waves hitting one slice tail lane by lane contend at L2).
+__device__ inline void push_global(bool active, uint32_t u, uint32_t rr, uint32_t* tail, uint32_t* bucket) {
+    const RankGroup g = group_by_rank(active, rr);
+    uint32_t base = g.cnt ? atomicAdd(&tail[rr], g.cnt) : 0u;
+    base = __shfl(base, (int)g.lead, 64);
+    if (active) bucket[base + g.off] = u;
 }
 
 // Seeds: Q0 = (inlets U their face neighbours) restricted to pore.
@@ -249,8 +267,9 @@ __device__ inline uint32_t lds_highest_below_uni(const LoopShared& s, uint32_t r
 // rank above r was pushed (`up`), the new maximum is the highest set bit,
 // since every rank above r was empty when the step began; otherwise it is r
 // itself if its slice refilled, else the highest non-empty rank below it.
-__device__ inline uint32_t next_top(LoopShared& s, uint32_t r, bool up, uint32_t R) {
-    const bool refilled = uni(s.tail[r]) > uni(s.head[r]);
+// `refilled`: whether the step pushed into slice r (known from the pushes
+// when wave 0 ran the step alone).
+__device__ inline uint32_t next_top_known(LoopShared& s, uint32_t r, bool up, bool refilled, uint32_t R) {
     if (!refilled) {
         const uint32_t wv = uni(s.bits[r >> 5]) & ~(1u << (r & 31));
         s.bits[r >> 5] = wv;
@@ -258,6 +277,10 @@ __device__ inline uint32_t next_top(LoopShared& s, uint32_t r, bool up, uint32_t
     }
     if (up) return lds_highest_below_uni(s, R + 1);
     return refilled ? r : lds_highest_below_uni(s, r);
+}
+
+__device__ inline uint32_t next_top(LoopShared& s, uint32_t r, bool up, uint32_t R) {
+    return next_top_known(s, r, up, uni(s.tail[r]) > uni(s.head[r]), R);
 }
 
 // Make c a centre of step k and claim its unseen pore face neighbours: one
@@ -350,73 +373,74 @@ __device__ inline uint32_t expand_lds(const bool (&have)[NC], const uint32_t (&c
 }
 
 // A step with at most kSmallRound centres, run by wave 0 alone. The centres
-// sit in s.cl; each lane takes one (centre, direction) pair per pass, so a
-// step with few centres is a single short pass, and the claims of all passes
-// are issued before the wave waits for any of them. Returns the largest rank
-// this lane pushed (0 if none); *logn receives the push-log length.
-__device__ inline uint32_t small_step(uint32_t cnt, uint32_t k, const LoopArgs& a, LoopShared& s, uint32_t sel,
-                                      uint32_t& logn) {
-    constexpr int kMaxPass = (6 * kSmallRound + 63) / 64;
-    const int lane = threadIdx.x & 63;
-    const uint32_t np = 6 * cnt;
-    const uint32_t passes = (np + 63) / 64;
-    const int64_t yz = (int64_t)a.Y * a.Z;
-    uint32_t old[kMaxPass], uv[kMaxPass];
-#pragma unroll
-    for (int p = 0; p < kMaxPass; p++) {
-        old[p] = kClaim;
-        uv[p] = 0;
-        if ((uint32_t)p < passes) {
-            const uint32_t i = (uint32_t)p * 64 + lane;
-            const bool act = i < np;
-            const uint32_t ci = i / 6u;
-            const uint32_t dir = i - ci * 6u;
-            const uint32_t c = act ? s.cl[ci < kSmallRound ? ci : kSmallRound - 1] : 0u;
-            const uint32_t t = fdiv(c, a.divZ);
-            const int z = (int)(c - t * (uint32_t)a.Z);
-            const int x = (int)fdiv(t, a.divY);
-            const int y = (int)(t - (uint32_t)x * (uint32_t)a.Y);
-            if (act && dir == 0) a.state[c] = (int32_t)k;
-            int64_t off;
-            bool ok;
-            switch (dir) {
-                case 0: off = -yz; ok = x > 0; break;
-                case 1: off = yz; ok = x < a.X - 1; break;
-                case 2: off = -(int64_t)a.Z; ok = y > 0; break;
-                case 3: off = a.Z; ok = y < a.Y - 1; break;
-                case 4: off = -1; ok = z > 0; break;
-                default: off = 1; ok = z < a.Z - 1; break;
-            }
-            ok = ok && act;
-            const uint32_t u = (uint32_t)((int64_t)c + off);
-            uv[p] = u;
-            if (ok) old[p] = atomicOr(&a.key[u], kClaim);
+// sit in s.cl; each lane takes one (centre, direction) pair per pass of 64
+// pairs. The direction becomes a stride and a bounds test by selects, not
+// branches, so the claims of the first two passes (21 centres) are issued
+// back to back and waited for once; steps with more centres run their further
+// passes one at a time. Returns the largest rank this lane pushed (0 if none);
+// `logn` receives the push-log length.
+__device__ inline void claim_pair(uint32_t p, uint32_t np, uint32_t k, const LoopArgs& a, const LoopShared& s,
+                                  uint32_t& old, uint32_t& u) {
+    const uint32_t i = p * 64 + (threadIdx.x & 63);
+    const bool act = i < np;
+    const uint32_t ci = act ? i / 6u : 0u;
+    const uint32_t dir = i - ci * 6u;
+    const uint32_t c = act ? s.cl[ci] : 0u;
+    const uint32_t t = fdiv(c, a.divZ);
+    const uint32_t z = c - t * (uint32_t)a.Z;
+    const uint32_t x = fdiv(t, a.divY);
+    const uint32_t y = t - x * (uint32_t)a.Y;
+    const uint32_t axis = dir >> 1;
+    const bool up = dir & 1u;
+    const uint32_t stride = axis == 0 ? (uint32_t)a.Y * (uint32_t)a.Z : axis == 1 ? (uint32_t)a.Z : 1u;
+    const uint32_t coord = axis == 0 ? x : axis == 1 ? y : z;
+    const uint32_t last = axis == 0 ? (uint32_t)a.X - 1u : axis == 1 ? (uint32_t)a.Y - 1u : (uint32_t)a.Z - 1u;
+    const bool ok = act && (up ? coord < last : coord > 0u);
+    u = up ? c + stride : c - stride;
+    old = kClaim;
+    if (ok) old = atomicOr(&a.key[u], kClaim);
+    // stores go after the claims: a wait for the claims then leaves them in flight
+    if (act && dir == 0) a.state[c] = (int32_t)k;
+}
+
+// Push the voxel of a won claim into the LDS slice of its rank and the push log.
+__device__ inline void push_pair(uint32_t old, uint32_t u, const LoopArgs& a, LoopShared& s, uint32_t sel,
+                                 uint32_t& logn, uint32_t& mymax, uint32_t r, bool& same) {
+    const uint32_t rr = old & kRankMask;
+    const bool won = !(old & kClaim) && rr != 0;
+    mymax = won && rr > mymax ? rr : mymax;
+    same |= won && rr == r;
+    uint32_t pos = 0, hd = 1;
+    if (won) {
+        pos = atomicAdd(&s.tail[rr], 1u);
+        hd = s.head[rr];
+    }
+    const uint64_t m = __ballot(won);
+    const uint32_t li = logn + (uint32_t)__popcll(m & lanemask_lt());
+    logn += (uint32_t)__popcll(m);
+    if (won) {
+        a.bucket[pos] = u;
+        if (pos == hd) lds_set(s, rr);
+        if (li < kLog) {
+            s.logu[sel][li] = u;
+            s.logr[sel][li] = rr;
         }
     }
-    uint32_t mymax = 0;
-    const uint64_t lt = lanemask_lt();
-#pragma unroll
-    for (int p = 0; p < kMaxPass; p++) {
-        if ((uint32_t)p >= passes) break;
-        const uint32_t rr = old[p] & kRankMask;
-        const bool won = !(old[p] & kClaim) && rr != 0;
-        mymax = won && rr > mymax ? rr : mymax;
-        uint32_t pos = 0, hd = 1;
-        if (won) {
-            pos = atomicAdd(&s.tail[rr], 1u);
-            hd = s.head[rr];
-        }
-        const uint64_t m = __ballot(won);
-        const uint32_t li = logn + (uint32_t)__popcll(m & lt);
-        logn += (uint32_t)__popcll(m);
-        if (won) {
-            a.bucket[pos] = uv[p];
-            if (pos == hd) lds_set(s, rr);
-            if (li < kLog) {
-                s.logu[sel][li] = uv[p];
-                s.logr[sel][li] = rr;
-            }
-        }
+}
+
+__device__ inline uint32_t small_step(uint32_t cnt, uint32_t k, uint32_t r, const LoopArgs& a, LoopShared& s,
+                                      uint32_t sel, uint32_t& logn, bool& same) {
+    const uint32_t np = 6 * cnt;
+    const uint32_t passes = (np + 63) >> 6;
+    uint32_t o0, u0, o1 = kClaim, u1 = 0, mymax = 0;
+    claim_pair(0, np, k, a, s, o0, u0);
+    if (passes > 1) claim_pair(1, np, k, a, s, o1, u1);
+    push_pair(o0, u0, a, s, sel, logn, mymax, r, same);
+    if (passes > 1) push_pair(o1, u1, a, s, sel, logn, mymax, r, same);
+    for (uint32_t p = 2; p < passes; p++) {
+        uint32_t o, u;
+        claim_pair(p, np, k, a, s, o, u);
+        push_pair(o, u, a, s, sel, logn, mymax, r, same);
     }
     return mymax;
 }
@@ -492,8 +516,8 @@ __device__ inline void loop_body(const LoopArgs& a, LoopShared& s) {
                 const uint32_t h = uni(s.head[r]), t = uni(s.tail[r]);
                 const uint32_t cnt = t - h;
                 s.head[r] = t;
-                a.M[k - 1] = r;  // rank; k_rank_to_value turns it into dt2 after the loop
                 const bool fromlog = log_ok && r >= prev_r;
+                if (cnt > a.small) a.M[k - 1] = r;  // rank; k_rank_to_value turns it into dt2 after the loop
                 if (cnt > a.wide) {
                     a.st->big_r = r;
                     a.st->big_h = h;
@@ -536,10 +560,12 @@ __device__ inline void loop_body(const LoopArgs& a, LoopShared& s) {
                     if (lane < cnt) s.cl[lane] = c0;
                     if (lane + 64 < cnt) s.cl[lane + 64] = c1;
                 }
-                const uint32_t lm = small_step(cnt, k, a, s, nsel, ln);
+                bool same = false;
+                const uint32_t lm = small_step(cnt, k, r, a, s, nsel, ln, same);
+                a.M[k - 1] = r;
                 s.logn[nsel] = ln;
                 const uint32_t r_done = r;
-                r = next_top(s, r, __ballot(lm > r) != 0, R);
+                r = next_top_known(s, r, __ballot(lm > r) != 0, __ballot(same) != 0, R);
                 prev_r = r_done;
                 k = k + 1;
                 sel = nsel;
@@ -611,7 +637,7 @@ __global__ __launch_bounds__(kLoopThreads) void k_loop_batch(const LoopArgs* __r
 }
 
 // expand() for the whole-GPU kernel: the same claims, pushed to the global
-// slice tails with one atomic per distinct rank in the wave.
+// slice tails with one atomic per distinct rank per direction in the wave.
 __device__ inline void expand_global(bool have, uint32_t c, uint32_t k, const LoopArgs& a) {
     const int64_t yz = (int64_t)a.Y * a.Z;
     int z = 0, y = 0, x = 0;
@@ -629,10 +655,23 @@ __device__ inline void expand_global(bool have, uint32_t c, uint32_t k, const Lo
     uint32_t old[6];
 #pragma unroll
     for (int j = 0; j < 6; j++) old[j] = okd[j] ? atomicOr(&a.key[uu[j]], kClaim) : kClaim;
+    // pushes grouped by rank per direction; every group's tail atomic is in
+    // flight before the first result is used
+    RankGroup g[6];
+    uint32_t rr[6], base[6];
+    bool won[6];
 #pragma unroll
     for (int j = 0; j < 6; j++) {
-        const uint32_t rr = old[j] & kRankMask;
-        push_global(!(old[j] & kClaim) && rr != 0, (uint32_t)uu[j], rr, a.tail, a.bucket);
+        rr[j] = old[j] & kRankMask;
+        won[j] = !(old[j] & kClaim) && rr[j] != 0;
+        g[j] = group_by_rank(won[j], rr[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < 6; j++) base[j] = g[j].cnt ? atomicAdd(&a.tail[rr[j]], g[j].cnt) : 0u;
+#pragma unroll
+    for (int j = 0; j < 6; j++) {
+        const uint32_t b = __shfl(base[j], (int)g[j].lead, 64);
+        if (won[j]) a.bucket[b + g[j].off] = (uint32_t)uu[j];
     }
 }
 
