@@ -299,7 +299,7 @@ def main() -> int:
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(images would shard one per GPU; see DESIGN.md)", file=sys.stderr)
+              "(independent images would shard one per GPU)", file=sys.stderr)
         return 2
 
     import numpy as np
@@ -412,6 +412,8 @@ def main() -> int:
         "loop": {"us_per_invasion_step": 1e3 * tm["loop_ms"] / max(tm["steps"], 1),
                  "invasion_steps_per_s": tm["steps"] / (tm["loop_ms"] * 1e-3) if tm["loop_ms"] > 0 else 0.0,
                  "loop_launches_per_call": tm["loop_launches"] / S, "wide_launches_per_call": tm["wide_launches"] / S,
+                 "wide_centres_per_call": tm["wide_centres"] / S,
+                 "ns_per_wide_centre": 1e6 * tm["wide_kernel_ms"] / max(tm["wide_centres"], 1),
                  "relax_sweeps_per_step": tm["relax_sweeps"] / S},
     }
     if not args.no_cpu_baseline:

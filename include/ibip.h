@@ -85,6 +85,7 @@ typedef struct {
     int64_t steps;          /* steps K summed over ibip_invade calls */
     int64_t popped;         /* centres summed over ibip_invade calls */
     int64_t relax_sweeps;   /* reconstruction sweeps (trapping and MIO) */
+    int64_t wide_centres;   /* centres of the steps run by the whole-GPU kernel */
 } ibip_timing;
 
 ibip_status ibip_ctx_enable_timing(ibip_ctx* ctx, int32_t enable);

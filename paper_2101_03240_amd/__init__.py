@@ -48,7 +48,8 @@ class _Dims(ctypes.Structure):
 class _Timing(ctypes.Structure):
     _fields_ = [(n, ctypes.c_double) for n in ("edt_ms", "setup_ms", "loop_ms", "loop_kernel_ms", "wide_kernel_ms",
                                                 "paint_ms", "steps_ms", "trap_ms", "mio_ms")] + \
-               [(n, ctypes.c_int64) for n in ("loop_launches", "wide_launches", "steps", "popped", "relax_sweeps")]
+               [(n, ctypes.c_int64) for n in ("loop_launches", "wide_launches", "steps", "popped", "relax_sweeps",
+                                                "wide_centres")]
 
 
 class _Job(ctypes.Structure):

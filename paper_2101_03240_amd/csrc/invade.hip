@@ -245,22 +245,41 @@ __device__ inline void lds_set(LoopShared& s, uint32_t r) {
 }
 
 // highest set rank strictly below r (0 = none), with every loaded word made
-// wave-uniform so the search runs on scalar branches
-__device__ inline uint32_t lds_highest_below_uni(const LoopShared& s, uint32_t r) {
+// wave-uniform so the search runs on scalar branches. A summary bit may
+// outlive its word (a rank bit cleared without a read-back of the word): such
+// a word reads zero, its summary bit is dropped and the search goes on. Only
+// wave 0 calls this, while no other wave touches the bitmap.
+__device__ inline uint32_t lds_highest_below_uni(LoopShared& s, uint32_t r) {
     uint32_t w = r >> 5, b = r & 31;
     uint32_t m = uni(s.bits[w]) & ((1u << b) - 1u);
     if (m) return (w << 5) + 31 - __clz(m);
     uint32_t sw = w >> 5, sb = w & 31;
     uint32_t ms = uni(s.sum[sw]) & ((1u << sb) - 1u);
     for (;;) {
-        if (ms) {
-            uint32_t ww = (sw << 5) + 31 - __clz(ms);
-            return (ww << 5) + 31 - __clz(uni(s.bits[ww]));
+        while (ms) {
+            const uint32_t wb = 31 - __clz(ms);
+            const uint32_t ww = (sw << 5) + wb;
+            const uint32_t bw = uni(s.bits[ww]);
+            if (bw) return (ww << 5) + 31 - __clz(bw);
+            ms &= ~(1u << wb);
+            atomicAnd(&s.sum[sw], ~(1u << wb));
         }
         if (sw == 0) return 0;
         sw--;
         ms = uni(s.sum[sw]);
     }
+}
+
+// Maximum of v over the 64 lanes of a wave (every lane active), by DPP row
+// shifts within rows of 16 lanes and row broadcasts across rows.
+__device__ inline uint32_t wave_max_u32(uint32_t v) {
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, true));  // row_shr:1
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, true));  // row_shr:2
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, true));  // row_shr:4
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, true));  // row_shr:8
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false)); // row_bcast:15
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false)); // row_bcast:31
+    return __builtin_amdgcn_readlane(v, 63);
 }
 
 // After step r: clear the occupancy bit of r if its slice stayed empty. If a
@@ -429,12 +448,16 @@ __device__ inline void push_pair(uint32_t old, uint32_t u, const LoopArgs& a, Lo
 }
 
 __device__ inline uint32_t small_step(uint32_t cnt, uint32_t k, uint32_t r, const LoopArgs& a, LoopShared& s,
-                                      uint32_t sel, uint32_t& logn, bool& same) {
+                                      uint32_t sel, uint32_t& logn, bool& same, uint32_t& below) {
     const uint32_t np = 6 * cnt;
     const uint32_t passes = (np + 63) >> 6;
     uint32_t o0, u0, o1 = kClaim, u1 = 0, mymax = 0;
     claim_pair(0, np, k, a, s, o0, u0);
     if (passes > 1) claim_pair(1, np, k, a, s, o1, u1);
+    // while the claims are in flight: the highest non-empty rank below r, the
+    // next maximum unless this step pushes at or above r (pushes below r are
+    // covered by the wave maximum of the pushed ranks)
+    below = lds_highest_below_uni(s, r);
     push_pair(o0, u0, a, s, sel, logn, mymax, r, same);
     if (passes > 1) push_pair(o1, u1, a, s, sel, logn, mymax, r, same);
     for (uint32_t p = 2; p < passes; p++) {
@@ -486,7 +509,7 @@ __device__ inline void loop_body(const LoopArgs& a, LoopShared& s) {
     const int64_t max_steps = a.st->max_steps;
     const uint32_t n_pore = a.st->n_pore;
     // driver state, live in wave 0
-    uint32_t r = 0, k = 0, prev_r = 0, sel = 0;
+    uint32_t r = 0, k = 0, prev_r = 0, sel = 0, nlog = 0;
     bool log_ok = false;
     if (wave0) {
         r = lds_highest_below_uni(s, R + 1);
@@ -544,7 +567,7 @@ __device__ inline void loop_body(const LoopArgs& a, LoopShared& s) {
                 // a small step, wave 0 alone: gather its centres into s.cl
                 uint32_t ln = 0;  // entries in the new push log
                 if (fromlog) {
-                    const uint32_t n = uni(s.logn[sel]);
+                    const uint32_t n = nlog;
                     uint32_t got = 0;
                     for (uint32_t b0 = 0; b0 < n; b0 += 64) {
                         const uint32_t i = b0 + lane;
@@ -561,15 +584,23 @@ __device__ inline void loop_body(const LoopArgs& a, LoopShared& s) {
                     if (lane + 64 < cnt) s.cl[lane + 64] = c1;
                 }
                 bool same = false;
-                const uint32_t lm = small_step(cnt, k, r, a, s, nsel, ln, same);
+                uint32_t below = 0;
+                const uint32_t lm = small_step(cnt, k, r, a, s, nsel, ln, same, below);
                 a.M[k - 1] = r;
                 s.logn[nsel] = ln;
                 const uint32_t r_done = r;
-                r = next_top_known(s, r, __ballot(lm > r) != 0, __ballot(same) != 0, R);
+                // next maximum: the highest pushed rank if above r (every rank above
+                // r was empty), else r if its slice refilled, else the larger of the
+                // highest pushed rank and the highest non-empty rank below r
+                const uint32_t pmax = wave_max_u32(lm);
+                const bool refilled = __ballot(same) != 0;
+                if (!refilled) atomicAnd(&s.bits[r >> 5], ~(1u << (r & 31)));
+                r = pmax > r ? pmax : refilled ? r : max(below, pmax);
                 prev_r = r_done;
                 k = k + 1;
                 sel = nsel;
                 log_ok = ln <= kLog;
+                nlog = ln;
             }
         }
         __syncthreads();
@@ -613,7 +644,8 @@ __device__ inline void loop_body(const LoopArgs& a, LoopShared& s) {
             prev_r = r_done;
             k = k + 1;
             sel ^= 1u;
-            log_ok = uni(s.logn[sel]) <= kLog;
+            nlog = uni(s.logn[sel]);
+            log_ok = nlog <= kLog;
         }
     }
     if (wave0) a.st->k = k;
@@ -971,6 +1003,7 @@ ibip_status run_invade(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlet
         if (++segments > n_pore + 2) return fail(ctx, IBIP_EDEVICE, "invade: too many loop segments");
         if (h_st->status == LS_WIDE) {
             const uint32_t cnt = h_st->big_t - h_st->big_h;
+            if (tm.on) ctx->timing.wide_centres += cnt;
             const unsigned g = (unsigned)std::min<int64_t>((cnt + 255) / 256, 4096);
             tm.mark(5, s);
             hipLaunchKernelGGL(k_wide, dim3(g), dim3(256), 0, s, la);
