@@ -225,7 +225,7 @@ constexpr uint32_t kLog = 2048;  // entries of the per-step push log
 
 struct LoopShared {
     uint32_t head[kMaxRanks + 1];
-    uint32_t tail[kMaxRanks + 1];
+    uint32_t tail[kMaxRanks + 1 + 64];  // + one dummy word per lane (see slice_pos)
     uint32_t bits[kBitWords];   // rank r non-empty
     uint32_t sum[kSumWords];    // bits word w non-zero
     // pushes of the last two steps (voxel, rank), double-buffered
@@ -238,6 +238,18 @@ struct LoopShared {
 };
 
 __device__ inline uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+
+
+// Position of a push into the LDS slice of rank rr, and that slice's head.
+// Every lane issues the atomic and the read: a lane that does not push adds 0
+// to a dummy word of its own. (An LDS atomic under a lane condition makes the
+// compiler wait for its result before the next one, serialising a lane's
+// several pushes into one LDS round trip each.)
+__device__ inline void slice_pos(LoopShared& s, bool push, uint32_t rr, uint32_t& pos, uint32_t& hd) {
+    const uint32_t lane = threadIdx.x & 63;
+    pos = atomicAdd(&s.tail[push ? rr : (uint32_t)kMaxRanks + 1u + lane], push ? 1u : 0u);
+    hd = s.head[push ? rr : 0u];
+}
 
 __device__ inline void lds_set(LoopShared& s, uint32_t r) {
     atomicOr(&s.bits[r >> 5], 1u << (r & 31));
@@ -353,8 +365,7 @@ __device__ inline uint32_t expand_lds(const bool (&have)[NC], const uint32_t (&c
     // the slice heads read alongside
 #pragma unroll
     for (int j = 0; j < ND; j++) {
-        pos[j] = won[j] ? atomicAdd(&s.tail[rr[j]], 1u) : 0u;
-        hd[j] = won[j] ? s.head[rr[j]] : 1u;
+        slice_pos(s, won[j], rr[j], pos[j], hd[j]);
     }
     // push-log entries
     uint64_t m[ND];
@@ -429,11 +440,8 @@ __device__ inline void push_pair(uint32_t old, uint32_t u, const LoopArgs& a, Lo
     const bool won = !(old & kClaim) && rr != 0;
     mymax = won && rr > mymax ? rr : mymax;
     same |= won && rr == r;
-    uint32_t pos = 0, hd = 1;
-    if (won) {
-        pos = atomicAdd(&s.tail[rr], 1u);
-        hd = s.head[rr];
-    }
+    uint32_t pos, hd;
+    slice_pos(s, won, rr, pos, hd);
     const uint64_t m = __ballot(won);
     const uint32_t li = logn + (uint32_t)__popcll(m & lanemask_lt());
     logn += (uint32_t)__popcll(m);
