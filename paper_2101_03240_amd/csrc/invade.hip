@@ -742,8 +742,22 @@ struct PaintArgs {
     int X, Y, Z;
 };
 
-__device__ inline void stamp(int32_t* seq, int64_t v, int32_t k) {
-    if (seq[v] > k) atomicMin(&seq[v], k);
+// Stamps go out in groups of kStampGroup: the current values of the whole
+// group are loaded together (a slot with nothing to stamp loads a valid
+// address instead of branching), then an atomicMin, whose result is not
+// used, goes only where the value is still larger. Most stamps land on
+// voxels that already hold a smaller step, so the loads save L2 atomics; one
+// load per stamp taken in turn would cost a round trip each.
+constexpr int kStampGroup = 4;
+
+__device__ inline void stamp_group(int32_t* seq, const int64_t (&v)[kStampGroup], const bool (&ok)[kStampGroup],
+                                   int32_t k) {
+    int32_t cur[kStampGroup];
+#pragma unroll
+    for (int t = 0; t < kStampGroup; t++) cur[t] = seq[v[t]];
+#pragma unroll
+    for (int t = 0; t < kStampGroup; t++)
+        if (ok[t] && cur[t] > k) atomicMin(&seq[v[t]], k);
 }
 
 // One thread per voxel: centres with an earlier, at-least-as-large face
@@ -763,15 +777,23 @@ __global__ __launch_bounds__(256) void k_paint_shell(PaintArgs a) {
     const int64_t off[6] = {-yz, yz, -(int64_t)a.Z, (int64_t)a.Z, -1, 1};
     uint32_t qmask = 0;
     uint32_t mp[6];
+    // the six neighbours read together (an outside neighbour reads c itself)
+    int32_t kp[6];
+    uint32_t rp[6];
 #pragma unroll
     for (int j = 0; j < 6; j++) {
-        mp[j] = 0;
-        if (!inb[j]) continue;
-        const int32_t kp = a.state[c + off[j]];
-        if (kp > 0 && kp < k) {
-            const uint32_t rp = a.key[c + off[j]] & kRankMask;
-            if (rp >= rc) { qmask |= 1u << j; mp[j] = a.val[rp]; }
-        }
+        const int64_t nb = inb[j] ? c + off[j] : c;
+        kp[j] = a.state[nb];
+        rp[j] = a.key[nb] & kRankMask;
+    }
+    uint32_t vp[6];
+#pragma unroll
+    for (int j = 0; j < 6; j++) vp[j] = a.val[rp[j]];
+#pragma unroll
+    for (int j = 0; j < 6; j++) {
+        const bool q = inb[j] && kp[j] > 0 && kp[j] < k && rp[j] >= rc;
+        qmask |= q ? 1u << j : 0u;
+        mp[j] = q ? vp[j] : 0u;
     }
     if (!qmask) {
         const uint32_t slot = atomicAdd(a.n_full, 1u);
@@ -791,27 +813,32 @@ __global__ __launch_bounds__(256) void k_paint_shell(PaintArgs a) {
         if (pb < 0 || pb >= dim[B]) continue;
         const uint32_t rem = m - 1 - (uint32_t)(p * p);
         const int U = (int)isqrt_u32(rem);
-        for (int q = -U; q <= U; q++) {
-            const int pc = pos[C] + q;
-            if (pc < 0 || pc >= dim[C]) continue;
-            const int w = (int)isqrt_u32(rem - (uint32_t)(q * q));
-            const int oa = sgn * w;
-            const int pa = pos[A] + oa;
-            if (pa < 0 || pa >= dim[A]) continue;
-            int o[3];
-            o[A] = oa; o[B] = p; o[C] = q;
-            const uint32_t oo = (uint32_t)(w * w + p * p + q * q);
-            bool covered = false;
-            uint32_t rest = qmask & ~(1u << j0);
-            while (rest) {
-                const int j = __ffs(rest) - 1;
-                rest &= rest - 1;
-                const int sj = (j & 1) ? 1 : -1;      // n_j component
-                const uint32_t d = oo - 2 * sj * o[j >> 1] + 1;  // |o - n_j|^2
-                if (d < mp[j]) { covered = true; break; }
+        for (int q0 = -U; q0 <= U; q0 += kStampGroup) {
+            int64_t tv[kStampGroup];
+            bool tok[kStampGroup];
+#pragma unroll
+            for (int t = 0; t < kStampGroup; t++) {
+                const int q = q0 + t;
+                const int pc = pos[C] + q;
+                const int w = q <= U ? (int)isqrt_u32(rem - (uint32_t)(q * q)) : 0;
+                const int oa = sgn * w;
+                const int pa = pos[A] + oa;
+                bool ok = q <= U && pc >= 0 && pc < dim[C] && pa >= 0 && pa < dim[A];
+                int o[3];
+                o[A] = oa; o[B] = p; o[C] = q;
+                const uint32_t oo = (uint32_t)(w * w + p * p + q * q);
+                uint32_t rest = ok ? qmask & ~(1u << j0) : 0u;
+                while (rest) {
+                    const int j = __ffs(rest) - 1;
+                    rest &= rest - 1;
+                    const int sj = (j & 1) ? 1 : -1;      // n_j component
+                    const uint32_t d = oo - 2 * sj * o[j >> 1] + 1;  // |o - n_j|^2
+                    if (d < mp[j]) { ok = false; break; }
+                }
+                tok[t] = ok;
+                tv[t] = ok ? c + (int64_t)oa * stride[A] + (int64_t)p * stride[B] + (int64_t)q * stride[C] : c;
             }
-            if (covered) continue;
-            stamp(a.seq, c + (int64_t)oa * stride[A] + (int64_t)p * stride[B] + (int64_t)q * stride[C], k);
+            stamp_group(a.seq, tv, tok, k);
         }
     }
 }
@@ -839,7 +866,16 @@ __global__ __launch_bounds__(256) void k_paint_full(PaintArgs a) {
                 const int W = (int)isqrt_u32(rem - (uint32_t)(dy * dy));
                 const int z0 = max(z - W, 0), z1 = min(z + W, a.Z - 1);
                 const int64_t rowv = ((int64_t)xx * a.Y + yy) * a.Z;
-                for (int zz = z0; zz <= z1; zz++) stamp(a.seq, rowv + zz, k);
+                for (int zz = z0; zz <= z1; zz += kStampGroup) {
+                    int64_t tv[kStampGroup];
+                    bool tok[kStampGroup];
+#pragma unroll
+                    for (int t = 0; t < kStampGroup; t++) {
+                        tok[t] = zz + t <= z1;
+                        tv[t] = rowv + min(zz + t, z1);
+                    }
+                    stamp_group(a.seq, tv, tok, k);
+                }
             }
         }
     }

@@ -25,19 +25,19 @@ __global__ __launch_bounds__(256) void k_mio_seed(const uint8_t* img, const uint
     const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
     bool pore = false;
     if (v < n) {
-        pore = img[v] != 0;
-        bool seed = false;
-        if (pore) {
-            seed = inlets[v] != 0;
-            const int z = (int)(v % Z), y = (int)((v / Z) % Y), x = (int)(v / yz);
-            if (!seed && x > 0) seed = inlets[v - yz] != 0;
-            if (!seed && x < X - 1) seed = inlets[v + yz] != 0;
-            if (!seed && y > 0) seed = inlets[v - Z] != 0;
-            if (!seed && y < Y - 1) seed = inlets[v + Z] != 0;
-            if (!seed && z > 0) seed = inlets[v - 1] != 0;
-            if (!seed && z < Z - 1) seed = inlets[v + 1] != 0;
-        }
-        k0[v] = seed ? dt2[v] : 0u;
+        // all seven inlet bytes and dt2 are loaded together (an outside
+        // neighbour reads v itself): a chain of conditional loads would wait
+        // for each in turn
+        const int z = (int)(v % Z), y = (int)((v / Z) % Y), x = (int)(v / yz);
+        const uint8_t im = img[v];
+        const uint32_t d = dt2[v];
+        const uint8_t i0 = inlets[v];
+        const uint8_t i1 = inlets[x > 0 ? v - yz : v], i2 = inlets[x < X - 1 ? v + yz : v];
+        const uint8_t i3 = inlets[y > 0 ? v - Z : v], i4 = inlets[y < Y - 1 ? v + Z : v];
+        const uint8_t i5 = inlets[z > 0 ? v - 1 : v], i6 = inlets[z < Z - 1 ? v + 1 : v];
+        pore = im != 0;
+        const bool seed = pore && (i0 | i1 | i2 | i3 | i4 | i5 | i6) != 0;
+        k0[v] = seed ? d : 0u;
     }
     block_add_u32(n_pore, pore ? 1u : 0u);
 }

@@ -58,12 +58,21 @@ __global__ __launch_bounds__(256) void k_relax_tiles(Cap cap, int X, int Y, int 
     const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
     const int64_t yz = (int64_t)Y * Z;
     if (tid < 6) face[tid] = 0;
-    for (int i = tid; i < HX * HY * HZ; i += 256) {
+    // Tile, halo and capacities: every load is issued before the first is
+    // used. Coordinates are clamped into the image and out-of-image values
+    // replaced afterwards, so no load sits under a lane condition (such a
+    // load is waited for at once, one round trip each).
+    constexpr int HN = HX * HY * HZ, HPER = (HN + 255) / 256;
+    uint32_t hv[HPER];
+#pragma unroll
+    for (int q = 0; q < HPER; q++) {
+        const int i = min(tid + q * 256, HN - 1);
         const int hz = i % HZ, hy = (i / HZ) % HY, hx = i / (HZ * HY);
         const int gx = x0 + hx - 1, gy = y0 + hy - 1, gz = z0 + hz - 1;
-        uint32_t val = 0;
-        if (gx >= 0 && gx < X && gy >= 0 && gy < Y && gz >= 0 && gz < Z) val = w[gx * yz + (int64_t)gy * Z + gz];
-        hw[i] = val;
+        const bool in = gx >= 0 && gx < X && gy >= 0 && gy < Y && gz >= 0 && gz < Z;
+        const int cx = min(max(gx, 0), X - 1), cy = min(max(gy, 0), Y - 1), cz = min(max(gz, 0), Z - 1);
+        const uint32_t val = w[cx * yz + (int64_t)cy * Z + cz];
+        hv[q] = in ? val : 0u;
     }
     const int lz = tid & 31, ly = tid >> 5;  // ly in [0, 8): rows ly and ly + 8
     constexpr int NV = TX * 2;
@@ -73,8 +82,12 @@ __global__ __launch_bounds__(256) void k_relax_tiles(Cap cap, int X, int Y, int 
     for (int j = 0; j < NV; j++) {
         const int gx = x0 + (j >> 1), gy = y0 + ly + 8 * (j & 1);
         const bool in = gx < X && gy < Y && gz < Z;
-        c[j] = in ? cap(gx * yz + (int64_t)gy * Z + gz) : 0u;
+        const uint32_t cv = cap(min(gx, X - 1) * yz + (int64_t)min(gy, Y - 1) * Z + min(gz, Z - 1));
+        c[j] = in ? cv : 0u;
     }
+#pragma unroll
+    for (int q = 0; q < HPER; q++)
+        if (tid + q * 256 < HN) hw[tid + q * 256] = hv[q];
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < NV; j++) orig[j] = hw[(((j >> 1) + 1) * HY + (ly + 8 * (j & 1) + 1)) * HZ + (lz + 1)];
