@@ -5,8 +5,10 @@ One step = the whole path over one synthetic image already resident in HBM:
 exact squared EDT, the invasion loop (steps, sphere insertion, per-step
 saturation and capillary pressure), defender trapping, and the pressure-based
 morphological-opening drainage at 25 radii used for the equal-saturation
-comparison. The reported value is invaded voxels per second of wall time over
-the timed steps.
+comparison. The opening needs only the image and the inlets, so it runs from a
+second host thread on a second stream while the invasion (whose step loop
+occupies one compute unit) and the trapping run. The reported value is invaded
+voxels per second of wall time over the timed steps.
 
     python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--workload packing200]
 
@@ -333,10 +335,22 @@ def main() -> int:
     n_vox = img.size
     n_pore = int(img.sum())
 
+    import concurrent.futures as cf
+    side_pool = cf.ThreadPoolExecutor(max_workers=1)  # one host thread, its own context and stream
+    side = torch.cuda.Stream(device=dev)
+
+    def opening():
+        with torch.cuda.stream(side):
+            return ibip.opening_drainage(img_d, inl_d, T)
+
+    def on_side(fn):
+        return side_pool.submit(fn).result()
+
     def step():
+        fut = side_pool.submit(opening)
         r = ibip.invade(img_d, inl_d)
         t = ibip.trap(r["seq"], out_d)
-        m = ibip.opening_drainage(img_d, inl_d, T)
+        m = fut.result()
         return r, t, m
 
     for _ in range(args.warmup):
@@ -348,6 +362,7 @@ def main() -> int:
 
     ibip.reset_timing()
     ibip.enable_timing(True)
+    on_side(lambda: (ibip.reset_timing(), ibip.enable_timing(True)))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -356,6 +371,11 @@ def main() -> int:
     elapsed = time.perf_counter() - t0
     ibip.enable_timing(False)
     tm = ibip.get_timing()
+    ts = on_side(ibip.get_timing)
+    on_side(lambda: ibip.enable_timing(False))
+    side_pool.shutdown()
+    tm["mio_ms"] += ts["mio_ms"]
+    tm["relax_sweeps"] += ts["relax_sweeps"]
 
     ms_per_step = 1e3 * elapsed / args.steps
     value = invaded * args.steps / elapsed
@@ -393,7 +413,8 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": args.workload, "description": WORKLOADS[args.workload],
                    "shape": list(img.shape), "pore_voxels": n_pore, "invaded_voxels": invaded,
-                   "invasion_steps": K, "mio_radii": len(T), "parallelism": "single GPU"},
+                   "invasion_steps": K, "mio_radii": len(T), "parallelism": "single GPU",
+                   "overlap": "the opening drainage runs on a second stream during invade + trap"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
                      "traffic": measured_traffic(dom, args.workload),

@@ -133,16 +133,20 @@ def _torch():
 
 
 def _context(device) -> ctypes.c_void_p:
+    """The calling thread's context on `device` (a context holds scratch
+    buffers and is used by one thread at a time, so each host thread gets its
+    own; calls from two threads on two streams then run concurrently)."""
     torch = _torch()
     lib = load_library()
     idx = device.index if device.index is not None else torch.cuda.current_device()
-    ctx = _ctx.get(idx)
+    key = (idx, threading.get_ident())
+    ctx = _ctx.get(key)
     if ctx is None:
         ctx = ctypes.c_void_p()
         st = lib.ibip_ctx_create(ctypes.byref(ctx), idx, None)
         if st != 0:
             raise IbipError(st, f"cannot create a context on device {idx}")
-        _ctx[idx] = ctx
+        _ctx[key] = ctx
     stream = torch.cuda.current_stream(idx).cuda_stream
     lib.ibip_ctx_set_stream(ctx, ctypes.c_void_p(stream))
     return ctx
@@ -404,7 +408,8 @@ def opening_drainage(image, inlets, thresholds):
 
 
 def enable_timing(enable: bool = True, device=None):
-    """Turn the library's per-phase HIP-event timing on or off (see ibip_timing)."""
+    """Turn the library's per-phase HIP-event timing on or off (see
+    ibip_timing) for the calling thread's context."""
     torch = _torch()
     ctx = _context(torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device()))
     _check(load_library().ibip_ctx_enable_timing(ctx, 1 if enable else 0), ctx)
@@ -417,7 +422,8 @@ def reset_timing(device=None):
 
 
 def get_timing(device=None) -> dict:
-    """Accumulated phase times (ms) and counters since the last reset."""
+    """Accumulated phase times (ms) and counters of the calling thread's
+    context since its last reset."""
     torch = _torch()
     ctx = _context(torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device()))
     t = _Timing()
