@@ -407,8 +407,7 @@ __device__ inline uint32_t expand_lds(const bool (&have)[NC], const uint32_t (&c
 // pairs. The direction becomes a stride and a bounds test by selects, not
 // branches, so the claims of the first two passes (21 centres) are issued
 // back to back and waited for once; steps with more centres run their further
-// passes one at a time. Returns the largest rank this lane pushed (0 if none);
-// `logn` receives the push-log length.
+// passes one at a time.
 __device__ inline void claim_pair(uint32_t p, uint32_t np, uint32_t k, const LoopArgs& a, const LoopShared& s,
                                   uint32_t& old, uint32_t& u) {
     const uint32_t i = p * 64 + (threadIdx.x & 63);
@@ -433,18 +432,29 @@ __device__ inline void claim_pair(uint32_t p, uint32_t np, uint32_t k, const Loo
     if (act && dir == 0) a.state[c] = (int32_t)k;
 }
 
-// Push the voxel of a won claim into the LDS slice of its rank and the push log.
-__device__ inline void push_pair(uint32_t old, uint32_t u, const LoopArgs& a, LoopShared& s, uint32_t sel,
-                                 uint32_t& logn, uint32_t& mymax, uint32_t r, bool& same) {
+// Rank of a won claim (0 if the claim lost or hit solid).
+__device__ inline uint32_t won_rank(uint32_t old) {
     const uint32_t rr = old & kRankMask;
-    const bool won = !(old & kClaim) && rr != 0;
-    mymax = won && rr > mymax ? rr : mymax;
-    same |= won && rr == r;
+    return !(old & kClaim) && rr != 0 ? rr : 0u;
+}
+
+// Push the voxel of a won claim into the LDS slice of its rank and the push
+// log; a push of rank rn (the next step's rank, when every live entry of its
+// slice comes from this step) is also listed in s.cl for the next step.
+__device__ inline void push_pair(uint32_t old, uint32_t u, const LoopArgs& a, LoopShared& s, uint32_t sel,
+                                 uint32_t& logn, uint32_t rn, uint32_t& dn) {
+    const uint32_t rr = won_rank(old);
+    const bool won = rr != 0;
     uint32_t pos, hd;
     slice_pos(s, won, rr, pos, hd);
+    const uint64_t lt = lanemask_lt();
     const uint64_t m = __ballot(won);
-    const uint32_t li = logn + (uint32_t)__popcll(m & lanemask_lt());
+    const uint32_t li = logn + (uint32_t)__popcll(m & lt);
     logn += (uint32_t)__popcll(m);
+    const bool nx = won && rr == rn;
+    const uint64_t mn = __ballot(nx);
+    const uint32_t di = dn + (uint32_t)__popcll(mn & lt);
+    dn += (uint32_t)__popcll(mn);
     if (won) {
         a.bucket[pos] = u;
         if (pos == hd) lds_set(s, rr);
@@ -452,28 +462,55 @@ __device__ inline void push_pair(uint32_t old, uint32_t u, const LoopArgs& a, Lo
             s.logu[sel][li] = u;
             s.logr[sel][li] = rr;
         }
+        if (nx && di < kSmallRound) s.cl[di] = u;
     }
 }
 
+// One small step; returns the next maximum rank. The next maximum is the
+// highest pushed rank if above r (every rank above r was empty), else r if
+// its slice refilled, else the larger of the highest pushed rank and the
+// highest non-empty rank below r (`below`, read while the claims are in
+// flight). With at most two passes it is known once the claims return, before
+// the pushes: if every live entry of its slice is a push of this step (it is
+// not `below`), the pushes list them in s.cl and `direct` is set, so the next
+// step gathers nothing.
 __device__ inline uint32_t small_step(uint32_t cnt, uint32_t k, uint32_t r, const LoopArgs& a, LoopShared& s,
-                                      uint32_t sel, uint32_t& logn, bool& same, uint32_t& below) {
+                                      uint32_t sel, uint32_t& logn, bool& direct) {
     const uint32_t np = 6 * cnt;
     const uint32_t passes = (np + 63) >> 6;
-    uint32_t o0, u0, o1 = kClaim, u1 = 0, mymax = 0;
+    uint32_t o0, u0, o1 = kClaim, u1 = 0, dn = 0;
     claim_pair(0, np, k, a, s, o0, u0);
     if (passes > 1) claim_pair(1, np, k, a, s, o1, u1);
-    // while the claims are in flight: the highest non-empty rank below r, the
-    // next maximum unless this step pushes at or above r (pushes below r are
-    // covered by the wave maximum of the pushed ranks)
-    below = lds_highest_below_uni(s, r);
-    push_pair(o0, u0, a, s, sel, logn, mymax, r, same);
-    if (passes > 1) push_pair(o1, u1, a, s, sel, logn, mymax, r, same);
+    const uint32_t below = lds_highest_below_uni(s, r);
+    const uint32_t w0 = won_rank(o0), w1 = won_rank(o1);
+    if (passes <= 2) {
+        const uint32_t pmax = wave_max_u32(max(w0, w1));
+        const bool refilled = __ballot(w0 == r || w1 == r) != 0;
+        if (!refilled) atomicAnd(&s.bits[r >> 5], ~(1u << (r & 31)));
+        const uint32_t rn = pmax > r ? pmax : refilled ? r : max(below, pmax);
+        direct = rn != 0 && rn != below;
+        const uint32_t rd = direct ? rn : 0u;  // rank 0 matches no push
+        push_pair(o0, u0, a, s, sel, logn, rd, dn);
+        if (passes > 1) push_pair(o1, u1, a, s, sel, logn, rd, dn);
+        return rn;
+    }
+    uint32_t lm = max(w0, w1);
+    bool same = w0 == r || w1 == r;
+    push_pair(o0, u0, a, s, sel, logn, 0u, dn);
+    push_pair(o1, u1, a, s, sel, logn, 0u, dn);
     for (uint32_t p = 2; p < passes; p++) {
         uint32_t o, u;
         claim_pair(p, np, k, a, s, o, u);
-        push_pair(o, u, a, s, sel, logn, mymax, r, same);
+        const uint32_t w = won_rank(o);
+        lm = max(lm, w);
+        same |= w == r;
+        push_pair(o, u, a, s, sel, logn, 0u, dn);
     }
-    return mymax;
+    const uint32_t pmax = wave_max_u32(lm);
+    const bool refilled = __ballot(same) != 0;
+    if (!refilled) atomicAnd(&s.bits[r >> 5], ~(1u << (r & 31)));
+    direct = false;
+    return pmax > r ? pmax : refilled ? r : max(below, pmax);
 }
 
 // Control flow: the step decisions run in all 64 lanes of wave 0 on values
@@ -518,7 +555,7 @@ __device__ inline void loop_body(const LoopArgs& a, LoopShared& s) {
     const uint32_t n_pore = a.st->n_pore;
     // driver state, live in wave 0
     uint32_t r = 0, k = 0, prev_r = 0, sel = 0, nlog = 0;
-    bool log_ok = false;
+    bool log_ok = false, direct = false;
     if (wave0) {
         r = lds_highest_below_uni(s, R + 1);
         k = uni(a.st->k);
@@ -547,7 +584,7 @@ __device__ inline void loop_body(const LoopArgs& a, LoopShared& s) {
                 const uint32_t h = uni(s.head[r]), t = uni(s.tail[r]);
                 const uint32_t cnt = t - h;
                 s.head[r] = t;
-                const bool fromlog = log_ok && r >= prev_r;
+                const bool fromlog = log_ok && (direct || r >= prev_r);
                 if (cnt > a.small) a.M[k - 1] = r;  // rank; k_rank_to_value turns it into dt2 after the loop
                 if (cnt > a.wide) {
                     a.st->big_r = r;
@@ -572,9 +609,11 @@ __device__ inline void loop_body(const LoopArgs& a, LoopShared& s) {
                     s.d_sel = sel;
                     break;
                 }
-                // a small step, wave 0 alone: gather its centres into s.cl
+                // a small step, wave 0 alone: its centres are listed in s.cl by the
+                // previous step, or gathered there from the log or the bucket
                 uint32_t ln = 0;  // entries in the new push log
-                if (fromlog) {
+                if (direct) {
+                } else if (fromlog) {
                     const uint32_t n = nlog;
                     uint32_t got = 0;
                     for (uint32_t b0 = 0; b0 < n; b0 += 64) {
@@ -591,20 +630,13 @@ __device__ inline void loop_body(const LoopArgs& a, LoopShared& s) {
                     if (lane < cnt) s.cl[lane] = c0;
                     if (lane + 64 < cnt) s.cl[lane + 64] = c1;
                 }
-                bool same = false;
-                uint32_t below = 0;
-                const uint32_t lm = small_step(cnt, k, r, a, s, nsel, ln, same, below);
+                bool dnext = false;
+                const uint32_t rn = small_step(cnt, k, r, a, s, nsel, ln, dnext);
                 a.M[k - 1] = r;
                 s.logn[nsel] = ln;
-                const uint32_t r_done = r;
-                // next maximum: the highest pushed rank if above r (every rank above
-                // r was empty), else r if its slice refilled, else the larger of the
-                // highest pushed rank and the highest non-empty rank below r
-                const uint32_t pmax = wave_max_u32(lm);
-                const bool refilled = __ballot(same) != 0;
-                if (!refilled) atomicAnd(&s.bits[r >> 5], ~(1u << (r & 31)));
-                r = pmax > r ? pmax : refilled ? r : max(below, pmax);
-                prev_r = r_done;
+                prev_r = r;
+                r = rn;
+                direct = dnext;
                 k = k + 1;
                 sel = nsel;
                 log_ok = ln <= kLog;
@@ -650,6 +682,7 @@ __device__ inline void loop_body(const LoopArgs& a, LoopShared& s) {
             const uint32_t r_done = r;
             r = next_top(s, r, uni(s.d_up) != 0, R);
             prev_r = r_done;
+            direct = false;
             k = k + 1;
             sel ^= 1u;
             nlog = uni(s.logn[sel]);
