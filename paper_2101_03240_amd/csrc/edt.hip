@@ -341,7 +341,7 @@ struct FeatThreshold8 {
 // row spans lpr = Z / 8 lanes, a wave holds 64 / lpr rows. The nearest
 // feature before / after each lane's voxels comes from a max / min scan over
 // the row's lanes.
-constexpr int kZGroups = 2;  // row groups per wave, their loads issued together
+constexpr int kZGroups = 4;  // row groups per wave, their loads issued together
 
 // pass z of one row group: lane li of lpr holds feature bits fb of voxels
 // v0..v0+7 of its row; writes their distances along z
@@ -402,8 +402,11 @@ __global__ __launch_bounds__(256) void edt_pass_z_vec(Feat feat, int64_t rows, i
     for (int q = 0; q < kZGroups; q++) {
         const int64_t row = (wave * kZGroups + q) * rpw + r;
         act[q] = r < rpw && row < rows;
-        v0[q] = row * Z + li * 8;
-        fb[q] = act[q] ? feat.bits8(v0[q]) : 0u;
+        // unconditional load (a lane past the last row reads row 0): a load
+        // under a lane condition would be waited for before the next one
+        v0[q] = (act[q] ? row : 0) * Z + li * 8;
+        const uint32_t b = feat.bits8(v0[q]);
+        fb[q] = act[q] ? b : 0u;
     }
     bool any = false;
 #pragma unroll
