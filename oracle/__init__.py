@@ -66,6 +66,10 @@ def _load():
         fn.restype = i64
     lib.ibipref_steps.argtypes = [P, i64, i64, P, d, P, P, P]
     lib.ibipref_steps.restype = i32
+    lib.ibipref_satmap.argtypes = [P, i64, i64, P, P]
+    lib.ibipref_satmap.restype = i32
+    lib.ibipref_remap_steps.argtypes = [P, P, i64, P, i64, i64, P]
+    lib.ibipref_remap_steps.restype = i32
     lib.ibipref_trap.argtypes = [P, P, i32, i32, i32, P, P, P]
     lib.ibipref_trap.restype = i32
     lib.ibipref_trap_brute.argtypes = [P, P, i32, i32, i32, P]
@@ -158,6 +162,27 @@ def steps(seq, M, c0: float = 2.0) -> dict:
     _check(_load().ibipref_steps(_p(seq), seq.size, K, _p(M), float(c0), _p(n_new), _p(sat), _p(pc)),
            "steps")
     return {"n_new": n_new, "sat": sat, "pc": pc}
+
+
+def satmap(seq, sat) -> np.ndarray:
+    """Saturation map: sat[seq-1] on invaded voxels, 0 on uninvaded pore, -1
+    on solid (Section 2.2.1, Figure 5 left)."""
+    seq = np.ascontiguousarray(seq, dtype=np.int32)
+    sat = np.ascontiguousarray(sat, dtype=np.float64)
+    out = np.empty(seq.shape, dtype=np.float64)
+    _check(_load().ibipref_satmap(_p(seq), seq.size, sat.shape[0], _p(sat), _p(out)), "satmap")
+    return out
+
+
+def remap_steps(seq, seq_after, M, K_after: int) -> np.ndarray:
+    """Squared radius of each re-ranked step after trapping (Section 2.2.3)."""
+    seq = np.ascontiguousarray(seq, dtype=np.int32)
+    sa = np.ascontiguousarray(seq_after, dtype=np.int32)
+    M = np.ascontiguousarray(M, dtype=np.uint32)
+    out = np.empty(int(K_after), dtype=np.uint32)
+    _check(_load().ibipref_remap_steps(_p(seq), _p(sa), seq.size, _p(M), M.shape[0], int(K_after), _p(out)),
+           "remap_steps")
+    return out
 
 
 def trap(seq, outlets) -> dict:

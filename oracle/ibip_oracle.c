@@ -25,6 +25,10 @@
  *                         an explicit candidate set grouped by dt value.
  *   ibipref_steps         Sections 2.2.1-2.2.2: per-step newly invaded counts,
  *                         saturation and Washburn capillary pressure.
+ *   ibipref_satmap        Section 2.2.1, Figure 5 (left): each invaded voxel
+ *                         labelled with the saturation after its step.
+ *   ibipref_remap_steps   Section 2.2.3: the squared radius of every step that
+ *                         survives trapping, in re-ranked order.
  *   ibipref_trap          Section 2.2.3: reverse sweep over the sequence with
  *                         union-find (Masson-style), then dense re-ranking.
  *   ibipref_trap_brute    trapping by definition: one breadth-first search per
@@ -413,6 +417,41 @@ int ibipref_steps(const int32_t* seq, int64_t N, int64_t K, const uint32_t* M, d
         if (pc && M) pc[k - 1] = c0 / sqrt((double)M[k - 1]);
     }
     free(cnt);
+    return REF_OK;
+}
+
+/* Saturation map (Section 2.2.1, Figure 5 left): satmap[v] = sat[seq[v]-1]
+ * for an invaded voxel, 0 for uninvaded pore, -1 on solid, where sat is the
+ * per-step saturation of ibipref_steps for the same labelling. Thresholding
+ * the map as 0 < satmap <= s gives the invaded configuration at saturation s. */
+int ibipref_satmap(const int32_t* seq, int64_t N, int64_t K, const double* sat, double* satmap) {
+    if (!seq || !satmap || N <= 0 || K < 0) return REF_EINVAL;
+    for (int64_t v = 0; v < N; v++) {
+        const int32_t s = seq[v];
+        if (s < 0) satmap[v] = -1.0;
+        else if (s == 0) satmap[v] = 0.0;
+        else if (s > K) return REF_EINVAL;
+        else satmap[v] = sat[s - 1];
+    }
+    return REF_OK;
+}
+
+/* Squared radii after trapping (Section 2.2.3): a re-ranked step k' holds the
+ * voxels of one surviving original step s, and keeps that step's spheres, so
+ * M_after[k'-1] = M[s-1]. seq is the sequence before trapping, seq_after the
+ * re-ranked one (0 where trapped). */
+int ibipref_remap_steps(const int32_t* seq, const int32_t* seq_after, int64_t N, const uint32_t* M, int64_t K,
+                        int64_t K_after, uint32_t* M_after) {
+    if (!seq || !seq_after || !M || !M_after || N <= 0 || K < 0 || K_after < 0) return REF_EINVAL;
+    for (int64_t j = 0; j < K_after; j++) M_after[j] = 0;
+    for (int64_t v = 0; v < N; v++) {
+        const int32_t a = seq_after[v];
+        if (a <= 0) continue;
+        const int32_t s = seq[v];
+        if (a > K_after || s <= 0 || s > K) return REF_EINVAL;
+        if (M_after[a - 1] != 0 && M_after[a - 1] != M[s - 1]) return REF_EINVAL;  /* one step per rank */
+        M_after[a - 1] = M[s - 1];
+    }
     return REF_OK;
 }
 
