@@ -215,6 +215,36 @@ ibip_status ibip_get_steps(ibip_ctx* ctx, uint32_t* M, int64_t* n_new, double* s
                            int64_t capacity);
 
 /*
+ * ibip_saturation -- per-step arrays and the saturation map of any step
+ * labelling (Sections 2.2.1, 2.2.2; Figure 5 left): the sequence written by
+ * ibip_invade, or the re-ranked one of ibip_trap for the trapping-aware curve.
+ * seq:     int32[N] in (-1 solid, 0 uninvaded, 1..K step).
+ * M:       uint32[K] in, squared radius of each step's spheres (needed for pc;
+ *          after trapping, from ibip_remap_steps).
+ * opts:    sigma, theta_rad, voxel_size for pc (NULL: 1, 0, 1); max_steps unused.
+ * n_new, sat, pc: as for ibip_get_steps, K entries each, saturation over all
+ *          pore voxels (seq >= 0). satmap: double[N], -1 on solid, 0 on
+ *          uninvaded pore, else the saturation after the voxel's step, so that
+ *          {0 < satmap <= s} is the invaded configuration at saturation s.
+ * Every array is a caller-owned DEVICE buffer; any output may be NULL.
+ * Errors: EINVAL (a label above K, no pore voxel), ENOMEM.
+ */
+ibip_status ibip_saturation(ibip_ctx* ctx, const int32_t* seq, ibip_dims dims, const uint32_t* M, int64_t K,
+                            const ibip_invade_opts* opts, int64_t* n_new, double* sat, double* pc,
+                            double* satmap);
+
+/*
+ * ibip_remap_steps -- squared radii of the steps that survive trapping
+ * (Section 2.2.3): re-ranked step k' keeps the spheres of the original step
+ * it came from, M_after[k'-1] = M[seq[v]-1] for any voxel v with
+ * seq_after[v] = k'. seq: the sequence before trapping (K steps); seq_after:
+ * the re-ranked sequence of ibip_trap (K_after steps). All DEVICE buffers.
+ * Errors: EINVAL (labels that do not come from one trapping of seq), ENOMEM.
+ */
+ibip_status ibip_remap_steps(ibip_ctx* ctx, const int32_t* seq, const int32_t* seq_after, ibip_dims dims,
+                             const uint32_t* M, int64_t K, int64_t K_after, uint32_t* M_after);
+
+/*
  * ibip_trap -- defender trapping and re-ranking (Section 2.2.3, Figure 7).
  * A voxel invaded at step k (seq[v] = k > 0) is trapped when the defender
  * region just before step k, {pore u : seq[u] == 0 or seq[u] >= k}, holds no

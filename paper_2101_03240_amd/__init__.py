@@ -22,8 +22,8 @@ import ctypes
 import os
 import threading
 
-__all__ = ["edt", "invade", "invade_batch", "Server", "trap", "opening_drainage", "IbipError", "library_path", "load_library",
-           "enable_timing", "get_timing", "reset_timing"]
+__all__ = ["edt", "invade", "invade_batch", "Server", "trap", "saturation", "remap_steps", "opening_drainage",
+           "IbipError", "library_path", "load_library", "enable_timing", "get_timing", "reset_timing"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libibip_hip.so")
@@ -115,6 +115,10 @@ def load_library():
         for fn in (lib.ibip_server_create, lib.ibip_server_submit, lib.ibip_server_poll, lib.ibip_server_wait,
                    lib.ibip_server_cancel, lib.ibip_server_stats_get, lib.ibip_server_destroy):
             fn.restype = i32
+        lib.ibip_saturation.argtypes = [P, P, _Dims, P, i64, ctypes.POINTER(_InvadeOpts), P, P, P, P]
+        lib.ibip_saturation.restype = i32
+        lib.ibip_remap_steps.argtypes = [P, P, P, _Dims, P, i64, i64, P]
+        lib.ibip_remap_steps.restype = i32
         lib.ibip_ctx_enable_timing.argtypes = [P, i32]
         lib.ibip_ctx_get_timing.argtypes = [P, ctypes.POINTER(_Timing)]
         lib.ibip_ctx_reset_timing.argtypes = [P]
@@ -384,6 +388,56 @@ def trap(seq, outlets, seq_trapped: bool = True):
     _check(load_library().ibip_trap(ctx, _ptr(seq), _ptr(outlets), dims, _ptr(tr),
                                     _ptr(st) if st is not None else None, ctypes.byref(K)), ctx)
     return {"trapped": tr, "seq_trapped": st, "K_after": int(K.value)}
+
+
+def _dev_i32(t, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.int32:
+        raise ValueError(f"{name} must be an int32 torch tensor on a GPU device")
+    return t.contiguous()
+
+
+def saturation(seq, M, sigma: float = 1.0, theta_rad: float = 0.0, voxel_size: float = 1.0,
+               satmap: bool = True) -> dict:
+    """Per-step arrays and the saturation map of a step labelling (Sections
+    2.2.1-2.2.2, Figure 5 left): the sequence of ``invade``, or the re-ranked
+    one of ``trap`` with the radii of ``remap_steps`` for the trapping-aware
+    curve. Returns ``n_new``, ``sat``, ``pc`` (K entries) and ``satmap``
+    (float64, -1 solid, 0 uninvaded, else the saturation after the voxel's
+    step)."""
+    torch = _torch()
+    seq = _dev_i32(seq, "seq")
+    dev = seq.device
+    M = M.to(device=dev, dtype=torch.int32).contiguous()
+    K = int(M.numel())
+    dims, _ = _dims_of(seq)
+    ctx = _context(dev)
+    n_new = torch.empty(max(K, 1), dtype=torch.int64, device=dev)
+    sat = torch.empty(max(K, 1), dtype=torch.float64, device=dev)
+    pc = torch.empty(max(K, 1), dtype=torch.float64, device=dev)
+    sm = torch.empty(seq.shape, dtype=torch.float64, device=dev) if satmap else None
+    opts = _InvadeOpts(0, float(sigma), float(theta_rad), float(voxel_size))
+    _check(load_library().ibip_saturation(ctx, _ptr(seq), dims, _ptr(M), K, ctypes.byref(opts), _ptr(n_new),
+                                          _ptr(sat), _ptr(pc), _ptr(sm) if sm is not None else None), ctx)
+    return {"n_new": n_new[:K], "sat": sat[:K], "pc": pc[:K], "satmap": sm}
+
+
+def remap_steps(seq, seq_trapped, M, K_after: int):
+    """Squared radius of each step that survives trapping, in re-ranked order
+    (Section 2.2.3); int32 tensor of K_after entries (uint32 values)."""
+    torch = _torch()
+    seq = _dev_i32(seq, "seq")
+    st = _dev_i32(seq_trapped, "seq_trapped")
+    if st.shape != seq.shape:
+        raise ValueError("seq_trapped must have the shape of seq")
+    dev = seq.device
+    M = M.to(device=dev, dtype=torch.int32).contiguous()
+    dims, _ = _dims_of(seq)
+    ctx = _context(dev)
+    out = torch.empty(max(int(K_after), 1), dtype=torch.int32, device=dev)
+    _check(load_library().ibip_remap_steps(ctx, _ptr(seq), _ptr(st), dims, _ptr(M), int(M.numel()), int(K_after),
+                                           _ptr(out)), ctx)
+    return out[:int(K_after)]
 
 
 def opening_drainage(image, inlets, thresholds):

@@ -26,7 +26,7 @@ HIP_FLAGS = [
     "-I", os.path.join(ROOT, "include"),
 ]
 
-SOURCES = ["api.hip", "edt.hip", "scan.hip", "invade.hip", "trap.hip", "mio.hip", "server.hip"]
+SOURCES = ["api.hip", "edt.hip", "scan.hip", "invade.hip", "trap.hip", "mio.hip", "server.hip", "saturation.hip"]
 
 
 def _compile(src: str) -> str:

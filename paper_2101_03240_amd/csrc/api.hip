@@ -78,22 +78,6 @@ bool dims_ok(ibip_dims d) {
     return nvox(d) < ((int64_t)1 << 31);
 }
 
-namespace {
-
-struct DeviceGuard {
-    int prev = -1;
-    bool ok = true;
-    explicit DeviceGuard(int dev) {
-        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
-    }
-    ~DeviceGuard() {
-        if (prev >= 0) (void)hipSetDevice(prev);
-    }
-};
-
-}  // namespace
-
 }  // namespace ibip
 
 using namespace ibip;

@@ -57,6 +57,19 @@ __device__ inline void block_add_u32(uint32_t* dst, uint32_t v) {
     }
 }
 
+// Makes `dev` current for a scope and restores the previous device after.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
 // One grow-only device allocation.
 struct Buf {
     void* p = nullptr;
@@ -85,6 +98,7 @@ enum BufId {
     B_ACT,         // uint8[2 * tiles] active-tile flags of the reconstruction
     B_CNT,         // uint32 per-sweep change counters
     B_BATCH,       // arena of a batch of jobs
+    B_SATW,        // counts and scan of ibip_saturation
     B_NUM
 };
 

@@ -1,0 +1,159 @@
+// Saturation map and per-step arrays of any step labelling (Sections 2.2.1,
+// 2.2.2; Figure 5 left), and the squared radii that survive trapping
+// (Section 2.2.3), so that the capillary pressure curve can be drawn with or
+// without trapping.
+#include <cmath>
+
+#include "ibip_internal.h"
+
+namespace ibip {
+
+namespace {
+
+inline unsigned blocks(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+// counts[k-1] = voxels labelled k; *n_pore += pore voxels (label >= 0). Lanes
+// of a wave are grouped by label with ballots, and each group adds its size
+// with one atomic (labels of neighbouring voxels repeat).
+__global__ __launch_bounds__(256) void k_count_steps(const int32_t* __restrict__ seq, int64_t n, int64_t K,
+                                                     uint32_t* counts, uint32_t* n_pore, uint32_t* bad) {
+    const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int32_t s = v < n ? seq[v] : -1;
+    const bool act = s > 0 && (int64_t)s <= K;
+    if (v < n && s > 0 && (int64_t)s > K) atomicOr(bad, 1u);
+    const int lane = threadIdx.x & 63;
+    uint64_t pending = __ballot(act);
+    while (pending) {
+        const int leader = __ffsll((unsigned long long)pending) - 1;
+        const int32_t ls = __builtin_amdgcn_readlane(s, leader);
+        const uint64_t same = __ballot(act && s == ls) & pending;
+        if (lane == leader) atomicAdd(&counts[ls - 1], (uint32_t)__popcll(same));
+        pending &= ~same;
+    }
+    block_add_u32(n_pore, v < n && s >= 0 ? 1u : 0u);
+}
+
+__global__ void k_curves(const uint32_t* counts, const uint32_t* excl, const uint32_t* M, int64_t K,
+                         const uint32_t* n_pore, double c0, int64_t* n_new, double* sat, double* pc) {
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k >= K) return;
+    const uint32_t c = counts[k];
+    const double s = (double)(excl[k] + c) / (double)*n_pore;
+    if (n_new) n_new[k] = c;
+    if (sat) sat[k] = s;
+    if (pc) pc[k] = c0 / sqrt((double)M[k]);
+}
+
+__global__ __launch_bounds__(256) void k_satmap(const int32_t* __restrict__ seq, int64_t n, const uint32_t* counts,
+                                                const uint32_t* excl, const uint32_t* n_pore, double* satmap) {
+    const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (v >= n) return;
+    const int32_t s = seq[v];
+    double m = s < 0 ? -1.0 : 0.0;
+    if (s > 0) m = (double)(excl[s - 1] + counts[s - 1]) / (double)*n_pore;
+    satmap[v] = m;
+}
+
+// M_after[seq_after[v]-1] = M[seq[v]-1]: every voxel of a re-ranked step
+// carries the same original step, so the writes agree; a mismatch is flagged.
+__global__ __launch_bounds__(256) void k_remap(const int32_t* __restrict__ seq, const int32_t* __restrict__ after,
+                                               int64_t n, const uint32_t* M, int64_t K, int64_t K_after,
+                                               uint32_t* M_after, uint32_t* bad) {
+    const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (v >= n) return;
+    const int32_t a = after[v];
+    if (a <= 0) return;
+    const int32_t s = seq[v];
+    if ((int64_t)a > K_after || s <= 0 || (int64_t)s > K) {
+        atomicOr(bad, 1u);
+        return;
+    }
+    M_after[a - 1] = M[s - 1];
+}
+
+__global__ __launch_bounds__(256) void k_remap_check(const int32_t* __restrict__ seq,
+                                                     const int32_t* __restrict__ after, int64_t n, const uint32_t* M,
+                                                     int64_t K, const uint32_t* M_after, uint32_t* bad) {
+    const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (v >= n) return;
+    const int32_t a = after[v], s = seq[v];
+    if (a > 0 && s > 0 && (int64_t)s <= K && M_after[a - 1] != M[s - 1]) atomicOr(bad, 1u);
+}
+
+}  // namespace
+
+}  // namespace ibip
+
+using namespace ibip;
+
+extern "C" {
+
+ibip_status ibip_saturation(ibip_ctx* ctx, const int32_t* seq, ibip_dims dims, const uint32_t* M, int64_t K,
+                            const ibip_invade_opts* opts, int64_t* n_new, double* sat, double* pc,
+                            double* satmap) {
+    if (!ctx) return IBIP_EINVAL;
+    if (!seq || !dims_ok(dims) || K < 0 || (K > 0 && pc && !M))
+        return fail(ctx, IBIP_EINVAL, "saturation: bad arguments");
+    DeviceGuard g(ctx->device);
+    hipStream_t s = ctx->stream;
+    const int64_t n = nvox(dims);
+    const double sigma = opts ? opts->sigma : 1.0, theta = opts ? opts->theta_rad : 0.0;
+    const double vs = opts ? opts->voxel_size : 1.0;
+    if (!(vs > 0)) return fail(ctx, IBIP_EINVAL, "saturation: voxel_size must be positive");
+    const double c0 = 2.0 * sigma * cos(theta) / vs;
+    uint32_t* w = (uint32_t*)ensure(ctx, B_SATW, sizeof(uint32_t) * (2 * (size_t)K + 64));
+    uint32_t* partials = (uint32_t*)ensure(ctx, B_SCAN, sizeof(uint32_t) * (K / 1000 + n / 1000 + 64));
+    uint32_t* h = (uint32_t*)pinned(ctx, 4096);
+    if (!w || !partials || !h) return fail(ctx, IBIP_ENOMEM, "saturation: allocation failed");
+    uint32_t* ctl = w;            // [0] n_pore, [1] bad label, [2] scan total
+    uint32_t* counts = w + 64;    // K
+    uint32_t* excl = counts + K;  // K
+    ibip_status rc;
+    if ((rc = hip_check(ctx, hipMemsetAsync(w, 0, sizeof(uint32_t) * (64 + (size_t)K), s), "memset")) != IBIP_OK)
+        return rc;
+    hipLaunchKernelGGL(k_count_steps, dim3(blocks(n)), dim3(256), 0, s, seq, n, K, counts, ctl, ctl + 1);
+    if (K > 0) {
+        if ((rc = hip_check(ctx, hipMemcpyAsync(excl, counts, sizeof(uint32_t) * K, hipMemcpyDeviceToDevice, s),
+                            "copy")) != IBIP_OK)
+            return rc;
+        if ((rc = hip_check(ctx, launch_scan_u32(excl, K, partials, ctl + 2, s), "scan")) != IBIP_OK) return rc;
+        if (n_new || sat || pc)
+            hipLaunchKernelGGL(k_curves, dim3(blocks(K)), dim3(256), 0, s, counts, excl, M, K, ctl, c0, n_new, sat,
+                               pc);
+    }
+    if (satmap) hipLaunchKernelGGL(k_satmap, dim3(blocks(n)), dim3(256), 0, s, seq, n, counts, excl, ctl, satmap);
+    if ((rc = hip_check(ctx, hipMemcpyAsync(h, ctl, sizeof(uint32_t) * 2, hipMemcpyDeviceToHost, s), "copy")) !=
+        IBIP_OK)
+        return rc;
+    if ((rc = hip_check(ctx, hipStreamSynchronize(s), "sync")) != IBIP_OK) return rc;
+    if (h[1]) return fail(ctx, IBIP_EINVAL, "saturation: a label exceeds K");
+    if (h[0] == 0 && K > 0) return fail(ctx, IBIP_EINVAL, "saturation: no pore voxel");
+    return IBIP_OK;
+}
+
+ibip_status ibip_remap_steps(ibip_ctx* ctx, const int32_t* seq, const int32_t* seq_after, ibip_dims dims,
+                             const uint32_t* M, int64_t K, int64_t K_after, uint32_t* M_after) {
+    if (!ctx) return IBIP_EINVAL;
+    if (!seq || !seq_after || !M_after || !dims_ok(dims) || K < 0 || K_after < 0 || (K > 0 && !M))
+        return fail(ctx, IBIP_EINVAL, "remap_steps: bad arguments");
+    DeviceGuard g(ctx->device);
+    hipStream_t s = ctx->stream;
+    const int64_t n = nvox(dims);
+    uint32_t* w = (uint32_t*)ensure(ctx, B_SATW, sizeof(uint32_t) * 64);
+    uint32_t* h = (uint32_t*)pinned(ctx, 4096);
+    if (!w || !h) return fail(ctx, IBIP_ENOMEM, "remap_steps: allocation failed");
+    ibip_status rc;
+    if ((rc = hip_check(ctx, hipMemsetAsync(w, 0, sizeof(uint32_t) * 4, s), "memset")) != IBIP_OK) return rc;
+    if (K_after > 0 &&
+        (rc = hip_check(ctx, hipMemsetAsync(M_after, 0, sizeof(uint32_t) * K_after, s), "memset")) != IBIP_OK)
+        return rc;
+    hipLaunchKernelGGL(k_remap, dim3(blocks(n)), dim3(256), 0, s, seq, seq_after, n, M, K, K_after, M_after, w);
+    hipLaunchKernelGGL(k_remap_check, dim3(blocks(n)), dim3(256), 0, s, seq, seq_after, n, M, K, M_after, w);
+    if ((rc = hip_check(ctx, hipMemcpyAsync(h, w, sizeof(uint32_t), hipMemcpyDeviceToHost, s), "copy")) != IBIP_OK)
+        return rc;
+    if ((rc = hip_check(ctx, hipStreamSynchronize(s), "sync")) != IBIP_OK) return rc;
+    if (h[0]) return fail(ctx, IBIP_EINVAL, "remap_steps: labels do not come from one trapping of this sequence");
+    return IBIP_OK;
+}
+
+}  // extern "C"
