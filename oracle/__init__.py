@@ -64,6 +64,17 @@ def _load():
     for fn in (lib.ibipref_invade_literal, lib.ibipref_invade):
         fn.argtypes = [P, P, i32, i32, i32, i64, P, P, P, P, i64]
         fn.restype = i64
+    for fn in (lib.ibipref_invade_literal_v, lib.ibipref_invade_v):
+        fn.argtypes = [P, P, i32, i32, i32, i64, i32, P, P, P, P, i64]
+        fn.restype = i64
+    lib.ibipref_trap_c.argtypes = [P, P, i32, i32, i32, i32, P, P, P]
+    lib.ibipref_trap_c.restype = i32
+    lib.ibipref_trap_brute_c.argtypes = [P, P, i32, i32, i32, i32, P]
+    lib.ibipref_trap_brute_c.restype = i32
+    lib.ibipref_mio_v.argtypes = [P, P, i32, i32, i32, P, i32, i32, i32, P, P]
+    lib.ibipref_mio_v.restype = i32
+    lib.ibipref_mio_kept_v.argtypes = [P, P, P, i32, i32, i32, ctypes.c_uint32, i32, P]
+    lib.ibipref_mio_kept_v.restype = i64
     lib.ibipref_steps.argtypes = [P, i64, i64, P, d, P, P, P]
     lib.ibipref_steps.restype = i32
     lib.ibipref_satmap.argtypes = [P, i64, i64, P, P]
@@ -133,8 +144,19 @@ def edt_at(img, x: int, y: int, z: int) -> int:
     return int(_load().ibipref_edt_at(_p(img), X, Y, Z, int(x), int(y), int(z)))
 
 
-def invade(img, inlets, max_steps: int = 0, literal: bool = False) -> dict:
-    """Returns dict(seq int32, rad2 uint32, centre_step int32, M uint32[K], K)."""
+INTEGER_BALL = 1  # footnote 1's integer sphere rule (variant)
+MASK_INLETS = 2   # solid inlet voxels contribute no neighbours to the seeds (variant)
+
+
+def _flags(integer_ball: bool, mask_inlets: bool) -> int:
+    return (INTEGER_BALL if integer_ball else 0) | (MASK_INLETS if mask_inlets else 0)
+
+
+def invade(img, inlets, max_steps: int = 0, literal: bool = False, integer_ball: bool = False,
+           mask_inlets: bool = False) -> dict:
+    """Returns dict(seq int32, rad2 uint32, centre_step int32, M uint32[K], K).
+    integer_ball / mask_inlets select the variant readings of the sphere rule
+    and of the seeds."""
     img = _u8(img)
     inl = _u8(inlets)
     if inl.shape != img.shape:
@@ -146,9 +168,9 @@ def invade(img, inlets, max_steps: int = 0, literal: bool = False) -> dict:
     cs = np.empty(img.shape, dtype=np.int32)
     cap = int(N) + 1
     M = np.zeros(cap, dtype=np.uint32)
-    fn = _load().ibipref_invade_literal if literal else _load().ibipref_invade
-    K = _check(fn(_p(img), _p(inl), X, Y, Z, int(max_steps), _p(seq), _p(rad2), _p(cs), _p(M), cap),
-               "invade")
+    fn = _load().ibipref_invade_literal_v if literal else _load().ibipref_invade_v
+    K = _check(fn(_p(img), _p(inl), X, Y, Z, int(max_steps), _flags(integer_ball, mask_inlets), _p(seq), _p(rad2),
+                  _p(cs), _p(M), cap), "invade")
     return {"seq": seq, "rad2": rad2, "centre_step": cs, "M": M[:K].copy(), "K": int(K)}
 
 
@@ -185,24 +207,25 @@ def remap_steps(seq, seq_after, M, K_after: int) -> np.ndarray:
     return out
 
 
-def trap(seq, outlets) -> dict:
+def trap(seq, outlets, conn: int = 6) -> dict:
+    """Trapping with 6- (faces) or 26-connectivity (faces, edges, corners)."""
     seq = np.ascontiguousarray(seq, dtype=np.int32)
     out = _u8(outlets)
     X, Y, Z = _dims(seq)
     trapped = np.empty(seq.shape, dtype=np.uint8)
     st = np.empty(seq.shape, dtype=np.int32)
     ka = ctypes.c_int64(0)
-    _check(_load().ibipref_trap(_p(seq), _p(out), X, Y, Z, _p(trapped), _p(st), ctypes.byref(ka)),
+    _check(_load().ibipref_trap_c(_p(seq), _p(out), X, Y, Z, int(conn), _p(trapped), _p(st), ctypes.byref(ka)),
            "trap")
     return {"trapped": trapped, "seq_trapped": st, "K_after": int(ka.value)}
 
 
-def trap_brute(seq, outlets) -> np.ndarray:
+def trap_brute(seq, outlets, conn: int = 6) -> np.ndarray:
     seq = np.ascontiguousarray(seq, dtype=np.int32)
     out = _u8(outlets)
     X, Y, Z = _dims(seq)
     trapped = np.empty(seq.shape, dtype=np.uint8)
-    _check(_load().ibipref_trap_brute(_p(seq), _p(out), X, Y, Z, _p(trapped)), "trap_brute")
+    _check(_load().ibipref_trap_brute_c(_p(seq), _p(out), X, Y, Z, int(conn), _p(trapped)), "trap_brute")
     return trapped
 
 
@@ -215,23 +238,24 @@ def rerank(seq, trapped) -> tuple[np.ndarray, int]:
     return st, int(ka.value)
 
 
-def mio(img, inlets, thresholds, brute_erosion: bool = False) -> dict:
+def mio(img, inlets, thresholds, brute_erosion: bool = False, mask_inlets: bool = False) -> dict:
     img = _u8(img)
     inl = _u8(inlets)
     X, Y, Z = _dims(img)
     T = np.ascontiguousarray(thresholds, dtype=np.uint32)
     r2 = np.empty(img.shape, dtype=np.uint32)
     sat = np.zeros(T.shape[0], dtype=np.float64)
-    _check(_load().ibipref_mio(_p(img), _p(inl), X, Y, Z, _p(T), int(T.shape[0]), int(brute_erosion),
-                               _p(r2), _p(sat)), "mio")
+    _check(_load().ibipref_mio_v(_p(img), _p(inl), X, Y, Z, _p(T), int(T.shape[0]), int(brute_erosion),
+                                 _flags(False, mask_inlets), _p(r2), _p(sat)), "mio")
     return {"mio_r2": r2, "mio_sat": sat}
 
 
-def mio_kept(img, inlets, dt2, T: int) -> np.ndarray:
+def mio_kept(img, inlets, dt2, T: int, mask_inlets: bool = False) -> np.ndarray:
     img = _u8(img)
     inl = _u8(inlets)
     d = np.ascontiguousarray(dt2, dtype=np.uint32)
     X, Y, Z = _dims(img)
     kept = np.empty(img.shape, dtype=np.uint8)
-    _check(_load().ibipref_mio_kept(_p(img), _p(inl), _p(d), X, Y, Z, int(T), _p(kept)), "mio_kept")
+    _check(_load().ibipref_mio_kept_v(_p(img), _p(inl), _p(d), X, Y, Z, int(T), _flags(False, mask_inlets),
+                                      _p(kept)), "mio_kept")
     return kept.astype(bool)

@@ -49,6 +49,14 @@
  *   - seq = -1 on solid, 0 on uninvaded pore, k >= 1 = step of invasion.
  *   - 6-connectivity (face neighbours) throughout.
  *
+ * Variants (the other readings of ambiguous passages, selected by flags):
+ *   IBIPREF_INTEGER_BALL  footnote 1's integer sphere: radius floor(sqrt(M)),
+ *                         ball {|v-c|^2 <= floor(sqrt(M))^2} restricted to pore.
+ *   IBIPREF_MASK_INLETS   solid inlet voxels contribute no neighbours to the
+ *                         seeds: Q0 = ((I & P) U N6(I & P)) & P (also for MIO).
+ *   connectivity 26       trapping connects voxels that share a face, an edge
+ *                         or a corner.
+ *
  * Status codes: 0 ok, -1 invalid argument, -3 no solid voxel (the distance
  * transform is undefined), -5 capacity (output array too short),
  * -2 out of memory.
@@ -66,6 +74,9 @@
 
 static const uint64_t REF_INF = (uint64_t)1 << 62;
 
+#define IBIPREF_INTEGER_BALL 1
+#define IBIPREF_MASK_INLETS 2
+
 static int dims_ok(int X, int Y, int Z) {
     return X > 0 && Y > 0 && Z > 0 && (int64_t)X * Y * Z < ((int64_t)1 << 32);
 }
@@ -81,6 +92,26 @@ static int neighbours6(int X, int Y, int Z, int64_t v, int64_t out[6]) {
     if (z > 0) out[n++] = v - 1;
     if (z < Z - 1) out[n++] = v + 1;
     return n;
+}
+
+/* the (up to) 26 voxels sharing a face, an edge or a corner with v */
+static int neighbours26(int X, int Y, int Z, int64_t v, int64_t out[26]) {
+    int64_t z = v % Z, y = (v / Z) % Y, x = v / ((int64_t)Y * Z);
+    int n = 0;
+    for (int dx = -1; dx <= 1; dx++)
+        for (int dy = -1; dy <= 1; dy++)
+            for (int dz = -1; dz <= 1; dz++) {
+                if (!dx && !dy && !dz) continue;
+                int64_t a = x + dx, b = y + dy, c = z + dz;
+                if (a < 0 || a >= X || b < 0 || b >= Y || c < 0 || c >= Z) continue;
+                out[n++] = (a * Y + b) * Z + c;
+            }
+    return n;
+}
+
+/* face neighbours (conn 6) or all 26 neighbours (conn 26) */
+static int neighbours(int conn, int X, int Y, int Z, int64_t v, int64_t out[26]) {
+    return conn == 26 ? neighbours26(X, Y, Z, v, out) : neighbours6(X, Y, Z, v, out);
 }
 
 /* largest integer q with q*q <= a */
@@ -221,18 +252,21 @@ int64_t ibipref_edt_at(const uint8_t* img, int X, int Y, int Z, int x, int y, in
 /* Sphere insertion (Section 2.1, footnote 1; Figure 2(h), (l)).             */
 /* ------------------------------------------------------------------------- */
 
-/* write `step` (and `m` into rad2) into every uninvaded voxel of B(c, m) */
+/* write `step` (and `m` into rad2) into every uninvaded voxel of B(c, m);
+   with the integer rule, into every uninvaded pore voxel with |v - c|^2 <=
+   floor(sqrt(m))^2 instead (solid voxels hold -1 and are never written) */
 static void insert_sphere(int X, int Y, int Z, int64_t c, uint32_t m, int32_t step,
-                          int32_t* seq, uint32_t* rad2) {
+                          int32_t* seq, uint32_t* rad2, int integer_ball) {
     int cz = (int)(c % Z), cy = (int)((c / Z) % Y), cx = (int)(c / ((int64_t)Y * Z));
-    int64_t R = isqrt64((int64_t)m - 1); /* largest R with R*R < m */
+    int64_t R = integer_ball ? isqrt64((int64_t)m) : isqrt64((int64_t)m - 1);
+    int64_t lim = integer_ball ? R * R + 1 : (int64_t)m; /* ball = {d^2 < lim} */
     for (int64_t dx = -R; dx <= R; dx++) {
         int64_t x = cx + dx; if (x < 0 || x >= X) continue;
         for (int64_t dy = -R; dy <= R; dy++) {
             int64_t y = cy + dy; if (y < 0 || y >= Y) continue;
             for (int64_t dz = -R; dz <= R; dz++) {
                 int64_t z = cz + dz; if (z < 0 || z >= Z) continue;
-                if (dx * dx + dy * dy + dz * dz >= (int64_t)m) continue;
+                if (dx * dx + dy * dy + dz * dz >= lim) continue;
                 int64_t v = (x * Y + y) * Z + z;
                 if (seq[v] == 0) { seq[v] = step; if (rad2) rad2[v] = m; }
             }
@@ -253,9 +287,9 @@ static void init_seq(const uint8_t* img, int64_t N, int32_t* seq, uint32_t* rad2
 /* Returns the number of steps K (>= 0) or a negative status.                */
 /* M_out[k-1] receives the squared radius inserted at step k.                */
 /* ------------------------------------------------------------------------- */
-int64_t ibipref_invade_literal(const uint8_t* img, const uint8_t* inlets, int X, int Y, int Z,
-                               int64_t max_steps, int32_t* seq, uint32_t* rad2,
-                               int32_t* centre_step, uint32_t* M_out, int64_t M_cap) {
+int64_t ibipref_invade_literal_v(const uint8_t* img, const uint8_t* inlets, int X, int Y, int Z,
+                                 int64_t max_steps, int flags, int32_t* seq, uint32_t* rad2,
+                                 int32_t* centre_step, uint32_t* M_out, int64_t M_cap) {
     if (!img || !inlets || !seq || !dims_ok(X, Y, Z)) return REF_EINVAL;
     int64_t N = (int64_t)X * Y * Z;
     uint32_t* dt = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)N);
@@ -265,7 +299,7 @@ int64_t ibipref_invade_literal(const uint8_t* img, const uint8_t* inlets, int X,
     if (!dt || !inl || !cand || !C) { free(dt); free(inl); free(cand); free(C); return REF_ENOMEM; }
     int st = ibipref_edt(img, X, Y, Z, dt);
     if (st != REF_OK) { free(dt); free(inl); free(cand); free(C); return st; }
-    for (int64_t i = 0; i < N; i++) inl[i] = inlets[i] != 0;
+    for (int64_t i = 0; i < N; i++) inl[i] = inlets[i] != 0 && (!(flags & IBIPREF_MASK_INLETS) || img[i]);
     init_seq(img, N, seq, rad2, centre_step);
     int64_t step = 0;
     for (;;) {
@@ -290,7 +324,8 @@ int64_t ibipref_invade_literal(const uint8_t* img, const uint8_t* inlets, int X,
             M_out[step - 1] = M;
         }
         /* (h) insert spheres at every maximum, only into uninvaded voxels */
-        for (int64_t i = 0; i < nc; i++) insert_sphere(X, Y, Z, C[i], M, (int32_t)step, seq, rad2);
+        for (int64_t i = 0; i < nc; i++)
+            insert_sphere(X, Y, Z, C[i], M, (int32_t)step, seq, rad2, flags & IBIPREF_INTEGER_BALL);
         /* (i) add the centres to the inlets image and zero dt there */
         for (int64_t i = 0; i < nc; i++) {
             inl[C[i]] = 1; dt[C[i]] = 0;
@@ -299,6 +334,12 @@ int64_t ibipref_invade_literal(const uint8_t* img, const uint8_t* inlets, int X,
     }
     free(dt); free(inl); free(cand); free(C);
     return step;
+}
+
+int64_t ibipref_invade_literal(const uint8_t* img, const uint8_t* inlets, int X, int Y, int Z,
+                               int64_t max_steps, int32_t* seq, uint32_t* rad2,
+                               int32_t* centre_step, uint32_t* M_out, int64_t M_cap) {
+    return ibipref_invade_literal_v(img, inlets, X, Y, Z, max_steps, 0, seq, rad2, centre_step, M_out, M_cap);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -321,9 +362,9 @@ static int vlist_push(vlist* l, int64_t v) {
     return 1;
 }
 
-int64_t ibipref_invade(const uint8_t* img, const uint8_t* inlets, int X, int Y, int Z,
-                       int64_t max_steps, int32_t* seq, uint32_t* rad2,
-                       int32_t* centre_step, uint32_t* M_out, int64_t M_cap) {
+int64_t ibipref_invade_v(const uint8_t* img, const uint8_t* inlets, int X, int Y, int Z,
+                         int64_t max_steps, int flags, int32_t* seq, uint32_t* rad2,
+                         int32_t* centre_step, uint32_t* M_out, int64_t M_cap) {
     if (!img || !inlets || !seq || !dims_ok(X, Y, Z)) return REF_EINVAL;
     int64_t N = (int64_t)X * Y * Z;
     uint32_t* dt = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)N);
@@ -339,7 +380,7 @@ int64_t ibipref_invade(const uint8_t* img, const uint8_t* inlets, int X, int Y, 
     int64_t rc = 0;
     /* initial candidates: inlets and their face neighbours, pore only */
     for (int64_t v = 0; v < N; v++) {
-        if (!inlets[v]) continue;
+        if (!inlets[v] || ((flags & IBIPREF_MASK_INLETS) && !img[v])) continue;
         int64_t nb[7]; int n = neighbours6(X, Y, Z, v, nb); nb[n++] = v;
         for (int j = 0; j < n; j++) {
             int64_t u = nb[j];
@@ -367,7 +408,7 @@ int64_t ibipref_invade(const uint8_t* img, const uint8_t* inlets, int X, int Y, 
         for (int64_t i = 0; i < cur.n; i++) {
             int64_t c = cur.v[i];
             if (centre_step) centre_step[c] = (int32_t)step;
-            insert_sphere(X, Y, Z, c, M, (int32_t)step, seq, rad2);
+            insert_sphere(X, Y, Z, c, M, (int32_t)step, seq, rad2, flags & IBIPREF_INTEGER_BALL);
         }
         for (int64_t i = 0; i < cur.n; i++) {
             int64_t nb[6]; int n = neighbours6(X, Y, Z, cur.v[i], nb);
@@ -388,6 +429,12 @@ done:
     for (uint32_t g = 0; g <= maxdt; g++) free(group[g].v);
     free(group); free(dt); free(seen);
     return rc;
+}
+
+int64_t ibipref_invade(const uint8_t* img, const uint8_t* inlets, int X, int Y, int Z,
+                       int64_t max_steps, int32_t* seq, uint32_t* rad2,
+                       int32_t* centre_step, uint32_t* M_out, int64_t M_cap) {
+    return ibipref_invade_v(img, inlets, X, Y, Z, max_steps, 0, seq, rad2, centre_step, M_out, M_cap);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -494,9 +541,9 @@ static int rerank(const int32_t* seq, const uint8_t* trapped, int64_t N, int64_t
     return REF_OK;
 }
 
-int ibipref_trap(const int32_t* seq, const uint8_t* outlets, int X, int Y, int Z,
-                 uint8_t* trapped, int32_t* seq_trapped, int64_t* K_after) {
-    if (!seq || !outlets || !trapped || !dims_ok(X, Y, Z)) return REF_EINVAL;
+int ibipref_trap_c(const int32_t* seq, const uint8_t* outlets, int X, int Y, int Z, int conn,
+                   uint8_t* trapped, int32_t* seq_trapped, int64_t* K_after) {
+    if (!seq || !outlets || !trapped || !dims_ok(X, Y, Z) || (conn != 6 && conn != 26)) return REF_EINVAL;
     int64_t N = (int64_t)X * Y * Z;
     int64_t K = 0;
     for (int64_t v = 0; v < N; v++) if (seq[v] > K) K = seq[v];
@@ -525,7 +572,7 @@ int ibipref_trap(const int32_t* seq, const uint8_t* outlets, int X, int Y, int Z
     /* the never-invaded pore is defender at every step */
     for (int64_t v = 0; v < N; v++) {
         if (seq[v] != 0) continue;
-        int64_t nb[6]; int n = neighbours6(X, Y, Z, v, nb);
+        int64_t nb[26]; int n = neighbours(conn, X, Y, Z, v, nb);
         for (int j = 0; j < n; j++) if (seq[nb[j]] == 0) uf_union(parent, flag, v, nb[j]);
     }
     /* thresholds in decreasing order: at level k the defender region gains
@@ -533,7 +580,7 @@ int ibipref_trap(const int32_t* seq, const uint8_t* outlets, int X, int Y, int Z
     for (int64_t k = K; k >= 1; k--) {
         for (int64_t i = start[k]; i < start[k + 1]; i++) {
             int64_t v = order[i];
-            int64_t nb[6]; int n = neighbours6(X, Y, Z, v, nb);
+            int64_t nb[26]; int n = neighbours(conn, X, Y, Z, v, nb);
             for (int j = 0; j < n; j++) {
                 int32_t s = seq[nb[j]];
                 if (s == 0 || s >= k) uf_union(parent, flag, v, nb[j]);
@@ -549,11 +596,16 @@ int ibipref_trap(const int32_t* seq, const uint8_t* outlets, int X, int Y, int Z
     return st;
 }
 
+int ibipref_trap(const int32_t* seq, const uint8_t* outlets, int X, int Y, int Z,
+                 uint8_t* trapped, int32_t* seq_trapped, int64_t* K_after) {
+    return ibipref_trap_c(seq, outlets, X, Y, Z, 6, trapped, seq_trapped, K_after);
+}
+
 /* Trapping by definition: for every invaded voxel v, a breadth-first search
    inside D_{seq[v]} from v; trapped if it reaches no outlet voxel. */
-int ibipref_trap_brute(const int32_t* seq, const uint8_t* outlets, int X, int Y, int Z,
-                       uint8_t* trapped) {
-    if (!seq || !outlets || !trapped || !dims_ok(X, Y, Z)) return REF_EINVAL;
+int ibipref_trap_brute_c(const int32_t* seq, const uint8_t* outlets, int X, int Y, int Z, int conn,
+                         uint8_t* trapped) {
+    if (!seq || !outlets || !trapped || !dims_ok(X, Y, Z) || (conn != 6 && conn != 26)) return REF_EINVAL;
     int64_t N = (int64_t)X * Y * Z;
     int64_t* queue = (int64_t*)malloc(sizeof(int64_t) * (size_t)N);
     uint8_t* vis = (uint8_t*)malloc((size_t)N);
@@ -569,7 +621,7 @@ int ibipref_trap_brute(const int32_t* seq, const uint8_t* outlets, int X, int Y,
         while (qh < qt && !reached) {
             int64_t u = queue[qh++];
             if (outlets[u]) { reached = 1; break; }
-            int64_t nb[6]; int n = neighbours6(X, Y, Z, u, nb);
+            int64_t nb[26]; int n = neighbours(conn, X, Y, Z, u, nb);
             for (int j = 0; j < n; j++) {
                 int64_t w = nb[j];
                 if (vis[w]) continue;
@@ -580,6 +632,10 @@ int ibipref_trap_brute(const int32_t* seq, const uint8_t* outlets, int X, int Y,
     }
     free(queue); free(vis);
     return REF_OK;
+}
+
+int ibipref_trap_brute(const int32_t* seq, const uint8_t* outlets, int X, int Y, int Z, uint8_t* trapped) {
+    return ibipref_trap_brute_c(seq, outlets, X, Y, Z, 6, trapped);
 }
 
 /* Dense re-ranking for a given trapped mask (exposed for tests). */
@@ -602,9 +658,18 @@ int ibipref_rerank(const int32_t* seq, const uint8_t* trapped, int64_t N,
 /* `brute_erosion` != 0 checks each ball voxel by voxel instead of reading   */
 /* the distance transform (tiny images only).                                */
 /* ------------------------------------------------------------------------- */
-int ibipref_mio(const uint8_t* img, const uint8_t* inlets, int X, int Y, int Z,
-                const uint32_t* T, int32_t n, int brute_erosion,
-                uint32_t* mio_r2, double* mio_sat) {
+/* inlet seed test of the opening (the same Q0 as the invasion) */
+static int mio_seed(const uint8_t* img, const uint8_t* inlets, int X, int Y, int Z, int64_t v, int flags) {
+    const int mask = flags & IBIPREF_MASK_INLETS;
+    if (inlets[v] && (!mask || img[v])) return 1;
+    int64_t nb[6]; int nn = neighbours6(X, Y, Z, v, nb);
+    for (int j = 0; j < nn; j++) if (inlets[nb[j]] && (!mask || img[nb[j]])) return 1;
+    return 0;
+}
+
+int ibipref_mio_v(const uint8_t* img, const uint8_t* inlets, int X, int Y, int Z,
+                  const uint32_t* T, int32_t n, int brute_erosion, int flags,
+                  uint32_t* mio_r2, double* mio_sat) {
     if (!img || !inlets || !T || n < 0 || !mio_r2 || !dims_ok(X, Y, Z)) return REF_EINVAL;
     for (int32_t i = 0; i < n; i++) if (T[i] == 0 || (i > 0 && T[i] >= T[i - 1])) return REF_EINVAL;
     int64_t N = (int64_t)X * Y * Z;
@@ -644,12 +709,7 @@ int ibipref_mio(const uint8_t* img, const uint8_t* inlets, int X, int Y, int Z,
         memset(kept, 0, (size_t)N);
         for (int64_t v = 0; v < N; v++) {
             if (!er[v] || kept[v]) continue;
-            int seed = inlets[v] != 0;
-            if (!seed) {
-                int64_t nb[6]; int nn = neighbours6(X, Y, Z, v, nb);
-                for (int j = 0; j < nn; j++) if (inlets[nb[j]]) { seed = 1; break; }
-            }
-            if (seed) { kept[v] = 1; queue[qt++] = v; }
+            if (mio_seed(img, inlets, X, Y, Z, v, flags)) { kept[v] = 1; queue[qt++] = v; }
         }
         while (qh < qt) {
             int64_t u = queue[qh++];
@@ -686,11 +746,17 @@ int ibipref_mio(const uint8_t* img, const uint8_t* inlets, int X, int Y, int Z,
     return REF_OK;
 }
 
+int ibipref_mio(const uint8_t* img, const uint8_t* inlets, int X, int Y, int Z,
+                const uint32_t* T, int32_t n, int brute_erosion,
+                uint32_t* mio_r2, double* mio_sat) {
+    return ibipref_mio_v(img, inlets, X, Y, Z, T, n, brute_erosion, 0, mio_r2, mio_sat);
+}
+
 /* The MIO kept set at one squared radius T: eroded pore voxels 6-connected
    (inside the eroded set) to the inlet candidates. Exposed for the exact
    IBIP / MIO invariant tests. Returns the number of kept voxels. */
-int64_t ibipref_mio_kept(const uint8_t* img, const uint8_t* inlets, const uint32_t* dt2,
-                         int X, int Y, int Z, uint32_t T, uint8_t* kept) {
+int64_t ibipref_mio_kept_v(const uint8_t* img, const uint8_t* inlets, const uint32_t* dt2,
+                           int X, int Y, int Z, uint32_t T, int flags, uint8_t* kept) {
     if (!img || !inlets || !dt2 || !kept || !dims_ok(X, Y, Z)) return REF_EINVAL;
     int64_t N = (int64_t)X * Y * Z;
     int64_t* queue = (int64_t*)malloc(sizeof(int64_t) * (size_t)N);
@@ -699,12 +765,7 @@ int64_t ibipref_mio_kept(const uint8_t* img, const uint8_t* inlets, const uint32
     int64_t qh = 0, qt = 0;
     for (int64_t v = 0; v < N; v++) {
         if (!img[v] || dt2[v] < T) continue;
-        int seed = inlets[v] != 0;
-        if (!seed) {
-            int64_t nb[6]; int nn = neighbours6(X, Y, Z, v, nb);
-            for (int j = 0; j < nn; j++) if (inlets[nb[j]]) { seed = 1; break; }
-        }
-        if (seed) { kept[v] = 1; queue[qt++] = v; }
+        if (mio_seed(img, inlets, X, Y, Z, v, flags)) { kept[v] = 1; queue[qt++] = v; }
     }
     while (qh < qt) {
         int64_t u = queue[qh++];
@@ -716,4 +777,9 @@ int64_t ibipref_mio_kept(const uint8_t* img, const uint8_t* inlets, const uint32
     }
     free(queue);
     return qt;
+}
+
+int64_t ibipref_mio_kept(const uint8_t* img, const uint8_t* inlets, const uint32_t* dt2,
+                         int X, int Y, int Z, uint32_t T, uint8_t* kept) {
+    return ibipref_mio_kept_v(img, inlets, dt2, X, Y, Z, T, 0, kept);
 }
