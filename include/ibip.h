@@ -88,6 +88,22 @@ typedef struct {
     int64_t wide_centres;   /* centres of the steps run by the whole-GPU kernel */
 } ibip_timing;
 
+/* Readings of passages the paper leaves ambiguous, for the following calls
+   on this context (default 0: the strict sphere, literal inlets, 6-connected
+   trapping).
+   IBIP_READ_INTEGER_BALL  footnote 1 of Section 2.1: a sphere of integer
+       radius floor(sqrt(M)), ball {|v - c|^2 <= floor(sqrt(M))^2} restricted to
+       pore, instead of {|v - c|^2 < M} (ibip_invade painting).
+   IBIP_READ_MASK_INLETS   solid inlet voxels contribute no neighbours to the
+       seed set (ibip_invade and the seeds of ibip_opening_drainage).
+   IBIP_READ_TRAP26        ibip_trap connects voxels sharing a face, an edge or
+       a corner (26-connectivity) instead of a face only.
+   Batches and the server always use the default readings. */
+#define IBIP_READ_INTEGER_BALL 1u
+#define IBIP_READ_MASK_INLETS 2u
+#define IBIP_READ_TRAP26 4u
+ibip_status ibip_ctx_set_readings(ibip_ctx* ctx, uint32_t flags);
+
 ibip_status ibip_ctx_enable_timing(ibip_ctx* ctx, int32_t enable);
 ibip_status ibip_ctx_get_timing(const ibip_ctx* ctx, ibip_timing* out);
 ibip_status ibip_ctx_reset_timing(ibip_ctx* ctx);

@@ -119,6 +119,8 @@ def load_library():
         lib.ibip_saturation.restype = i32
         lib.ibip_remap_steps.argtypes = [P, P, P, _Dims, P, i64, i64, P]
         lib.ibip_remap_steps.restype = i32
+        lib.ibip_ctx_set_readings.argtypes = [P, ctypes.c_uint32]
+        lib.ibip_ctx_set_readings.restype = i32
         lib.ibip_ctx_enable_timing.argtypes = [P, i32]
         lib.ibip_ctx_get_timing.argtypes = [P, ctypes.POINTER(_Timing)]
         lib.ibip_ctx_reset_timing.argtypes = [P]
@@ -154,6 +156,18 @@ def _context(device) -> ctypes.c_void_p:
     stream = torch.cuda.current_stream(idx).cuda_stream
     lib.ibip_ctx_set_stream(ctx, ctypes.c_void_p(stream))
     return ctx
+
+
+READ_INTEGER_BALL, READ_MASK_INLETS, READ_TRAP26 = 1, 2, 4
+
+
+def _readings(ctx, integer_ball: bool = False, mask_inlets: bool = False, connectivity: int = 6):
+    """Set the context's readings of the ambiguous passages for the next call."""
+    if connectivity not in (6, 26):
+        raise ValueError("connectivity must be 6 or 26")
+    flags = ((READ_INTEGER_BALL if integer_ball else 0) | (READ_MASK_INLETS if mask_inlets else 0) |
+             (READ_TRAP26 if connectivity == 26 else 0))
+    _check(load_library().ibip_ctx_set_readings(ctx, flags), ctx)
 
 
 def _check(st: int, ctx):
@@ -198,11 +212,14 @@ def edt(image):
 
 
 def invade(image, inlets, max_steps: int = 0, sigma: float = 1.0, theta_rad: float = 0.0,
-           voxel_size: float = 1.0, rad2: bool = True, centre_step: bool = True, steps: bool = True):
+           voxel_size: float = 1.0, rad2: bool = True, centre_step: bool = True, steps: bool = True,
+           integer_ball: bool = False, mask_inlets: bool = False):
     """The invasion loop of Section 2.1 with the per-step arrays of Sections
     2.2.1-2.2.2. Returns a dict with ``seq`` (int32: -1 solid, 0 uninvaded,
     k = step), ``rad2``, ``centre_step``, ``K`` and, when ``steps``, the
-    per-step ``M``, ``n_new``, ``sat`` and ``pc`` (device tensors)."""
+    per-step ``M``, ``n_new``, ``sat`` and ``pc`` (device tensors).
+    ``integer_ball`` paints footnote 1's integer sphere; ``mask_inlets`` lets
+    only pore inlet voxels seed (variant readings)."""
     torch = _torch()
     image = _dev_u8(image, "image")
     inlets = _dev_u8(inlets, "inlets")
@@ -211,6 +228,7 @@ def invade(image, inlets, max_steps: int = 0, sigma: float = 1.0, theta_rad: flo
     dims, shape = _dims_of(image)
     dev = image.device
     ctx = _context(dev)
+    _readings(ctx, integer_ball=integer_ball, mask_inlets=mask_inlets)
     lib = load_library()
     seq = torch.empty(image.shape, dtype=torch.int32, device=dev)
     r2 = torch.empty(image.shape, dtype=torch.int32, device=dev) if rad2 else None
@@ -369,9 +387,10 @@ class Server:
         self.close()
 
 
-def trap(seq, outlets, seq_trapped: bool = True):
+def trap(seq, outlets, seq_trapped: bool = True, connectivity: int = 6):
     """Defender trapping and re-ranking (Section 2.2.3). Returns a dict with
-    ``trapped`` (uint8), ``seq_trapped`` (int32) and ``K_after``."""
+    ``trapped`` (uint8), ``seq_trapped`` (int32) and ``K_after``.
+    ``connectivity`` 26 connects voxels across edges and corners (variant)."""
     torch = _torch()
     if not isinstance(seq, torch.Tensor) or not seq.is_cuda or seq.dtype != torch.int32:
         raise ValueError("seq must be an int32 torch tensor on a GPU device")
@@ -382,6 +401,7 @@ def trap(seq, outlets, seq_trapped: bool = True):
     dims, shape = _dims_of(seq)
     dev = seq.device
     ctx = _context(dev)
+    _readings(ctx, connectivity=connectivity)
     tr = torch.empty(seq.shape, dtype=torch.uint8, device=dev)
     st = torch.empty(seq.shape, dtype=torch.int32, device=dev) if seq_trapped else None
     K = ctypes.c_int64(0)
@@ -440,10 +460,11 @@ def remap_steps(seq, seq_trapped, M, K_after: int):
     return out[:int(K_after)]
 
 
-def opening_drainage(image, inlets, thresholds):
+def opening_drainage(image, inlets, thresholds, mask_inlets: bool = False):
     """Pressure-based drainage by morphological image opening (Section 2.4.1)
     at the squared radii ``thresholds`` (strictly decreasing, >= 1). Returns a
-    dict with ``mio_r2`` (int32 bits of uint32) and ``mio_sat`` (list)."""
+    dict with ``mio_r2`` (int32 bits of uint32) and ``mio_sat`` (list).
+    ``mask_inlets``: only pore inlet voxels seed (variant reading)."""
     torch = _torch()
     image = _dev_u8(image, "image")
     inlets = _dev_u8(inlets, "inlets")
@@ -452,6 +473,7 @@ def opening_drainage(image, inlets, thresholds):
     dims, shape = _dims_of(image)
     dev = image.device
     ctx = _context(dev)
+    _readings(ctx, mask_inlets=mask_inlets)
     T = [int(t) for t in thresholds]
     arr = (ctypes.c_uint32 * max(len(T), 1))(*T)
     sat = (ctypes.c_double * max(len(T), 1))()

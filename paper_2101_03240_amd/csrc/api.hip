@@ -84,6 +84,14 @@ using namespace ibip;
 
 extern "C" {
 
+ibip_status ibip_ctx_set_readings(ibip_ctx* ctx, uint32_t flags) {
+    if (!ctx) return IBIP_EINVAL;
+    if (flags & ~(IBIP_READ_INTEGER_BALL | IBIP_READ_MASK_INLETS | IBIP_READ_TRAP26))
+        return fail(ctx, IBIP_EINVAL, "set_readings: unknown flag");
+    ctx->readings = flags;
+    return IBIP_OK;
+}
+
 ibip_status ibip_ctx_create(ibip_ctx** out, int32_t device, void* stream) {
     if (!out) return IBIP_EINVAL;
     *out = nullptr;

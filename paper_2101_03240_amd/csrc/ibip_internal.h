@@ -166,6 +166,7 @@ struct ibip_ctx {
     int64_t last_K = -1;
     int64_t last_n_pore = 0;
     bool have_steps = false;
+    uint32_t readings = 0;         // IBIP_READ_* flags for the following calls
 };
 
 namespace ibip {
@@ -203,7 +204,7 @@ hipError_t launch_scan_u32(uint32_t* data, int64_t n, uint32_t* partials, uint32
 // is derived from a step image: 0 on solid (seq < 0), 0xFFFFFFFF on uninvaded
 // pore (seq == 0), seq[v] on invaded voxels. Iterates to the fixed point;
 // *n_iter receives the number of sweeps.
-ibip_status reconstruct(ibip_ctx* ctx, const int32_t* seq, const uint32_t* cap32, ibip_dims d,
+ibip_status reconstruct(ibip_ctx* ctx, const int32_t* seq, const uint32_t* cap32, bool conn26, ibip_dims d,
                         uint32_t* w, int* n_iter);
 
 ibip_status run_invade(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlets, ibip_dims d,

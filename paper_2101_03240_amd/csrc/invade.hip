@@ -170,11 +170,12 @@ __device__ inline void push_global(bool active, uint32_t u, uint32_t rr, uint32_
 }
 
 // Seeds: Q0 = (inlets U their face neighbours) restricted to pore.
+// mask: a solid inlet voxel (rank 0) seeds nothing (the masked reading).
 __global__ __launch_bounds__(256) void k_seed(const uint8_t* __restrict__ inlets, uint32_t* key, int X, int Y,
-                                              int Z, uint32_t* tail, uint32_t* bucket) {
+                                              int Z, uint32_t* tail, uint32_t* bucket, bool mask) {
     const int64_t n = (int64_t)X * Y * Z;
     const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const bool inl = v < n && inlets[v] != 0;
+    const bool inl = v < n && inlets[v] != 0 && (!mask || (key[v] & kRankMask) != 0);
     if (!__any(inl)) return;
     const int64_t yz = (int64_t)Y * Z;
     int z = 0, y = 0, x = 0;
@@ -773,7 +774,19 @@ struct PaintArgs {
     uint32_t* full;
     uint32_t* n_full;
     int X, Y, Z;
+    bool integer_ball;  // footnote 1's integer sphere instead of the strict ball
 };
+
+// The painted ball of a centre of squared distance m is {|o|^2 < ball_m(m)}:
+// m itself (the strict ball), or floor(sqrt(m))^2 + 1, i.e. the integer sphere
+// {|o|^2 <= floor(sqrt(m))^2}. The integer ball can reach solid voxels when m
+// is a perfect square; they hold -1, below every step, so atomicMin leaves
+// them. The shell trick holds for any non-decreasing ball_m.
+__device__ inline uint32_t ball_m(const PaintArgs& a, uint32_t m) {
+    if (!a.integer_ball) return m;
+    const uint32_t q = isqrt_u32(m);
+    return q * q + 1;
+}
 
 // Stamps go out in groups of kStampGroup: the current values of the whole
 // group are loaded together (a slot with nothing to stamp loads a valid
@@ -803,7 +816,7 @@ __global__ __launch_bounds__(256) void k_paint_shell(PaintArgs a) {
     const int32_t k = a.state[c];
     if (k <= 0) return;
     const uint32_t rc = a.key[c] & kRankMask;
-    const uint32_t m = a.val[rc];
+    const uint32_t m = ball_m(a, a.val[rc]);
     const int z = (int)(c % a.Z), y = (int)((c / a.Z) % a.Y), x = (int)(c / yz);
     // neighbour j sits at c + n_j: axis j >> 1, sign (j & 1) ? +1 : -1
     const bool inb[6] = {x > 0, x < a.X - 1, y > 0, y < a.Y - 1, z > 0, z < a.Z - 1};
@@ -826,7 +839,7 @@ __global__ __launch_bounds__(256) void k_paint_shell(PaintArgs a) {
     for (int j = 0; j < 6; j++) {
         const bool q = inb[j] && kp[j] > 0 && kp[j] < k && rp[j] >= rc;
         qmask |= q ? 1u << j : 0u;
-        mp[j] = q ? vp[j] : 0u;
+        mp[j] = q ? ball_m(a, vp[j]) : 0u;
     }
     if (!qmask) {
         const uint32_t slot = atomicAdd(a.n_full, 1u);
@@ -885,7 +898,7 @@ __global__ __launch_bounds__(256) void k_paint_full(PaintArgs a) {
     for (uint32_t i = blockIdx.x * 4 + (threadIdx.x >> 6); i < nf; i += gridDim.x * 4) {
         const int64_t c = a.full[i];
         const int32_t k = a.state[c];
-        const uint32_t m = a.val[a.key[c] & kRankMask];
+        const uint32_t m = ball_m(a, a.val[a.key[c] & kRankMask]);
         const int z = (int)(c % a.Z), y = (int)((c / a.Z) % a.Y), x = (int)(c / yz);
         const int Rb = (int)isqrt_u32(m - 1);
         for (int dx = -Rb; dx <= Rb; dx++) {
@@ -1038,7 +1051,8 @@ ibip_status run_invade(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlet
     hipLaunchKernelGGL(k_rank_tables, dim3(blocks(V)), dim3(256), 0, s, hist, present, flags, V, val, off, head, tail);
     hipLaunchKernelGGL(k_convert, dim3(blocks(n)), dim3(256), 0, s, image, key, present, n, (uint32_t)(V - 1), state,
                        seq);
-    hipLaunchKernelGGL(k_seed, dim3(blocks(n)), dim3(256), 0, s, inlets, key, d.X, d.Y, d.Z, tail, bucket);
+    hipLaunchKernelGGL(k_seed, dim3(blocks(n)), dim3(256), 0, s, inlets, key, d.X, d.Y, d.Z, tail, bucket,
+                       (ctx->readings & IBIP_READ_MASK_INLETS) != 0);
     tm.mark(2, s);
     // loop control
     h_st->k = 1;
@@ -1096,7 +1110,8 @@ ibip_status run_invade(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlet
     tm.mark(7, s);
     if (K > 0) hipLaunchKernelGGL(k_rank_to_value, dim3(blocks(K)), dim3(256), 0, s, M, K, val);
     // a5: sphere insertion
-    PaintArgs pa{state, key, val, seq, full, &st->n_full, d.X, d.Y, d.Z};
+    PaintArgs pa{state, key, val, seq, full, &st->n_full, d.X, d.Y, d.Z,
+                 (ctx->readings & IBIP_READ_INTEGER_BALL) != 0};
     hipLaunchKernelGGL(k_paint_shell, dim3(blocks(n)), dim3(256), 0, s, pa);
     hipLaunchKernelGGL(k_paint_full, dim3(2048), dim3(256), 0, s, pa);
     tm.mark(8, s);
@@ -1231,7 +1246,8 @@ hipError_t job_setup(const JobBufs& j, LoopState* st, const uint8_t* image, cons
                        j.head, j.tail);
     hipLaunchKernelGGL(k_convert, dim3(blocks(n)), dim3(256), 0, s, image, j.key, present, n, (uint32_t)(V - 1),
                        j.state, seq);
-    hipLaunchKernelGGL(k_seed, dim3(blocks(n)), dim3(256), 0, s, inlets, j.key, d.X, d.Y, d.Z, j.tail, j.bucket);
+    hipLaunchKernelGGL(k_seed, dim3(blocks(n)), dim3(256), 0, s, inlets, j.key, d.X, d.Y, d.Z, j.tail, j.bucket,
+                       false);
     return hipGetLastError();
 }
 
@@ -1240,7 +1256,7 @@ hipError_t job_post(const JobBufs& j, LoopState* st, ibip_dims d, int64_t K, int
     const int64_t n = nvox(d);
     hipError_t e;
     if (K > 0) hipLaunchKernelGGL(k_rank_to_value, dim3(blocks(K)), dim3(256), 0, s, j.M, K, j.val);
-    PaintArgs pa{j.state, j.key, j.val, seq, j.full, &st->n_full, d.X, d.Y, d.Z};
+    PaintArgs pa{j.state, j.key, j.val, seq, j.full, &st->n_full, d.X, d.Y, d.Z, false};
     hipLaunchKernelGGL(k_paint_shell, dim3(blocks(n)), dim3(256), 0, s, pa);
     hipLaunchKernelGGL(k_paint_full, dim3(std::min<int64_t>(blocks(n), 2048)), dim3(256), 0, s, pa);
     uint32_t* counts = j.counts;
@@ -1275,7 +1291,7 @@ hipError_t job_post_devk(const JobBufs& j, LoopState* st, ibip_dims d, int32_t* 
     const int64_t n = nvox(d);
     hipLaunchKernelGGL(k_rank_to_value_dev, dim3((unsigned)std::min<int64_t>(blocks(n), 1024)), dim3(256), 0, s,
                        j.M, st, j.val, M_out);
-    PaintArgs pa{j.state, j.key, j.val, seq, j.full, &st->n_full, d.X, d.Y, d.Z};
+    PaintArgs pa{j.state, j.key, j.val, seq, j.full, &st->n_full, d.X, d.Y, d.Z, false};
     hipLaunchKernelGGL(k_paint_shell, dim3(blocks(n)), dim3(256), 0, s, pa);
     hipLaunchKernelGGL(k_paint_full, dim3(std::min<int64_t>(blocks(n), 2048)), dim3(256), 0, s, pa);
     hipLaunchKernelGGL(k_finalise, dim3(blocks(n)), dim3(256), 0, s, seq, j.state, true, n, j.M, rad2,

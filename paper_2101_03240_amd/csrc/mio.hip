@@ -18,26 +18,32 @@ namespace ibip {
 namespace {
 
 // K0(v) = dt2(v) on Q0, 0 elsewhere; also counts pore voxels.
+// Seeds of the opening: pore voxels in Q0 (an inlet voxel or a face
+// neighbour of one); with mask, only pore inlet voxels count.
 __global__ __launch_bounds__(256) void k_mio_seed(const uint8_t* img, const uint8_t* inlets, const uint32_t* dt2,
-                                                  int X, int Y, int Z, uint32_t* k0, uint32_t* n_pore) {
+                                                  int X, int Y, int Z, uint32_t* k0, uint32_t* n_pore, bool mask) {
     const int64_t yz = (int64_t)Y * Z;
     const int64_t n = (int64_t)X * yz;
     const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
     bool pore = false;
     if (v < n) {
-        // all seven inlet bytes and dt2 are loaded together (an outside
-        // neighbour reads v itself): a chain of conditional loads would wait
-        // for each in turn
+        // the seven positions are loaded together (an outside neighbour reads
+        // v itself): a chain of conditional loads would wait for each in turn
         const int z = (int)(v % Z), y = (int)((v / Z) % Y), x = (int)(v / yz);
-        const uint8_t im = img[v];
+        const int64_t nb[7] = {v, x > 0 ? v - yz : v, x < X - 1 ? v + yz : v, y > 0 ? v - Z : v,
+                               y < Y - 1 ? v + Z : v, z > 0 ? v - 1 : v, z < Z - 1 ? v + 1 : v};
         const uint32_t d = dt2[v];
-        const uint8_t i0 = inlets[v];
-        const uint8_t i1 = inlets[x > 0 ? v - yz : v], i2 = inlets[x < X - 1 ? v + yz : v];
-        const uint8_t i3 = inlets[y > 0 ? v - Z : v], i4 = inlets[y < Y - 1 ? v + Z : v];
-        const uint8_t i5 = inlets[z > 0 ? v - 1 : v], i6 = inlets[z < Z - 1 ? v + 1 : v];
-        pore = im != 0;
-        const bool seed = pore && (i0 | i1 | i2 | i3 | i4 | i5 | i6) != 0;
-        k0[v] = seed ? d : 0u;
+        uint8_t in[7], im[7];
+#pragma unroll
+        for (int j = 0; j < 7; j++) {
+            in[j] = inlets[nb[j]];
+            im[j] = img[nb[j]];
+        }
+        bool any = false;
+#pragma unroll
+        for (int j = 0; j < 7; j++) any |= in[j] != 0 && (!mask || im[j] != 0);
+        pore = im[0] != 0;
+        k0[v] = pore && any ? d : 0u;
     }
     block_add_u32(n_pore, pore ? 1u : 0u);
 }
@@ -83,13 +89,13 @@ ibip_status run_mio(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlets, 
     if ((rc = hip_check(ctx, launch_edt(image, nullptr, 0, 0, d, g16, tmp32, dt2, &flags[0], s), "edt")) != IBIP_OK)
         return rc;
     hipLaunchKernelGGL(k_mio_seed, dim3(blocks(n)), dim3(256), 0, s, image, inlets, dt2, d.X, d.Y, d.Z, kmap,
-                       &flags[1]);
+                       &flags[1], (ctx->readings & IBIP_READ_MASK_INLETS) != 0);
     if ((rc = hip_check(ctx, hipMemcpyAsync(h, flags, 8, hipMemcpyDeviceToHost, s), "copy")) != IBIP_OK) return rc;
     if ((rc = hip_check(ctx, hipStreamSynchronize(s), "sync")) != IBIP_OK) return rc;
     if (!h[0]) return fail(ctx, IBIP_ENOSOLID, "opening_drainage: image holds no solid voxel");
     const uint32_t n_pore = h[1];
     int iters = 0;
-    if ((rc = reconstruct(ctx, nullptr, dt2, d, kmap, &iters)) != IBIP_OK) return rc;
+    if ((rc = reconstruct(ctx, nullptr, dt2, false, d, kmap, &iters)) != IBIP_OK) return rc;
     for (int32_t i = 0; i < nT; i++) {
         // distance to the kept centres, capped at T; the last pass writes T
         // into mio_r2 where it is still 0 and the distance is below T

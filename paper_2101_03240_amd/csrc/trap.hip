@@ -42,8 +42,12 @@ struct CapU32 {
 
 // One sweep over the active tiles. A tile whose boundary layer changed
 // activates the face-neighbour tiles across the changed faces for the next
-// sweep (act_out); *changed counts tiles that changed anything.
-template <class Cap>
+// sweep (act_out); *changed counts tiles that changed anything. kConn26: the
+// neighbours of a voxel are the 26 that share a face, an edge or a corner,
+// and the edge and corner tiles are activated too (a tile across an edge or
+// a corner when every face it lies across changed, which covers every
+// changed voxel on that edge or corner).
+template <class Cap, bool kConn26>
 __global__ __launch_bounds__(256) void k_relax_tiles(Cap cap, int X, int Y, int Z, int ntx, int nty, int ntz,
                                                      uint32_t* w, const uint8_t* act_in, uint8_t* act_out,
                                                      uint32_t* changed) {
@@ -100,8 +104,20 @@ __global__ __launch_bounds__(256) void k_relax_tiles(Cap cap, int X, int Y, int 
             const int idx = (((j >> 1) + 1) * HY + (ly + 8 * (j & 1) + 1)) * HZ + (lz + 1);
             const uint32_t cur = hw[idx];
             if (cur >= c[j]) continue;
-            uint32_t nb = max(max(hw[idx - 1], hw[idx + 1]), max(hw[idx - HZ], hw[idx + HZ]));
-            nb = max(nb, max(hw[idx - HY * HZ], hw[idx + HY * HZ]));
+            uint32_t nb;
+            if (kConn26) {
+                nb = 0;
+#pragma unroll
+                for (int dx = -1; dx <= 1; dx++)
+#pragma unroll
+                    for (int dy = -1; dy <= 1; dy++)
+#pragma unroll
+                        for (int dz = -1; dz <= 1; dz++)
+                            if (dx || dy || dz) nb = max(nb, hw[idx + (dx * HY + dy) * HZ + dz]);
+            } else {
+                nb = max(max(hw[idx - 1], hw[idx + 1]), max(hw[idx - HZ], hw[idx + HZ]));
+                nb = max(nb, max(hw[idx - HY * HZ], hw[idx + HY * HZ]));
+            }
             const uint32_t cand = min(c[j], nb);
             if (cand > cur) { hw[idx] = cand; ch = true; }
         }
@@ -130,7 +146,16 @@ __global__ __launch_bounds__(256) void k_relax_tiles(Cap cap, int X, int Y, int 
     }
     if (__builtin_amdgcn_readfirstlane(__syncthreads_or(wrote))) {
         if (tid == 0) atomicAdd(changed, 1u);
-        if (tid < 6 && face[tid]) {
+        if (kConn26) {
+            if (tid < 27 && tid != 13) {
+                const int dx = tid / 9 - 1, dy = (tid / 3) % 3 - 1, dz = tid % 3 - 1;
+                const bool cross = (dx == 0 || face[dx < 0 ? 0 : 1]) && (dy == 0 || face[dy < 0 ? 2 : 3]) &&
+                                   (dz == 0 || face[dz < 0 ? 4 : 5]);
+                const int nx = tx + dx, ny = ty + dy, nz = tz + dz;
+                if (cross && nx >= 0 && nx < ntx && ny >= 0 && ny < nty && nz >= 0 && nz < ntz)
+                    act_out[((int64_t)nx * nty + ny) * ntz + nz] = 1;
+            }
+        } else if (tid < 6 && face[tid]) {
             int nx = tx, ny = ty, nz = tz;
             if (tid == 0) nx--;
             if (tid == 1) nx++;
@@ -189,8 +214,8 @@ inline unsigned blocks(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 }  // namespace
 
-ibip_status reconstruct(ibip_ctx* ctx, const int32_t* seq, const uint32_t* cap32, ibip_dims d, uint32_t* w,
-                        int* n_iter) {
+ibip_status reconstruct(ibip_ctx* ctx, const int32_t* seq, const uint32_t* cap32, bool conn26, ibip_dims d,
+                        uint32_t* w, int* n_iter) {
     hipStream_t s = ctx->stream;
     const int ntx = (d.X + TX - 1) / TX, nty = (d.Y + TY - 1) / TY, ntz = (d.Z + TZ - 1) / TZ;
     const int64_t ntiles = (int64_t)ntx * nty * ntz;
@@ -214,11 +239,14 @@ ibip_status reconstruct(ibip_ctx* ctx, const int32_t* seq, const uint32_t* cap32
             uint8_t* out = (it & 1) ? a0 : a1;
             if ((rc = hip_check(ctx, hipMemsetAsync(out, 0, ntiles, s), "memset")) != IBIP_OK) return rc;
             if (cap32)
-                hipLaunchKernelGGL(k_relax_tiles<CapU32>, dim3((unsigned)ntiles), dim3(256), 0, s, CapU32{cap32}, d.X,
-                                   d.Y, d.Z, ntx, nty, ntz, w, in, out, cnt + b);
+                hipLaunchKernelGGL((k_relax_tiles<CapU32, false>), dim3((unsigned)ntiles), dim3(256), 0, s,
+                                   CapU32{cap32}, d.X, d.Y, d.Z, ntx, nty, ntz, w, in, out, cnt + b);
+            else if (conn26)
+                hipLaunchKernelGGL((k_relax_tiles<CapSeq, true>), dim3((unsigned)ntiles), dim3(256), 0, s,
+                                   CapSeq{seq}, d.X, d.Y, d.Z, ntx, nty, ntz, w, in, out, cnt + b);
             else
-                hipLaunchKernelGGL(k_relax_tiles<CapSeq>, dim3((unsigned)ntiles), dim3(256), 0, s, CapSeq{seq}, d.X,
-                                   d.Y, d.Z, ntx, nty, ntz, w, in, out, cnt + b);
+                hipLaunchKernelGGL((k_relax_tiles<CapSeq, false>), dim3((unsigned)ntiles), dim3(256), 0, s,
+                                   CapSeq{seq}, d.X, d.Y, d.Z, ntx, nty, ntz, w, in, out, cnt + b);
         }
         if ((rc = hip_check(ctx, hipGetLastError(), "relax launch")) != IBIP_OK) return rc;
         if ((rc = hip_check(ctx, hipMemcpyAsync(h_changed, cnt + kBatch - 1, sizeof(uint32_t), hipMemcpyDeviceToHost,
@@ -252,7 +280,8 @@ ibip_status run_trap(ibip_ctx* ctx, const int32_t* seq, const uint8_t* outlets, 
     if ((rc = hip_check(ctx, hipStreamSynchronize(s), "sync")) != IBIP_OK) return rc;
     const int64_t K = (int32_t)h[0];
     int iters = 0;
-    if ((rc = reconstruct(ctx, seq, nullptr, d, w, &iters)) != IBIP_OK) return rc;
+    if ((rc = reconstruct(ctx, seq, nullptr, (ctx->readings & IBIP_READ_TRAP26) != 0, d, w, &iters)) != IBIP_OK)
+        return rc;
     uint32_t* present = (uint32_t*)ensure(ctx, B_TMP2, sizeof(uint32_t) * (K + 1));
     uint32_t* partials = (uint32_t*)ensure(ctx, B_SCAN, sizeof(uint32_t) * (K / 1000 + n / 1000 + 64));
     if (!present || !partials) return fail(ctx, IBIP_ENOMEM, "trap: allocation failed");
