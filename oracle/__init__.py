@@ -207,6 +207,25 @@ def remap_steps(seq, seq_after, M, K_after: int) -> np.ndarray:
     return out
 
 
+def compare_opening(satmap, mio_r2, T, sat_T, trapped=None) -> dict:
+    """Equal-saturation comparison of IBIP and the opening (Section 3.1.1,
+    Figures 8 and 9), level by level from the definition: at level i the IBIP
+    configuration is {0 < satmap <= sat_T[i]} and the opening's is
+    {mio_r2 >= T[i]}; ``disagree[i]`` = pixels in exactly one of them,
+    ``mio_trapped[i]`` = pixels the opening holds that IBIP leaves trapped."""
+    satmap = np.asarray(satmap, dtype=np.float64)
+    r2 = np.asarray(mio_r2).astype(np.uint32)
+    dis = np.zeros(len(T), dtype=np.int64)
+    mt = np.zeros(len(T), dtype=np.int64)
+    for i, (t, s) in enumerate(zip(T, sat_T)):
+        a = (satmap > 0) & (satmap <= s)
+        b = r2 >= np.uint32(t)
+        dis[i] = int(np.count_nonzero(a ^ b))
+        if trapped is not None:
+            mt[i] = int(np.count_nonzero(b & (np.asarray(trapped) != 0)))
+    return {"disagree": dis, "mio_trapped": mt}
+
+
 def trap(seq, outlets, conn: int = 6) -> dict:
     """Trapping with 6- (faces) or 26-connectivity (faces, edges, corners)."""
     seq = np.ascontiguousarray(seq, dtype=np.int32)

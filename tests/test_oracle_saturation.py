@@ -77,3 +77,32 @@ def test_remap_rejects_inconsistent_labels():
     bad = np.array([[[1, 1, 2]]], np.int32)  # two original steps in one re-ranked step
     with pytest.raises(Exception):
         oracle.remap_steps(seq, bad, np.array([9, 4, 1], np.uint32), 2)
+
+
+def test_compare_opening_fixture():
+    g = _golden.load("compare_1d.txt")
+    sat_T = g["sat_T_x6"].reshape(-1) / 6.0
+    sm = (g["satmap_x6"].reshape(-1) / 6.0).reshape(1, 1, -1)
+    c = oracle.compare_opening(sm, g["mio_r2"].reshape(1, 1, -1), g["T"].reshape(-1), sat_T,
+                               trapped=g["trapped"].reshape(1, 1, -1))
+    np.testing.assert_array_equal(c["disagree"], g["disagree"].reshape(-1))
+    np.testing.assert_array_equal(c["mio_trapped"], g["mio_trapped"].reshape(-1))
+
+
+def test_compare_opening_identical_configurations():
+    # an opening that holds exactly IBIP's configuration at every level agrees
+    # everywhere: levels = the distinct saturations l_0 < l_1 < ..., T[i] =
+    # n - i, and a voxel with satmap l_j first held at level j (mio_r2 = T[j])
+    img, inl, out = _case(2)
+    r = oracle.invade(img, inl)
+    s = oracle.steps(r["seq"], r["M"])
+    m = oracle.satmap(r["seq"], s["sat"])
+    levels = np.unique(m[m > 0])
+    n = len(levels)
+    T = np.arange(n, 0, -1).astype(np.uint32)
+    r2 = np.where(m > 0, T[np.searchsorted(levels, m)], 0).astype(np.uint32) if n else np.zeros(img.shape, np.uint32)
+    c = oracle.compare_opening(m, r2, T, levels)
+    assert (c["disagree"] == 0).all()
+    # shifting the opening one level later disagrees by exactly the voxels of each next level
+    c2 = oracle.compare_opening(m, r2, T, np.concatenate([levels[1:], [2.0]])[: n])
+    np.testing.assert_array_equal(c2["disagree"][:-1], [int((m == lv).sum()) for lv in levels[1:]])
