@@ -261,6 +261,25 @@ ibip_status ibip_remap_steps(ibip_ctx* ctx, const int32_t* seq, const int32_t* s
                              const uint32_t* M, int64_t K, int64_t K_after, uint32_t* M_after);
 
 /*
+ * ibip_compare_opening -- equal-saturation comparison of IBIP with the
+ * opening drainage (Section 3.1.1, Figures 8 and 9). At level i (one per
+ * opening radius) the IBIP configuration is {0 < satmap <= sat_T[i]} and the
+ * opening's is {mio_r2 >= T[i]}.
+ * satmap:      double[N] DEVICE, from ibip_saturation (of ibip_invade's seq).
+ * mio_r2:      uint32[N] DEVICE, from ibip_opening_drainage at the radii T.
+ * trapped:     uint8[N] DEVICE or NULL, from ibip_trap.
+ * T, sat_T:    HOST arrays of n_levels entries: the opening's squared radii
+ *              (strictly decreasing, >= 1) and its saturations (non-decreasing).
+ * disagree:    int64[n_levels] DEVICE out: voxels in exactly one configuration.
+ * mio_trapped: int64[n_levels] DEVICE out (needed with trapped): voxels the
+ *              opening holds that IBIP leaves trapped.
+ * Errors: EINVAL, ENOMEM.
+ */
+ibip_status ibip_compare_opening(ibip_ctx* ctx, const double* satmap, const uint32_t* mio_r2,
+                                 const uint8_t* trapped, ibip_dims dims, const uint32_t* T, const double* sat_T,
+                                 int32_t n_levels, int64_t* disagree, int64_t* mio_trapped);
+
+/*
  * ibip_trap -- defender trapping and re-ranking (Section 2.2.3, Figure 7).
  * A voxel invaded at step k (seq[v] = k > 0) is trapped when the defender
  * region just before step k, {pore u : seq[u] == 0 or seq[u] >= k}, holds no

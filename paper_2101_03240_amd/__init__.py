@@ -22,7 +22,7 @@ import ctypes
 import os
 import threading
 
-__all__ = ["edt", "invade", "invade_batch", "Server", "trap", "saturation", "remap_steps", "opening_drainage",
+__all__ = ["edt", "invade", "invade_batch", "Server", "trap", "saturation", "remap_steps", "compare_opening", "opening_drainage",
            "IbipError", "library_path", "load_library", "enable_timing", "get_timing", "reset_timing"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -120,6 +120,8 @@ def load_library():
         lib.ibip_remap_steps.argtypes = [P, P, P, _Dims, P, i64, i64, P]
         lib.ibip_remap_steps.restype = i32
         lib.ibip_ctx_set_readings.argtypes = [P, ctypes.c_uint32]
+        lib.ibip_compare_opening.argtypes = [P, P, P, P, _Dims, P, P, i32, P, P]
+        lib.ibip_compare_opening.restype = i32
         lib.ibip_ctx_set_readings.restype = i32
         lib.ibip_ctx_enable_timing.argtypes = [P, i32]
         lib.ibip_ctx_get_timing.argtypes = [P, ctypes.POINTER(_Timing)]
@@ -481,6 +483,41 @@ def opening_drainage(image, inlets, thresholds, mask_inlets: bool = False):
     _check(load_library().ibip_opening_drainage(ctx, _ptr(image), _ptr(inlets), dims, ctypes.cast(arr, ctypes.c_void_p),
                                                 len(T), _ptr(out), ctypes.cast(sat, ctypes.c_void_p)), ctx)
     return {"mio_r2": out, "mio_sat": [sat[i] for i in range(len(T))]}
+
+
+def compare_opening(satmap, mio_r2, thresholds, mio_sat, trapped=None) -> dict:
+    """Equal-saturation comparison of IBIP with the opening (Section 3.1.1,
+    Figures 8 and 9): at each opening level i, ``disagree[i]`` voxels lie in
+    exactly one of {0 < satmap <= mio_sat[i]} and {mio_r2 >= thresholds[i]},
+    and ``mio_trapped[i]`` of the opening's voxels are ``trapped`` (zeros
+    without it). Returns int64 tensors of one entry per level."""
+    torch = _torch()
+    if not isinstance(satmap, torch.Tensor) or not satmap.is_cuda or satmap.dtype != torch.float64:
+        raise ValueError("satmap must be a float64 torch tensor on a GPU device")
+    satmap = satmap.contiguous()
+    r2 = _dev_i32(mio_r2, "mio_r2")
+    if r2.shape != satmap.shape:
+        raise ValueError("mio_r2 must have the shape of satmap")
+    if trapped is not None:
+        trapped = _dev_u8(trapped, "trapped")
+        if trapped.shape != satmap.shape:
+            raise ValueError("trapped must have the shape of satmap")
+    dims, _ = _dims_of(satmap)
+    dev = satmap.device
+    ctx = _context(dev)
+    T = [int(t) for t in thresholds]
+    S = [float(x) for x in mio_sat]
+    if len(T) != len(S) or not T:
+        raise ValueError("thresholds and mio_sat need one entry per level")
+    tarr = (ctypes.c_uint32 * len(T))(*T)
+    sarr = (ctypes.c_double * len(S))(*S)
+    dis = torch.empty(len(T), dtype=torch.int64, device=dev)
+    mt = torch.zeros(len(T), dtype=torch.int64, device=dev)
+    _check(load_library().ibip_compare_opening(
+        ctx, _ptr(satmap), _ptr(r2), _ptr(trapped) if trapped is not None else None, dims,
+        ctypes.cast(tarr, ctypes.c_void_p), ctypes.cast(sarr, ctypes.c_void_p), len(T), _ptr(dis),
+        _ptr(mt) if trapped is not None else None), ctx)
+    return {"disagree": dis, "mio_trapped": mt}
 
 
 def enable_timing(enable: bool = True, device=None):

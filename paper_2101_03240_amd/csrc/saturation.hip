@@ -2,6 +2,7 @@
 // 2.2.2; Figure 5 left), and the squared radii that survive trapping
 // (Section 2.2.3), so that the capillary pressure curve can be drawn with or
 // without trapping.
+#include <algorithm>
 #include <cmath>
 
 #include "ibip_internal.h"
@@ -80,6 +81,84 @@ __global__ __launch_bounds__(256) void k_remap_check(const int32_t* __restrict__
     if (a > 0 && s > 0 && (int64_t)s <= K && M_after[a - 1] != M[s - 1]) atomicOr(bad, 1u);
 }
 
+// Equal-saturation comparison with the opening. Voxel v is in the IBIP
+// configuration of level i when 0 < satmap[v] <= sat_T[i] (sat_T increasing),
+// i.e. from level a = first i with sat_T[i] >= satmap[v] on, and in the
+// opening's from level b = first i with mio_r2[v] >= T[i] (T decreasing) on.
+// It disagrees on the levels between min(a, b) and max(a, b): +1 at the first,
+// -1 at the second of a difference array over levels (n = no such level),
+// whose prefix sum is the disagreement per level. A trapped voxel adds +1 at
+// b to the second array (held by the opening from level b on).
+constexpr int32_t kCmpLdsLevels = 2048;
+
+__device__ __forceinline__ int32_t first_level_sat(const double* sat_T, int32_t nl, double m) {
+    int32_t lo = 0, hi = nl;  // first level whose saturation reaches m
+    while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (sat_T[mid] >= m) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int32_t first_level_r2(const uint32_t* T, int32_t nl, uint32_t r) {
+    int32_t lo = 0, hi = nl;  // first level whose threshold r reaches
+    while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (r >= T[mid]) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo;
+}
+
+// kLds: the difference arrays are binned per block in LDS (nl <= kCmpLdsLevels)
+// and flushed with one global atomic per non-zero bin; else straight to HBM.
+template <bool kLds>
+__global__ __launch_bounds__(256) void k_compare_opening(const double* __restrict__ satmap,
+                                                         const uint32_t* __restrict__ mio_r2,
+                                                         const uint8_t* __restrict__ trapped, int64_t n,
+                                                         const uint32_t* T, const double* sat_T, int32_t nl,
+                                                         int32_t* diff, int32_t* tdiff) {
+    __shared__ int32_t bins[kLds ? 2 * kCmpLdsLevels : 1];
+    int32_t* ld = kLds ? bins : diff;
+    int32_t* lt = kLds ? bins + kCmpLdsLevels : tdiff;
+    if (kLds) {
+        for (int32_t i = threadIdx.x; i < 2 * kCmpLdsLevels; i += 256) bins[i] = 0;
+        __syncthreads();
+    }
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < n; v += stride) {
+        const double m = satmap[v];
+        const uint32_t r = mio_r2[v];
+        const int32_t a = m > 0 ? first_level_sat(sat_T, nl, m) : nl;
+        const int32_t b = r > 0 ? first_level_r2(T, nl, r) : nl;
+        const int32_t x = min(a, b), y = max(a, b);
+        if (x < y) {
+            atomicAdd(&ld[x], 1);
+            if (y < nl) atomicAdd(&ld[y], -1);
+        }
+        if (trapped && trapped[v] && b < nl) atomicAdd(&lt[b], 1);
+    }
+    if (kLds) {
+        __syncthreads();
+        for (int32_t i = threadIdx.x; i < nl; i += 256) {
+            if (bins[i]) atomicAdd(&diff[i], bins[i]);
+            if (bins[kCmpLdsLevels + i]) atomicAdd(&tdiff[i], bins[kCmpLdsLevels + i]);
+        }
+    }
+}
+
+__global__ void k_prefix_levels(const int32_t* diff, int32_t nl, int64_t* out) {
+    // nl is small (the opening's levels): one thread
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        int64_t acc = 0;
+        for (int32_t i = 0; i < nl; i++) {
+            acc += diff[i];
+            out[i] = acc;
+        }
+    }
+}
+
 }  // namespace
 
 }  // namespace ibip
@@ -154,6 +233,47 @@ ibip_status ibip_remap_steps(ibip_ctx* ctx, const int32_t* seq, const int32_t* s
     if ((rc = hip_check(ctx, hipStreamSynchronize(s), "sync")) != IBIP_OK) return rc;
     if (h[0]) return fail(ctx, IBIP_EINVAL, "remap_steps: labels do not come from one trapping of this sequence");
     return IBIP_OK;
+}
+
+ibip_status ibip_compare_opening(ibip_ctx* ctx, const double* satmap, const uint32_t* mio_r2,
+                                 const uint8_t* trapped, ibip_dims dims, const uint32_t* T, const double* sat_T,
+                                 int32_t n_levels, int64_t* disagree, int64_t* mio_trapped) {
+    if (!ctx) return IBIP_EINVAL;
+    if (!satmap || !mio_r2 || !T || !sat_T || !disagree || !dims_ok(dims) || n_levels <= 0 ||
+        n_levels > (1 << 20) || (trapped && !mio_trapped))
+        return fail(ctx, IBIP_EINVAL, "compare_opening: bad arguments");
+    if (T[n_levels - 1] < 1) return fail(ctx, IBIP_EINVAL, "compare_opening: radii must be >= 1");
+    for (int32_t i = 1; i < n_levels; i++)
+        if (T[i] >= T[i - 1] || sat_T[i] < sat_T[i - 1])
+            return fail(ctx, IBIP_EINVAL, "compare_opening: T must decrease and sat_T must not");
+    DeviceGuard g(ctx->device);
+    hipStream_t s = ctx->stream;
+    const int64_t n = nvox(dims);
+    const size_t nl = (size_t)n_levels;
+    // device copies of the levels, and two difference arrays
+    uint8_t* w = (uint8_t*)ensure(ctx, B_SATW, 256 + nl * (4 + 8 + 4 + 4) + 256);
+    if (!w) return fail(ctx, IBIP_ENOMEM, "compare_opening: allocation failed");
+    uint32_t* dT = (uint32_t*)w;
+    double* dS = (double*)(w + align256(4 * nl));
+    int32_t* diff = (int32_t*)((uint8_t*)dS + 8 * nl);
+    int32_t* tdiff = diff + nl;
+    ibip_status rc;
+    if ((rc = hip_check(ctx, hipMemcpyAsync(dT, T, 4 * nl, hipMemcpyHostToDevice, s), "copy")) != IBIP_OK) return rc;
+    if ((rc = hip_check(ctx, hipMemcpyAsync(dS, sat_T, 8 * nl, hipMemcpyHostToDevice, s), "copy")) != IBIP_OK)
+        return rc;
+    if ((rc = hip_check(ctx, hipMemsetAsync(diff, 0, 8 * nl, s), "memset")) != IBIP_OK) return rc;
+    // enough blocks to fill the chip; each strides over the volume
+    const int64_t nb = std::max<int64_t>(1, std::min<int64_t>(blocks(n), 2048));
+    if (n_levels <= kCmpLdsLevels)
+        hipLaunchKernelGGL(k_compare_opening<true>, dim3(nb), dim3(256), 0, s, satmap, mio_r2, trapped, n, dT, dS,
+                           (int32_t)n_levels, diff, tdiff);
+    else
+        hipLaunchKernelGGL(k_compare_opening<false>, dim3(nb), dim3(256), 0, s, satmap, mio_r2, trapped, n, dT, dS,
+                           (int32_t)n_levels, diff, tdiff);
+    hipLaunchKernelGGL(k_prefix_levels, dim3(1), dim3(64), 0, s, diff, (int32_t)n_levels, disagree);
+    if (trapped) hipLaunchKernelGGL(k_prefix_levels, dim3(1), dim3(64), 0, s, tdiff, (int32_t)n_levels, mio_trapped);
+    if ((rc = hip_check(ctx, hipGetLastError(), "compare launch")) != IBIP_OK) return rc;
+    return hip_check(ctx, hipStreamSynchronize(s), "sync");
 }
 
 }  // extern "C"
