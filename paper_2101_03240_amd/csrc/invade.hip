@@ -626,10 +626,17 @@ __device__ inline void loop_body(const LoopArgs& a, LoopShared& s) {
                         got += (uint32_t)__popcll(mm);
                     }
                 } else {
-                    const uint32_t c0 = lane < cnt ? a.bucket[h + lane] : 0u;
-                    const uint32_t c1 = lane + 64 < cnt ? a.bucket[h + 64 + lane] : 0u;
-                    if (lane < cnt) s.cl[lane] = c0;
-                    if (lane + 64 < cnt) s.cl[lane + 64] = c1;
+                    // unconditional loads (clamped into the slice) and LDS stores:
+                    // entries past cnt are never read. A load under a lane
+                    // condition would leave its register pending past this
+                    // block, and the compiler would then wait for every
+                    // outstanding store before the claims.
+                    const uint32_t c0 = a.bucket[h + min((uint32_t)lane, cnt - 1u)];
+                    s.cl[lane] = c0;
+                    if (cnt > 64) {
+                        const uint32_t c1 = a.bucket[h + min((uint32_t)lane + 64u, cnt - 1u)];
+                        s.cl[lane + 64] = c1;
+                    }
                 }
                 bool dnext = false;
                 const uint32_t rn = small_step(cnt, k, r, a, s, nsel, ln, dnext);
