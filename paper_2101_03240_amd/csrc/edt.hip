@@ -274,7 +274,7 @@ __global__ __launch_bounds__(256) void edt_pass_x_tile(const uint32_t* __restric
             hits += outp.hit(x * yz + col, best);
         }
     }
-    if (count) block_add_u32(count, hits);
+    if (count) block_add_slots(count, hits);
 }
 
 // Non-tiled pass x with the opening epilogue (lines longer than the tile).
@@ -303,7 +303,7 @@ __global__ __launch_bounds__(256) void edt_pass_x_opening(const uint32_t* __rest
         }
         hits = outp.hit(v, best);
     }
-    block_add_u32(count, hits);
+    block_add_slots(count, hits);
 }
 
 // ---------------------------------------------------------------------------
@@ -554,7 +554,7 @@ __global__ __launch_bounds__(kThreadsX) void edt_pass_x_vec(const uint32_t* __re
             hits += outp.hit(v, b);
         }
     }
-    if (count) block_add_u32(count, hits);
+    if (count) block_add_slots(count, hits);
 }
 
 // LDS a workgroup may use on the current device (the pass-x tile of a

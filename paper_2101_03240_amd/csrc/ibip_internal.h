@@ -57,6 +57,24 @@ __device__ inline void block_add_u32(uint32_t* dst, uint32_t v) {
     }
 }
 
+// Sum of v over the block, added to one of kCountSlots words chosen by the
+// block index: one word taking an atomic from every block of a large grid
+// queues them all at one L2 channel. The count is the sum of the slots.
+constexpr int kCountSlots = 64;
+__device__ inline void block_add_slots(uint32_t* slots, uint32_t v) {
+    __shared__ uint32_t part[16];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (lane == 0) part[wid] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); w++) t += part[w];
+        if (t) atomicAdd(&slots[blockIdx.x % kCountSlots], t);
+    }
+}
+
 // Makes `dev` current for a scope and restores the previous device after.
 struct DeviceGuard {
     int prev = -1;
@@ -99,6 +117,7 @@ enum BufId {
     B_CNT,         // uint32 per-sweep change counters
     B_BATCH,       // arena of a batch of jobs
     B_SATW,        // counts and scan of ibip_saturation
+    B_MIOCNT,      // per-level counts of the opening (kept apart from B_M, which ibip_get_steps reads)
     B_NUM
 };
 
@@ -116,7 +135,7 @@ struct LoopState {
     uint32_t n_full;   // centres that need a full ball
     uint32_t err;
     uint32_t big_k;    // step number of the pending wide step
-    uint32_t popped;   // centres (voxels with state > 0) after the loop
+    uint32_t popped;   // centres of the steps the loop kernels ran (wide steps not included)
     uint32_t pad2;
     int64_t max_steps;
 };
@@ -195,6 +214,8 @@ hipError_t launch_edt(const uint8_t* image, const uint32_t* w, uint32_t thr, uin
                       hipStream_t s, uint32_t* mio_r2 = nullptr, uint32_t* mio_count = nullptr);
 
 // Exclusive scan of n uint32 values in place; returns the total in *total (device).
+// *dst = the sum of kCountSlots slot words (see block_add_slots).
+hipError_t launch_sum_slots(const uint32_t* slots, uint32_t* dst, hipStream_t s);
 hipError_t launch_scan_u32(uint32_t* data, int64_t n, uint32_t* partials, uint32_t* total,
                            hipStream_t s);
 

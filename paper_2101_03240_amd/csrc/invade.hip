@@ -555,7 +555,7 @@ __device__ inline void loop_body(const LoopArgs& a, LoopShared& s) {
     const int64_t max_steps = a.st->max_steps;
     const uint32_t n_pore = a.st->n_pore;
     // driver state, live in wave 0
-    uint32_t r = 0, k = 0, prev_r = 0, sel = 0, nlog = 0;
+    uint32_t r = 0, k = 0, prev_r = 0, sel = 0, nlog = 0, npop = 0;
     bool log_ok = false, direct = false;
     if (wave0) {
         r = lds_highest_below_uni(s, R + 1);
@@ -586,6 +586,7 @@ __device__ inline void loop_body(const LoopArgs& a, LoopShared& s) {
                 const uint32_t cnt = t - h;
                 s.head[r] = t;
                 const bool fromlog = log_ok && (direct || r >= prev_r);
+                if (cnt <= a.wide) npop += cnt;  // a wide step's centres are counted by the host
                 if (cnt > a.small) a.M[k - 1] = r;  // rank; k_rank_to_value turns it into dt2 after the loop
                 if (cnt > a.wide) {
                     a.st->big_r = r;
@@ -697,7 +698,10 @@ __device__ inline void loop_body(const LoopArgs& a, LoopShared& s) {
             log_ok = nlog <= kLog;
         }
     }
-    if (wave0) a.st->k = k;
+    if (wave0) {
+        a.st->k = k;
+        a.st->popped = uni(a.st->popped) + npop;
+    }
     for (uint32_t q = tid; q <= R; q += kLoopThreads) {
         a.head[q] = s.head[q];
         a.tail[q] = s.tail[q];
@@ -849,8 +853,14 @@ __global__ __launch_bounds__(256) void k_paint_shell(PaintArgs a) {
         mp[j] = q ? ball_m(a, vp[j]) : 0u;
     }
     if (!qmask) {
-        const uint32_t slot = atomicAdd(a.n_full, 1u);
-        a.full[slot] = (uint32_t)c;
+        // the lanes here list their centres with one atomic per wave
+        const uint64_t mk = __ballot(true);
+        const int lane = threadIdx.x & 63;
+        const int leader = __ffsll((unsigned long long)mk) - 1;
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(a.n_full, (uint32_t)__popcll(mk));
+        base = __shfl(base, leader, 64);
+        a.full[base + (uint32_t)__popcll(mk & lanemask_lt())] = (uint32_t)c;
         return;
     }
     const int j0 = __ffs(qmask) - 1;
@@ -944,21 +954,17 @@ __global__ void k_rank_to_value(uint32_t* M, int64_t K, const uint32_t* val) {
 }
 
 __global__ __launch_bounds__(256) void k_finalise(int32_t* seq, int32_t* state_io, bool map_state, int64_t n,
-                                                  const uint32_t* M, uint32_t* rad2, uint32_t* count,
-                                                  uint32_t* popped) {
+                                                  const uint32_t* M, uint32_t* rad2, uint32_t* count) {
     const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
     bool have = v < n;
     int32_t s = 0;
-    bool centre = false;
     if (have) {
         s = seq[v];
         if (s == INT_MAX) { s = 0; seq[v] = 0; }
         if (rad2) rad2[v] = s > 0 ? M[s - 1] : 0u;
         const int32_t t = state_io[v];
-        centre = t > 0;
         if (map_state && t < 0) state_io[v] = 0;
     }
-    block_add_u32(popped, centre ? 1u : 0u);
     // per-step counts (when requested), one atomic per distinct step in the wave
     bool act = count != nullptr && have && s > 0;
     uint64_t pending = __ballot(act);
@@ -1078,7 +1084,7 @@ ibip_status run_invade(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlet
     }
     LoopArgs la{st,     head, tail, val, bucket, state, key, M, d.X, d.Y, d.Z, kWideRound, kSmallRound,
                 make_fastdiv((uint32_t)d.Z), make_fastdiv((uint32_t)d.Y)};
-    int64_t segments = 0;
+    int64_t segments = 0, wide_centres = 0;
     bool wide_pending_timing = false;
     for (;;) {
         tm.mark(3, s);
@@ -1101,6 +1107,7 @@ ibip_status run_invade(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlet
         if (++segments > n_pore + 2) return fail(ctx, IBIP_EDEVICE, "invade: too many loop segments");
         if (h_st->status == LS_WIDE) {
             const uint32_t cnt = h_st->big_t - h_st->big_h;
+            wide_centres += cnt;
             if (tm.on) ctx->timing.wide_centres += cnt;
             const unsigned g = (unsigned)std::min<int64_t>((cnt + 255) / 256, 4096);
             tm.mark(5, s);
@@ -1130,8 +1137,7 @@ ibip_status run_invade(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlet
     partials = (uint32_t*)ensure(ctx, B_SCAN, sizeof(uint32_t) * (V / 1000 + n / 1000 + 64));
     if (!n_new || !sat || !pc || !counts || !partials) return fail(ctx, IBIP_ENOMEM, "invade: scratch allocation failed");
     if ((rc = hip_check(ctx, hipMemsetAsync(counts, 0, sizeof(uint32_t) * (K + 1), s), "memset")) != IBIP_OK) return rc;
-    hipLaunchKernelGGL(k_finalise, dim3(blocks(n)), dim3(256), 0, s, seq, state, true, n, M, rad2, counts,
-                       &st->popped);
+    hipLaunchKernelGGL(k_finalise, dim3(blocks(n)), dim3(256), 0, s, seq, state, true, n, M, rad2, counts);
     if (K > 0) {
         uint32_t* excl = counts + (K + 1);
         hipLaunchKernelGGL(k_copy_u32, dim3(blocks(K)), dim3(256), 0, s, counts, excl, K);
@@ -1155,7 +1161,7 @@ ibip_status run_invade(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlet
         T.paint_ms += tm.ms(7, 8);
         T.steps_ms += tm.ms(8, 9);
         T.steps += K;
-        T.popped += h_st->popped;
+        T.popped += h_st->popped + wide_centres;
     }
     ctx->last_K = K;
     ctx->last_n_pore = n_pore;
@@ -1268,8 +1274,7 @@ hipError_t job_post(const JobBufs& j, LoopState* st, ibip_dims d, int64_t K, int
     hipLaunchKernelGGL(k_paint_full, dim3(std::min<int64_t>(blocks(n), 2048)), dim3(256), 0, s, pa);
     uint32_t* counts = j.counts;
     if (counts && (e = hipMemsetAsync(counts, 0, sizeof(uint32_t) * (K + 1), s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_finalise, dim3(blocks(n)), dim3(256), 0, s, seq, j.state, true, n, j.M, rad2, counts,
-                       &st->popped);
+    hipLaunchKernelGGL(k_finalise, dim3(blocks(n)), dim3(256), 0, s, seq, j.state, true, n, j.M, rad2, counts);
     if (K > 0 && M_out)
         if ((e = hipMemcpyAsync(M_out, j.M, sizeof(uint32_t) * K, hipMemcpyDeviceToDevice, s)) != hipSuccess) return e;
     if (K > 0 && sat_out && counts) {
@@ -1302,7 +1307,7 @@ hipError_t job_post_devk(const JobBufs& j, LoopState* st, ibip_dims d, int32_t* 
     hipLaunchKernelGGL(k_paint_shell, dim3(blocks(n)), dim3(256), 0, s, pa);
     hipLaunchKernelGGL(k_paint_full, dim3(std::min<int64_t>(blocks(n), 2048)), dim3(256), 0, s, pa);
     hipLaunchKernelGGL(k_finalise, dim3(blocks(n)), dim3(256), 0, s, seq, j.state, true, n, j.M, rad2,
-                       (uint32_t*)nullptr, &st->popped);
+                       (uint32_t*)nullptr);
     return hipGetLastError();
 }
 

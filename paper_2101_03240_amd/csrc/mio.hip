@@ -45,7 +45,7 @@ __global__ __launch_bounds__(256) void k_mio_seed(const uint8_t* img, const uint
         pore = im[0] != 0;
         k0[v] = pore && any ? d : 0u;
     }
-    block_add_u32(n_pore, pore ? 1u : 0u);
+    block_add_slots(n_pore, pore ? 1u : 0u);
 }
 
 // First write in decreasing T; count voxels with mio_r2 >= T.
@@ -58,7 +58,7 @@ __global__ __launch_bounds__(256) void k_mio_update(const uint32_t* d2, uint32_t
         if (r == 0 && d2[v] < T) { r = T; mio_r2[v] = T; }
         hit = r >= T;
     }
-    block_add_u32(count, hit ? 1u : 0u);
+    block_add_slots(count, hit ? 1u : 0u);
 }
 
 inline unsigned blocks(int64_t n) { return (unsigned)((n + 255) / 256); }
@@ -74,39 +74,46 @@ ibip_status run_mio(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlets, 
     uint16_t* g16 = (uint16_t*)ensure(ctx, B_TMP0, sizeof(uint16_t) * n);
     uint32_t* tmp32 = (uint32_t*)ensure(ctx, B_TMP1, sizeof(uint32_t) * n);
     uint32_t* d2 = (uint32_t*)ensure(ctx, B_TMP2, sizeof(uint32_t) * n);
-    uint32_t* counts = (uint32_t*)ensure(ctx, B_M, sizeof(uint32_t) * (nT + 8));
+    // per-level counts and the pore count, kCountSlots words each
+    const size_t ncount = (size_t)kCountSlots * ((size_t)nT + 1);
+    uint32_t* counts = (uint32_t*)ensure(ctx, B_MIOCNT, sizeof(uint32_t) * ncount);
     uint8_t* misc = (uint8_t*)ensure(ctx, B_MISC, 4096);
-    uint32_t* h = (uint32_t*)pinned(ctx, 4096 + sizeof(uint32_t) * (nT + 8));
+    uint32_t* h = (uint32_t*)pinned(ctx, 4096 + sizeof(uint32_t) * ncount);
     if (!dt2 || !kmap || !g16 || !tmp32 || !d2 || !counts || !misc || !h)
         return fail(ctx, IBIP_ENOMEM, "opening_drainage: allocation failed");
-    uint32_t* flags = (uint32_t*)(misc + 3584);  // [0] solid seen, [1] n_pore, [2] scratch flag
+    uint32_t* flags = (uint32_t*)(misc + 3584);  // [0] solid seen, [2] scratch flag
+    uint32_t* pore_slots = counts + (size_t)kCountSlots * nT;
     ibip_status rc;
     ctx->timer.mark(10, s);
     if ((rc = hip_check(ctx, hipMemsetAsync(flags, 0, 16, s), "memset")) != IBIP_OK) return rc;
-    if ((rc = hip_check(ctx, hipMemsetAsync(counts, 0, sizeof(uint32_t) * (nT + 8), s), "memset")) != IBIP_OK)
+    if ((rc = hip_check(ctx, hipMemsetAsync(counts, 0, sizeof(uint32_t) * ncount, s), "memset")) != IBIP_OK)
         return rc;
     if ((rc = hip_check(ctx, hipMemsetAsync(mio_r2, 0, sizeof(uint32_t) * n, s), "memset")) != IBIP_OK) return rc;
     if ((rc = hip_check(ctx, launch_edt(image, nullptr, 0, 0, d, g16, tmp32, dt2, &flags[0], s), "edt")) != IBIP_OK)
         return rc;
     hipLaunchKernelGGL(k_mio_seed, dim3(blocks(n)), dim3(256), 0, s, image, inlets, dt2, d.X, d.Y, d.Z, kmap,
-                       &flags[1], (ctx->readings & IBIP_READ_MASK_INLETS) != 0);
-    if ((rc = hip_check(ctx, hipMemcpyAsync(h, flags, 8, hipMemcpyDeviceToHost, s), "copy")) != IBIP_OK) return rc;
+                       pore_slots, (ctx->readings & IBIP_READ_MASK_INLETS) != 0);
+    if ((rc = hip_check(ctx, hipMemcpyAsync(h, flags, 4, hipMemcpyDeviceToHost, s), "copy")) != IBIP_OK) return rc;
+    if ((rc = hip_check(ctx, hipMemcpyAsync(h + 64, pore_slots, sizeof(uint32_t) * kCountSlots,
+                                            hipMemcpyDeviceToHost, s), "copy")) != IBIP_OK)
+        return rc;
     if ((rc = hip_check(ctx, hipStreamSynchronize(s), "sync")) != IBIP_OK) return rc;
     if (!h[0]) return fail(ctx, IBIP_ENOSOLID, "opening_drainage: image holds no solid voxel");
-    const uint32_t n_pore = h[1];
+    uint64_t n_pore = 0;
+    for (int q = 0; q < kCountSlots; q++) n_pore += h[64 + q];
     int iters = 0;
     if ((rc = reconstruct(ctx, nullptr, dt2, false, d, kmap, &iters)) != IBIP_OK) return rc;
     for (int32_t i = 0; i < nT; i++) {
         // distance to the kept centres, capped at T; the last pass writes T
         // into mio_r2 where it is still 0 and the distance is below T
         if ((rc = hip_check(ctx, launch_edt(nullptr, kmap, T[i], T[i], d, g16, tmp32, nullptr, &flags[2], s, mio_r2,
-                                            &counts[i]), "edt")) != IBIP_OK)
+                                            counts + (size_t)kCountSlots * i), "edt")) != IBIP_OK)
             return rc;
     }
     if ((rc = hip_check(ctx, hipGetLastError(), "mio launch")) != IBIP_OK) return rc;
     uint32_t* hc = h + 1024;
-    if ((rc = hip_check(ctx, hipMemcpyAsync(hc, counts, sizeof(uint32_t) * nT, hipMemcpyDeviceToHost, s), "copy")) !=
-        IBIP_OK)
+    if ((rc = hip_check(ctx, hipMemcpyAsync(hc, counts, sizeof(uint32_t) * kCountSlots * nT, hipMemcpyDeviceToHost,
+                                            s), "copy")) != IBIP_OK)
         return rc;
     ctx->timer.mark(11, s);
     if ((rc = hip_check(ctx, hipStreamSynchronize(s), "sync")) != IBIP_OK) return rc;
@@ -115,7 +122,11 @@ ibip_status run_mio(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlets, 
         ctx->timing.relax_sweeps += iters;
     }
     if (mio_sat)
-        for (int32_t i = 0; i < nT; i++) mio_sat[i] = n_pore ? (double)hc[i] / (double)n_pore : 0.0;
+        for (int32_t i = 0; i < nT; i++) {
+            uint64_t c = 0;
+            for (int q = 0; q < kCountSlots; q++) c += hc[(size_t)kCountSlots * i + q];
+            mio_sat[i] = n_pore ? (double)c / (double)n_pore : 0.0;
+        }
     return IBIP_OK;
 }
 

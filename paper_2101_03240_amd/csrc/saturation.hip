@@ -13,7 +13,7 @@ namespace {
 
 inline unsigned blocks(int64_t n) { return (unsigned)((n + 255) / 256); }
 
-// counts[k-1] = voxels labelled k; *n_pore += pore voxels (label >= 0). Lanes
+// counts[k-1] = voxels labelled k; n_pore slots += pore voxels (label >= 0). Lanes
 // of a wave are grouped by label with ballots, and each group adds its size
 // with one atomic (labels of neighbouring voxels repeat).
 __global__ __launch_bounds__(256) void k_count_steps(const int32_t* __restrict__ seq, int64_t n, int64_t K,
@@ -31,7 +31,7 @@ __global__ __launch_bounds__(256) void k_count_steps(const int32_t* __restrict__
         if (lane == leader) atomicAdd(&counts[ls - 1], (uint32_t)__popcll(same));
         pending &= ~same;
     }
-    block_add_u32(n_pore, v < n && s >= 0 ? 1u : 0u);
+    block_add_slots(n_pore, v < n && s >= 0 ? 1u : 0u);
 }
 
 __global__ void k_curves(const uint32_t* counts, const uint32_t* excl, const uint32_t* M, int64_t K,
@@ -180,17 +180,20 @@ ibip_status ibip_saturation(ibip_ctx* ctx, const int32_t* seq, ibip_dims dims, c
     const double vs = opts ? opts->voxel_size : 1.0;
     if (!(vs > 0)) return fail(ctx, IBIP_EINVAL, "saturation: voxel_size must be positive");
     const double c0 = 2.0 * sigma * cos(theta) / vs;
-    uint32_t* w = (uint32_t*)ensure(ctx, B_SATW, sizeof(uint32_t) * (2 * (size_t)K + 64));
+    uint32_t* w = (uint32_t*)ensure(ctx, B_SATW, sizeof(uint32_t) * (2 * (size_t)K + 64 + kCountSlots));
     uint32_t* partials = (uint32_t*)ensure(ctx, B_SCAN, sizeof(uint32_t) * (K / 1000 + n / 1000 + 64));
     uint32_t* h = (uint32_t*)pinned(ctx, 4096);
     if (!w || !partials || !h) return fail(ctx, IBIP_ENOMEM, "saturation: allocation failed");
-    uint32_t* ctl = w;            // [0] n_pore, [1] bad label, [2] scan total
-    uint32_t* counts = w + 64;    // K
-    uint32_t* excl = counts + K;  // K
+    uint32_t* ctl = w;                // [0] n_pore, [1] bad label, [2] scan total
+    uint32_t* slots = w + 64;         // n_pore, by block
+    uint32_t* counts = slots + kCountSlots;  // K
+    uint32_t* excl = counts + K;      // K
     ibip_status rc;
-    if ((rc = hip_check(ctx, hipMemsetAsync(w, 0, sizeof(uint32_t) * (64 + (size_t)K), s), "memset")) != IBIP_OK)
+    if ((rc = hip_check(ctx, hipMemsetAsync(w, 0, sizeof(uint32_t) * (64 + kCountSlots + (size_t)K), s), "memset")) !=
+        IBIP_OK)
         return rc;
-    hipLaunchKernelGGL(k_count_steps, dim3(blocks(n)), dim3(256), 0, s, seq, n, K, counts, ctl, ctl + 1);
+    hipLaunchKernelGGL(k_count_steps, dim3(blocks(n)), dim3(256), 0, s, seq, n, K, counts, slots, ctl + 1);
+    if ((rc = hip_check(ctx, launch_sum_slots(slots, ctl, s), "sum")) != IBIP_OK) return rc;
     if (K > 0) {
         if ((rc = hip_check(ctx, hipMemcpyAsync(excl, counts, sizeof(uint32_t) * K, hipMemcpyDeviceToDevice, s),
                             "copy")) != IBIP_OK)

@@ -75,7 +75,19 @@ hipError_t scan_rec(uint32_t* data, int64_t n, uint32_t* partials, uint32_t* tot
     return hipGetLastError();
 }
 
+__global__ void k_sum_slots(const uint32_t* slots, uint32_t* dst) {
+    uint32_t v = threadIdx.x < kCountSlots ? slots[threadIdx.x] : 0u;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (threadIdx.x == 0) *dst = v;
+}
+
 }  // namespace
+
+hipError_t launch_sum_slots(const uint32_t* slots, uint32_t* dst, hipStream_t s) {
+    hipLaunchKernelGGL(k_sum_slots, dim3(1), dim3(64), 0, s, slots, dst);
+    return hipGetLastError();
+}
 
 // `partials` must hold at least n / 1023 + 8 entries.
 hipError_t launch_scan_u32(uint32_t* data, int64_t n, uint32_t* partials, uint32_t* total, hipStream_t s) {
