@@ -13,7 +13,8 @@
 //   W(v) = max(W0(v), min(cap(v), max over face neighbours u of W(u))).
 //
 // Relaxation runs per 8 x 16 x 32 tile: the tile and a one-voxel halo sit in
-// LDS and are swept until nothing changes. Sweeps repeat over the active
+// LDS and are relaxed until nothing changes (6-connected: rounds of forward and
+// backward scans along the lines of each axis; 26-connected: neighbour sweeps). Sweeps repeat over the active
 // tiles (all at first, then those whose face-neighbour changed its boundary
 // layer) until no tile changes. W only grows and is bounded, so this ends at
 // the unique fixed point.
@@ -52,6 +53,7 @@ __global__ __launch_bounds__(256) void k_relax_tiles(Cap cap, int X, int Y, int 
                                                      uint32_t* w, const uint8_t* act_in, uint8_t* act_out,
                                                      uint32_t* changed) {
     __shared__ uint32_t hw[HX * HY * HZ];
+    __shared__ uint32_t hc[kConn26 ? 1 : TX * TY * TZ];  // capacities, for the line scans
     __shared__ uint32_t face[6];
     const int tid = threadIdx.x;
     const int64_t tile = blockIdx.x;
@@ -96,34 +98,139 @@ __global__ __launch_bounds__(256) void k_relax_tiles(Cap cap, int X, int Y, int 
 #pragma unroll
     for (int j = 0; j < NV; j++) orig[j] = hw[(((j >> 1) + 1) * HY + (ly + 8 * (j & 1) + 1)) * HZ + (lz + 1)];
     bool any_change = false;
-    for (;;) {
-        bool ch = false;
+    if (!kConn26) {
+        // Rounds of line scans: along each axis every line is relaxed forward
+        // and backward in registers, w[i] = max(w[i], min(cap[i], w[i -+ 1])),
+        // so a value travels the whole line in one scan and a round moves it
+        // around as many corners as a path takes in the tile, where a
+        // neighbour-by-neighbour sweep needs as many rounds as the path has
+        // voxels. Each update only raises w towards the fixed point, so the
+        // result is the same.
 #pragma unroll
-        for (int j = 0; j < NV; j++) {
-            if (c[j] == 0) continue;
-            const int idx = (((j >> 1) + 1) * HY + (ly + 8 * (j & 1) + 1)) * HZ + (lz + 1);
-            const uint32_t cur = hw[idx];
-            if (cur >= c[j]) continue;
-            uint32_t nb;
-            if (kConn26) {
-                nb = 0;
+        for (int j = 0; j < NV; j++) hc[((j >> 1) * TY + (ly + 8 * (j & 1))) * TZ + lz] = c[j];
+        __syncthreads();
+        for (;;) {
+            bool ch = false;
+            if (tid < TX * TY) {  // lines along z (waves 0 and 1)
+                const int lx = tid >> 4, lyy = tid & 15;
+                const int base = ((lx + 1) * HY + (lyy + 1)) * HZ;
+                const int cb = (lx * TY + lyy) * TZ;
+                uint32_t v[HZ], cc[TZ];
 #pragma unroll
-                for (int dx = -1; dx <= 1; dx++)
+                for (int i = 0; i < HZ; i++) v[i] = hw[base + i];
 #pragma unroll
-                    for (int dy = -1; dy <= 1; dy++)
+                for (int i = 0; i < TZ; i++) cc[i] = hc[cb + i];
+                bool lc = false;
 #pragma unroll
-                        for (int dz = -1; dz <= 1; dz++)
-                            if (dx || dy || dz) nb = max(nb, hw[idx + (dx * HY + dy) * HZ + dz]);
-            } else {
-                nb = max(max(hw[idx - 1], hw[idx + 1]), max(hw[idx - HZ], hw[idx + HZ]));
-                nb = max(nb, max(hw[idx - HY * HZ], hw[idx + HY * HZ]));
+                for (int i = 1; i <= TZ; i++) {
+                    const uint32_t nv = max(v[i], min(cc[i - 1], v[i - 1]));
+                    lc |= nv != v[i];
+                    v[i] = nv;
+                }
+#pragma unroll
+                for (int i = TZ; i >= 1; i--) {
+                    const uint32_t nv = max(v[i], min(cc[i - 1], v[i + 1]));
+                    lc |= nv != v[i];
+                    v[i] = nv;
+                }
+                if (lc) {
+#pragma unroll
+                    for (int i = 1; i <= TZ; i++) hw[base + i] = v[i];
+                }
+                ch |= lc;
             }
-            const uint32_t cand = min(c[j], nb);
-            if (cand > cur) { hw[idx] = cand; ch = true; }
+            __syncthreads();
+            {  // lines along y: one per thread
+                const int lx = tid >> 5, lzz = tid & 31;
+                const int base = (lx + 1) * HY * HZ + (lzz + 1);
+                uint32_t v[HY], cc[TY];
+#pragma unroll
+                for (int i = 0; i < HY; i++) v[i] = hw[base + i * HZ];
+#pragma unroll
+                for (int i = 0; i < TY; i++) cc[i] = hc[(lx * TY + i) * TZ + lzz];
+                bool lc = false;
+#pragma unroll
+                for (int i = 1; i <= TY; i++) {
+                    const uint32_t nv = max(v[i], min(cc[i - 1], v[i - 1]));
+                    lc |= nv != v[i];
+                    v[i] = nv;
+                }
+#pragma unroll
+                for (int i = TY; i >= 1; i--) {
+                    const uint32_t nv = max(v[i], min(cc[i - 1], v[i + 1]));
+                    lc |= nv != v[i];
+                    v[i] = nv;
+                }
+                if (lc) {
+#pragma unroll
+                    for (int i = 1; i <= TY; i++) hw[base + i * HZ] = v[i];
+                }
+                ch |= lc;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int hh = 0; hh < 2; hh++) {  // lines along x: two per thread
+                const int line = tid + 256 * hh;
+                const int lyy = line >> 5, lzz = line & 31;
+                const int base = (lyy + 1) * HZ + (lzz + 1);
+                uint32_t v[HX], cc[TX];
+#pragma unroll
+                for (int i = 0; i < HX; i++) v[i] = hw[base + i * HY * HZ];
+#pragma unroll
+                for (int i = 0; i < TX; i++) cc[i] = hc[(i * TY + lyy) * TZ + lzz];
+                bool lc = false;
+#pragma unroll
+                for (int i = 1; i <= TX; i++) {
+                    const uint32_t nv = max(v[i], min(cc[i - 1], v[i - 1]));
+                    lc |= nv != v[i];
+                    v[i] = nv;
+                }
+#pragma unroll
+                for (int i = TX; i >= 1; i--) {
+                    const uint32_t nv = max(v[i], min(cc[i - 1], v[i + 1]));
+                    lc |= nv != v[i];
+                    v[i] = nv;
+                }
+                if (lc) {
+#pragma unroll
+                    for (int i = 1; i <= TX; i++) hw[base + i * HY * HZ] = v[i];
+                }
+                ch |= lc;
+            }
+            // wave-uniform exit (see the note on loop control in invade.hip)
+            if (!__builtin_amdgcn_readfirstlane(__syncthreads_or(ch))) break;
+            any_change = true;
         }
-        // wave-uniform exit (see the note on loop control in invade.hip)
-        if (!__builtin_amdgcn_readfirstlane(__syncthreads_or(ch))) break;
-        any_change = true;
+    } else {
+        for (;;) {
+            bool ch = false;
+#pragma unroll
+            for (int j = 0; j < NV; j++) {
+                if (c[j] == 0) continue;
+                const int idx = (((j >> 1) + 1) * HY + (ly + 8 * (j & 1) + 1)) * HZ + (lz + 1);
+                const uint32_t cur = hw[idx];
+                if (cur >= c[j]) continue;
+                uint32_t nb;
+                if (kConn26) {
+                    nb = 0;
+#pragma unroll
+                    for (int dx = -1; dx <= 1; dx++)
+#pragma unroll
+                        for (int dy = -1; dy <= 1; dy++)
+#pragma unroll
+                            for (int dz = -1; dz <= 1; dz++)
+                                if (dx || dy || dz) nb = max(nb, hw[idx + (dx * HY + dy) * HZ + dz]);
+                } else {
+                    nb = max(max(hw[idx - 1], hw[idx + 1]), max(hw[idx - HZ], hw[idx + HZ]));
+                    nb = max(nb, max(hw[idx - HY * HZ], hw[idx + HY * HZ]));
+                }
+                const uint32_t cand = min(c[j], nb);
+                if (cand > cur) { hw[idx] = cand; ch = true; }
+            }
+            // wave-uniform exit (see the note on loop control in invade.hip)
+            if (!__builtin_amdgcn_readfirstlane(__syncthreads_or(ch))) break;
+            any_change = true;
+        }
     }
     if (!any_change) return;
     bool wrote = false;
