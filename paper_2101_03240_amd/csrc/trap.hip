@@ -43,14 +43,16 @@ struct CapU32 {
 
 // One sweep over the active tiles. A tile whose boundary layer changed
 // activates the face-neighbour tiles across the changed faces for the next
-// sweep (act_out); *changed counts tiles that changed anything. kConn26: the
+// sweep (act_out); *changed counts tiles that changed anything. Each active
+// tile clears its own act_in flag, so act_in is all zero afterwards and
+// serves as act_out of the next sweep. kConn26: the
 // neighbours of a voxel are the 26 that share a face, an edge or a corner,
 // and the edge and corner tiles are activated too (a tile across an edge or
 // a corner when every face it lies across changed, which covers every
 // changed voxel on that edge or corner).
 template <class Cap, bool kConn26>
 __global__ __launch_bounds__(256) void k_relax_tiles(Cap cap, int X, int Y, int Z, int ntx, int nty, int ntz,
-                                                     uint32_t* w, const uint8_t* act_in, uint8_t* act_out,
+                                                     uint32_t* w, uint8_t* act_in, uint8_t* act_out,
                                                      uint32_t* changed) {
     __shared__ uint32_t hw[HX * HY * HZ];
     __shared__ uint32_t hc[kConn26 ? 1 : TX * TY * TZ];  // capacities, for the line scans
@@ -58,6 +60,8 @@ __global__ __launch_bounds__(256) void k_relax_tiles(Cap cap, int X, int Y, int 
     const int tid = threadIdx.x;
     const int64_t tile = blockIdx.x;
     if (!act_in[tile]) return;
+    __syncthreads();  // every thread has read the flag
+    if (tid == 0) act_in[tile] = 0;
     const int tz = (int)(tile % ntz);
     const int ty = (int)((tile / ntz) % nty);
     const int tx = (int)(tile / ((int64_t)ntz * nty));
@@ -337,14 +341,14 @@ ibip_status reconstruct(ibip_ctx* ctx, const int32_t* seq, const uint32_t* cap32
     uint32_t* h_changed = h + 512;
     ibip_status rc;
     if ((rc = hip_check(ctx, hipMemsetAsync(a0, 1, ntiles, s), "memset")) != IBIP_OK) return rc;
+    if ((rc = hip_check(ctx, hipMemsetAsync(a1, 0, ntiles, s), "memset")) != IBIP_OK) return rc;
     int it = 0;
     const int limit = 4 * (d.X + d.Y + d.Z) + 100000;
     for (;;) {
         if ((rc = hip_check(ctx, hipMemsetAsync(cnt, 0, sizeof(uint32_t) * kBatch, s), "memset")) != IBIP_OK) return rc;
         for (int b = 0; b < kBatch; b++, it++) {
             uint8_t* in = (it & 1) ? a1 : a0;
-            uint8_t* out = (it & 1) ? a0 : a1;
-            if ((rc = hip_check(ctx, hipMemsetAsync(out, 0, ntiles, s), "memset")) != IBIP_OK) return rc;
+            uint8_t* out = (it & 1) ? a0 : a1;  // all zero: cleared by the sweep that read it
             if (cap32)
                 hipLaunchKernelGGL((k_relax_tiles<CapU32, false>), dim3((unsigned)ntiles), dim3(256), 0, s,
                                    CapU32{cap32}, d.X, d.Y, d.Z, ntx, nty, ntz, w, in, out, cnt + b);
