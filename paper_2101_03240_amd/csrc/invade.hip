@@ -483,8 +483,8 @@ __device__ inline uint32_t small_step(uint32_t cnt, uint32_t k, uint32_t r, cons
     claim_pair(0, np, k, a, s, o0, u0);
     if (passes > 1) claim_pair(1, np, k, a, s, o1, u1);
     const uint32_t below = lds_highest_below_uni(s, r);
-    const uint32_t w0 = won_rank(o0), w1 = won_rank(o1);
     if (passes <= 2) {
+        const uint32_t w0 = won_rank(o0), w1 = won_rank(o1);
         const uint32_t pmax = wave_max_u32(max(w0, w1));
         const bool refilled = __ballot(w0 == r || w1 == r) != 0;
         if (!refilled) atomicAnd(&s.bits[r >> 5], ~(1u << (r & 31)));
@@ -495,17 +495,34 @@ __device__ inline uint32_t small_step(uint32_t cnt, uint32_t k, uint32_t r, cons
         if (passes > 1) push_pair(o1, u1, a, s, sel, logn, rd, dn);
         return rn;
     }
-    uint32_t lm = max(w0, w1);
-    bool same = w0 == r || w1 == r;
-    push_pair(o0, u0, a, s, sel, logn, 0u, dn);
-    push_pair(o1, u1, a, s, sel, logn, 0u, dn);
-    for (uint32_t p = 2; p < passes; p++) {
-        uint32_t o, u;
-        claim_pair(p, np, k, a, s, o, u);
-        const uint32_t w = won_rank(o);
-        lm = max(lm, w);
-        same |= w == r;
-        push_pair(o, u, a, s, sel, logn, 0u, dn);
+    // more passes (up to 12): the claims of passes 2-5 join those of passes
+    // 0 and 1 before the first wait, and passes 6-11 go in flight together
+    uint32_t lm = 0;
+    bool same = false;
+    for (uint32_t p = 2; p < passes; p += 4) {
+        uint32_t q0, v0, q1 = kClaim, v1 = 0, q2 = kClaim, v2 = 0, q3 = kClaim, v3 = 0;
+        claim_pair(p, np, k, a, s, q0, v0);
+        if (p + 1 < passes) claim_pair(p + 1, np, k, a, s, q1, v1);
+        if (p + 2 < passes) claim_pair(p + 2, np, k, a, s, q2, v2);
+        if (p + 3 < passes) claim_pair(p + 3, np, k, a, s, q3, v3);
+        if (p == 2) {
+            // (an empty asm that takes o0 and o1 keeps the compiler from
+            // computing their ranks, and so waiting for them, before the
+            // claims of passes 2-5 are issued)
+            asm volatile("" : "+v"(o0), "+v"(o1));
+            const uint32_t w0 = won_rank(o0), w1 = won_rank(o1);
+            lm = max(w0, w1);
+            same = w0 == r || w1 == r;
+            push_pair(o0, u0, a, s, sel, logn, 0u, dn);
+            push_pair(o1, u1, a, s, sel, logn, 0u, dn);
+        }
+        const uint32_t x0 = won_rank(q0), x1 = won_rank(q1), x2 = won_rank(q2), x3 = won_rank(q3);
+        lm = max(lm, max(max(x0, x1), max(x2, x3)));
+        same |= x0 == r || x1 == r || x2 == r || x3 == r;
+        push_pair(q0, v0, a, s, sel, logn, 0u, dn);
+        if (p + 1 < passes) push_pair(q1, v1, a, s, sel, logn, 0u, dn);
+        if (p + 2 < passes) push_pair(q2, v2, a, s, sel, logn, 0u, dn);
+        if (p + 3 < passes) push_pair(q3, v3, a, s, sel, logn, 0u, dn);
     }
     const uint32_t pmax = wave_max_u32(lm);
     const bool refilled = __ballot(same) != 0;
