@@ -803,7 +803,17 @@ struct PaintArgs {
     uint32_t* n_full;
     int X, Y, Z;
     bool integer_ball;  // footnote 1's integer sphere instead of the strict ball
+    FastDiv divZ, divY;  // voxel index -> coordinates (indices fit 31 bits)
 };
+
+// Coordinates of voxel c (c < 2^31) by two multiplicative divisions.
+__device__ inline void coords(uint32_t c, const PaintArgs& a, int& x, int& y, int& z) {
+    const uint32_t t = fdiv(c, a.divZ);
+    z = (int)(c - t * (uint32_t)a.Z);
+    const uint32_t xx = fdiv(t, a.divY);
+    y = (int)(t - xx * (uint32_t)a.Y);
+    x = (int)xx;
+}
 
 // The painted ball of a centre of squared distance m is {|o|^2 < ball_m(m)}:
 // m itself (the strict ball), or floor(sqrt(m))^2 + 1, i.e. the integer sphere
@@ -845,7 +855,8 @@ __global__ __launch_bounds__(256) void k_paint_shell(PaintArgs a) {
     if (k <= 0) return;
     const uint32_t rc = a.key[c] & kRankMask;
     const uint32_t m = ball_m(a, a.val[rc]);
-    const int z = (int)(c % a.Z), y = (int)((c / a.Z) % a.Y), x = (int)(c / yz);
+    int x, y, z;
+    coords((uint32_t)c, a, x, y, z);
     // neighbour j sits at c + n_j: axis j >> 1, sign (j & 1) ? +1 : -1
     const bool inb[6] = {x > 0, x < a.X - 1, y > 0, y < a.Y - 1, z > 0, z < a.Z - 1};
     const int64_t off[6] = {-yz, yz, -(int64_t)a.Z, (int64_t)a.Z, -1, 1};
@@ -933,7 +944,8 @@ __global__ __launch_bounds__(256) void k_paint_full(PaintArgs a) {
         const int64_t c = a.full[i];
         const int32_t k = a.state[c];
         const uint32_t m = ball_m(a, a.val[a.key[c] & kRankMask]);
-        const int z = (int)(c % a.Z), y = (int)((c / a.Z) % a.Y), x = (int)(c / yz);
+        int x, y, z;
+        coords((uint32_t)c, a, x, y, z);
         const int Rb = (int)isqrt_u32(m - 1);
         for (int dx = -Rb; dx <= Rb; dx++) {
             const int xx = x + dx;
@@ -1142,7 +1154,8 @@ ibip_status run_invade(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlet
     if (K > 0) hipLaunchKernelGGL(k_rank_to_value, dim3(blocks(K)), dim3(256), 0, s, M, K, val);
     // a5: sphere insertion
     PaintArgs pa{state, key, val, seq, full, &st->n_full, d.X, d.Y, d.Z,
-                 (ctx->readings & IBIP_READ_INTEGER_BALL) != 0};
+                 (ctx->readings & IBIP_READ_INTEGER_BALL) != 0, make_fastdiv((uint32_t)d.Z),
+                 make_fastdiv((uint32_t)d.Y)};
     hipLaunchKernelGGL(k_paint_shell, dim3(blocks(n)), dim3(256), 0, s, pa);
     hipLaunchKernelGGL(k_paint_full, dim3(2048), dim3(256), 0, s, pa);
     tm.mark(8, s);
@@ -1286,7 +1299,8 @@ hipError_t job_post(const JobBufs& j, LoopState* st, ibip_dims d, int64_t K, int
     const int64_t n = nvox(d);
     hipError_t e;
     if (K > 0) hipLaunchKernelGGL(k_rank_to_value, dim3(blocks(K)), dim3(256), 0, s, j.M, K, j.val);
-    PaintArgs pa{j.state, j.key, j.val, seq, j.full, &st->n_full, d.X, d.Y, d.Z, false};
+    PaintArgs pa{j.state, j.key, j.val, seq, j.full, &st->n_full, d.X, d.Y, d.Z, false,
+                 make_fastdiv((uint32_t)d.Z), make_fastdiv((uint32_t)d.Y)};
     hipLaunchKernelGGL(k_paint_shell, dim3(blocks(n)), dim3(256), 0, s, pa);
     hipLaunchKernelGGL(k_paint_full, dim3(std::min<int64_t>(blocks(n), 2048)), dim3(256), 0, s, pa);
     uint32_t* counts = j.counts;
@@ -1320,7 +1334,8 @@ hipError_t job_post_devk(const JobBufs& j, LoopState* st, ibip_dims d, int32_t* 
     const int64_t n = nvox(d);
     hipLaunchKernelGGL(k_rank_to_value_dev, dim3((unsigned)std::min<int64_t>(blocks(n), 1024)), dim3(256), 0, s,
                        j.M, st, j.val, M_out);
-    PaintArgs pa{j.state, j.key, j.val, seq, j.full, &st->n_full, d.X, d.Y, d.Z, false};
+    PaintArgs pa{j.state, j.key, j.val, seq, j.full, &st->n_full, d.X, d.Y, d.Z, false,
+                 make_fastdiv((uint32_t)d.Z), make_fastdiv((uint32_t)d.Y)};
     hipLaunchKernelGGL(k_paint_shell, dim3(blocks(n)), dim3(256), 0, s, pa);
     hipLaunchKernelGGL(k_paint_full, dim3(std::min<int64_t>(blocks(n), 2048)), dim3(256), 0, s, pa);
     hipLaunchKernelGGL(k_finalise, dim3(blocks(n)), dim3(256), 0, s, seq, j.state, true, n, j.M, rad2,

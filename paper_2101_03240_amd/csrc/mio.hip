@@ -21,7 +21,8 @@ namespace {
 // Seeds of the opening: pore voxels in Q0 (an inlet voxel or a face
 // neighbour of one); with mask, only pore inlet voxels count.
 __global__ __launch_bounds__(256) void k_mio_seed(const uint8_t* img, const uint8_t* inlets, const uint32_t* dt2,
-                                                  int X, int Y, int Z, uint32_t* k0, uint32_t* n_pore, bool mask) {
+                                                  int X, int Y, int Z, FastDiv divZ, FastDiv divY, uint32_t* k0,
+                                                  uint32_t* n_pore, bool mask) {
     const int64_t yz = (int64_t)Y * Z;
     const int64_t n = (int64_t)X * yz;
     const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -29,7 +30,9 @@ __global__ __launch_bounds__(256) void k_mio_seed(const uint8_t* img, const uint
     if (v < n) {
         // the seven positions are loaded together (an outside neighbour reads
         // v itself): a chain of conditional loads would wait for each in turn
-        const int z = (int)(v % Z), y = (int)((v / Z) % Y), x = (int)(v / yz);
+        // coordinates by multiplicative division (indices fit 31 bits)
+        const uint32_t t = fdiv((uint32_t)v, divZ), xx = fdiv(t, divY);
+        const int z = (int)((uint32_t)v - t * (uint32_t)Z), y = (int)(t - xx * (uint32_t)Y), x = (int)xx;
         const int64_t nb[7] = {v, x > 0 ? v - yz : v, x < X - 1 ? v + yz : v, y > 0 ? v - Z : v,
                                y < Y - 1 ? v + Z : v, z > 0 ? v - 1 : v, z < Z - 1 ? v + 1 : v};
         const uint32_t d = dt2[v];
@@ -91,8 +94,8 @@ ibip_status run_mio(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlets, 
     if ((rc = hip_check(ctx, hipMemsetAsync(mio_r2, 0, sizeof(uint32_t) * n, s), "memset")) != IBIP_OK) return rc;
     if ((rc = hip_check(ctx, launch_edt(image, nullptr, 0, 0, d, g16, tmp32, dt2, &flags[0], s), "edt")) != IBIP_OK)
         return rc;
-    hipLaunchKernelGGL(k_mio_seed, dim3(blocks(n)), dim3(256), 0, s, image, inlets, dt2, d.X, d.Y, d.Z, kmap,
-                       pore_slots, (ctx->readings & IBIP_READ_MASK_INLETS) != 0);
+    hipLaunchKernelGGL(k_mio_seed, dim3(blocks(n)), dim3(256), 0, s, image, inlets, dt2, d.X, d.Y, d.Z,
+                       make_fastdiv((uint32_t)d.Z), make_fastdiv((uint32_t)d.Y), kmap, pore_slots, (ctx->readings & IBIP_READ_MASK_INLETS) != 0);
     if ((rc = hip_check(ctx, hipMemcpyAsync(h, flags, 4, hipMemcpyDeviceToHost, s), "copy")) != IBIP_OK) return rc;
     if ((rc = hip_check(ctx, hipMemcpyAsync(h + 64, pore_slots, sizeof(uint32_t) * kCountSlots,
                                             hipMemcpyDeviceToHost, s), "copy")) != IBIP_OK)
