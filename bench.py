@@ -385,7 +385,9 @@ def main() -> int:
         "edt (3 passes, inside invade)": (tm["edt_ms"] / S, EDT_BYTES_PER_VOXEL * n_vox, S),
         "step loop (single-workgroup kernel)": (
             tm["loop_kernel_ms"] / max(tm["loop_launches"], 1),
-            LOOP_BYTES_PER_CENTRE * tm["popped"] / max(tm["loop_launches"], 1), tm["loop_launches"]),
+            # centres of the steps this kernel ran (the wide steps' centres go to k_wide)
+            LOOP_BYTES_PER_CENTRE * (tm["popped"] - tm["wide_centres"]) / max(tm["loop_launches"], 1),
+            tm["loop_launches"]),
         "sphere insertion": (tm["paint_ms"] / S, PAINT_BYTES_PER_PORE * n_pore, S),
         "trapping": (tm["trap_ms"] / S, TRAP_BYTES_PER_VOXEL * n_vox, S),
         "opening drainage": (tm["mio_ms"] / S, MIO_BYTES_PER_VOXEL_RADIUS * n_vox * len(T), S),
