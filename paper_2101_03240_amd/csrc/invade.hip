@@ -315,6 +315,27 @@ __device__ inline uint32_t next_top(LoopShared& s, uint32_t r, bool up, uint32_t
     return next_top_known(s, r, up, uni(s.tail[r]) > uni(s.head[r]), R);
 }
 
+// Claims of a wide step (run over the whole GPU): each key is read first
+// (from L2, not the CU cache, which atomics do not update) and the atomic
+// goes only to voxels that read unclaimed pore. A voxel claimed earlier, or
+// solid, costs a load instead of an atomic; the atomic still decides every
+// race. Wide steps issue millions of claims and are bound by the atomic rate;
+// steps run inside one workgroup are bound by latency, and the extra round
+// trip made them slower, so they claim directly.
+template <int N>
+__device__ inline void claim_filtered(const uint32_t* key_ro, uint32_t* key, const int64_t (&uu)[N],
+                                      const bool (&okd)[N], uint32_t c, uint32_t (&old)[N]) {
+    uint32_t pre[N];
+#pragma unroll
+    for (int j = 0; j < N; j++)
+        pre[j] = __hip_atomic_load(&key_ro[okd[j] ? uu[j] : (int64_t)c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+    for (int j = 0; j < N; j++) {
+        const bool go = okd[j] && !(pre[j] & kClaim) && (pre[j] & kRankMask) != 0;
+        old[j] = go ? atomicOr(&key[uu[j]], kClaim) : kClaim;
+    }
+}
+
 // Make c a centre of step k and claim its unseen pore face neighbours: one
 // atomicOr per neighbour sets the claim bit and returns the rank, so a claim
 // costs one round trip; the six claims are in flight together. The claimed
@@ -755,8 +776,7 @@ __device__ inline void expand_global(bool have, uint32_t c, uint32_t k, const Lo
     const bool okd[6] = {have && x > 0, have && x < a.X - 1, have && y > 0, have && y < a.Y - 1,
                          have && z > 0, have && z < a.Z - 1};
     uint32_t old[6];
-#pragma unroll
-    for (int j = 0; j < 6; j++) old[j] = okd[j] ? atomicOr(&a.key[uu[j]], kClaim) : kClaim;
+    claim_filtered<6>(a.key, a.key, uu, okd, c, old);
     // pushes grouped by rank per direction; every group's tail atomic is in
     // flight before the first result is used
     RankGroup g[6];
