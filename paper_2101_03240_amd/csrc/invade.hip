@@ -42,8 +42,16 @@ namespace ibip {
 
 namespace {
 
-// largest q with q * q <= a (64-bit products: no overflow for any a)
+// largest q with q * q <= a. Below 2^24 a is exact as a float and the float
+// square root is within one of the answer, so one step each way corrects it
+// in 32-bit arithmetic; larger a take 64-bit correction loops.
 __device__ inline uint32_t isqrt_u32(uint32_t a) {
+    if (a < (1u << 24)) {
+        uint32_t q = (uint32_t)sqrtf((float)a);
+        q -= q * q > a ? 1u : 0u;
+        q += (q + 1u) * (q + 1u) <= a ? 1u : 0u;
+        return q;
+    }
     uint64_t q = (uint64_t)sqrtf((float)a);
     while (q * q > a) q--;
     while ((q + 1) * (q + 1) <= a) q++;
@@ -854,7 +862,7 @@ __device__ inline uint32_t ball_m(const PaintArgs& a, uint32_t m) {
 // load per stamp taken in turn would cost a round trip each.
 constexpr int kStampGroup = 4;
 
-__device__ inline void stamp_group(int32_t* seq, const int64_t (&v)[kStampGroup], const bool (&ok)[kStampGroup],
+__device__ inline void stamp_group(int32_t* seq, const uint32_t (&v)[kStampGroup], const bool (&ok)[kStampGroup],
                                    int32_t k) {
     int32_t cur[kStampGroup];
 #pragma unroll
@@ -915,39 +923,50 @@ __global__ __launch_bounds__(256) void k_paint_shell(PaintArgs a) {
     const int A = j0 >> 1;                  // axis of the cap
     const int sgn = (j0 & 1) ? -1 : 1;      // cap on the side away from the neighbour
     const int B = (A + 1) % 3, C = (A + 2) % 3;
-    const int pos[3] = {x, y, z};
-    const int dim[3] = {a.X, a.Y, a.Z};
-    const int64_t stride[3] = {yz, (int64_t)a.Z, 1};
+    // per-axis values of A, B and C, chosen once (indices fit 31 bits, so the
+    // stamp addresses are 32-bit sums)
+    const int yzi = a.Y * a.Z;
+    const int posA = A == 0 ? x : A == 1 ? y : z, posB = B == 0 ? x : B == 1 ? y : z, posC = C == 0 ? x : C == 1 ? y : z;
+    const int dimA = A == 0 ? a.X : A == 1 ? a.Y : a.Z, dimB = B == 0 ? a.X : B == 1 ? a.Y : a.Z;
+    const int dimC = C == 0 ? a.X : C == 1 ? a.Y : a.Z;
+    const int sA = A == 0 ? yzi : A == 1 ? a.Z : 1, sB = B == 0 ? yzi : B == 1 ? a.Z : 1;
+    const int sC = C == 0 ? yzi : C == 1 ? a.Z : 1;
+    // the other preceding neighbours filter the cap: neighbour j tests
+    // |o - n_j|^2 = |o|^2 - 2 s_j o_(axis j) + 1 < mp[j], where o_(axis j) is
+    // the cap offset along A (0), B (1) or C (2)
+    const uint32_t rest0 = qmask & ~(1u << j0);
+    int comp[6];
+#pragma unroll
+    for (int j = 0; j < 6; j++) comp[j] = (j >> 1) == A ? 0 : (j >> 1) == B ? 1 : 2;
     const int Rb = (int)isqrt_u32(m - 1);
     for (int p = -Rb; p <= Rb; p++) {
-        const int pb = pos[B] + p;
-        if (pb < 0 || pb >= dim[B]) continue;
+        const int pb = posB + p;
+        if (pb < 0 || pb >= dimB) continue;
         const uint32_t rem = m - 1 - (uint32_t)(p * p);
         const int U = (int)isqrt_u32(rem);
         for (int q0 = -U; q0 <= U; q0 += kStampGroup) {
-            int64_t tv[kStampGroup];
+            uint32_t tv[kStampGroup];
             bool tok[kStampGroup];
 #pragma unroll
             for (int t = 0; t < kStampGroup; t++) {
                 const int q = q0 + t;
-                const int pc = pos[C] + q;
+                const int pc = posC + q;
                 const int w = q <= U ? (int)isqrt_u32(rem - (uint32_t)(q * q)) : 0;
                 const int oa = sgn * w;
-                const int pa = pos[A] + oa;
-                bool ok = q <= U && pc >= 0 && pc < dim[C] && pa >= 0 && pa < dim[A];
-                int o[3];
-                o[A] = oa; o[B] = p; o[C] = q;
+                const int pa = posA + oa;
+                bool ok = q <= U && pc >= 0 && pc < dimC && pa >= 0 && pa < dimA;
                 const uint32_t oo = (uint32_t)(w * w + p * p + q * q);
-                uint32_t rest = ok ? qmask & ~(1u << j0) : 0u;
+                uint32_t rest = ok ? rest0 : 0u;
                 while (rest) {
                     const int j = __ffs(rest) - 1;
                     rest &= rest - 1;
                     const int sj = (j & 1) ? 1 : -1;      // n_j component
-                    const uint32_t d = oo - 2 * sj * o[j >> 1] + 1;  // |o - n_j|^2
+                    const int oj = comp[j] == 0 ? oa : comp[j] == 1 ? p : q;
+                    const uint32_t d = oo - 2 * sj * oj + 1;  // |o - n_j|^2
                     if (d < mp[j]) { ok = false; break; }
                 }
                 tok[t] = ok;
-                tv[t] = ok ? c + (int64_t)oa * stride[A] + (int64_t)p * stride[B] + (int64_t)q * stride[C] : c;
+                tv[t] = ok ? (uint32_t)((int)c + oa * sA + p * sB + q * sC) : (uint32_t)c;
             }
             stamp_group(a.seq, tv, tok, k);
         }
@@ -977,14 +996,14 @@ __global__ __launch_bounds__(256) void k_paint_full(PaintArgs a) {
                 if (yy < 0 || yy >= a.Y) continue;
                 const int W = (int)isqrt_u32(rem - (uint32_t)(dy * dy));
                 const int z0 = max(z - W, 0), z1 = min(z + W, a.Z - 1);
-                const int64_t rowv = ((int64_t)xx * a.Y + yy) * a.Z;
+                const uint32_t rowv = ((uint32_t)xx * (uint32_t)a.Y + (uint32_t)yy) * (uint32_t)a.Z;
                 for (int zz = z0; zz <= z1; zz += kStampGroup) {
-                    int64_t tv[kStampGroup];
+                    uint32_t tv[kStampGroup];
                     bool tok[kStampGroup];
 #pragma unroll
                     for (int t = 0; t < kStampGroup; t++) {
                         tok[t] = zz + t <= z1;
-                        tv[t] = rowv + min(zz + t, z1);
+                        tv[t] = rowv + (uint32_t)min(zz + t, z1);
                     }
                     stamp_group(a.seq, tv, tok, k);
                 }
