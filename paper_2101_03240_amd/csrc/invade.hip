@@ -2,9 +2,11 @@
 // post-processing (Sections 2.2.1-2.2.2).
 //
 // Data layout in HBM (N voxels, N_pore pore voxels, R distinct dt2 values):
-//   key[N]      uint32  rank of dt2 among the distinct pore values (1..R), 0 on solid
-//   key[N] bit 31 marks a voxel claimed as a candidate (one atomicOr claims
-//               a neighbour and returns its rank)
+//   key[N]      uint32  bits 0..23: rank of dt2 among the distinct pore values
+//               (1..R), 0 on solid; bits 24..29: which of the six face
+//               neighbours lie inside the image (pore voxels only); bit 31:
+//               claimed as a candidate (one atomicOr claims a neighbour and
+//               returns its rank and its in-image neighbours)
 //   state[N]    int32   k > 0: centre of step k; 0 otherwise
 //   bucket[N_pore] uint32  candidates grouped by rank; rank r owns the slice
 //               [off[r], off[r+1]) whose length is the number of pore voxels
@@ -58,10 +60,21 @@ __device__ inline uint32_t isqrt_u32(uint32_t a) {
     return (uint32_t)q;
 }
 
-// Key words: bits 0..30 hold the rank of dt2 among the distinct pore values
-// (0 on solid); bit 31 marks a voxel claimed as a candidate.
+// Key words: bits 0..23 hold the rank of dt2 among the distinct pore values
+// (0 on solid); bit 24 + d is set when the face neighbour in direction d
+// (0 -x, 1 +x, 2 -y, 3 +y, 4 -z, 5 +z) lies inside the image; bit 31 marks
+// a voxel claimed as a candidate. A claim thus returns, with the rank, what a
+// later step needs to claim the voxel's own neighbours without dividing its
+// index into coordinates.
 constexpr uint32_t kClaim = 0x80000000u;
-constexpr uint32_t kRankMask = 0x7FFFFFFFu;
+constexpr uint32_t kRankMask = 0x00FFFFFFu;
+constexpr int kNbShift = 24;
+
+// in-image neighbour bits of the voxel at (x, y, z)
+__device__ inline uint32_t nb_bits(uint32_t x, uint32_t y, uint32_t z, int X, int Y, int Z) {
+    return (x > 0 ? 1u : 0u) | (x + 1 < (uint32_t)X ? 2u : 0u) | (y > 0 ? 4u : 0u) |
+           (y + 1 < (uint32_t)Y ? 8u : 0u) | (z > 0 ? 16u : 0u) | (z + 1 < (uint32_t)Z ? 32u : 0u);
+}
 
 __device__ inline uint64_t lanemask_lt() {
     const int lane = threadIdx.x & 63;
@@ -124,10 +137,12 @@ __global__ void k_rank_tables(const uint32_t* cnt_scanned, const uint32_t* prese
     tail[r] = cnt_scanned[v];
 }
 
-// key = rank (0 on solid); state = 0; seq = INT_MAX on pore, -1 on solid.
+// key = rank and in-image neighbour bits (0 on solid); state = 0;
+// seq = INT_MAX on pore, -1 on solid.
 __global__ __launch_bounds__(256) void k_convert(const uint8_t* __restrict__ img, uint32_t* key,
                                                  const uint32_t* __restrict__ present_scanned, int64_t n,
-                                                 uint32_t vlimit, int32_t* state, int32_t* seq) {
+                                                 uint32_t vlimit, int32_t* state, int32_t* seq, int X, int Y, int Z,
+                                                 FastDiv divZ, FastDiv divY) {
     int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (v >= n) return;
     state[v] = 0;
@@ -135,7 +150,9 @@ __global__ __launch_bounds__(256) void k_convert(const uint8_t* __restrict__ img
         const uint32_t d = key[v];
         // d >= vlimit only without any solid voxel; such images are rejected
         const uint32_t rk = d < vlimit ? present_scanned[d] + 1 : 0u;
-        key[v] = rk > (uint32_t)kMaxRanks ? 0u : rk;
+        const uint32_t t = fdiv((uint32_t)v, divZ), xx = fdiv(t, divY);
+        const uint32_t nb = nb_bits(xx, t - xx * (uint32_t)Y, (uint32_t)v - t * (uint32_t)Z, X, Y, Z);
+        key[v] = rk > (uint32_t)kMaxRanks ? 0u : rk | (nb << kNbShift);
         seq[v] = INT_MAX;
     } else {
         key[v] = 0;
@@ -242,11 +259,18 @@ struct LoopShared {
     uint32_t logr[2][kLog];
     uint32_t logn[2];           // pushes counted (more than kLog = log incomplete)
     uint32_t cl[kSmallRound];   // centres of a small step gathered from the log
+    uint8_t clb[kSmallRound];   // their in-image neighbour bits
     // descriptor of a step run by all waves
     uint32_t d_exit, d_h, d_cnt, d_k, d_r, d_fromlog, d_sel, d_up;
 };
 
 __device__ inline uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+
+// in-image neighbour bits of voxel c, from its coordinates
+__device__ inline uint32_t nb_of(uint32_t c, const LoopArgs& a) {
+    const uint32_t t = fdiv(c, a.divZ), x = fdiv(t, a.divY);
+    return nb_bits(x, t - x * (uint32_t)a.Y, c - t * (uint32_t)a.Z, a.X, a.Y, a.Z);
+}
 
 
 // Position of a push into the LDS slice of rank rr, and that slice's head.
@@ -426,7 +450,7 @@ __device__ inline uint32_t expand_lds(const bool (&have)[NC], const uint32_t (&c
         const uint32_t li = lbase + before[j] + (uint32_t)__popcll(m[j] & lt);
         if (li < kLog) {
             s.logu[sel][li] = (uint32_t)uu[j];
-            s.logr[sel][li] = rr[j];
+            s.logr[sel][li] = old[j] & ~kClaim;  // rank and in-image neighbour bits
         }
     }
     return mymax;
@@ -445,16 +469,11 @@ __device__ inline void claim_pair(uint32_t p, uint32_t np, uint32_t k, const Loo
     const uint32_t ci = act ? i / 6u : 0u;
     const uint32_t dir = i - ci * 6u;
     const uint32_t c = act ? s.cl[ci] : 0u;
-    const uint32_t t = fdiv(c, a.divZ);
-    const uint32_t z = c - t * (uint32_t)a.Z;
-    const uint32_t x = fdiv(t, a.divY);
-    const uint32_t y = t - x * (uint32_t)a.Y;
+    const uint32_t nb = act ? s.clb[ci] : 0u;  // the centre's in-image neighbours
     const uint32_t axis = dir >> 1;
     const bool up = dir & 1u;
     const uint32_t stride = axis == 0 ? (uint32_t)a.Y * (uint32_t)a.Z : axis == 1 ? (uint32_t)a.Z : 1u;
-    const uint32_t coord = axis == 0 ? x : axis == 1 ? y : z;
-    const uint32_t last = axis == 0 ? (uint32_t)a.X - 1u : axis == 1 ? (uint32_t)a.Y - 1u : (uint32_t)a.Z - 1u;
-    const bool ok = act && (up ? coord < last : coord > 0u);
+    const bool ok = act && ((nb >> dir) & 1u);
     u = up ? c + stride : c - stride;
     old = kClaim;
     if (ok) old = atomicOr(&a.key[u], kClaim);
@@ -490,9 +509,12 @@ __device__ inline void push_pair(uint32_t old, uint32_t u, const LoopArgs& a, Lo
         if (pos == hd) lds_set(s, rr);
         if (li < kLog) {
             s.logu[sel][li] = u;
-            s.logr[sel][li] = rr;
+            s.logr[sel][li] = old & ~kClaim;  // rank and in-image neighbour bits
         }
-        if (nx && di < kSmallRound) s.cl[di] = u;
+        if (nx && di < kSmallRound) {
+            s.cl[di] = u;
+            s.clb[di] = (uint8_t)(old >> kNbShift);
+        }
     }
 }
 
@@ -666,10 +688,14 @@ __device__ inline void loop_body(const LoopArgs& a, LoopShared& s) {
                     uint32_t got = 0;
                     for (uint32_t b0 = 0; b0 < n; b0 += 64) {
                         const uint32_t i = b0 + lane;
-                        const bool match = i < n && s.logr[sel][i] == r;
+                        const uint32_t lr = i < n ? s.logr[sel][i] : 0u;
+                        const bool match = (lr & kRankMask) == r;
                         const uint64_t mm = __ballot(match);
                         const uint32_t slot = got + (uint32_t)__popcll(mm & lanemask_lt());
-                        if (match && slot < kSmallRound) s.cl[slot] = s.logu[sel][i];
+                        if (match && slot < kSmallRound) {
+                            s.cl[slot] = s.logu[sel][i];
+                            s.clb[slot] = (uint8_t)(lr >> kNbShift);
+                        }
                         got += (uint32_t)__popcll(mm);
                     }
                 } else {
@@ -678,11 +704,15 @@ __device__ inline void loop_body(const LoopArgs& a, LoopShared& s) {
                     // condition would leave its register pending past this
                     // block, and the compiler would then wait for every
                     // outstanding store before the claims.
+                    // (the bucket holds voxel indices only: their neighbour bits
+                    // come from their coordinates)
                     const uint32_t c0 = a.bucket[h + min((uint32_t)lane, cnt - 1u)];
                     s.cl[lane] = c0;
+                    s.clb[lane] = (uint8_t)nb_of(c0, a);
                     if (cnt > 64) {
                         const uint32_t c1 = a.bucket[h + min((uint32_t)lane + 64u, cnt - 1u)];
                         s.cl[lane + 64] = c1;
+                        s.clb[lane + 64] = (uint8_t)nb_of(c1, a);
                     }
                 }
                 bool dnext = false;
@@ -712,7 +742,7 @@ __device__ inline void loop_body(const LoopArgs& a, LoopShared& s) {
                     bool have = false;
                     uint32_t c = 0;
                     if (i < n) {
-                        have = s.logr[osel][i] == rr0;
+                        have = (s.logr[osel][i] & kRankMask) == rr0;
                         c = s.logu[osel][i];
                     }
                     const bool hv[1] = {have};
@@ -1131,7 +1161,7 @@ ibip_status run_invade(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlet
     if ((rc = hip_check(ctx, hipMemsetAsync(tail, 0, sizeof(uint32_t) * (R + 2), s), "memset")) != IBIP_OK) return rc;
     hipLaunchKernelGGL(k_rank_tables, dim3(blocks(V)), dim3(256), 0, s, hist, present, flags, V, val, off, head, tail);
     hipLaunchKernelGGL(k_convert, dim3(blocks(n)), dim3(256), 0, s, image, key, present, n, (uint32_t)(V - 1), state,
-                       seq);
+                       seq, d.X, d.Y, d.Z, make_fastdiv((uint32_t)d.Z), make_fastdiv((uint32_t)d.Y));
     hipLaunchKernelGGL(k_seed, dim3(blocks(n)), dim3(256), 0, s, inlets, key, d.X, d.Y, d.Z, tail, bucket,
                        (ctx->readings & IBIP_READ_MASK_INLETS) != 0);
     tm.mark(2, s);
@@ -1327,7 +1357,7 @@ hipError_t job_setup(const JobBufs& j, LoopState* st, const uint8_t* image, cons
     hipLaunchKernelGGL(k_rank_tables, dim3(blocks(V)), dim3(256), 0, s, j.hist, present, flags, V, j.val, j.off,
                        j.head, j.tail);
     hipLaunchKernelGGL(k_convert, dim3(blocks(n)), dim3(256), 0, s, image, j.key, present, n, (uint32_t)(V - 1),
-                       j.state, seq);
+                       j.state, seq, d.X, d.Y, d.Z, make_fastdiv((uint32_t)d.Z), make_fastdiv((uint32_t)d.Y));
     hipLaunchKernelGGL(k_seed, dim3(blocks(n)), dim3(256), 0, s, inlets, j.key, d.X, d.Y, d.Z, j.tail, j.bucket,
                        false);
     return hipGetLastError();
