@@ -468,8 +468,9 @@ __device__ inline void claim_pair(uint32_t p, uint32_t np, uint32_t k, const Loo
     const bool act = i < np;
     const uint32_t ci = act ? i / 6u : 0u;
     const uint32_t dir = i - ci * 6u;
-    const uint32_t c = act ? s.cl[ci] : 0u;
-    const uint32_t nb = act ? s.clb[ci] : 0u;  // the centre's in-image neighbours
+    // slot ci (0 on idle lanes) lies inside s.cl: the reads need no lane condition
+    const uint32_t c = s.cl[ci];
+    const uint32_t nb = s.clb[ci];  // the centre's in-image neighbours
     const uint32_t axis = dir >> 1;
     const bool up = dir & 1u;
     const uint32_t stride = axis == 0 ? (uint32_t)a.Y * (uint32_t)a.Z : axis == 1 ? (uint32_t)a.Z : 1u;
