@@ -623,6 +623,10 @@ __device__ inline void loop_body(const LoopArgs& a, LoopShared& s) {
     __syncthreads();
     const int64_t max_steps = a.st->max_steps;
     const uint32_t n_pore = a.st->n_pore;
+    // one bound for both stops: steps past max_steps, or more steps than pore
+    // voxels (every step takes at least one new pore voxel)
+    const uint32_t klim =
+        max_steps > 0 && max_steps < (int64_t)n_pore ? (uint32_t)max_steps : n_pore;
     // driver state, live in wave 0
     uint32_t r = 0, k = 0, prev_r = 0, sel = 0, nlog = 0, npop = 0;
     bool log_ok = false, direct = false;
@@ -633,21 +637,17 @@ __device__ inline void loop_body(const LoopArgs& a, LoopShared& s) {
     for (;;) {
         if (wave0) {
             for (;;) {
-                uint32_t ex = 0;
-                if (r == 0) {
-                    a.st->status = LS_DONE;
-                    ex = 1;
-                } else if (k > n_pore) {
-                    // every step takes at least one new pore voxel: more steps than
-                    // pore voxels means corrupted state; stop instead of looping
-                    a.st->err = 1;
-                    a.st->status = LS_DONE;
-                    ex = 1;
-                } else if (max_steps > 0 && (int64_t)k > max_steps) {
-                    a.st->status = LS_MAXSTEPS;
-                    ex = 1;
-                }
-                if (ex) {
+                if (r == 0 || k > klim) {
+                    if (r == 0) {
+                        a.st->status = LS_DONE;
+                    } else if (k > n_pore) {
+                        // more steps than pore voxels means corrupted state; stop
+                        // instead of looping
+                        a.st->err = 1;
+                        a.st->status = LS_DONE;
+                    } else {
+                        a.st->status = LS_MAXSTEPS;
+                    }
                     s.d_exit = 1;
                     break;
                 }
