@@ -655,21 +655,20 @@ __device__ inline void loop_body(const LoopArgs& a, LoopShared& s) {
                 const uint32_t cnt = t - h;
                 s.head[r] = t;
                 const bool fromlog = log_ok && (direct || r >= prev_r);
-                if (cnt <= a.wide) npop += cnt;  // a wide step's centres are counted by the host
-                if (cnt > a.small) a.M[k - 1] = r;  // rank; k_rank_to_value turns it into dt2 after the loop
-                if (cnt > a.wide) {
-                    a.st->big_r = r;
-                    a.st->big_h = h;
-                    a.st->big_t = t;
-                    a.st->big_k = k;
-                    a.st->status = LS_WIDE;
-                    k = k + 1;
-                    s.d_exit = 1;
-                    break;
-                }
-                const uint32_t nsel = sel ^ 1u;
-                s.logn[nsel] = 0;
                 if (cnt > a.small) {
+                    a.M[k - 1] = r;  // rank; k_rank_to_value turns it into dt2 after the loop
+                    if (cnt > a.wide) {  // its centres are counted by the host
+                        a.st->big_r = r;
+                        a.st->big_h = h;
+                        a.st->big_t = t;
+                        a.st->big_k = k;
+                        a.st->status = LS_WIDE;
+                        k = k + 1;
+                        s.d_exit = 1;
+                        break;
+                    }
+                    npop += cnt;
+                    s.logn[sel ^ 1u] = 0;  // the waves count their pushes there
                     s.d_up = 0;
                     s.d_exit = 0;
                     s.d_h = h;
@@ -680,6 +679,8 @@ __device__ inline void loop_body(const LoopArgs& a, LoopShared& s) {
                     s.d_sel = sel;
                     break;
                 }
+                npop += cnt;
+                const uint32_t nsel = sel ^ 1u;
                 // a small step, wave 0 alone: its centres are listed in s.cl by the
                 // previous step, or gathered there from the log or the bucket
                 uint32_t ln = 0;  // entries in the new push log
