@@ -527,13 +527,17 @@ __device__ inline void push_pair(uint32_t old, uint32_t u, const LoopArgs& a, Lo
 // the pushes: if every live entry of its slice is a push of this step (it is
 // not `below`), the pushes list them in s.cl and `direct` is set, so the next
 // step gathers nothing.
-__device__ inline uint32_t small_step(uint32_t cnt, uint32_t k, uint32_t r, const LoopArgs& a, LoopShared& s,
-                                      uint32_t sel, uint32_t& logn, bool& direct) {
+__device__ inline uint32_t small_step(uint32_t cnt, uint32_t k, uint32_t r, uint32_t t, const LoopArgs& a,
+                                      LoopShared& s, uint32_t sel, uint32_t& logn, bool& direct) {
     const uint32_t np = 6 * cnt;
     const uint32_t passes = (np + 63) >> 6;
     uint32_t o0, u0, o1 = kClaim, u1 = 0, dn = 0;
     claim_pair(0, np, k, a, s, o0, u0);
     if (passes > 1) claim_pair(1, np, k, a, s, o1, u1);
+    // pop slice r (its head moves to tail t) once the claims are out: only the
+    // pushes read it, and LDS operations complete in order, so a write ahead of
+    // the centre reads would delay them
+    s.head[r] = t;
     const uint32_t below = lds_highest_below_uni(s, r);
     if (passes <= 2) {
         const uint32_t w0 = won_rank(o0), w1 = won_rank(o1);
@@ -653,9 +657,9 @@ __device__ inline void loop_body(const LoopArgs& a, LoopShared& s) {
                 }
                 const uint32_t h = uni(s.head[r]), t = uni(s.tail[r]);
                 const uint32_t cnt = t - h;
-                s.head[r] = t;
                 const bool fromlog = log_ok && (direct || r >= prev_r);
                 if (cnt > a.small) {
+                    s.head[r] = t;
                     a.M[k - 1] = r;  // rank; k_rank_to_value turns it into dt2 after the loop
                     if (cnt > a.wide) {  // its centres are counted by the host
                         a.st->big_r = r;
@@ -718,7 +722,7 @@ __device__ inline void loop_body(const LoopArgs& a, LoopShared& s) {
                     }
                 }
                 bool dnext = false;
-                const uint32_t rn = small_step(cnt, k, r, a, s, nsel, ln, dnext);
+                const uint32_t rn = small_step(cnt, k, r, t, a, s, nsel, ln, dnext);
                 a.M[k - 1] = r;
                 s.logn[nsel] = ln;
                 prev_r = r;
