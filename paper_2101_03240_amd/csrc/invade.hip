@@ -672,6 +672,7 @@ __device__ inline void loop_body(const LoopArgs& a, LoopShared& s) {
                         break;
                     }
                     npop += cnt;
+                    s.logn[sel] = nlog;    // the log this step may gather from
                     s.logn[sel ^ 1u] = 0;  // the waves count their pushes there
                     s.d_up = 0;
                     s.d_exit = 0;
@@ -724,7 +725,6 @@ __device__ inline void loop_body(const LoopArgs& a, LoopShared& s) {
                 bool dnext = false;
                 const uint32_t rn = small_step(cnt, k, r, t, a, s, nsel, ln, dnext);
                 a.M[k - 1] = r;
-                s.logn[nsel] = ln;
                 prev_r = r;
                 r = rn;
                 direct = dnext;
