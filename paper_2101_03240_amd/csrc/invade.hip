@@ -488,9 +488,12 @@ __device__ inline uint32_t won_rank(uint32_t old) {
     return !(old & kClaim) && rr != 0 ? rr : 0u;
 }
 
-// Push the voxel of a won claim into the LDS slice of its rank and the push
-// log; a push of rank rn (the next step's rank, when every live entry of its
-// slice comes from this step) is also listed in s.cl for the next step.
+// Push the voxel of a won claim into the LDS slice of its rank and (kLogged)
+// the push log; a push of rank rn (the next step's rank, when every live
+// entry of its slice comes from this step) is also listed in s.cl for the
+// next step. A step of at most two passes needs no log: the step after it
+// either takes the list in s.cl or pops an older slice, from the bucket.
+template <bool kLogged>
 __device__ inline void push_pair(uint32_t old, uint32_t u, const LoopArgs& a, LoopShared& s, uint32_t sel,
                                  uint32_t& logn, uint32_t rn, uint32_t& dn) {
     const uint32_t rr = won_rank(old);
@@ -498,9 +501,12 @@ __device__ inline void push_pair(uint32_t old, uint32_t u, const LoopArgs& a, Lo
     uint32_t pos, hd;
     slice_pos(s, won, rr, pos, hd);
     const uint64_t lt = lanemask_lt();
-    const uint64_t m = __ballot(won);
-    const uint32_t li = logn + (uint32_t)__popcll(m & lt);
-    logn += (uint32_t)__popcll(m);
+    uint32_t li = 0;
+    if (kLogged) {
+        const uint64_t m = __ballot(won);
+        li = logn + (uint32_t)__popcll(m & lt);
+        logn += (uint32_t)__popcll(m);
+    }
     const bool nx = won && rr == rn;
     const uint64_t mn = __ballot(nx);
     const uint32_t di = dn + (uint32_t)__popcll(mn & lt);
@@ -508,7 +514,7 @@ __device__ inline void push_pair(uint32_t old, uint32_t u, const LoopArgs& a, Lo
     if (won) {
         a.bucket[pos] = u;
         if (pos == hd) lds_set(s, rr);
-        if (li < kLog) {
+        if (kLogged && li < kLog) {
             s.logu[sel][li] = u;
             s.logr[sel][li] = old & ~kClaim;  // rank and in-image neighbour bits
         }
@@ -547,8 +553,9 @@ __device__ inline uint32_t small_step(uint32_t cnt, uint32_t k, uint32_t r, uint
         const uint32_t rn = pmax > r ? pmax : refilled ? r : max(below, pmax);
         direct = rn != 0 && rn != below;
         const uint32_t rd = direct ? rn : 0u;  // rank 0 matches no push
-        push_pair(o0, u0, a, s, sel, logn, rd, dn);
-        if (passes > 1) push_pair(o1, u1, a, s, sel, logn, rd, dn);
+        push_pair<false>(o0, u0, a, s, sel, logn, rd, dn);
+        if (passes > 1) push_pair<false>(o1, u1, a, s, sel, logn, rd, dn);
+        logn = kLog + 1;  // no log of this step: the next one never reads it
         return rn;
     }
     // more passes (up to 12): the claims of passes 2-5 join those of passes
@@ -569,16 +576,16 @@ __device__ inline uint32_t small_step(uint32_t cnt, uint32_t k, uint32_t r, uint
             const uint32_t w0 = won_rank(o0), w1 = won_rank(o1);
             lm = max(w0, w1);
             same = w0 == r || w1 == r;
-            push_pair(o0, u0, a, s, sel, logn, 0u, dn);
-            push_pair(o1, u1, a, s, sel, logn, 0u, dn);
+            push_pair<true>(o0, u0, a, s, sel, logn, 0u, dn);
+            push_pair<true>(o1, u1, a, s, sel, logn, 0u, dn);
         }
         const uint32_t x0 = won_rank(q0), x1 = won_rank(q1), x2 = won_rank(q2), x3 = won_rank(q3);
         lm = max(lm, max(max(x0, x1), max(x2, x3)));
         same |= x0 == r || x1 == r || x2 == r || x3 == r;
-        push_pair(q0, v0, a, s, sel, logn, 0u, dn);
-        if (p + 1 < passes) push_pair(q1, v1, a, s, sel, logn, 0u, dn);
-        if (p + 2 < passes) push_pair(q2, v2, a, s, sel, logn, 0u, dn);
-        if (p + 3 < passes) push_pair(q3, v3, a, s, sel, logn, 0u, dn);
+        push_pair<true>(q0, v0, a, s, sel, logn, 0u, dn);
+        if (p + 1 < passes) push_pair<true>(q1, v1, a, s, sel, logn, 0u, dn);
+        if (p + 2 < passes) push_pair<true>(q2, v2, a, s, sel, logn, 0u, dn);
+        if (p + 3 < passes) push_pair<true>(q3, v3, a, s, sel, logn, 0u, dn);
     }
     const uint32_t pmax = wave_max_u32(lm);
     const bool refilled = __ballot(same) != 0;
