@@ -75,6 +75,61 @@ __device__ inline void block_add_slots(uint32_t* slots, uint32_t v) {
     }
 }
 
+// Per-key counts (keys >= 1, e.g. step numbers) over a grid whose blocks each
+// cover a contiguous chunk of voxels. A block first sums its chunk in an LDS
+// hash table and then adds each distinct key once, to one of kCntCopies
+// copies of the count array (chosen by the block index; copy c starts at
+// c * stride). Atomics on one global word, or on neighbouring words of one
+// cache line, from every wave of a large grid serialise at one place; here a
+// line takes at most one atomic per key from the blocks of its copy.
+constexpr int kCntHash = 2048;  // table entries (power of two)
+constexpr int kCntProbes = 16;  // a key that finds no slot goes straight to the copy
+constexpr int kCntChunk = 4096; // voxels per block
+constexpr int kCntCopies = 16;
+struct CountTable {
+    int32_t key[kCntHash];  // 0 = empty
+    uint32_t cnt[kCntHash];
+};
+
+__device__ inline void count_table_clear(CountTable& t) {
+    for (int i = threadIdx.x; i < kCntHash; i += blockDim.x) {
+        t.key[i] = 0;
+        t.cnt[i] = 0;
+    }
+}
+
+// Adds 1 for every active lane to the count of its key. Runs of equal keys
+// in consecutive lanes are added once, by the run's first lane.
+__device__ inline void count_table_add(CountTable& t, bool act, int32_t key, uint32_t* copy) {
+    const int lane = threadIdx.x & 63;
+    const int32_t prev = __shfl_up(key, 1, 64);
+    const bool prev_act = __shfl_up(act ? 1 : 0, 1, 64) != 0;
+    const bool head = act && (lane == 0 || !prev_act || prev != key);
+    const uint64_t brk = __ballot(!act || head);
+    if (!head) return;
+    // the run ends at the next lane that is inactive or starts another run
+    const uint64_t after = lane == 63 ? 0ull : brk & (~0ull << (lane + 1));
+    const uint32_t len = (uint32_t)((after ? __ffsll((unsigned long long)after) - 1 : 64) - lane);
+    uint32_t h = ((uint32_t)key * 2654435761u) >> 21;  // 11 bits: kCntHash slots
+    for (int p = 0; p < kCntProbes; p++) {
+        const int32_t old = atomicCAS(&t.key[h], 0, key);
+        if (old == 0 || old == key) {
+            atomicAdd(&t.cnt[h], len);
+            return;
+        }
+        h = (h + 1) & (kCntHash - 1);
+    }
+    atomicAdd(&copy[key - 1], len);
+}
+
+// After a barrier: each distinct key of the table is added to the copy.
+__device__ inline void count_table_flush(const CountTable& t, uint32_t* copy) {
+    for (int i = threadIdx.x; i < kCntHash; i += blockDim.x) {
+        const int32_t k = t.key[i];
+        if (k != 0) atomicAdd(&copy[k - 1], t.cnt[i]);
+    }
+}
+
 // Makes `dev` current for a scope and restores the previous device after.
 struct DeviceGuard {
     int prev = -1;
@@ -213,9 +268,14 @@ hipError_t launch_edt(const uint8_t* image, const uint32_t* w, uint32_t thr, uin
                       uint16_t* g16, uint32_t* tmp32, uint32_t* out, uint32_t* solid_flag,
                       hipStream_t s, uint32_t* mio_r2 = nullptr, uint32_t* mio_count = nullptr);
 
-// Exclusive scan of n uint32 values in place; returns the total in *total (device).
 // *dst = the sum of kCountSlots slot words (see block_add_slots).
 hipError_t launch_sum_slots(const uint32_t* slots, uint32_t* dst, hipStream_t s);
+// out[k] = sum over c < copies of in[c * K + k], for k < K (see count_table_flush).
+hipError_t launch_sum_copies(const uint32_t* in, int copies, int64_t K, uint32_t* out, hipStream_t s);
+// Number of count copies for K keys over n voxels: kCntCopies when the
+// copies take at most 4 B per voxel, else 1.
+inline int count_copies(int64_t K, int64_t n) { return K > 0 && (int64_t)kCntCopies * K <= n ? kCntCopies : 1; }
+// Exclusive scan of n uint32 values in place; returns the total in *total (device).
 hipError_t launch_scan_u32(uint32_t* data, int64_t n, uint32_t* partials, uint32_t* total,
                            hipStream_t s);
 

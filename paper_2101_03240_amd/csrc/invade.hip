@@ -87,6 +87,9 @@ __device__ inline uint64_t lanemask_lt() {
 
 // Histogram of dt2 over pore voxels, pore count, largest value.
 constexpr int kHistLds = 2048;
+// k_hist's grid: every block adds each of its non-empty bins to the global
+// histogram, so the common distances take one atomic per block
+constexpr int kHistBlocks = 1024;
 // Values >= vlimit (the no-solid sentinel) are skipped; the host rejects such
 // images before anything reads the tables.
 __global__ __launch_bounds__(256) void k_hist(const uint8_t* __restrict__ img, const uint32_t* __restrict__ dt2,
@@ -1064,27 +1067,34 @@ __global__ void k_rank_to_value(uint32_t* M, int64_t K, const uint32_t* val) {
     if (k < K) M[k] = val[M[k]];
 }
 
+// Each block finalises a contiguous chunk of kCntChunk voxels. With `copies`
+// given, the per-step counts of painted voxels go to copy blockIdx % ncopies
+// (copy c at copies + c * K), summed per block in LDS first.
 __global__ __launch_bounds__(256) void k_finalise(int32_t* seq, int32_t* state_io, bool map_state, int64_t n,
-                                                  const uint32_t* M, uint32_t* rad2, uint32_t* count) {
-    const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    bool have = v < n;
-    int32_t s = 0;
-    if (have) {
-        s = seq[v];
-        if (s == INT_MAX) { s = 0; seq[v] = 0; }
-        if (rad2) rad2[v] = s > 0 ? M[s - 1] : 0u;
-        const int32_t t = state_io[v];
-        if (map_state && t < 0) state_io[v] = 0;
+                                                  const uint32_t* M, uint32_t* rad2, uint32_t* copies, int64_t K,
+                                                  int ncopies) {
+    __shared__ CountTable tab;
+    const bool counting = copies != nullptr;
+    if (counting) count_table_clear(tab);
+    __syncthreads();
+    uint32_t* copy = counting ? copies + (int64_t)(blockIdx.x % (unsigned)ncopies) * K : nullptr;
+    const int64_t base = (int64_t)blockIdx.x * kCntChunk;
+    for (int j = 0; j < kCntChunk; j += 256) {
+        const int64_t v = base + j + threadIdx.x;
+        const bool have = v < n;
+        int32_t s = 0;
+        if (have) {
+            s = seq[v];
+            if (s == INT_MAX) { s = 0; seq[v] = 0; }
+            if (rad2) rad2[v] = s > 0 ? M[s - 1] : 0u;
+            const int32_t t = state_io[v];
+            if (map_state && t < 0) state_io[v] = 0;
+        }
+        if (counting) count_table_add(tab, have && s > 0, s, copy);
     }
-    // per-step counts (when requested), one atomic per distinct step in the wave
-    bool act = count != nullptr && have && s > 0;
-    uint64_t pending = __ballot(act);
-    while (pending) {
-        const int leader = __ffsll((unsigned long long)pending) - 1;
-        const int32_t ls = __shfl(s, leader, 64);
-        const uint64_t same = __ballot(act && s == ls) & pending;
-        if ((threadIdx.x & 63) == leader) atomicAdd(&count[ls - 1], (uint32_t)__popcll(same));
-        pending &= ~same;
+    if (counting) {
+        __syncthreads();
+        count_table_flush(tab, copy);
     }
 }
 
@@ -1108,6 +1118,26 @@ __global__ void k_steps(const uint32_t* counts, const uint32_t* count_excl, cons
 inline unsigned blocks(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace
+
+// k_finalise over n voxels. With counts given (K > 0), counts[0..K) receives
+// the number of voxels of each step; `spare` holds the copies when there is
+// more than one (kCntCopies * K words, see count_copies).
+hipError_t launch_finalise(int32_t* seq, int32_t* state, int64_t n, const uint32_t* M, uint32_t* rad2,
+                           uint32_t* counts, uint32_t* spare, int64_t K, hipStream_t s) {
+    const unsigned g = (unsigned)((n + kCntChunk - 1) / kCntChunk);
+    if (!counts || K <= 0) {
+        hipLaunchKernelGGL(k_finalise, dim3(g), dim3(256), 0, s, seq, state, true, n, M, rad2, (uint32_t*)nullptr,
+                           (int64_t)0, 1);
+        return hipGetLastError();
+    }
+    const int S = count_copies(K, n);
+    uint32_t* dst = S > 1 ? spare : counts;
+    hipError_t e = hipMemsetAsync(dst, 0, sizeof(uint32_t) * (size_t)S * (size_t)K, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_finalise, dim3(g), dim3(256), 0, s, seq, state, true, n, M, rad2, dst, K, S);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return S > 1 ? launch_sum_copies(spare, S, K, counts, s) : hipSuccess;
+}
 
 // ---------------------------------------------------------------------------
 // Host driver
@@ -1147,7 +1177,7 @@ ibip_status run_invade(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlet
         return rc;
     tm.mark(1, s);
     // a2: histogram -> ranks and bucket slices
-    hipLaunchKernelGGL(k_hist, dim3(std::min<int64_t>(blocks(n), 4096)), dim3(256), 0, s, image, key, n,
+    hipLaunchKernelGGL(k_hist, dim3(std::min<int64_t>(blocks(n), kHistBlocks)), dim3(256), 0, s, image, key, n,
                        (uint32_t)(V - 1), hist, st);
     hipLaunchKernelGGL(k_present, dim3(blocks(V)), dim3(256), 0, s, hist, present, V);
     hipLaunchKernelGGL(k_copy_u32, dim3(blocks(V)), dim3(256), 0, s, present, flags, V);
@@ -1245,11 +1275,14 @@ ibip_status run_invade(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlet
     int64_t* n_new = (int64_t*)ensure(ctx, B_NNEW, sizeof(int64_t) * (K + 1));
     double* sat = (double*)ensure(ctx, B_SAT, sizeof(double) * (K + 1));
     double* pc = (double*)ensure(ctx, B_PC, sizeof(double) * (K + 1));
-    uint32_t* counts = (uint32_t*)ensure(ctx, B_TMP2, sizeof(uint32_t) * 2 * (K + 1));
+    // counts (K + 1), their exclusive scan (K + 1), then the count copies
+    const size_t ncopy = count_copies(K, n) > 1 ? (size_t)kCntCopies * (size_t)K : 0;
+    uint32_t* counts = (uint32_t*)ensure(ctx, B_TMP2, sizeof(uint32_t) * (2 * (K + 1) + ncopy));
     partials = (uint32_t*)ensure(ctx, B_SCAN, sizeof(uint32_t) * (V / 1000 + n / 1000 + 64));
     if (!n_new || !sat || !pc || !counts || !partials) return fail(ctx, IBIP_ENOMEM, "invade: scratch allocation failed");
-    if ((rc = hip_check(ctx, hipMemsetAsync(counts, 0, sizeof(uint32_t) * (K + 1), s), "memset")) != IBIP_OK) return rc;
-    hipLaunchKernelGGL(k_finalise, dim3(blocks(n)), dim3(256), 0, s, seq, state, true, n, M, rad2, counts);
+    if ((rc = hip_check(ctx, launch_finalise(seq, state, n, M, rad2, counts, counts + 2 * (K + 1), K, s),
+                        "finalise")) != IBIP_OK)
+        return rc;
     if (K > 0) {
         uint32_t* excl = counts + (K + 1);
         hipLaunchKernelGGL(k_copy_u32, dim3(blocks(K)), dim3(256), 0, s, counts, excl, K);
@@ -1361,7 +1394,7 @@ hipError_t job_setup(const JobBufs& j, LoopState* st, const uint8_t* image, cons
     if ((e = launch_edt(image, nullptr, 0, 0, d, j.g16, j.tmp32, j.key, &st->solid_seen, s)) != hipSuccess) return e;
     uint32_t* present = j.hist + V;
     uint32_t* flags = j.hist + 2 * V;
-    hipLaunchKernelGGL(k_hist, dim3(std::min<int64_t>(blocks(n), 4096)), dim3(256), 0, s, image, j.key, n,
+    hipLaunchKernelGGL(k_hist, dim3(std::min<int64_t>(blocks(n), kHistBlocks)), dim3(256), 0, s, image, j.key, n,
                        (uint32_t)(V - 1), j.hist, st);
     hipLaunchKernelGGL(k_present, dim3(blocks(V)), dim3(256), 0, s, j.hist, present, V);
     hipLaunchKernelGGL(k_copy_u32, dim3(blocks(V)), dim3(256), 0, s, present, flags, V);
@@ -1385,9 +1418,12 @@ hipError_t job_post(const JobBufs& j, LoopState* st, ibip_dims d, int64_t K, int
                  make_fastdiv((uint32_t)d.Z), make_fastdiv((uint32_t)d.Y)};
     hipLaunchKernelGGL(k_paint_shell, dim3(blocks(n)), dim3(256), 0, s, pa);
     hipLaunchKernelGGL(k_paint_full, dim3(std::min<int64_t>(blocks(n), 2048)), dim3(256), 0, s, pa);
+    // the job's counts region holds 2 (n + 1) words: counts, their scan and,
+    // when used, the copies (at most n words, and then 2 K <= n)
     uint32_t* counts = j.counts;
-    if (counts && (e = hipMemsetAsync(counts, 0, sizeof(uint32_t) * (K + 1), s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_finalise, dim3(blocks(n)), dim3(256), 0, s, seq, j.state, true, n, j.M, rad2, counts);
+    if ((e = launch_finalise(seq, j.state, n, j.M, rad2, counts, counts ? counts + 2 * (K + 1) : nullptr,
+                             counts ? K : 0, s)) != hipSuccess)
+        return e;
     if (K > 0 && M_out)
         if ((e = hipMemcpyAsync(M_out, j.M, sizeof(uint32_t) * K, hipMemcpyDeviceToDevice, s)) != hipSuccess) return e;
     if (K > 0 && sat_out && counts) {
@@ -1420,9 +1456,7 @@ hipError_t job_post_devk(const JobBufs& j, LoopState* st, ibip_dims d, int32_t* 
                  make_fastdiv((uint32_t)d.Z), make_fastdiv((uint32_t)d.Y)};
     hipLaunchKernelGGL(k_paint_shell, dim3(blocks(n)), dim3(256), 0, s, pa);
     hipLaunchKernelGGL(k_paint_full, dim3(std::min<int64_t>(blocks(n), 2048)), dim3(256), 0, s, pa);
-    hipLaunchKernelGGL(k_finalise, dim3(blocks(n)), dim3(256), 0, s, seq, j.state, true, n, j.M, rad2,
-                       (uint32_t*)nullptr);
-    return hipGetLastError();
+    return launch_finalise(seq, j.state, n, j.M, rad2, nullptr, nullptr, 0, s);
 }
 
 hipError_t launch_loop_jobs(const void* d_args, int32_t n, hipStream_t s) {

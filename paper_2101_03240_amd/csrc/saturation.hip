@@ -16,22 +16,29 @@ inline unsigned blocks(int64_t n) { return (unsigned)((n + 255) / 256); }
 // counts[k-1] = voxels labelled k; n_pore slots += pore voxels (label >= 0). Lanes
 // of a wave are grouped by label with ballots, and each group adds its size
 // with one atomic (labels of neighbouring voxels repeat).
+// Per-step counts into copy blockIdx % ncopies (copy c at copies + c * K),
+// each block summing its chunk of kCntChunk voxels in LDS first; the pore
+// count into the slots; *bad set if a step exceeds K.
 __global__ __launch_bounds__(256) void k_count_steps(const int32_t* __restrict__ seq, int64_t n, int64_t K,
-                                                     uint32_t* counts, uint32_t* n_pore, uint32_t* bad) {
-    const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int32_t s = v < n ? seq[v] : -1;
-    const bool act = s > 0 && (int64_t)s <= K;
-    if (v < n && s > 0 && (int64_t)s > K) atomicOr(bad, 1u);
-    const int lane = threadIdx.x & 63;
-    uint64_t pending = __ballot(act);
-    while (pending) {
-        const int leader = __ffsll((unsigned long long)pending) - 1;
-        const int32_t ls = __builtin_amdgcn_readlane(s, leader);
-        const uint64_t same = __ballot(act && s == ls) & pending;
-        if (lane == leader) atomicAdd(&counts[ls - 1], (uint32_t)__popcll(same));
-        pending &= ~same;
+                                                     uint32_t* copies, int ncopies, uint32_t* n_pore, uint32_t* bad) {
+    __shared__ CountTable tab;
+    count_table_clear(tab);
+    __syncthreads();
+    uint32_t* copy = copies + (int64_t)(blockIdx.x % (unsigned)ncopies) * K;
+    const int64_t base = (int64_t)blockIdx.x * kCntChunk;
+    uint32_t pore = 0;
+    bool over = false;
+    for (int j = 0; j < kCntChunk; j += 256) {
+        const int64_t v = base + j + threadIdx.x;
+        const int32_t s = v < n ? seq[v] : -1;
+        over |= s > 0 && (int64_t)s > K;
+        pore += s >= 0 ? 1u : 0u;
+        count_table_add(tab, s > 0 && (int64_t)s <= K, s, copy);
     }
-    block_add_slots(n_pore, v < n && s >= 0 ? 1u : 0u);
+    if (over) atomicOr(bad, 1u);
+    __syncthreads();
+    count_table_flush(tab, copy);
+    block_add_slots(n_pore, pore);
 }
 
 __global__ void k_curves(const uint32_t* counts, const uint32_t* excl, const uint32_t* M, int64_t K,
@@ -180,7 +187,9 @@ ibip_status ibip_saturation(ibip_ctx* ctx, const int32_t* seq, ibip_dims dims, c
     const double vs = opts ? opts->voxel_size : 1.0;
     if (!(vs > 0)) return fail(ctx, IBIP_EINVAL, "saturation: voxel_size must be positive");
     const double c0 = 2.0 * sigma * cos(theta) / vs;
-    uint32_t* w = (uint32_t*)ensure(ctx, B_SATW, sizeof(uint32_t) * (2 * (size_t)K + 64 + kCountSlots));
+    const int S = count_copies(K, n);
+    const size_t ncopy = S > 1 ? (size_t)S * (size_t)K : 0;
+    uint32_t* w = (uint32_t*)ensure(ctx, B_SATW, sizeof(uint32_t) * (2 * (size_t)K + 64 + kCountSlots + ncopy));
     uint32_t* partials = (uint32_t*)ensure(ctx, B_SCAN, sizeof(uint32_t) * (K / 1000 + n / 1000 + 64));
     uint32_t* h = (uint32_t*)pinned(ctx, 4096);
     if (!w || !partials || !h) return fail(ctx, IBIP_ENOMEM, "saturation: allocation failed");
@@ -188,12 +197,17 @@ ibip_status ibip_saturation(ibip_ctx* ctx, const int32_t* seq, ibip_dims dims, c
     uint32_t* slots = w + 64;         // n_pore, by block
     uint32_t* counts = slots + kCountSlots;  // K
     uint32_t* excl = counts + K;      // K
+    uint32_t* copies = S > 1 ? excl + K : counts;  // S * K
     ibip_status rc;
     if ((rc = hip_check(ctx, hipMemsetAsync(w, 0, sizeof(uint32_t) * (64 + kCountSlots + (size_t)K), s), "memset")) !=
         IBIP_OK)
         return rc;
-    hipLaunchKernelGGL(k_count_steps, dim3(blocks(n)), dim3(256), 0, s, seq, n, K, counts, slots, ctl + 1);
+    if (S > 1 && (rc = hip_check(ctx, hipMemsetAsync(copies, 0, sizeof(uint32_t) * ncopy, s), "memset")) != IBIP_OK)
+        return rc;
+    hipLaunchKernelGGL(k_count_steps, dim3((unsigned)((n + kCntChunk - 1) / kCntChunk)), dim3(256), 0, s, seq, n, K,
+                       copies, S, slots, ctl + 1);
     if ((rc = hip_check(ctx, launch_sum_slots(slots, ctl, s), "sum")) != IBIP_OK) return rc;
+    if (S > 1 && (rc = hip_check(ctx, launch_sum_copies(copies, S, K, counts, s), "sum")) != IBIP_OK) return rc;
     if (K > 0) {
         if ((rc = hip_check(ctx, hipMemcpyAsync(excl, counts, sizeof(uint32_t) * K, hipMemcpyDeviceToDevice, s),
                             "copy")) != IBIP_OK)

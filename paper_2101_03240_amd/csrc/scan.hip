@@ -82,7 +82,21 @@ __global__ void k_sum_slots(const uint32_t* slots, uint32_t* dst) {
     if (threadIdx.x == 0) *dst = v;
 }
 
+__global__ void k_sum_copies(const uint32_t* in, int copies, int64_t K, uint32_t* out) {
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k >= K) return;
+    uint32_t v = 0;
+    for (int c = 0; c < copies; c++) v += in[c * K + k];
+    out[k] = v;
+}
+
 }  // namespace
+
+hipError_t launch_sum_copies(const uint32_t* in, int copies, int64_t K, uint32_t* out, hipStream_t s) {
+    if (K <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sum_copies, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, s, in, copies, K, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_sum_slots(const uint32_t* slots, uint32_t* dst, hipStream_t s) {
     hipLaunchKernelGGL(k_sum_slots, dim3(1), dim3(64), 0, s, slots, dst);

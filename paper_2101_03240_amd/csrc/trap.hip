@@ -281,22 +281,33 @@ __global__ __launch_bounds__(256) void k_relax_tiles(Cap cap, int X, int Y, int 
 }
 
 // ---- trapping ----
-__global__ __launch_bounds__(256) void k_max_seq(const int32_t* seq, int64_t n, int32_t* out) {
-    int32_t m = 0;
-    for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < n; v += (int64_t)gridDim.x * 256)
-        m = max(m, seq[v]);
-    for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o, 64));
-    if ((threadIdx.x & 63) == 0) atomicMax(out, m);
-}
-
+// w[v] = the seed of the maximin reconstruction (the step on outlet voxels,
+// kInf32 on uninvaded outlet pore, 0 elsewhere), and the largest step of the
+// image into max_slots[block % kCountSlots]: each block covers a contiguous
+// chunk of kCntChunk voxels and adds one atomic.
 __global__ __launch_bounds__(256) void k_trap_init(const int32_t* seq, const uint8_t* outlets, int64_t n,
-                                                   uint32_t* w) {
-    int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (v >= n) return;
-    const int32_t s = seq[v];
-    uint32_t val = 0;
-    if (s >= 0 && outlets[v]) val = s == 0 ? kInf32 : (uint32_t)s;
-    w[v] = val;
+                                                   uint32_t* w, int32_t* max_slots) {
+    __shared__ int32_t part[4];
+    int32_t m = 0;
+    const int64_t base = (int64_t)blockIdx.x * kCntChunk;
+    for (int j = 0; j < kCntChunk; j += 256) {
+        const int64_t v = base + j + threadIdx.x;
+        if (v < n) {
+            const int32_t s = seq[v];
+            m = max(m, s);
+            uint32_t val = 0;
+            if (s >= 0 && outlets[v]) val = s == 0 ? kInf32 : (uint32_t)s;
+            w[v] = val;
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        m = max(max(part[0], part[1]), max(part[2], part[3]));
+        if (m > 0) atomicMax(&max_slots[blockIdx.x % kCountSlots], m);
+    }
 }
 
 __global__ __launch_bounds__(256) void k_trap_mark(const int32_t* seq, const uint32_t* w, int64_t n,
@@ -379,17 +390,21 @@ ibip_status run_trap(ibip_ctx* ctx, const int32_t* seq, const uint8_t* outlets, 
     uint8_t* misc = (uint8_t*)ensure(ctx, B_MISC, 4096);
     uint32_t* h = (uint32_t*)pinned(ctx, 4096);
     if (!w || !misc || !h) return fail(ctx, IBIP_ENOMEM, "trap: allocation failed");
-    int32_t* dmax = (int32_t*)(misc + 3072);
+    int32_t* dmax = (int32_t*)(misc + 2048);  // kCountSlots words
     uint32_t* dtotal = (uint32_t*)(misc + 3076);
     ibip_status rc;
     ctx->timer.mark(10, s);
-    if ((rc = hip_check(ctx, hipMemsetAsync(dmax, 0, 8, s), "memset")) != IBIP_OK) return rc;
-    hipLaunchKernelGGL(k_max_seq, dim3(std::min<int64_t>(blocks(n), 2048)), dim3(256), 0, s, seq, n, dmax);
-    hipLaunchKernelGGL(k_trap_init, dim3(blocks(n)), dim3(256), 0, s, seq, outlets, n, w);
-    if ((rc = hip_check(ctx, hipMemcpyAsync(h, dmax, sizeof(int32_t), hipMemcpyDeviceToHost, s), "copy")) != IBIP_OK)
+    if ((rc = hip_check(ctx, hipMemsetAsync(dmax, 0, sizeof(int32_t) * kCountSlots, s), "memset")) != IBIP_OK)
+        return rc;
+    hipLaunchKernelGGL(k_trap_init, dim3((unsigned)((n + kCntChunk - 1) / kCntChunk)), dim3(256), 0, s, seq, outlets,
+                       n, w, dmax);
+    if ((rc = hip_check(ctx, hipMemcpyAsync(h, dmax, sizeof(int32_t) * kCountSlots, hipMemcpyDeviceToHost, s),
+                        "copy")) != IBIP_OK)
         return rc;
     if ((rc = hip_check(ctx, hipStreamSynchronize(s), "sync")) != IBIP_OK) return rc;
-    const int64_t K = (int32_t)h[0];
+    int32_t kmax = 0;
+    for (int q = 0; q < kCountSlots; q++) kmax = std::max(kmax, (int32_t)h[q]);
+    const int64_t K = kmax;
     int iters = 0;
     if ((rc = reconstruct(ctx, seq, nullptr, (ctx->readings & IBIP_READ_TRAP26) != 0, d, w, &iters)) != IBIP_OK)
         return rc;
