@@ -71,7 +71,7 @@ int64_t ibip_ctx_scratch_bytes(const ibip_ctx* ctx);
    on the context's stream around each phase and each launch of the step
    loop, and add the elapsed times (milliseconds) to the counters below. */
 typedef struct {
-    double edt_ms;          /* distance transform inside ibip_invade */
+    double edt_ms;          /* distance transform kernels (ibip_edt, and inside ibip_invade) */
     double setup_ms;        /* histogram, ranks, buckets, seeding */
     double loop_ms;         /* the whole step loop, host round trips included */
     double loop_kernel_ms;  /* sum of the single-workgroup loop kernel durations */

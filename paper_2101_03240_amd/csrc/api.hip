@@ -170,12 +170,15 @@ ibip_status ibip_edt(ibip_ctx* ctx, const uint8_t* image, ibip_dims dims, uint32
     uint32_t* flag = (uint32_t*)(misc + 3600);
     ibip_status rc;
     if ((rc = hip_check(ctx, hipMemsetAsync(flag, 0, 4, ctx->stream), "memset")) != IBIP_OK) return rc;
+    ctx->timer.mark(0, ctx->stream);
     if ((rc = hip_check(ctx, launch_edt(image, nullptr, 0, 0, dims, g16, tmp, dt2, flag, ctx->stream), "edt launch")) !=
         IBIP_OK)
         return rc;
+    ctx->timer.mark(1, ctx->stream);
     if ((rc = hip_check(ctx, hipMemcpyAsync(h, flag, 4, hipMemcpyDeviceToHost, ctx->stream), "copy")) != IBIP_OK)
         return rc;
     if ((rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "sync")) != IBIP_OK) return rc;
+    if (ctx->timer.on) ctx->timing.edt_ms += ctx->timer.ms(0, 1);  // the three passes' kernels
     if (!h[0]) return fail(ctx, IBIP_ENOSOLID, "edt: image holds no solid voxel");
     return IBIP_OK;
 }

@@ -92,7 +92,7 @@ constexpr int kHistLds = 2048;
 constexpr int kHistBlocks = 1024;
 // Values >= vlimit (the no-solid sentinel) are skipped; the host rejects such
 // images before anything reads the tables.
-__global__ __launch_bounds__(256) void k_hist(const uint8_t* __restrict__ img, const uint32_t* __restrict__ dt2,
+__global__ __launch_bounds__(256) void k_hist(const uint32_t* __restrict__ dt2,
                                               int64_t n, uint32_t vlimit, uint32_t* hist, LoopState* st) {
     __shared__ uint32_t h[kHistLds];
     __shared__ uint32_t s_pore, s_max;
@@ -100,14 +100,21 @@ __global__ __launch_bounds__(256) void k_hist(const uint8_t* __restrict__ img, c
     if (threadIdx.x == 0) { s_pore = 0; s_max = 0; }
     __syncthreads();
     uint32_t pore = 0, mx = 0;
-    for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < n; v += (int64_t)gridDim.x * 256) {
-        if (!img[v]) continue;
-        uint32_t d = dt2[v];
-        if (d >= vlimit) continue;
-        pore++;
-        mx = d > mx ? d : mx;
-        if (d < kHistLds) atomicAdd(&h[d], 1u);
-        else atomicAdd(&hist[d], 1u);
+    // dt2 is 0 exactly on solid, so the image itself is not read; four
+    // voxels per thread and round, their loads issued together
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t v0 = (int64_t)blockIdx.x * 256 + threadIdx.x; v0 < n; v0 += 4 * stride) {
+        uint32_t d[4];
+#pragma unroll
+        for (int j = 0; j < 4; j++) d[j] = v0 + j * stride < n ? dt2[v0 + j * stride] : 0u;
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            if (d[j] == 0 || d[j] >= vlimit) continue;
+            pore++;
+            mx = d[j] > mx ? d[j] : mx;
+            if (d[j] < kHistLds) atomicAdd(&h[d[j]], 1u);
+            else atomicAdd(&hist[d[j]], 1u);
+        }
     }
     atomicAdd(&s_pore, pore);
     atomicMax(&s_max, mx);
@@ -1177,7 +1184,7 @@ ibip_status run_invade(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlet
         return rc;
     tm.mark(1, s);
     // a2: histogram -> ranks and bucket slices
-    hipLaunchKernelGGL(k_hist, dim3(std::min<int64_t>(blocks(n), kHistBlocks)), dim3(256), 0, s, image, key, n,
+    hipLaunchKernelGGL(k_hist, dim3(std::min<int64_t>(blocks(n), kHistBlocks)), dim3(256), 0, s, key, n,
                        (uint32_t)(V - 1), hist, st);
     hipLaunchKernelGGL(k_present, dim3(blocks(V)), dim3(256), 0, s, hist, present, V);
     hipLaunchKernelGGL(k_copy_u32, dim3(blocks(V)), dim3(256), 0, s, present, flags, V);
@@ -1394,7 +1401,7 @@ hipError_t job_setup(const JobBufs& j, LoopState* st, const uint8_t* image, cons
     if ((e = launch_edt(image, nullptr, 0, 0, d, j.g16, j.tmp32, j.key, &st->solid_seen, s)) != hipSuccess) return e;
     uint32_t* present = j.hist + V;
     uint32_t* flags = j.hist + 2 * V;
-    hipLaunchKernelGGL(k_hist, dim3(std::min<int64_t>(blocks(n), kHistBlocks)), dim3(256), 0, s, image, j.key, n,
+    hipLaunchKernelGGL(k_hist, dim3(std::min<int64_t>(blocks(n), kHistBlocks)), dim3(256), 0, s, j.key, n,
                        (uint32_t)(V - 1), j.hist, st);
     hipLaunchKernelGGL(k_present, dim3(blocks(V)), dim3(256), 0, s, j.hist, present, V);
     hipLaunchKernelGGL(k_copy_u32, dim3(blocks(V)), dim3(256), 0, s, present, flags, V);

@@ -102,3 +102,36 @@ def test_label_above_K_is_an_error(dev):
     with pytest.raises(ibip.IbipError):
         ibip.remap_steps(_d(np.array([[[1, 2, 3, -1]]], np.int32), dev), _d(bad, dev),
                          _d(np.array([9, 4, 1], np.int32), dev), 2)
+
+
+def _count_case(shape, K, seed, hot=None, runs=False):
+    rng = np.random.default_rng(seed)
+    n = int(np.prod(shape))
+    seq = rng.integers(1, K + 1, size=n).astype(np.int32)
+    if runs:  # long runs of one step in consecutive voxels, crossing wave and block edges
+        seq = np.repeat(rng.integers(1, K + 1, size=n // 37 + 1), 37)[:n].astype(np.int32)
+    if hot is not None:  # one step holding most voxels, in every block
+        seq[rng.random(n) < 0.7] = hot
+    seq[rng.random(n) < 0.1] = -1
+    seq[rng.random(n) < 0.05] = 0
+    seq[0] = K  # every step up to K may hold no voxel; K itself holds one
+    M = rng.integers(1, 400, size=K).astype(np.int32)
+    return seq.reshape(shape), M
+
+
+@pytest.mark.parametrize("case", ["copies_hot", "copies_runs", "one_copy_overflow"])
+def test_step_counts_paths(dev, case):
+    """Per-step counts through both layouts of the count kernels: 16 spread
+    copies (K <= n / 16) with a step that holds most voxels, long runs of one
+    step across lanes, and one copy with more distinct steps per block than
+    the block's table holds (the direct-atomic path)."""
+    if case == "copies_hot":
+        seq, M = _count_case((64, 128, 128), 1000, 1, hot=7)
+    elif case == "copies_runs":
+        seq, M = _count_case((48, 96, 100), 3000, 2, runs=True)
+    else:
+        seq, M = _count_case((32, 64, 64), 100000, 3)
+    s = ibip.saturation(_d(seq, dev), _d(M, dev), satmap=False)
+    r = oracle.steps(seq, M.view(np.uint32), c0=2.0)
+    np.testing.assert_array_equal(s["n_new"].cpu().numpy(), r["n_new"])
+    np.testing.assert_array_equal(s["sat"].cpu().numpy(), r["sat"])
