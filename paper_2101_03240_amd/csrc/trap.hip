@@ -41,7 +41,12 @@ struct CapU32 {
     __device__ uint32_t operator()(int64_t v) const { return cap[v]; }
 };
 
-// One sweep over the active tiles. A tile whose boundary layer changed
+// One sweep over the active tiles, in ascending tile order or (rev) in
+// descending order. Tiles update w in place, so a tile that starts after a
+// neighbour has written reads the neighbour's new boundary in the same sweep;
+// alternating the order lets values travel several tiles per sweep towards
+// either end of the image (any order reaches the same fixed point: w only
+// grows). A tile whose boundary layer changed
 // activates the face-neighbour tiles across the changed faces for the next
 // sweep (act_out); *changed counts tiles that changed anything. Each active
 // tile clears its own act_in flag, so act_in is all zero afterwards and
@@ -53,12 +58,12 @@ struct CapU32 {
 template <class Cap, bool kConn26>
 __global__ __launch_bounds__(256) void k_relax_tiles(Cap cap, int X, int Y, int Z, int ntx, int nty, int ntz,
                                                      uint32_t* w, uint8_t* act_in, uint8_t* act_out,
-                                                     uint32_t* changed) {
+                                                     uint32_t* changed, bool rev) {
     __shared__ uint32_t hw[HX * HY * HZ];
     __shared__ uint32_t hc[kConn26 ? 1 : TX * TY * TZ];  // capacities, for the line scans
     __shared__ uint32_t face[6];
     const int tid = threadIdx.x;
-    const int64_t tile = blockIdx.x;
+    const int64_t tile = rev ? (int64_t)gridDim.x - 1 - blockIdx.x : (int64_t)blockIdx.x;
     if (!act_in[tile]) return;
     __syncthreads();  // every thread has read the flag
     if (tid == 0) act_in[tile] = 0;
@@ -360,15 +365,16 @@ ibip_status reconstruct(ibip_ctx* ctx, const int32_t* seq, const uint32_t* cap32
         for (int b = 0; b < kBatch; b++, it++) {
             uint8_t* in = (it & 1) ? a1 : a0;
             uint8_t* out = (it & 1) ? a0 : a1;  // all zero: cleared by the sweep that read it
+            const bool rev = (it & 1) != 0;     // alternate the tile order
             if (cap32)
                 hipLaunchKernelGGL((k_relax_tiles<CapU32, false>), dim3((unsigned)ntiles), dim3(256), 0, s,
-                                   CapU32{cap32}, d.X, d.Y, d.Z, ntx, nty, ntz, w, in, out, cnt + b);
+                                   CapU32{cap32}, d.X, d.Y, d.Z, ntx, nty, ntz, w, in, out, cnt + b, rev);
             else if (conn26)
                 hipLaunchKernelGGL((k_relax_tiles<CapSeq, true>), dim3((unsigned)ntiles), dim3(256), 0, s,
-                                   CapSeq{seq}, d.X, d.Y, d.Z, ntx, nty, ntz, w, in, out, cnt + b);
+                                   CapSeq{seq}, d.X, d.Y, d.Z, ntx, nty, ntz, w, in, out, cnt + b, rev);
             else
                 hipLaunchKernelGGL((k_relax_tiles<CapSeq, false>), dim3((unsigned)ntiles), dim3(256), 0, s,
-                                   CapSeq{seq}, d.X, d.Y, d.Z, ntx, nty, ntz, w, in, out, cnt + b);
+                                   CapSeq{seq}, d.X, d.Y, d.Z, ntx, nty, ntz, w, in, out, cnt + b, rev);
         }
         if ((rc = hip_check(ctx, hipGetLastError(), "relax launch")) != IBIP_OK) return rc;
         if ((rc = hip_check(ctx, hipMemcpyAsync(h_changed, cnt + kBatch - 1, sizeof(uint32_t), hipMemcpyDeviceToHost,
