@@ -218,12 +218,14 @@ def run_serve(args) -> int:
     dev = torch.device("cuda:0")
     specs = synth.serve_specs(args.requests)
     imgs, inls = [], []
-    for sp in specs:
+    for j, sp in enumerate(specs):
         L = sp.L
         imgs.append(synth.blurred_noise_device((L, L, L), sp.sigma, sp.porosity, sp.seed, dev))
         m = torch.zeros((L, L, L), dtype=torch.uint8, device=dev)
         m[0] = 1
         inls.append(m)
+        if (j + 1) % 16 == 0:
+            print(f"serve: {j + 1} of {len(specs)} requests generated", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     vox = np.array([x.numel() for x in imgs], dtype=np.float64)
     print(f"serve: {len(imgs)} requests generated, {vox.sum() / 1e9:.2f} G voxels", file=sys.stderr, flush=True)
@@ -241,6 +243,8 @@ def run_serve(args) -> int:
             i, t = item
             r = srv.wait(t)
             out[i] = (r["status"], r["latency_ms"], r["K"], int((r["seq"] > 0).sum().item()))
+            if len(out) % 32 == 0:
+                print(f"serve: {len(out)} results", file=sys.stderr, flush=True)
 
     def run(arrivals):
         q, out = queue.Queue(), {}
@@ -479,6 +483,11 @@ def main() -> int:
             "paint": tm["paint_ms"] / S, "steps": tm["steps_ms"] / S, "trap": tm["trap_ms"] / S,
             "mio": tm["mio_ms"] / S},
         "loop": {"us_per_invasion_step": 1e3 * tm["loop_ms"] / max(tm["steps"], 1),
+                 # the loop's time outside its kernels: host synchronisation, state copies and
+                 # relaunches around the wide steps
+                 "host_overhead_ms_per_call": (tm["loop_ms"] - tm["loop_kernel_ms"] - tm["wide_kernel_ms"]) / S,
+                 "host_overhead_us_per_launch": 1e3 * (tm["loop_ms"] - tm["loop_kernel_ms"] - tm["wide_kernel_ms"])
+                 / max(tm["loop_launches"], 1),
                  "invasion_steps_per_s": tm["steps"] / (tm["loop_ms"] * 1e-3) if tm["loop_ms"] > 0 else 0.0,
                  "loop_launches_per_call": tm["loop_launches"] / S, "wide_launches_per_call": tm["wide_launches"] / S,
                  "wide_centres_per_call": tm["wide_centres"] / S,
