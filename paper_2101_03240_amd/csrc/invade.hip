@@ -820,55 +820,57 @@ __global__ __launch_bounds__(kLoopThreads) void k_loop_batch(const LoopArgs* __r
     loop_body(a, s);
 }
 
-// expand() for the whole-GPU kernel: the same claims, pushed to the global
-// slice tails with one atomic per distinct rank per direction in the wave.
-__device__ inline void expand_global(bool have, uint32_t c, uint32_t k, const LoopArgs& a) {
-    const int64_t yz = (int64_t)a.Y * a.Z;
-    int z = 0, y = 0, x = 0;
-    if (have) {
-        a.state[c] = (int32_t)k;
-        const uint32_t t = fdiv(c, a.divZ);
-        z = (int)(c - t * (uint32_t)a.Z);
-        x = (int)fdiv(t, a.divY);
-        y = (int)(t - (uint32_t)x * (uint32_t)a.Y);
-    }
-    const int64_t uu[6] = {(int64_t)c - yz, (int64_t)c + yz, (int64_t)c - a.Z, (int64_t)c + a.Z,
-                           (int64_t)c - 1, (int64_t)c + 1};
-    const bool okd[6] = {have && x > 0, have && x < a.X - 1, have && y > 0, have && y < a.Y - 1,
-                         have && z > 0, have && z < a.Z - 1};
-    uint32_t old[6];
-    claim_filtered<6>(a.key, a.key, uu, okd, c, old);
-    // pushes grouped by rank per direction; every group's tail atomic is in
-    // flight before the first result is used
-    RankGroup g[6];
-    uint32_t rr[6], base[6];
-    bool won[6];
-#pragma unroll
-    for (int j = 0; j < 6; j++) {
-        rr[j] = old[j] & kRankMask;
-        won[j] = !(old[j] & kClaim) && rr[j] != 0;
-        g[j] = group_by_rank(won[j], rr[j]);
-    }
-#pragma unroll
-    for (int j = 0; j < 6; j++) base[j] = g[j].cnt ? atomicAdd(&a.tail[rr[j]], g[j].cnt) : 0u;
-#pragma unroll
-    for (int j = 0; j < 6; j++) {
-        const uint32_t b = __shfl(base[j], (int)g[j].lead, 64);
-        if (won[j]) a.bucket[b + g[j].off] = (uint32_t)uu[j];
-    }
-}
-
-// One step with many centres, spread over the whole GPU.
+// One step with many centres, spread over the whole GPU. Claims as in the
+// loop (filtered by a read of the key first). The pushes of a block are
+// counted per rank in LDS, each rank then takes one slice-tail atomic per
+// block, and every push lands at that base plus its place in the block's
+// count: slice tails are few and hot, and one atomic per wave and rank
+// queued thousands of atomics on each of them.
 __global__ __launch_bounds__(256) void k_wide(LoopArgs a) {
-    const uint32_t h = a.st->big_h, t = a.st->big_t, k = a.st->big_k;
+    __shared__ uint32_t lcnt[kMaxRanks + 1];  // per rank: the block's pushes, then their base
+    const uint32_t h = a.st->big_h, t = a.st->big_t, k = a.st->big_k, R = a.st->R;
     const uint32_t cnt = t - h;
     const uint32_t stride = gridDim.x * 256;
     const uint32_t ntrip = (cnt + stride - 1) / stride;
+    const int64_t yz = (int64_t)a.Y * a.Z;
     for (uint32_t it = 0; it < ntrip; it++) {
+        for (uint32_t q = threadIdx.x; q <= R; q += 256) lcnt[q] = 0;
+        __syncthreads();
         const uint32_t i = it * stride + blockIdx.x * 256 + threadIdx.x;
         const bool have = i < cnt;
         const uint32_t c = have ? a.bucket[h + i] : 0u;
-        expand_global(have, c, k, a);
+        int z = 0, y = 0, x = 0;
+        if (have) {
+            a.state[c] = (int32_t)k;
+            const uint32_t tt = fdiv(c, a.divZ);
+            z = (int)(c - tt * (uint32_t)a.Z);
+            x = (int)fdiv(tt, a.divY);
+            y = (int)(tt - (uint32_t)x * (uint32_t)a.Y);
+        }
+        const int64_t uu[6] = {(int64_t)c - yz, (int64_t)c + yz, (int64_t)c - a.Z, (int64_t)c + a.Z,
+                               (int64_t)c - 1, (int64_t)c + 1};
+        const bool okd[6] = {have && x > 0, have && x < a.X - 1, have && y > 0, have && y < a.Y - 1,
+                             have && z > 0, have && z < a.Z - 1};
+        uint32_t old[6];
+        claim_filtered<6>(a.key, a.key, uu, okd, c, old);
+        uint32_t rr[6], off[6];
+#pragma unroll
+        for (int j = 0; j < 6; j++) {
+            rr[j] = old[j] & kRankMask;
+            if ((old[j] & kClaim) || rr[j] > R) rr[j] = 0;  // 0: no push (ranks above R do not occur)
+        }
+#pragma unroll
+        for (int j = 0; j < 6; j++) off[j] = rr[j] ? atomicAdd(&lcnt[rr[j]], 1u) : 0u;
+        __syncthreads();
+        for (uint32_t q = threadIdx.x; q <= R; q += 256) {
+            const uint32_t nq = lcnt[q];
+            if (nq) lcnt[q] = atomicAdd(&a.tail[q], nq);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < 6; j++)
+            if (rr[j]) a.bucket[lcnt[rr[j]] + off[j]] = (uint32_t)uu[j];
+        __syncthreads();
     }
 }
 
