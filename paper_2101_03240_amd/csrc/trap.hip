@@ -48,7 +48,7 @@ struct CapU32 {
 // either end of the image (any order reaches the same fixed point: w only
 // grows). A tile whose boundary layer changed
 // activates the face-neighbour tiles across the changed faces for the next
-// sweep (act_out); *changed counts tiles that changed anything. Each active
+// sweep (act_out); *changed is set when a tile changed anything. Each active
 // tile clears its own act_in flag, so act_in is all zero afterwards and
 // serves as act_out of the next sweep. kConn26: the
 // neighbours of a voxel are the 26 that share a face, an edge or a corner,
@@ -261,7 +261,10 @@ __global__ __launch_bounds__(256) void k_relax_tiles(Cap cap, int X, int Y, int 
         }
     }
     if (__builtin_amdgcn_readfirstlane(__syncthreads_or(wrote))) {
-        if (tid == 0) atomicAdd(changed, 1u);
+        // a flag, read first: one word taking an atomic from every tile that
+        // changed would queue them all at one place
+        if (tid == 0 && __hip_atomic_load(changed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
+            atomicOr(changed, 1u);
         if (kConn26) {
             if (tid < 27 && tid != 13) {
                 const int dx = tid / 9 - 1, dy = (tid / 3) % 3 - 1, dz = tid % 3 - 1;
@@ -322,7 +325,9 @@ __global__ __launch_bounds__(256) void k_trap_mark(const int32_t* seq, const uin
     const int32_t s = seq[v];
     const bool t = s > 0 && w[v] < (uint32_t)s;
     trapped[v] = t ? 1 : 0;
-    if (s > 0 && !t) present[s - 1] = 1u;
+    // most voxels of a step find its flag already set: read before writing
+    if (s > 0 && !t && __hip_atomic_load(&present[s - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
+        present[s - 1] = 1u;
 }
 
 __global__ __launch_bounds__(256) void k_trap_rank(const int32_t* seq, const uint8_t* trapped,
