@@ -927,104 +927,197 @@ __device__ inline void stamp_group(int32_t* seq, const uint32_t (&v)[kStampGroup
         if (ok[t] && cur[t] > k) atomicMin(&seq[v[t]], k);
 }
 
-// One thread per voxel: centres with an earlier, at-least-as-large face
-// neighbour stamp their cap; the others are listed for the full-ball pass.
-__global__ __launch_bounds__(256) void k_paint_shell(PaintArgs a) {
-    const int64_t yz = (int64_t)a.Y * a.Z;
-    const int64_t n = (int64_t)a.X * yz;
-    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (c >= n) return;
-    const int32_t k = a.state[c];
-    if (k <= 0) return;
-    const uint32_t rc = a.key[c] & kRankMask;
-    const uint32_t m = ball_m(a, a.val[rc]);
-    int x, y, z;
-    coords((uint32_t)c, a, x, y, z);
-    // neighbour j sits at c + n_j: axis j >> 1, sign (j & 1) ? +1 : -1
-    const bool inb[6] = {x > 0, x < a.X - 1, y > 0, y < a.Y - 1, z > 0, z < a.Z - 1};
-    const int64_t off[6] = {-yz, yz, -(int64_t)a.Z, (int64_t)a.Z, -1, 1};
-    uint32_t qmask = 0;
-    uint32_t mp[6];
-    // the six neighbours read together (an outside neighbour reads c itself)
-    int32_t kp[6];
-    uint32_t rp[6];
-#pragma unroll
-    for (int j = 0; j < 6; j++) {
-        const int64_t nb = inb[j] ? c + off[j] : c;
-        kp[j] = a.state[nb];
-        rp[j] = a.key[nb] & kRankMask;
-    }
-    uint32_t vp[6];
-#pragma unroll
-    for (int j = 0; j < 6; j++) vp[j] = a.val[rp[j]];
-#pragma unroll
-    for (int j = 0; j < 6; j++) {
-        const bool q = inb[j] && kp[j] > 0 && kp[j] < k && rp[j] >= rc;
-        qmask |= q ? 1u << j : 0u;
-        mp[j] = q ? ball_m(a, vp[j]) : 0u;
-    }
-    if (!qmask) {
-        // the lanes here list their centres with one atomic per wave
-        const uint64_t mk = __ballot(true);
-        const int lane = threadIdx.x & 63;
-        const int leader = __ffsll((unsigned long long)mk) - 1;
-        uint32_t base = 0;
-        if (lane == leader) base = atomicAdd(a.n_full, (uint32_t)__popcll(mk));
-        base = __shfl(base, leader, 64);
-        a.full[base + (uint32_t)__popcll(mk & lanemask_lt())] = (uint32_t)c;
-        return;
-    }
+// The cap of centre c (step k, painted ball {|o|^2 < m}) away from its first
+// preceding neighbour in qmask, filtered by the other preceding neighbours:
+// for each point (p, q) of the disk p^2 + q^2 <= m - 1 across the cap's axis,
+// one stamp at the ball's outermost voxel along that axis.
+struct CapGeom {
+    int sgn, posA, posB, posC, dimA, dimB, dimC, sA, sB, sC, Rb;
+    uint32_t rest0;
+    int comp[6];
+};
+
+__device__ inline CapGeom cap_geom(const PaintArgs& a, uint32_t m, uint32_t qmask, int x, int y, int z) {
+    CapGeom g;
     const int j0 = __ffs(qmask) - 1;
-    const int A = j0 >> 1;                  // axis of the cap
-    const int sgn = (j0 & 1) ? -1 : 1;      // cap on the side away from the neighbour
+    const int A = j0 >> 1;              // axis of the cap
+    g.sgn = (j0 & 1) ? -1 : 1;          // cap on the side away from the neighbour
     const int B = (A + 1) % 3, C = (A + 2) % 3;
-    // per-axis values of A, B and C, chosen once (indices fit 31 bits, so the
-    // stamp addresses are 32-bit sums)
+    // per-axis values of A, B and C (indices fit 31 bits, so the stamp
+    // addresses are 32-bit sums)
     const int yzi = a.Y * a.Z;
-    const int posA = A == 0 ? x : A == 1 ? y : z, posB = B == 0 ? x : B == 1 ? y : z, posC = C == 0 ? x : C == 1 ? y : z;
-    const int dimA = A == 0 ? a.X : A == 1 ? a.Y : a.Z, dimB = B == 0 ? a.X : B == 1 ? a.Y : a.Z;
-    const int dimC = C == 0 ? a.X : C == 1 ? a.Y : a.Z;
-    const int sA = A == 0 ? yzi : A == 1 ? a.Z : 1, sB = B == 0 ? yzi : B == 1 ? a.Z : 1;
-    const int sC = C == 0 ? yzi : C == 1 ? a.Z : 1;
+    g.posA = A == 0 ? x : A == 1 ? y : z;
+    g.posB = B == 0 ? x : B == 1 ? y : z;
+    g.posC = C == 0 ? x : C == 1 ? y : z;
+    g.dimA = A == 0 ? a.X : A == 1 ? a.Y : a.Z;
+    g.dimB = B == 0 ? a.X : B == 1 ? a.Y : a.Z;
+    g.dimC = C == 0 ? a.X : C == 1 ? a.Y : a.Z;
+    g.sA = A == 0 ? yzi : A == 1 ? a.Z : 1;
+    g.sB = B == 0 ? yzi : B == 1 ? a.Z : 1;
+    g.sC = C == 0 ? yzi : C == 1 ? a.Z : 1;
     // the other preceding neighbours filter the cap: neighbour j tests
     // |o - n_j|^2 = |o|^2 - 2 s_j o_(axis j) + 1 < mp[j], where o_(axis j) is
     // the cap offset along A (0), B (1) or C (2)
-    const uint32_t rest0 = qmask & ~(1u << j0);
-    int comp[6];
+    g.rest0 = qmask & ~(1u << j0);
 #pragma unroll
-    for (int j = 0; j < 6; j++) comp[j] = (j >> 1) == A ? 0 : (j >> 1) == B ? 1 : 2;
-    const int Rb = (int)isqrt_u32(m - 1);
-    for (int p = -Rb; p <= Rb; p++) {
-        const int pb = posB + p;
-        if (pb < 0 || pb >= dimB) continue;
-        const uint32_t rem = m - 1 - (uint32_t)(p * p);
-        const int U = (int)isqrt_u32(rem);
+    for (int j = 0; j < 6; j++) g.comp[j] = (j >> 1) == A ? 0 : (j >> 1) == B ? 1 : 2;
+    g.Rb = (int)isqrt_u32(m - 1);
+    return g;
+}
+
+// The stamp of point (p, q) (in the disk when ok), false if none.
+__device__ inline bool cap_point(const CapGeom& g, int c, uint32_t m, const uint32_t (&mp)[6], int p, int q, bool ok,
+                                 uint32_t& tv) {
+    const int pb = g.posB + p, pc = g.posC + q;
+    const int rem = (int)(m - 1) - p * p - q * q;
+    ok = ok && rem >= 0 && pb >= 0 && pb < g.dimB && pc >= 0 && pc < g.dimC;
+    const int w = ok ? (int)isqrt_u32((uint32_t)rem) : 0;
+    const int oa = g.sgn * w;
+    const int pa = g.posA + oa;
+    ok = ok && pa >= 0 && pa < g.dimA;
+    const uint32_t oo = (uint32_t)(w * w + p * p + q * q);
+    // (unrolled over the six neighbours: a loop over the set bits indexes
+    // the arrays at run time, which puts them in scratch memory)
+#pragma unroll
+    for (int j = 0; j < 6; j++) {
+        if (!((g.rest0 >> j) & 1u)) continue;
+        const int sj = (j & 1) ? 1 : -1;      // n_j component
+        const int oj = g.comp[j] == 0 ? oa : g.comp[j] == 1 ? p : q;
+        const uint32_t d = oo - 2 * sj * oj + 1;  // |o - n_j|^2
+        ok = ok && d >= mp[j];
+    }
+    tv = ok ? (uint32_t)(c + oa * g.sA + p * g.sB + q * g.sC) : (uint32_t)c;
+    return ok;
+}
+
+// A lane stamps its own cap: rows p, and along each row groups of q.
+__device__ inline void stamp_cap_lane(const PaintArgs& a, int c, int32_t k, uint32_t m, uint32_t qmask, int x, int y,
+                                      int z, const uint32_t (&mp)[6]) {
+    const CapGeom g = cap_geom(a, m, qmask, x, y, z);
+    for (int p = -g.Rb; p <= g.Rb; p++) {
+        if (g.posB + p < 0 || g.posB + p >= g.dimB) continue;
+        const int U = (int)isqrt_u32(m - 1 - (uint32_t)(p * p));
         for (int q0 = -U; q0 <= U; q0 += kStampGroup) {
             uint32_t tv[kStampGroup];
             bool tok[kStampGroup];
 #pragma unroll
+            for (int t = 0; t < kStampGroup; t++) tok[t] = cap_point(g, c, m, mp, p, q0 + t, q0 + t <= U, tv[t]);
+            stamp_group(a.seq, tv, tok, k);
+        }
+    }
+}
+
+// The whole wave stamps one cap (arguments uniform): the rows of the
+// square holding the disk side by side, a lane per (row, column) point.
+__device__ inline void stamp_cap_wave(const PaintArgs& a, int c, int32_t k, uint32_t m, uint32_t qmask, int x, int y,
+                                      int z, const uint32_t (&mp)[6]) {
+    const int lane = threadIdx.x & 63;
+    const CapGeom g = cap_geom(a, m, qmask, x, y, z);
+    const int L = 2 * g.Rb + 1;
+    if (L <= 64) {
+        const int rpr = 64 / L;  // rows per round
+        const int r0 = lane / L, q = lane - r0 * L - g.Rb;
+        const bool lane_ok = r0 < rpr;
+        for (int p0 = -g.Rb; p0 <= g.Rb; p0 += kStampGroup * rpr) {
+            uint32_t tv[kStampGroup];
+            bool tok[kStampGroup];
+#pragma unroll
             for (int t = 0; t < kStampGroup; t++) {
-                const int q = q0 + t;
-                const int pc = posC + q;
-                const int w = q <= U ? (int)isqrt_u32(rem - (uint32_t)(q * q)) : 0;
-                const int oa = sgn * w;
-                const int pa = posA + oa;
-                bool ok = q <= U && pc >= 0 && pc < dimC && pa >= 0 && pa < dimA;
-                const uint32_t oo = (uint32_t)(w * w + p * p + q * q);
-                uint32_t rest = ok ? rest0 : 0u;
-                while (rest) {
-                    const int j = __ffs(rest) - 1;
-                    rest &= rest - 1;
-                    const int sj = (j & 1) ? 1 : -1;      // n_j component
-                    const int oj = comp[j] == 0 ? oa : comp[j] == 1 ? p : q;
-                    const uint32_t d = oo - 2 * sj * oj + 1;  // |o - n_j|^2
-                    if (d < mp[j]) { ok = false; break; }
-                }
-                tok[t] = ok;
-                tv[t] = ok ? (uint32_t)((int)c + oa * sA + p * sB + q * sC) : (uint32_t)c;
+                const int p = p0 + r0 + t * rpr;
+                tok[t] = cap_point(g, c, m, mp, p, q, lane_ok && p <= g.Rb, tv[t]);
             }
             stamp_group(a.seq, tv, tok, k);
         }
+    } else {
+        for (int p = -g.Rb; p <= g.Rb; p++) {
+            if (g.posB + p < 0 || g.posB + p >= g.dimB) continue;
+            for (int q0 = -g.Rb; q0 <= g.Rb; q0 += 64 * kStampGroup) {
+                uint32_t tv[kStampGroup];
+                bool tok[kStampGroup];
+#pragma unroll
+                for (int t = 0; t < kStampGroup; t++) {
+                    const int q = q0 + lane + 64 * t;
+                    tok[t] = cap_point(g, c, m, mp, p, q, q <= g.Rb, tv[t]);
+                }
+                stamp_group(a.seq, tv, tok, k);
+            }
+        }
+    }
+}
+
+// Caps up to this radius are stamped by their own lane, larger ones by the
+// whole wave.
+constexpr int kSmallCap = 2;
+
+// One thread per voxel finds its centre's cap: centres with an earlier,
+// at-least-as-large face neighbour stamp a cap, the others are listed for the
+// full-ball pass. Caps differ widely in size, and with one lane per centre
+// most lanes of a wave idled while the largest cap among them was stamped:
+// small caps stay with their lane, large ones are stamped one centre at a
+// time by all 64 lanes, lanes over the points of the cap's disk.
+__global__ __launch_bounds__(256) void k_paint_shell(PaintArgs a) {
+    const int64_t yz = (int64_t)a.Y * a.Z;
+    const int64_t n = (int64_t)a.X * yz;
+    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    int32_t k = 0;
+    uint32_t m = 0, qmask = 0;
+    uint32_t mp[6] = {0u, 0u, 0u, 0u, 0u, 0u};
+    int x = 0, y = 0, z = 0;
+    if (c < n) k = a.state[c];
+    if (k > 0) {
+        const uint32_t rc = a.key[c] & kRankMask;
+        m = ball_m(a, a.val[rc]);
+        coords((uint32_t)c, a, x, y, z);
+        // neighbour j sits at c + n_j: axis j >> 1, sign (j & 1) ? +1 : -1
+        const bool inb[6] = {x > 0, x < a.X - 1, y > 0, y < a.Y - 1, z > 0, z < a.Z - 1};
+        const int64_t off[6] = {-yz, yz, -(int64_t)a.Z, (int64_t)a.Z, -1, 1};
+        // the six neighbours read together (an outside neighbour reads c itself)
+        int32_t kp[6];
+        uint32_t rp[6];
+#pragma unroll
+        for (int j = 0; j < 6; j++) {
+            const int64_t nb = inb[j] ? c + off[j] : c;
+            kp[j] = a.state[nb];
+            rp[j] = a.key[nb] & kRankMask;
+        }
+        uint32_t vp[6];
+#pragma unroll
+        for (int j = 0; j < 6; j++) vp[j] = a.val[rp[j]];
+#pragma unroll
+        for (int j = 0; j < 6; j++) {
+            const bool q = inb[j] && kp[j] > 0 && kp[j] < k && rp[j] >= rc;
+            qmask |= q ? 1u << j : 0u;
+            mp[j] = q ? ball_m(a, vp[j]) : 0u;
+        }
+    }
+    // full balls: listed with one atomic per wave
+    const bool full = k > 0 && qmask == 0;
+    const uint64_t mf = __ballot(full);
+    if (mf) {
+        const int leader = __ffsll((unsigned long long)mf) - 1;
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(a.n_full, (uint32_t)__popcll(mf));
+        base = __shfl(base, leader, 64);
+        if (full) a.full[base + (uint32_t)__popcll(mf & lanemask_lt())] = (uint32_t)c;
+    }
+    // small caps: each lane stamps its own (the wave runs as long as its
+    // largest small cap); large caps: the whole wave on one cap at a time
+    const bool cap = k > 0 && qmask != 0;
+    const uint32_t rbl = cap ? isqrt_u32(m - 1) : 0u;
+    if (cap && rbl <= (uint32_t)kSmallCap)
+        stamp_cap_lane(a, (int)c, k, m, qmask, x, y, z, mp);
+    uint64_t pending = __ballot(cap && rbl > (uint32_t)kSmallCap);
+    while (pending) {
+        const int src = __ffsll((unsigned long long)pending) - 1;
+        pending &= pending - 1;
+        uint32_t mps[6];
+#pragma unroll
+        for (int j = 0; j < 6; j++) mps[j] = __builtin_amdgcn_readlane(mp[j], src);
+        stamp_cap_wave(a, __builtin_amdgcn_readlane((int)c, src), __builtin_amdgcn_readlane(k, src),
+                       __builtin_amdgcn_readlane(m, src), __builtin_amdgcn_readlane(qmask, src),
+                       __builtin_amdgcn_readlane(x, src), __builtin_amdgcn_readlane(y, src),
+                       __builtin_amdgcn_readlane(z, src), mps);
     }
 }
 
