@@ -169,6 +169,22 @@ def test_invade_sphere_images(dev, seed):
     _check_invade(img, synth.face_mask(img.shape, 0, 0), dev)
 
 
+def test_invade_large_balls(dev):
+    """Cavities of radius 30 and 35 behind a narrow inlet channel: caps wider
+    than a wave (disk squares over 64 points on a side) and full balls of
+    radius near 35."""
+    X, Y, Z = 104, 80, 80
+    v = np.indices((X, Y, Z))
+    pore = np.zeros((X, Y, Z), bool)
+    for (cx, cy, cz), r in [((37, 40, 40), 35), ((72, 38, 42), 30)]:
+        pore |= (v[0] - cx) ** 2 + (v[1] - cy) ** 2 + (v[2] - cz) ** 2 < r * r
+    pore[:8] |= (v[1][:8] - 40) ** 2 + (v[2][:8] - 40) ** 2 < 25  # the inlet channel
+    img = pore.astype(np.uint8)
+    inl = synth.face_mask(img.shape, 0, 0)
+    g, r = _check_invade(img, inl, dev)
+    assert int(r["rad2"].max()) > 33 * 33  # some ball's cap disk is wider than 64 points
+
+
 @pytest.mark.parametrize("max_steps", [1, 7, 150])
 def test_invade_max_steps(dev, max_steps):
     img = synth.overlapping_spheres((30, 30, 30), r2=9, porosity=0.6, seed=2)
