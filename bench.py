@@ -494,6 +494,15 @@ def main() -> int:
                  "ns_per_wide_centre": 1e6 * tm["wide_kernel_ms"] / max(tm["wide_centres"], 1),
                  "relax_sweeps_per_step": tm["relax_sweeps"] / S},
     }
+    # the latency the loop's steps are bound by: one claim (a returning
+    # atomic) per step at least, from L2 (a 256 KiB chain), from the
+    # memory-side cache (64 MiB) or from HBM (1 GiB)
+    lat = {f"{name}_ns": ibip.probe_claim_latency(span, 20000)
+           for name, span in (("l2", 256 << 10), ("mall", 64 << 20), ("hbm", 1 << 30))}
+    us_step = res["loop"]["us_per_invasion_step"]
+    res["loop"]["claim_round_trip"] = lat
+    # how many L2 claim round trips one step takes
+    res["loop"]["step_in_l2_claim_round_trips"] = 1e3 * us_step / lat["l2_ns"]
     # the EDT alone at the 512^3 size, where it is not dominated by launches
     if not args.no_edt512:
         res["edt512_roofline"] = edt_alone(dev)

@@ -108,6 +108,16 @@ ibip_status ibip_ctx_enable_timing(ibip_ctx* ctx, int32_t enable);
 ibip_status ibip_ctx_get_timing(const ibip_ctx* ctx, ibip_timing* out);
 ibip_status ibip_ctx_reset_timing(ibip_ctx* ctx);
 
+/* Measurement aid for the step loop, whose steps each wait for at least one
+   claim (an atomic that returns the claimed word) before the next step's
+   maximum is known. One lane follows a chain of n_chain dependent atomics
+   through a device buffer of span_bytes (each atomic's result is the next
+   address, consecutive ones on different cache lines); *ns_per_claim (host)
+   receives the average time of one. A small span stays in the L2 cache, a
+   large one goes to memory. The buffer is context scratch.
+   Errors: EINVAL (span_bytes < 4096 or >= 2^34, n_chain < 1), ENOMEM. */
+ibip_status ibip_probe_claim_latency(ibip_ctx* ctx, int64_t span_bytes, int32_t n_chain, double* ns_per_claim);
+
 /*
  * ibip_edt -- distance transform of the pore space (Section 2.1, Figure 2(b)).
  * dt2[v] = min over solid voxels s of |v - s|^2 (exact, integer), 0 on solid.

@@ -23,7 +23,8 @@ import os
 import threading
 
 __all__ = ["edt", "invade", "invade_batch", "Server", "trap", "saturation", "remap_steps", "compare_opening", "opening_drainage",
-           "IbipError", "library_path", "load_library", "enable_timing", "get_timing", "reset_timing"]
+           "IbipError", "library_path", "load_library", "enable_timing", "get_timing", "reset_timing",
+           "probe_claim_latency"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libibip_hip.so")
@@ -126,7 +127,9 @@ def load_library():
         lib.ibip_ctx_enable_timing.argtypes = [P, i32]
         lib.ibip_ctx_get_timing.argtypes = [P, ctypes.POINTER(_Timing)]
         lib.ibip_ctx_reset_timing.argtypes = [P]
-        for fn in (lib.ibip_ctx_enable_timing, lib.ibip_ctx_get_timing, lib.ibip_ctx_reset_timing):
+        lib.ibip_probe_claim_latency.argtypes = [P, i64, i32, ctypes.POINTER(ctypes.c_double)]
+        for fn in (lib.ibip_ctx_enable_timing, lib.ibip_ctx_get_timing, lib.ibip_ctx_reset_timing,
+                   lib.ibip_probe_claim_latency):
             fn.restype = i32
         for fn in (lib.ibip_ctx_create, lib.ibip_ctx_destroy, lib.ibip_ctx_set_stream, lib.ibip_edt,
                    lib.ibip_invade, lib.ibip_get_steps, lib.ibip_trap, lib.ibip_opening_drainage):
@@ -532,6 +535,16 @@ def reset_timing(device=None):
     torch = _torch()
     ctx = _context(torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device()))
     _check(load_library().ibip_ctx_reset_timing(ctx), ctx)
+
+
+def probe_claim_latency(span_bytes: int, n_chain: int = 20000, device=None) -> float:
+    """Average time (ns) of one claim in a chain of dependent atomics through
+    a buffer of ``span_bytes`` (ibip_probe_claim_latency)."""
+    torch = _torch()
+    ctx = _context(torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device()))
+    ns = ctypes.c_double(0.0)
+    _check(load_library().ibip_probe_claim_latency(ctx, int(span_bytes), int(n_chain), ctypes.byref(ns)), ctx)
+    return ns.value
 
 
 def get_timing(device=None) -> dict:

@@ -148,6 +148,58 @@ ibip_status ibip_ctx_set_stream(ibip_ctx* ctx, void* stream) {
 
 const char* ibip_last_error(const ibip_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
+namespace {
+
+// buf[i] = the next index of the chain: a fixed odd stride of more than a
+// cache line, so consecutive claims touch different lines
+__global__ void k_probe_fill(uint32_t* buf, uint32_t span) {
+    const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < span) buf[i] = (uint32_t)((i + 32673u) % span);
+}
+
+__global__ void k_probe_chase(uint32_t* buf, int32_t n, uint32_t* out) {
+    uint32_t i = 0;
+    for (int32_t j = 0; j < n; j++) i = atomicOr(&buf[i], 0u);
+    *out = i;
+}
+
+}  // namespace
+
+ibip_status ibip_probe_claim_latency(ibip_ctx* ctx, int64_t span_bytes, int32_t n_chain, double* ns_per_claim) {
+    if (!ctx) return IBIP_EINVAL;
+    if (!ns_per_claim || span_bytes < 4096 || span_bytes >= ((int64_t)1 << 34) || n_chain < 1)
+        return fail(ctx, IBIP_EINVAL, "probe: bad arguments");
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(ctx, IBIP_EDEVICE, "probe: cannot select device");
+    const uint32_t span = (uint32_t)(span_bytes / 4);
+    uint32_t* buf = (uint32_t*)ensure(ctx, B_TMP0, (size_t)span * 4 + 256);
+    if (!buf) return fail(ctx, IBIP_ENOMEM, "probe: allocation failed");
+    hipStream_t s = ctx->stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ibip_status rc;
+    if ((rc = hip_check(ctx, hipEventCreate(&e0), "event")) != IBIP_OK) return rc;
+    if ((rc = hip_check(ctx, hipEventCreate(&e1), "event")) != IBIP_OK) {
+        (void)hipEventDestroy(e0);
+        return rc;
+    }
+    hipLaunchKernelGGL(k_probe_fill, dim3((span + 255) / 256), dim3(256), 0, s, buf, span);
+    // one short chase first, so that the timed one finds the code and the
+    // buffer's pages ready
+    hipLaunchKernelGGL(k_probe_chase, dim3(1), dim3(1), 0, s, buf, std::min(n_chain, 64), buf + span);
+    (void)hipEventRecord(e0, s);
+    hipLaunchKernelGGL(k_probe_chase, dim3(1), dim3(1), 0, s, buf, n_chain, buf + span);
+    (void)hipEventRecord(e1, s);
+    rc = hip_check(ctx, hipGetLastError(), "probe launch");
+    if (rc == IBIP_OK) rc = hip_check(ctx, hipEventSynchronize(e1), "sync");
+    float ms = 0.f;
+    if (rc == IBIP_OK) rc = hip_check(ctx, hipEventElapsedTime(&ms, e0, e1), "event");
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != IBIP_OK) return rc;
+    *ns_per_claim = (double)ms * 1e6 / (double)n_chain;
+    return IBIP_OK;
+}
+
 int64_t ibip_ctx_scratch_bytes(const ibip_ctx* ctx) {
     if (!ctx) return -1;
     int64_t t = 0;

@@ -49,3 +49,4 @@ def test_two_threads_two_streams(dev):
             assert torch.equal(ra["seq"], ref_a["seq"]) and ra["K"] == ref_a["K"]
             assert torch.equal(m["mio_r2"], ref_b["mio_r2"]) and m["mio_sat"] == ref_b["mio_sat"]
             assert torch.equal(c["seq"], ref_c["seq"]) and torch.equal(c["M"], ref_c["M"])
+
