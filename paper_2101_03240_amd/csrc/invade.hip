@@ -702,6 +702,39 @@ __device__ inline void loop_body(const LoopArgs& a, LoopShared& s) {
                     break;
                 }
                 npop += cnt;
+                if (direct && cnt <= 10) {
+                    // A run of one-pass steps whose centres the previous step
+                    // listed: a loop of its own, without the gathers, the
+                    // push log and the longer forms, until a step lists no
+                    // centres for the next one or the next has more than 10.
+                    uint32_t tt = t, c1 = cnt;
+                    for (;;) {
+                        uint32_t o0, u0, dn = 0, unused = 0;
+                        claim_pair(0, 6 * c1, k, a, s, o0, u0);
+                        s.head[r] = tt;
+                        const uint32_t below = lds_highest_below_uni(s, r);
+                        const uint32_t w0 = won_rank(o0);
+                        const uint32_t pmax = wave_max_u32(w0);
+                        const bool refilled = __ballot(w0 == r) != 0;
+                        if (!refilled) atomicAnd(&s.bits[r >> 5], ~(1u << (r & 31)));
+                        const uint32_t rn = pmax > r ? pmax : refilled ? r : max(below, pmax);
+                        direct = rn != 0 && rn != below;
+                        push_pair<false>(o0, u0, a, s, sel, unused, direct ? rn : 0u, dn);
+                        a.M[k - 1] = r;
+                        prev_r = r;
+                        r = rn;
+                        k = k + 1;
+                        if (!direct || k > klim) break;
+                        const uint32_t hh = uni(s.head[r]);
+                        tt = uni(s.tail[r]);
+                        c1 = tt - hh;
+                        if (c1 > 10) break;
+                        npop += c1;
+                    }
+                    log_ok = false;  // no push log was written
+                    nlog = kLog + 1;
+                    continue;
+                }
                 const uint32_t nsel = sel ^ 1u;
                 // a small step, wave 0 alone: its centres are listed in s.cl by the
                 // previous step, or gathered there from the log or the bucket
