@@ -198,6 +198,29 @@ def test_invade_no_inlet(dev):
     np.testing.assert_array_equal(g["seq"].cpu().numpy(), np.where(img > 0, 0, -1))
 
 
+def test_invade_too_many_distance_values_is_an_error(dev):
+    """A ball-shaped pore of radius 130 holds 9,326 distinct squared distances,
+    more than the loop's 8,192 rank slots: the call fails with ECAPACITY (the
+    distance transform itself is not limited)."""
+    L, c, r = 264, 132, 130
+    v = np.indices((L, L, L), dtype=np.int32)
+    img = (((v[0] - c) ** 2 + (v[1] - c) ** 2 + (v[2] - c) ** 2) < r * r).astype(np.uint8)
+    del v
+    inl = synth.face_mask(img.shape, 0, 0)
+    img_d = _d(img, dev)
+    assert int(_u32(ibip.edt(img_d)).max()) == r * r
+    with pytest.raises(ibip.IbipError, match="ECAPACITY|8192"):
+        ibip.invade(img_d, _d(inl, dev))
+    # in a batch only that job fails; the other one runs
+    small = synth.overlapping_spheres((24, 20, 28), r2=9, porosity=0.6, seed=3)
+    sinl = synth.face_mask(small.shape, 0, 0)
+    out = ibip.invade_batch([img_d, _d(small, dev)], [_d(inl, dev), _d(sinl, dev)], raise_on_error=False)
+    assert out[0]["status"] == -5 and out[1]["status"] == 0
+    r = oracle.invade(small, sinl)
+    assert out[1]["K"] == r["K"]
+    np.testing.assert_array_equal(out[1]["seq"].cpu().numpy(), r["seq"])
+
+
 def test_invade_no_solid_is_an_error(dev):
     img = np.ones((8, 8, 8), np.uint8)
     with pytest.raises(ibip.IbipError) as e:
