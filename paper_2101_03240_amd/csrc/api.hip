@@ -133,6 +133,7 @@ ibip_status ibip_ctx_destroy(ibip_ctx* ctx) {
     }
     if (ctx->timer.made)
         for (auto& e : ctx->timer.ev) (void)hipEventDestroy(e);
+    if (ctx->copy_ev) (void)hipEventDestroy(ctx->copy_ev);
     for (auto& b : ctx->buf)
         if (b.p) (void)hipFree(b.p);
     if (ctx->host_pinned) (void)hipHostFree(ctx->host_pinned);

@@ -203,7 +203,7 @@ namespace ibip {
 // Optional event-based phase timer (see ibip_timing).
 struct Timer {
     bool on = false;
-    hipEvent_t ev[12] = {};
+    hipEvent_t ev[16] = {};
     bool made = false;
     // record event i on stream s (no-op when off)
     void mark(int i, hipStream_t s) {
@@ -235,6 +235,7 @@ struct ibip_ctx {
     std::string err;
     ibip::Buf buf[ibip::B_NUM];
     void* host_pinned = nullptr;   // pinned mirror of LoopState and small results
+    hipEvent_t copy_ev = nullptr;  // the loop state's copy to the host (no timing)
     size_t host_pinned_bytes = 0;
     // results of the last invade
     int64_t last_K = -1;

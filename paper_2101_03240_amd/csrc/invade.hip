@@ -840,8 +840,12 @@ __device__ inline void loop_body(const LoopArgs& a, LoopShared& s) {
     }
 }
 
+// The host queues each launch before it knows whether the previous one
+// finished the loop: a launch after the end does nothing.
 __global__ __launch_bounds__(kLoopThreads) void k_loop(LoopArgs a) {
     __shared__ LoopShared s;
+    const uint32_t status = a.st->status;
+    if (status != LS_RUN && status != LS_WIDE) return;
     loop_body(a, s);
 }
 
@@ -859,8 +863,11 @@ __global__ __launch_bounds__(kLoopThreads) void k_loop_batch(const LoopArgs* __r
 // block, and every push lands at that base plus its place in the block's
 // count: slice tails are few and hot, and one atomic per wave and rank
 // queued thousands of atomics on each of them.
+// It is queued after every loop launch and does nothing unless that launch
+// stopped at a wide step.
 __global__ __launch_bounds__(256) void k_wide(LoopArgs a) {
     __shared__ uint32_t lcnt[kMaxRanks + 1];  // per rank: the block's pushes, then their base
+    if (a.st->status != LS_WIDE) return;
     const uint32_t h = a.st->big_h, t = a.st->big_t, k = a.st->big_k, R = a.st->R;
     const uint32_t cnt = t - h;
     const uint32_t stride = gridDim.x * 256;
@@ -1360,40 +1367,53 @@ ibip_status run_invade(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlet
     }
     LoopArgs la{st,     head, tail, val, bucket, state, key, M, d.X, d.Y, d.Z, kWideRound, kSmallRound,
                 make_fastdiv((uint32_t)d.Z), make_fastdiv((uint32_t)d.Y)};
+    // The loop kernel stops at each wide step; the host reads the loop state
+    // after each stop. The wide step and the next loop segment are queued
+    // before that read (each does nothing if the loop had ended), so the GPU
+    // does not wait for the host between segments. Timing events alternate
+    // between two slots, since a launch's events are read only after the
+    // launch queued behind it was recorded.
+    const unsigned gw = (unsigned)std::min<int64_t>((n_pore + 255) / 256, 4096);
+    if (!ctx->copy_ev &&
+        (rc = hip_check(ctx, hipEventCreateWithFlags(&ctx->copy_ev, hipEventDisableTiming), "event")) != IBIP_OK)
+        return rc;
+    auto loop_ev = [](int p, int e) { return p ? 12 + e : 3 + e; };  // e = 0 start, 1 end
+    auto wide_ev = [](int p, int e) { return p ? 14 + e : 5 + e; };
     int64_t segments = 0, wide_centres = 0;
-    bool wide_pending_timing = false;
+    int p = 0;
+    bool wide_ran = false;  // the wide launch read this round ran a wide step
+    tm.mark(loop_ev(p, 0), s);
+    hipLaunchKernelGGL(k_loop, dim3(1), dim3(kLoopThreads), 0, s, la);
+    tm.mark(loop_ev(p, 1), s);
     for (;;) {
-        tm.mark(3, s);
-        hipLaunchKernelGGL(k_loop, dim3(1), dim3(kLoopThreads), 0, s, la);
-        tm.mark(4, s);
         if ((rc = hip_check(ctx, hipGetLastError(), "loop launch")) != IBIP_OK) return rc;
         if ((rc = hip_check(ctx, hipMemcpyAsync(h_st, st, sizeof(LoopState), hipMemcpyDeviceToHost, s), "copy")) !=
             IBIP_OK)
             return rc;
-        if ((rc = hip_check(ctx, hipStreamSynchronize(s), "sync")) != IBIP_OK) return rc;
+        if ((rc = hip_check(ctx, hipEventRecord(ctx->copy_ev, s), "event")) != IBIP_OK) return rc;
+        tm.mark(wide_ev(p, 0), s);
+        hipLaunchKernelGGL(k_wide, dim3(gw), dim3(256), 0, s, la);
+        tm.mark(wide_ev(p, 1), s);
+        tm.mark(loop_ev(p ^ 1, 0), s);
+        hipLaunchKernelGGL(k_loop, dim3(1), dim3(kLoopThreads), 0, s, la);
+        tm.mark(loop_ev(p ^ 1, 1), s);
+        if ((rc = hip_check(ctx, hipGetLastError(), "wide launch")) != IBIP_OK) return rc;
+        if ((rc = hip_check(ctx, hipEventSynchronize(ctx->copy_ev), "sync")) != IBIP_OK) return rc;
         if (tm.on) {
-            ctx->timing.loop_kernel_ms += tm.ms(3, 4);
+            ctx->timing.loop_kernel_ms += tm.ms(loop_ev(p, 0), loop_ev(p, 1));
             ctx->timing.loop_launches++;
-            if (wide_pending_timing) {
-                ctx->timing.wide_kernel_ms += tm.ms(5, 6);
+            if (wide_ran) {
+                ctx->timing.wide_kernel_ms += tm.ms(wide_ev(p ^ 1, 0), wide_ev(p ^ 1, 1));
                 ctx->timing.wide_launches++;
-                wide_pending_timing = false;
             }
         }
         if (++segments > n_pore + 2) return fail(ctx, IBIP_EDEVICE, "invade: too many loop segments");
-        if (h_st->status == LS_WIDE) {
-            const uint32_t cnt = h_st->big_t - h_st->big_h;
-            wide_centres += cnt;
-            if (tm.on) ctx->timing.wide_centres += cnt;
-            const unsigned g = (unsigned)std::min<int64_t>((cnt + 255) / 256, 4096);
-            tm.mark(5, s);
-            hipLaunchKernelGGL(k_wide, dim3(g), dim3(256), 0, s, la);
-            tm.mark(6, s);
-            wide_pending_timing = true;
-            if ((rc = hip_check(ctx, hipGetLastError(), "wide launch")) != IBIP_OK) return rc;
-            continue;
-        }
-        break;
+        if (h_st->status != LS_WIDE) break;
+        const uint32_t cnt = h_st->big_t - h_st->big_h;
+        wide_centres += cnt;
+        if (tm.on) ctx->timing.wide_centres += cnt;
+        wide_ran = true;
+        p ^= 1;
     }
     if (h_st->err) return fail(ctx, IBIP_EDEVICE, "invade: step loop exceeded the pore count");
     const int64_t K = (int64_t)h_st->k - 1;
