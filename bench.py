@@ -161,7 +161,9 @@ def run_batch(args) -> int:
     from paper_2101_03240_amd import synth
 
     dev = torch.device("cuda:0")
+    print("batch96: generating 96 images", file=sys.stderr, flush=True)
     imgs = batch_images(96)
+    print("batch96: images generated", file=sys.stderr, flush=True)
     d_imgs = [torch.from_numpy(a).to(dev) for a in imgs]
     d_inls = [torch.from_numpy(synth.face_mask(a.shape, 0, 0)).to(dev) for a in imgs]
     n_vox = int(sum(a.size for a in imgs))
