@@ -41,6 +41,33 @@ void* ensure(ibip_ctx* ctx, BufId id, size_t bytes) {
     return p;
 }
 
+bool done_records(ibip_ctx* ctx, size_t words) {
+    if (ctx->done_words < words) {
+        if (ctx->done_host) {
+            if (hipStreamSynchronize(ctx->stream) != hipSuccess) return false;
+            (void)hipHostFree(ctx->done_host);
+            ctx->done_host = ctx->done_dev = nullptr;
+            ctx->done_words = 0;
+        }
+        void* p = nullptr;
+        if (hipHostMalloc(&p, words * sizeof(uint32_t), hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess) {
+            (void)hipGetLastError();
+            return false;
+        }
+        void* d = nullptr;
+        if (hipHostGetDevicePointer(&d, p, 0) != hipSuccess) {
+            (void)hipGetLastError();
+            (void)hipHostFree(p);
+            return false;
+        }
+        ctx->done_host = (uint32_t*)p;
+        ctx->done_dev = (uint32_t*)d;
+        ctx->done_words = words;
+    }
+    std::memset(ctx->done_host, 0, words * sizeof(uint32_t));
+    return true;
+}
+
 void* pinned(ibip_ctx* ctx, size_t bytes) {
     if (ctx->host_pinned_bytes >= bytes) return ctx->host_pinned;
     if (ctx->host_pinned) {
@@ -137,6 +164,7 @@ ibip_status ibip_ctx_destroy(ibip_ctx* ctx) {
     for (auto& b : ctx->buf)
         if (b.p) (void)hipFree(b.p);
     if (ctx->host_pinned) (void)hipHostFree(ctx->host_pinned);
+    if (ctx->done_host) (void)hipHostFree(ctx->done_host);
     delete ctx;
     return IBIP_OK;
 }

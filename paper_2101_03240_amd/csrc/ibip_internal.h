@@ -236,6 +236,11 @@ struct ibip_ctx {
     ibip::Buf buf[ibip::B_NUM];
     void* host_pinned = nullptr;   // pinned mirror of LoopState and small results
     hipEvent_t copy_ev = nullptr;  // the loop state's copy to the host (no timing)
+    // per-job completion records of a batch (3 words each: done, k, err) in
+    // coherent pinned host memory that the loop kernel writes directly
+    uint32_t* done_host = nullptr;
+    uint32_t* done_dev = nullptr;
+    size_t done_words = 0;
     size_t host_pinned_bytes = 0;
     // results of the last invade
     int64_t last_K = -1;
@@ -253,6 +258,8 @@ ibip_status hip_check(ibip_ctx* ctx, hipError_t e, const char* what);
 // Ensure buffer `id` holds at least `bytes`; returns its pointer or nullptr.
 void* ensure(ibip_ctx* ctx, BufId id, size_t bytes);
 void* pinned(ibip_ctx* ctx, size_t bytes);
+// ctx->done_host/done_dev with at least `words` words, zeroed; false on failure.
+bool done_records(ibip_ctx* ctx, size_t words);
 bool dims_ok(ibip_dims d);
 inline int64_t nvox(ibip_dims d) { return (int64_t)d.X * d.Y * d.Z; }
 

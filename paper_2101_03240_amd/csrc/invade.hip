@@ -35,7 +35,9 @@
 // S = {o : |o|^2 < M <= |o - n|^2} (n = p - c), filtered by every other such
 // neighbour. This is exact: the smallest step covering a voxel always stamps
 // it, since a ball it skipped is covered by an earlier ball.
+#include <chrono>
 #include <climits>
+#include <thread>
 #include <vector>
 
 #include "ibip_internal.h"
@@ -252,6 +254,8 @@ struct LoopArgs {
     uint32_t wide;    // steps with more centres go to the whole-GPU kernel
     uint32_t small;   // steps with at most this many centres run in wave 0 alone
     FastDiv divZ, divY;
+    // a batch job's completion record in host memory (done, k, err), or null
+    uint32_t* done = nullptr;
 };
 
 constexpr int kLoopThreads = 1024;
@@ -837,6 +841,20 @@ __device__ inline void loop_body(const LoopArgs& a, LoopShared& s) {
     for (uint32_t q = tid; q <= R; q += kLoopThreads) {
         a.head[q] = s.head[q];
         a.tail[q] = s.tail[q];
+    }
+    if (a.done) {
+        // a batch job: tell the host, which starts the job's post-processing
+        // while other jobs' loops still run. The barrier orders every
+        // thread's writes before thread 0's fence, which makes them visible
+        // before the record; the record's fields precede its flag.
+        __syncthreads();
+        if (tid == 0) {
+            __threadfence_system();
+            a.done[1] = k;
+            a.done[2] = a.st->err;
+            __threadfence_system();
+            a.done[0] = 1u;
+        }
     }
 }
 
@@ -1672,7 +1690,13 @@ ibip_status run_invade_batch(ibip_ctx* ctx, ibip_job* jobs, int32_t nj) {
         const JobBufs& j = bufs[q];
         h_args[q] = job_loop_args(j, states + q, jb.dims);
     }
-    // join, then one launch runs every job's step loop
+    // join, then one launch runs every job's step loop. Each job's workgroup
+    // writes a completion record to host memory when its loop ends, and the
+    // host starts that job's post-processing on the batch streams while the
+    // launch still runs the other (larger) jobs; the jobs left when the
+    // launch ends take their results from the state copy.
+    if (!done_records(ctx, 3 * (size_t)nj)) return fail(ctx, IBIP_ENOMEM, "invade_batch: pinned allocation failed");
+    for (int32_t q = 0; q < nj; q++) h_args[q].done = ctx->done_dev + 3 * q;
     for (int i = 0; i < S; i++) {
         if ((rc = hip_check(ctx, hipEventRecord(ctx->bev[i], ctx->bstream[i]), "event")) != IBIP_OK) return rc;
         if ((rc = hip_check(ctx, hipStreamWaitEvent(s0, ctx->bev[i], 0), "wait")) != IBIP_OK) return rc;
@@ -1688,33 +1712,54 @@ ibip_status run_invade_batch(ibip_ctx* ctx, ibip_job* jobs, int32_t nj) {
     if ((rc = hip_check(ctx, hipMemcpyAsync(h_st, states, sizeof(LoopState) * nj, hipMemcpyDeviceToHost, s0),
                         "copy")) != IBIP_OK)
         return rc;
-    if ((rc = hip_check(ctx, hipStreamSynchronize(s0), "sync")) != IBIP_OK) return rc;
+    if (!ctx->copy_ev &&
+        (rc = hip_check(ctx, hipEventCreateWithFlags(&ctx->copy_ev, hipEventDisableTiming), "event")) != IBIP_OK)
+        return rc;
+    if ((rc = hip_check(ctx, hipEventRecord(ctx->copy_ev, s0), "event")) != IBIP_OK) return rc;
+    ibip_status first = IBIP_OK;
+    auto post = [&](int32_t q, uint32_t k, uint32_t err) -> ibip_status {
+        ibip_job& jb = jobs[order[q]];
+        jb.status = IBIP_OK;
+        jb.n_steps = 0;
+        if (err == 2) jb.status = IBIP_ENOSOLID;
+        else if (err == 3) jb.status = IBIP_ECAPACITY;
+        else if (err) jb.status = IBIP_EDEVICE;
+        if (jb.status != IBIP_OK) {
+            if (first == IBIP_OK) first = (ibip_status)jb.status;
+            return IBIP_OK;
+        }
+        const int64_t K = (int64_t)k - 1;
+        jb.n_steps = K;
+        return hip_check(ctx, job_post(bufs[q], states + q, jb.dims, K, jb.seq, jb.rad2, jb.M, jb.sat,
+                                       ctx->bstream[q % S]), "post");
+    };
+    std::vector<uint8_t> posted(nj, 0);
+    int32_t left = nj;
+    for (;;) {
+        bool progress = false;
+        for (int32_t q = 0; q < nj; q++) {
+            if (posted[q] || __atomic_load_n(&ctx->done_host[3 * q], __ATOMIC_ACQUIRE) == 0) continue;
+            if ((rc = post(q, ctx->done_host[3 * q + 1], ctx->done_host[3 * q + 2])) != IBIP_OK) return rc;
+            posted[q] = 1;
+            left--;
+            progress = true;
+        }
+        if (left == 0) break;
+        const hipError_t qe = hipEventQuery(ctx->copy_ev);
+        if (qe == hipSuccess) break;
+        if (qe != hipErrorNotReady) return hip_check(ctx, qe, "event query");
+        if (!progress) std::this_thread::sleep_for(std::chrono::microseconds(20));
+    }
+    if ((rc = hip_check(ctx, hipEventSynchronize(ctx->copy_ev), "sync")) != IBIP_OK) return rc;
     if (tm.on) {
         ctx->timing.loop_kernel_ms += tm.ms(3, 4);
         ctx->timing.loop_launches++;
     }
-    // post-processing, again spread over the streams
-    if ((rc = hip_check(ctx, hipEventRecord(ctx->bev[S], s0), "event")) != IBIP_OK) return rc;
-    for (int i = 0; i < S; i++)
-        if ((rc = hip_check(ctx, hipStreamWaitEvent(ctx->bstream[i], ctx->bev[S], 0), "wait")) != IBIP_OK) return rc;
-    ibip_status first = IBIP_OK;
+    // jobs that wrote no record (rejected before their loop) or were not seen
+    // before the launch ended
     for (int32_t q = 0; q < nj; q++) {
-        ibip_job& jb = jobs[order[q]];
-        const LoopState& hs = h_st[q];
-        jb.status = IBIP_OK;
-        jb.n_steps = 0;
-        if (hs.err == 2) jb.status = IBIP_ENOSOLID;
-        else if (hs.err == 3) jb.status = IBIP_ECAPACITY;
-        else if (hs.err) jb.status = IBIP_EDEVICE;
-        if (jb.status != IBIP_OK) {
-            if (first == IBIP_OK) first = (ibip_status)jb.status;
-            continue;
-        }
-        const int64_t K = (int64_t)hs.k - 1;
-        jb.n_steps = K;
-        if ((rc = hip_check(ctx, job_post(bufs[q], states + q, jb.dims, K, jb.seq, jb.rad2, jb.M, jb.sat,
-                                          ctx->bstream[q % S]), "post")) != IBIP_OK)
-            return rc;
+        if (posted[q]) continue;
+        if ((rc = post(q, h_st[q].k, h_st[q].err)) != IBIP_OK) return rc;
     }
     for (int i = 0; i < S; i++) {
         if ((rc = hip_check(ctx, hipEventRecord(ctx->bev[i], ctx->bstream[i]), "event")) != IBIP_OK) return rc;
