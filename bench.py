@@ -335,9 +335,13 @@ def main() -> int:
     ap.add_argument("--depth", type=int, default=32, help="serve: outstanding requests in the closed loop")
     ap.add_argument("--serve-budget-gb", type=float, default=96.0, help="serve: HBM pool for job scratch")
     ap.add_argument("--check-large", type=int, default=0, help="serve: also rerun the largest request alone")
-    ap.add_argument("--hw-queues", type=int, default=0,
+    ap.add_argument("--hw-queues", type=int, default=-1,
                     help="hardware queues per process for the HIP runtime (0: its default)")
     args = ap.parse_args()
+    if args.hw_queues < 0:
+        # the batch and the server spread work over 8 and 16 streams, whose
+        # kernels serialise when they share a hardware queue
+        args.hw_queues = 16 if args.workload in ("batch96", "serve") else 0
     if args.hw_queues:
         os.environ["GPU_MAX_HW_QUEUES"] = str(min(args.hw_queues, 32))
     world = int(os.environ.get("WORLD_SIZE", "1"))
