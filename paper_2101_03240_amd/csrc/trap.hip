@@ -351,7 +351,7 @@ ibip_status reconstruct(ibip_ctx* ctx, const int32_t* seq, const uint32_t* cap32
     hipStream_t s = ctx->stream;
     const int ntx = (d.X + TX - 1) / TX, nty = (d.Y + TY - 1) / TY, ntz = (d.Z + TZ - 1) / TZ;
     const int64_t ntiles = (int64_t)ntx * nty * ntz;
-    constexpr int kBatch = 8;  // sweeps per host check
+    constexpr int kBatch = 16;  // sweeps per host check
     uint8_t* misc = (uint8_t*)ensure(ctx, B_MISC, 4096);
     uint8_t* act = (uint8_t*)ensure(ctx, B_ACT, 2 * (size_t)ntiles + 64);
     uint32_t* cnt = (uint32_t*)ensure(ctx, B_CNT, sizeof(uint32_t) * kBatch);
