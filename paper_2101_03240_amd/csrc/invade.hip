@@ -1391,7 +1391,8 @@ ibip_status run_invade(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlet
     // does not wait for the host between segments. Timing events alternate
     // between two slots, since a launch's events are read only after the
     // launch queued behind it was recorded.
-    const unsigned gw = (unsigned)std::min<int64_t>((n_pore + 255) / 256, 4096);
+    // at least one block: an image with no pore voxel still takes the launches
+    const unsigned gw = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n_pore + 255) / 256, 4096));
     if (!ctx->copy_ev &&
         (rc = hip_check(ctx, hipEventCreateWithFlags(&ctx->copy_ev, hipEventDisableTiming), "event")) != IBIP_OK)
         return rc;

@@ -84,6 +84,7 @@ struct Slot {
     uint8_t* dev_small = nullptr;   // device: LoopState at 0, loop arguments at 512
     uint8_t* host_small = nullptr;  // pinned: LoopState copy at 0, loop-argument staging at 512
     int64_t ticket = -1;
+    bool broken = false;            // its stream failed; no job is admitted to it again
 };
 
 }  // namespace
@@ -131,6 +132,13 @@ bool start_job(ibip_server* S, int64_t t, int si) {
     if (e == hipSuccess) e = hipEventRecord(sl.done, sl.stream);
     if (e != hipSuccess) {
         set_err(S, std::string("server: launch failed: ") + hipGetErrorString(e));
+        // work queued before the failure may still write into the job's
+        // region: wait for it before the caller returns the region to the
+        // pool, and retire the slot if its stream is in an error state
+        if (hipStreamSynchronize(sl.stream) != hipSuccess) {
+            (void)hipGetLastError();
+            sl.broken = true;
+        }
         return false;
     }
     J.slot = si;
@@ -181,7 +189,7 @@ void worker_main(ibip_server* S) {
         for (;;) {
             int free_slot = -1;
             for (size_t si = 0; si < S->slots.size(); si++)
-                if (S->slots[si].ticket < 0) {
+                if (S->slots[si].ticket < 0 && !S->slots[si].broken) {
                     free_slot = (int)si;
                     break;
                 }
@@ -213,6 +221,20 @@ void worker_main(ibip_server* S) {
                 break;
             }
             if (!started) break;
+        }
+        // with every slot retired no pending job can run: report them failed
+        if (!S->pending.empty() &&
+            std::all_of(S->slots.begin(), S->slots.end(), [](const Slot& x) { return x.broken; })) {
+            for (const int64_t t : S->pending) {
+                Job& J = S->jobs[t];
+                J.job.status = IBIP_EDEVICE;
+                J.state = J_DONE;
+                J.t_done = Clock::now();
+                S->stats.pending--;
+                S->stats.completed++;
+            }
+            S->pending.clear();
+            S->cv_done.notify_all();
         }
         const bool idle = S->stats.running == 0;
         if (S->stop && idle && S->pending.empty()) break;

@@ -221,6 +221,26 @@ def test_invade_too_many_distance_values_is_an_error(dev):
     np.testing.assert_array_equal(out[1]["seq"].cpu().numpy(), r["seq"])
 
 
+@pytest.mark.parametrize("shape", [(12, 10, 16), (1, 9, 14)])
+def test_invade_no_pore(dev, shape):
+    """An image with solid but no pore voxel: no step, seq = -1 everywhere,
+    through ibip_invade (whose wide-step launches then have no pore voxel to
+    size their grid by) and as a job of a batch; trapping finds nothing."""
+    img = np.zeros(shape, np.uint8)
+    inl = synth.face_mask(shape, 0, 0)
+    r = oracle.invade(img, inl)
+    assert r["K"] == 0
+    g = ibip.invade(_d(img, dev), _d(inl, dev))
+    assert g["K"] == 0
+    np.testing.assert_array_equal(g["seq"].cpu().numpy(), r["seq"])
+    np.testing.assert_array_equal(_u32(g["rad2"]), r["rad2"])
+    b = ibip.invade_batch([_d(img, dev)], [_d(inl, dev)])
+    assert b[0]["status"] == 0 and b[0]["K"] == 0
+    np.testing.assert_array_equal(b[0]["seq"].cpu().numpy(), r["seq"])
+    t = ibip.trap(g["seq"], _d(synth.face_mask(shape, 0, shape[0] - 1), dev))
+    assert t["K_after"] == 0 and int(t["trapped"].sum().item()) == 0
+
+
 def test_invade_no_solid_is_an_error(dev):
     img = np.ones((8, 8, 8), np.uint8)
     with pytest.raises(ibip.IbipError) as e:
