@@ -127,6 +127,26 @@ ibip_status ibip_probe_claim_latency(ibip_ctx* ctx, int64_t span_bytes, int32_t 
 ibip_status ibip_edt(ibip_ctx* ctx, const uint8_t* image, ibip_dims dims, uint32_t* dt2);
 
 /*
+ * ibip_edt_noalloc -- ibip_edt for callers that cannot allocate memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc). Same dt2 as ibip_edt, but the call allocates nothing: its
+ * intermediate distances (6 bytes per voxel) live in one fixed scratch array
+ * of the library, 96 MiB per device, held from the first context created on
+ * that device until the process ends. It does not synchronise: the solid
+ * check is returned on the device instead of as ENOSOLID.
+ * image, dt2:  as for ibip_edt, caller-owned DEVICE buffers.
+ * solid_flag:  DEVICE uint32 out, set to 1 when the image holds a solid
+ *              voxel, 0 when it holds none (dt2 is then unspecified).
+ * Every call on one device shares that device's scratch: two calls that
+ * overlap on the device (on different streams or contexts) race and give
+ * wrong results. Calls ordered on one stream are safe.
+ * Errors: EINVAL, ECAPACITY (more than 2^24 voxels), EDEVICE (launch failure,
+ * or the scratch has no address on this device).
+ */
+ibip_status ibip_edt_noalloc(ibip_ctx* ctx, const uint8_t* image, ibip_dims dims, uint32_t* dt2,
+                             uint32_t* solid_flag);
+
+/*
  * ibip_invade -- the invasion loop of Section 2.1 (Figure 2(e)-(l)).
  * Step k takes the candidates (inlets, plus the face neighbours of the inlets
  * and of every earlier centre, pore only, not yet a centre), finds the

@@ -22,7 +22,7 @@ import ctypes
 import os
 import threading
 
-__all__ = ["edt", "invade", "invade_batch", "Server", "trap", "saturation", "remap_steps", "compare_opening", "opening_drainage",
+__all__ = ["edt", "edt_noalloc", "invade", "invade_batch", "Server", "trap", "saturation", "remap_steps", "compare_opening", "opening_drainage",
            "IbipError", "library_path", "load_library", "enable_timing", "get_timing", "reset_timing",
            "probe_claim_latency"]
 
@@ -98,6 +98,8 @@ def load_library():
         lib.ibip_ctx_scratch_bytes.argtypes = [P]
         lib.ibip_ctx_scratch_bytes.restype = i64
         lib.ibip_edt.argtypes = [P, P, _Dims, P]
+        lib.ibip_edt_noalloc.argtypes = [P, P, _Dims, P, P]
+        lib.ibip_edt_noalloc.restype = i32
         lib.ibip_invade.argtypes = [P, P, P, _Dims, ctypes.POINTER(_InvadeOpts), P, P, P, ctypes.POINTER(i64)]
         lib.ibip_get_steps.argtypes = [P, P, P, P, P, i64]
         lib.ibip_trap.argtypes = [P, P, P, _Dims, P, P, ctypes.POINTER(i64)]
@@ -214,6 +216,25 @@ def edt(image):
     out = torch.empty(image.shape, dtype=torch.int32, device=image.device)
     _check(load_library().ibip_edt(ctx, _ptr(image), dims, _ptr(out)), ctx)
     return out
+
+
+def edt_noalloc(image, out=None, solid_flag=None):
+    """``edt`` through ibip_edt_noalloc, which allocates no device memory
+    (its intermediate distances live in the library's fixed scratch; images
+    of at most 2^24 voxels). ``out`` (int32, the image's shape) and
+    ``solid_flag`` (int32, one entry) may be given to avoid allocations here
+    too. Returns (dt2, solid_flag); solid_flag[0] == 0 means the image holds
+    no solid voxel. Does not synchronise."""
+    torch = _torch()
+    image = _dev_u8(image, "image")
+    dims, shape = _dims_of(image)
+    ctx = _context(image.device)
+    if out is None:
+        out = torch.empty(image.shape, dtype=torch.int32, device=image.device)
+    if solid_flag is None:
+        solid_flag = torch.empty(1, dtype=torch.int32, device=image.device)
+    _check(load_library().ibip_edt_noalloc(ctx, _ptr(image), dims, _ptr(out), _ptr(solid_flag)), ctx)
+    return out, solid_flag
 
 
 def invade(image, inlets, max_steps: int = 0, sigma: float = 1.0, theta_rad: float = 0.0,

@@ -1,12 +1,56 @@
 // C ABI of the library (declared in include/ibip.h): context, scratch arena,
 // argument checks and error plumbing around the kernels of edt.hip,
 // invade.hip, trap.hip and mio.hip.
+#include <atomic>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "ibip_internal.h"
 
 namespace ibip {
+
+// Scratch of ibip_edt_noalloc: the z pass's uint16 distances (2 B per voxel)
+// followed by the y pass's uint32 values (4 B per voxel) of one image of at
+// most kNoAllocMaxVoxels voxels. Every device the library runs on holds one
+// copy for the life of the process. Host code never passes `scratch` itself
+// to a kernel (in host code the name is only a stand-in): it uses the
+// device address that hipGetSymbolAddress returned for the current device.
+constexpr int64_t kNoAllocMaxVoxels = (int64_t)1 << 24;
+constexpr size_t kNoAllocScratchBytes = (size_t)6 << 24;
+static __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+std::atomic<void*> g_scratch_ptr[kMaxDevices];
+std::atomic<int> g_scratch_state[kMaxDevices];  // 0 not looked up, 1 ok, -1 lookup failed
+
+// The address of `scratch` on `device`, looked up once per device with that
+// device current (the caller's DeviceGuard makes it current).
+void* scratch_on(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    if (g_scratch_state[device].load(std::memory_order_acquire) == 0) {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (g_scratch_state[device].load(std::memory_order_relaxed) == 0) {
+            void* p = nullptr;
+            const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !p) {
+                (void)hipGetLastError();
+                g_scratch_state[device].store(-1, std::memory_order_release);
+            } else {
+                g_scratch_ptr[device].store(p, std::memory_order_relaxed);
+                g_scratch_state[device].store(1, std::memory_order_release);
+            }
+        }
+    }
+    return g_scratch_state[device].load(std::memory_order_acquire) == 1
+               ? g_scratch_ptr[device].load(std::memory_order_relaxed)
+               : nullptr;
+}
+
+__global__ void k_clear_word(uint32_t* w) { *w = 0u; }
+}  // namespace
 
 ibip_status fail(ibip_ctx* ctx, ibip_status st, const std::string& what) {
     if (ctx) ctx->err = what;
@@ -126,6 +170,13 @@ ibip_status ibip_ctx_create(ibip_ctx** out, int32_t device, void* stream) {
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return IBIP_EDEVICE;
     ibip_ctx* ctx = new (std::nothrow) ibip_ctx();
     if (!ctx) return IBIP_ENOMEM;
+    {
+        // the device address of the no-allocation scratch, looked up once
+        // per device while that device is current (a failed lookup is
+        // reported by ibip_edt_noalloc)
+        DeviceGuard g(device);
+        if (g.ok) (void)scratch_on(device);
+    }
     ctx->device = device;
     ctx->stream = (hipStream_t)stream;
     *out = ctx;
@@ -262,6 +313,26 @@ ibip_status ibip_edt(ibip_ctx* ctx, const uint8_t* image, ibip_dims dims, uint32
     if (ctx->timer.on) ctx->timing.edt_ms += ctx->timer.ms(0, 1);  // the three passes' kernels
     if (!h[0]) return fail(ctx, IBIP_ENOSOLID, "edt: image holds no solid voxel");
     return IBIP_OK;
+}
+
+ibip_status ibip_edt_noalloc(ibip_ctx* ctx, const uint8_t* image, ibip_dims dims, uint32_t* dt2,
+                             uint32_t* solid_flag) {
+    if (!ctx) return IBIP_EINVAL;
+    if (!image || !dt2 || !solid_flag) return fail(ctx, IBIP_EINVAL, "edt_noalloc: null pointer");
+    if (!dims_ok(dims)) return fail(ctx, IBIP_EINVAL, "edt_noalloc: bad dims");
+    const int64_t n = nvox(dims);
+    if (n > kNoAllocMaxVoxels)
+        return fail(ctx, IBIP_ECAPACITY,
+                    "edt_noalloc: the image has more than 2^24 voxels, the limit of the fixed scratch");
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(ctx, IBIP_EDEVICE, "edt_noalloc: cannot select device");
+    uint8_t* base = (uint8_t*)scratch_on(ctx->device);
+    if (!base) return fail(ctx, IBIP_EDEVICE, "edt_noalloc: no device address for the fixed scratch");
+    uint16_t* g16 = (uint16_t*)base;
+    uint32_t* tmp = (uint32_t*)(base + align256(sizeof(uint16_t) * (size_t)n));
+    hipLaunchKernelGGL(k_clear_word, dim3(1), dim3(1), 0, ctx->stream, solid_flag);
+    return hip_check(ctx, launch_edt(image, nullptr, 0, 0, dims, g16, tmp, dt2, solid_flag, ctx->stream),
+                     "edt_noalloc launch");
 }
 
 ibip_status ibip_invade(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlets, ibip_dims dims,
