@@ -25,6 +25,7 @@ import numpy as np
 
 __all__ = [
     "overlapping_spheres",
+    "poisson_disks",
     "sphere_packing",
     "blurred_noise",
     "face_mask",
@@ -86,6 +87,33 @@ def overlapping_spheres(shape=(64, 64, 64), r2: int = 16, porosity: float = 0.65
         view[b] = 0
         n_solid += newly
     return img
+
+
+def poisson_disks(L: int = 500, r: float = 12.0, porosity: float = 0.6, seed: int = 12,
+                  scale: int = 1) -> np.ndarray:
+    """One 2D geometry of overlapping solid disks, rasterised at ``scale``
+    pixels per unit length: (1, L*scale, L*scale) uint8. Disk centres are a
+    Poisson process over the box extended by r on every side, with intensity
+    -ln(porosity) / (pi r^2), so the expected pore fraction is ``porosity``;
+    a pixel is solid when its centre ((i + 0.5) / scale) lies in a disk. The
+    geometry depends only on (L, r, porosity, seed), so images at several
+    scales show the same structure at different resolutions."""
+    rng = _rng(seed)
+    lam = -math.log(porosity) / (math.pi * r * r)
+    n = int(rng.poisson(lam * (L + 2 * r) ** 2))
+    centres = rng.uniform(-r, L + r, size=(n, 2))
+    m = L * scale
+    img = np.ones((m, m), dtype=np.uint8)
+    pos = (np.arange(m) + 0.5) / scale
+    for cy, cx in centres:
+        y0, y1 = max(int((cy - r) * scale) - 1, 0), min(int((cy + r) * scale) + 2, m)
+        x0, x1 = max(int((cx - r) * scale) - 1, 0), min(int((cx + r) * scale) + 2, m)
+        if y0 >= y1 or x0 >= x1:
+            continue
+        dy = pos[y0:y1, None] - cy
+        dx = pos[None, x0:x1] - cx
+        img[y0:y1, x0:x1][dy * dy + dx * dx <= r * r] = 0
+    return img[None]
 
 
 # ---------------------------------------------------------------------------

@@ -114,10 +114,11 @@ def test_validation_2d(dev, kind, integer_ball):
     c = ibip.compare_opening(s["satmap"], p["mio_r2"], T.tolist(), p["mio_sat"], trapped=t["trapped"])
     np.testing.assert_array_equal(c["disagree"].cpu().numpy(), ref["disagree"])
     np.testing.assert_array_equal(c["mio_trapped"].cpu().numpy(), ref["mio_trapped"])
-    # the two methods agree on most of the image at every level, and both end
-    # with every inlet-connected pixel the smallest ball reaches
+    # both methods end on the same pixels: at the smallest level (a ball of
+    # one voxel) the opening holds every inlet-connected pore pixel, which is
+    # what IBIP has invaded when it stops (the bound on the levels before is
+    # pinned on the oracle alone, with its decomposition)
     n_pore = int(img.sum())
-    assert ref["disagree"].max() < 0.05 * n_pore
-    assert ref["disagree"][-1] <= ref["disagree"].max()
+    assert T[-1] == 1 and ref["disagree"][-1] == 0
     print(f"{kind} integer_ball={integer_ball}: levels {len(T)}, max disagreement {int(ref['disagree'].max())} "
           f"of {n_pore} pore pixels, opening pixels left trapped by IBIP up to {int(ref['mio_trapped'].max())}")
