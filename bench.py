@@ -3,14 +3,20 @@
 
 One step = the whole path over one synthetic image already resident in HBM:
 exact squared EDT, the invasion loop (steps, sphere insertion, per-step
-saturation and capillary pressure), defender trapping, and the pressure-based
-morphological-opening drainage at 25 radii used for the equal-saturation
-comparison. The opening needs only the image and the inlets, so it runs from a
-second host thread on a second stream while the invasion (whose step loop
-occupies one compute unit) and the trapping run. The reported value is invaded
-voxels per second of wall time over the timed steps.
+saturation and capillary pressure) and defender trapping. The default workload
+is the 512^3 blurred-noise image (invasion + trapping). On the 200^3 packing
+(and the 64^3 spheres) a step also runs the pressure-based morphological-
+opening drainage at 25 radii used for the equal-saturation comparison; the
+opening needs only the image and the inlets, so it runs from a second host
+thread on a second stream while the invasion (whose step loop occupies one
+compute unit) and the trapping run. The reported value is invaded voxels per
+second of wall time over the timed steps.
 
-    python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--workload packing200]
+Outside the timed region the default run also reports the equal-saturation
+comparison with the opening on the 200^3 packing (trapping off) and the EDT
+alone at 512^3, and times the CPU oracle on a thin slab of the same image.
+
+    python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--workload noise512]
 
 Prints ONE JSON line. Only one GPU is supported: --gpus N with N > 1 exits with
 a message.
@@ -37,7 +43,7 @@ WORKLOADS = {
     "packing200": "200^3 sphere packing (lognormal radii mean 12 sd 3 voxels, porosity ~0.40, seed 0); "
                   "inlets x=0, outlets x=199; invade + trap + MIO at 25 radii",
     "noise512": "512^3 Gaussian-blurred noise (sigma 6, porosity 0.55, seed 0); inlets x=0, outlets x=511; "
-                "invade + trap + MIO at 25 radii",
+                "invade + trap",
     "edt512": "the exact squared EDT alone (passes z, y, x) on 512^3 Gaussian-blurred noise (sigma 6, porosity "
               "0.55, seed 0, generated on the device), kernel time over 20 calls",
     "serve": "continuous-batching server: blurred-noise requests (sigma 6, porosity U[0.45, 0.65], side "
@@ -63,29 +69,45 @@ def thresholds_for(dt2_max: int, n: int = 25) -> list[int]:
     return sorted({max(1, math.ceil((rmax * i / n) ** 2)) for i in range(1, n + 1)}, reverse=True)
 
 
-def cpu_baseline(img, seconds_hint: float = 20.0) -> dict:
-    """The CPU oracle (single-threaded C) on a bounded slab of the same image."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(img, with_mio: bool) -> dict:
+    """The CPU oracle (single-threaded C) on a bounded slab of the same image:
+    48 x-planes of a 512^2 cross-section, 128 of a 200^2 one (10-20 s)."""
     import numpy as np
 
     import oracle
     from paper_2101_03240_amd import synth
 
     X = img.shape[0]
-    L = min(X, 128)
+    L = min(X, 128 if img.shape[1] * img.shape[2] <= 200 * 200 else 48)
     sl = np.ascontiguousarray(img[:L])
     inl = synth.face_mask(sl.shape, 0, 0)
     out = synth.face_mask(sl.shape, 0, L - 1)
     t0 = time.perf_counter()
     r = oracle.invade(sl, inl)
     oracle.trap(r["seq"], out)
-    dt2 = oracle.edt(sl)
-    T = thresholds_for(int(dt2.max()))
-    oracle.mio(sl, inl, np.array(T, np.uint32))
+    what = "invade + trap"
+    if with_mio:
+        dt2 = oracle.edt(sl)
+        T = thresholds_for(int(dt2.max()))
+        oracle.mio(sl, inl, np.array(T, np.uint32))
+        what += f" + MIO at {len(T)} radii"
     dt = time.perf_counter() - t0
     invaded = int((r["seq"] > 0).sum())
     return {"value": invaded / dt, "unit": "invaded voxels/s", "cores": 1, "kind": "oracle",
+            "cpu": cpu_model(), "host_threads": os.cpu_count(),
             "sample": f"slab x<{L} of the same image ({L}x{img.shape[1]}x{img.shape[2]}), inlets x=0, "
-                      f"outlets x={L - 1}: invade + trap + MIO at {len(T)} radii in {dt:.1f} s"}
+                      f"outlets x={L - 1}: {what} in {dt:.1f} s, {invaded} invaded voxels, one thread"}
 
 
 def edt_alone(dev, L: int = 512, reps: int = 20) -> dict:
@@ -119,6 +141,51 @@ def edt_alone(dev, L: int = 512, reps: int = 20) -> dict:
             "traffic": traffic, "avg_launch_ms": ms, "budget_gbps": budget, "budget_frac": budget / HBM_PEAK_GBPS,
             "measured_gbps": traffic / (ms * 1e-3) / 1e9 if traffic else None,
             "measured_frac": traffic / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS if traffic else None}
+
+
+def eqsat_report(dev) -> dict:
+    """Equal-saturation comparison of IBIP with the opening on the 200^3
+    packing, trapping off (Section 3.1.1, Figures 6 and 8), from the GPU path:
+    the opening at the 25 radii T_i, IBIP's saturation map, the per-level
+    symmetric difference, its split 2a + gap (a: voxels IBIP holds through
+    balls larger than the opening's; gap: IBIP's step granularity at equal
+    count), and the peak-pressure envelope: IBIP's saturation just before its
+    first step below T_i against the opening's saturation at T_i."""
+    import numpy as np
+    import torch
+
+    import paper_2101_03240_amd as ibip
+    from paper_2101_03240_amd import synth
+
+    img = synth.config_image("packing200")
+    img_d = torch.from_numpy(img).to(dev)
+    inl_d = torch.from_numpy(synth.face_mask(img.shape, 0, 0)).to(dev)
+    T = thresholds_for(int(ibip.edt(img_d).max().item()))
+    r = ibip.invade(img_d, inl_d)
+    s = ibip.saturation(r["seq"], r["M"])
+    m = ibip.opening_drainage(img_d, inl_d, T)
+    c = ibip.compare_opening(s["satmap"], m["mio_r2"], T, m["mio_sat"])
+    dis = c["disagree"].cpu().numpy()
+    M = r["M"].cpu().numpy().view(np.uint32).astype(np.int64)
+    cum = np.cumsum(r["n_new"].cpu().numpy())
+    n_pore = int(img.sum())
+    lv = []
+    for i, t in enumerate(T):
+        mcount = int(round(m["mio_sat"][i] * n_pore))
+        keq = int(np.searchsorted(cum, mcount, side="right"))
+        gap = mcount - (int(cum[keq - 1]) if keq else 0)
+        below = np.nonzero(M < t)[0]
+        kstar = int(below[0]) + 1 if below.size else len(M) + 1
+        env = (int(cum[kstar - 2]) if kstar >= 2 else 0) - mcount
+        lv.append((int(t), int(dis[i]), (int(dis[i]) - gap) // 2, gap, env))
+    worst = max(lv, key=lambda x: x[1])
+    return {"image": "packing200 (200^3 sphere packing), inlets x=0, trapping off, 25 radii",
+            "pore_voxels": n_pore, "levels": len(T),
+            "max_disagreement": worst[1], "max_disagreement_frac": worst[1] / n_pore, "at_T": worst[0],
+            "larger_balls_a": worst[2], "granularity_gap": worst[3],
+            "max_larger_balls_frac": max(x[2] for x in lv) / n_pore,
+            "max_envelope_excess": max(x[4] for x in lv), "max_envelope_excess_frac": max(x[4] for x in lv) / n_pore,
+            "per_level": [{"T": x[0], "disagree": x[1], "a": x[2], "gap": x[3], "envelope_excess": x[4]} for x in lv]}
 
 
 def measured_traffic(kernel: str, workload: str):
@@ -321,10 +388,12 @@ def make_image(name: str):
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="packing200", choices=sorted(WORKLOADS))
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="noise512", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-eqsat", action="store_true",
+                    help="skip the equal-saturation comparison on the 200^3 packing")
     ap.add_argument("--no-edt512", action="store_true", help="skip the EDT-alone measurement at 512^3")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="run one device-to-device copy of this many MiB before the workload, as a reference "
@@ -380,7 +449,9 @@ def main() -> int:
                        "parallelism": "single GPU"},
             "roofline": e}), flush=True)
         return 0
+    print(f"bench: generating {args.workload}", file=sys.stderr, flush=True)
     img = make_image(args.workload)
+    with_mio = args.workload in ("packing200", "spheres64")
     inl = synth.face_mask(img.shape, 0, 0)
     out = synth.face_mask(img.shape, 0, img.shape[0] - 1)
     img_d = torch.from_numpy(img).to(dev)
@@ -403,12 +474,13 @@ def main() -> int:
         return side_pool.submit(fn).result()
 
     def step():
-        fut = side_pool.submit(opening)
+        fut = side_pool.submit(opening) if with_mio else None
         r = ibip.invade(img_d, inl_d)
         t = ibip.trap(r["seq"], out_d)
-        m = fut.result()
+        m = fut.result() if fut is not None else None
         return r, t, m
 
+    print("bench: warmup", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         r, t, m = step()
     torch.cuda.synchronize()
@@ -419,12 +491,14 @@ def main() -> int:
     ibip.reset_timing()
     ibip.enable_timing(True)
     on_side(lambda: (ibip.reset_timing(), ibip.enable_timing(True)))
+    print(f"bench: timing {args.steps} steps", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         step()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    print(f"bench: {1e3 * elapsed / args.steps:.1f} ms per step", file=sys.stderr, flush=True)
     ibip.enable_timing(False)
     tm = ibip.get_timing()
     ts = on_side(ibip.get_timing)
@@ -446,8 +520,9 @@ def main() -> int:
             tm["loop_launches"]),
         "sphere insertion": (tm["paint_ms"] / S, PAINT_BYTES_PER_PORE * n_pore, S),
         "trapping": (tm["trap_ms"] / S, TRAP_BYTES_PER_VOXEL * n_vox, S),
-        "opening drainage": (tm["mio_ms"] / S, MIO_BYTES_PER_VOXEL_RADIUS * n_vox * len(T), S),
     }
+    if with_mio:
+        phases["opening drainage"] = (tm["mio_ms"] / S, MIO_BYTES_PER_VOXEL_RADIUS * n_vox * len(T), S)
     totals = {k: v[0] * v[2] for k, v in phases.items()}
     dom = max(totals, key=totals.get)
     d_ms, d_bytes, d_launches = phases[dom]
@@ -471,8 +546,7 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": args.workload, "description": WORKLOADS[args.workload],
                    "shape": list(img.shape), "pore_voxels": n_pore, "invaded_voxels": invaded,
-                   "invasion_steps": K, "mio_radii": len(T), "parallelism": "single GPU",
-                   "overlap": "the opening drainage runs on a second stream during invade + trap"},
+                   "invasion_steps": K, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
                      "traffic": measured_traffic(dom, args.workload),
@@ -510,10 +584,18 @@ def main() -> int:
     # how many L2 claim round trips one step takes
     res["loop"]["step_in_l2_claim_round_trips"] = 1e3 * us_step / lat["l2_ns"]
     # the EDT alone at the 512^3 size, where it is not dominated by launches
+    if with_mio:
+        res["config"]["mio_radii"] = len(T)
+        res["config"]["overlap"] = "the opening drainage runs on a second stream during invade + trap"
     if not args.no_edt512:
+        print("bench: edt alone at 512^3", file=sys.stderr, flush=True)
         res["edt512_roofline"] = edt_alone(dev)
+    if not args.no_eqsat:
+        print("bench: equal-saturation comparison on the 200^3 packing", file=sys.stderr, flush=True)
+        res["equal_saturation_packing200"] = eqsat_report(dev)
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(img)
+        print("bench: cpu baseline (oracle on a slab)", file=sys.stderr, flush=True)
+        res["cpu_baseline"] = cpu_baseline(img, with_mio)
     print(json.dumps(res), flush=True)
     del np
     return 0
