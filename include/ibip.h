@@ -104,6 +104,22 @@ typedef struct {
 #define IBIP_READ_TRAP26 4u
 ibip_status ibip_ctx_set_readings(ibip_ctx* ctx, uint32_t flags);
 
+/* Launch parameters, for the following calls on this context (chosen per
+   size class by the package's autotuner; results never depend on them).
+   edt_tile_y  z columns per LDS tile of the EDT's pass y: 32 or 64 (0: 32)
+   edt_tile_x  z columns per LDS tile of the EDT's pass x: 16 or 32 (0: 32)
+   batch_wide  a batch job's step with more centres than this leaves the job's
+               workgroup: the step runs over the whole GPU and the job's loop
+               resumes in its own launch (0: 8192; negative: never).
+   Errors: EINVAL (a tile width not listed). NULL restores the defaults. */
+typedef struct {
+    int32_t edt_tile_y;
+    int32_t edt_tile_x;
+    int64_t batch_wide;
+} ibip_tuning;
+ibip_status ibip_ctx_set_tuning(ibip_ctx* ctx, const ibip_tuning* t);
+ibip_status ibip_ctx_get_tuning(const ibip_ctx* ctx, ibip_tuning* out);
+
 ibip_status ibip_ctx_enable_timing(ibip_ctx* ctx, int32_t enable);
 ibip_status ibip_ctx_get_timing(const ibip_ctx* ctx, ibip_timing* out);
 ibip_status ibip_ctx_reset_timing(ibip_ctx* ctx);
@@ -243,6 +259,10 @@ ibip_status ibip_server_wait(ibip_server* s, int64_t ticket, ibip_job* result, d
    if it is running, done or unknown. */
 ibip_status ibip_server_cancel(ibip_server* s, int64_t ticket);
 ibip_status ibip_server_stats_get(ibip_server* s, ibip_server_stats* out);
+/* Launch parameters of the jobs admitted from now on (ibip_tuning:
+   edt_tile_y, edt_tile_x, and batch_wide for the served jobs' wide steps).
+   NULL restores the defaults. Errors: EINVAL. */
+ibip_status ibip_server_set_tuning(ibip_server* s, const ibip_tuning* t);
 const char* ibip_server_last_error(const ibip_server* s);
 /* Cancel pending jobs, let running ones finish, free everything. */
 ibip_status ibip_server_destroy(ibip_server* s);

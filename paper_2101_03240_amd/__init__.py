@@ -22,7 +22,7 @@ import ctypes
 import os
 import threading
 
-__all__ = ["edt", "edt_noalloc", "invade", "invade_batch", "Server", "trap", "saturation", "remap_steps", "compare_opening", "opening_drainage",
+__all__ = ["edt", "edt_noalloc", "invade", "invade_batch", "set_tuning", "get_tuning", "Server", "trap", "saturation", "remap_steps", "compare_opening", "opening_drainage",
            "IbipError", "library_path", "load_library", "enable_timing", "get_timing", "reset_timing",
            "probe_claim_latency"]
 
@@ -67,6 +67,18 @@ class _ServerOpts(ctypes.Structure):
 class _ServerStats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in ("submitted", "completed", "cancelled", "pending", "running",
                                                 "bytes_in_use", "peak_bytes", "peak_running")]
+
+
+class _Tuning(ctypes.Structure):
+    _fields_ = [("edt_tile_y", ctypes.c_int32), ("edt_tile_x", ctypes.c_int32), ("batch_wide", ctypes.c_int64)]
+
+
+def _tuning_struct(t: dict | None) -> "_Tuning":
+    t = t or {}
+    unknown = set(t) - {"edt_tile_y", "edt_tile_x", "batch_wide"}
+    if unknown:
+        raise ValueError(f"unknown tuning keys {sorted(unknown)}")
+    return _Tuning(int(t.get("edt_tile_y", 0)), int(t.get("edt_tile_x", 0)), int(t.get("batch_wide", 0)))
 
 
 class _InvadeOpts(ctypes.Structure):
@@ -126,6 +138,12 @@ def load_library():
         lib.ibip_compare_opening.argtypes = [P, P, P, P, _Dims, P, P, i32, P, P]
         lib.ibip_compare_opening.restype = i32
         lib.ibip_ctx_set_readings.restype = i32
+        lib.ibip_ctx_set_tuning.argtypes = [P, ctypes.POINTER(_Tuning)]
+        lib.ibip_ctx_set_tuning.restype = i32
+        lib.ibip_ctx_get_tuning.argtypes = [P, ctypes.POINTER(_Tuning)]
+        lib.ibip_ctx_get_tuning.restype = i32
+        lib.ibip_server_set_tuning.argtypes = [P, ctypes.POINTER(_Tuning)]
+        lib.ibip_server_set_tuning.restype = i32
         lib.ibip_ctx_enable_timing.argtypes = [P, i32]
         lib.ibip_ctx_get_timing.argtypes = [P, ctypes.POINTER(_Timing)]
         lib.ibip_ctx_reset_timing.argtypes = [P]
@@ -277,12 +295,33 @@ def invade(image, inlets, max_steps: int = 0, sigma: float = 1.0, theta_rad: flo
     return out
 
 
+def set_tuning(tuning: dict | None = None, device=None):
+    """Launch parameters for the calling thread's context (ibip_ctx_set_tuning):
+    ``edt_tile_y`` (32 or 64), ``edt_tile_x`` (16 or 32), ``batch_wide`` (a
+    batch job's steps above it run over the whole GPU; negative: never).
+    Missing keys or None: defaults. Results never depend on them."""
+    torch = _torch()
+    ctx = _context(torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device()))
+    t = _tuning_struct(tuning)
+    _check(load_library().ibip_ctx_set_tuning(ctx, ctypes.byref(t)), ctx)
+
+
+def get_tuning(device=None) -> dict:
+    torch = _torch()
+    ctx = _context(torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device()))
+    t = _Tuning()
+    _check(load_library().ibip_ctx_get_tuning(ctx, ctypes.byref(t)), ctx)
+    return {n: getattr(t, n) for n, _ in _Tuning._fields_}
+
+
 def invade_batch(images, inlets, max_steps=0, rad2: bool = True, centre_step: bool = True, M: bool = True,
-                 sat: bool = False, raise_on_error: bool = True):
+                 sat: bool = False, raise_on_error: bool = True, tuning: dict | None = None):
     """ibip_invade over a list of images of uneven size in one call (the step
-    loops of all jobs run in one launch). ``inlets`` is a list of masks of
-    matching shapes; ``max_steps`` an int or a list. Returns a list of dicts
-    like ``invade`` (``seq``, ``rad2``, ``centre_step``, ``K``, ``M``, ``sat``)
+    loops of all jobs run in one launch; a job's step above the wide
+    threshold continues over the whole GPU). ``inlets`` is a list of masks of
+    matching shapes; ``max_steps`` an int or a list. ``tuning`` (keys of
+    ``set_tuning``) applies to this call only. Returns a list of dicts like
+    ``invade`` (``seq``, ``rad2``, ``centre_step``, ``K``, ``M``, ``sat``)
     plus each job's ``status``."""
     torch = _torch()
     n = len(images)
@@ -313,7 +352,18 @@ def invade_batch(images, inlets, max_steps=0, rad2: bool = True, centre_step: bo
         jobs[i].max_steps = int(ms[i])
         for f in ("seq", "rad2", "centre_step", "M", "sat"):
             setattr(jobs[i], f, o[f].data_ptr() if o[f] is not None else None)
-    st = load_library().ibip_invade_batch(ctx, jobs, n)
+    lib = load_library()
+    saved = None
+    if tuning is not None:
+        saved = _Tuning()
+        _check(lib.ibip_ctx_get_tuning(ctx, ctypes.byref(saved)), ctx)
+        t = _tuning_struct(tuning)
+        _check(lib.ibip_ctx_set_tuning(ctx, ctypes.byref(t)), ctx)
+    try:
+        st = lib.ibip_invade_batch(ctx, jobs, n)
+    finally:
+        if saved is not None:
+            lib.ibip_ctx_set_tuning(ctx, ctypes.byref(saved))
     if st != 0 and raise_on_error:
         _check(st, ctx)
     for i, o in enumerate(outs):
@@ -374,6 +424,14 @@ class Server:
             raise IbipError(st, (self._lib.ibip_server_last_error(self._h) or b"").decode())
         self._live[int(t.value)] = o
         return int(t.value)
+
+    def set_tuning(self, tuning: dict | None = None):
+        """Launch parameters of the jobs admitted from now on (keys of
+        ``set_tuning``; ``batch_wide`` applies to the served jobs)."""
+        t = _tuning_struct(tuning)
+        st = self._lib.ibip_server_set_tuning(self._h, ctypes.byref(t))
+        if st != 0:
+            raise IbipError(st, "bad tuning")
 
     def done(self, ticket: int) -> bool:
         d = ctypes.c_int32(0)

@@ -183,6 +183,23 @@ ibip_status ibip_ctx_create(ibip_ctx** out, int32_t device, void* stream) {
     return IBIP_OK;
 }
 
+ibip_status ibip_ctx_set_tuning(ibip_ctx* ctx, const ibip_tuning* t) {
+    if (!ctx) return IBIP_EINVAL;
+    if (!t) {
+        ctx->tuning = ibip_tuning{};
+        return IBIP_OK;
+    }
+    if (!tuning_ok(*t)) return fail(ctx, IBIP_EINVAL, "set_tuning: tile width not among 32/64 (y) and 16/32 (x)");
+    ctx->tuning = *t;
+    return IBIP_OK;
+}
+
+ibip_status ibip_ctx_get_tuning(const ibip_ctx* ctx, ibip_tuning* out) {
+    if (!ctx || !out) return IBIP_EINVAL;
+    *out = ctx->tuning;
+    return IBIP_OK;
+}
+
 ibip_status ibip_ctx_enable_timing(ibip_ctx* ctx, int32_t enable) {
     if (!ctx) return IBIP_EINVAL;
     ctx->timer.on = enable != 0;
@@ -212,6 +229,7 @@ ibip_status ibip_ctx_destroy(ibip_ctx* ctx) {
     if (ctx->timer.made)
         for (auto& e : ctx->timer.ev) (void)hipEventDestroy(e);
     if (ctx->copy_ev) (void)hipEventDestroy(ctx->copy_ev);
+    for (auto& e : ctx->job_ev) (void)hipEventDestroy(e);
     for (auto& b : ctx->buf)
         if (b.p) (void)hipFree(b.p);
     if (ctx->host_pinned) (void)hipHostFree(ctx->host_pinned);
@@ -303,7 +321,8 @@ ibip_status ibip_edt(ibip_ctx* ctx, const uint8_t* image, ibip_dims dims, uint32
     ibip_status rc;
     if ((rc = hip_check(ctx, hipMemsetAsync(flag, 0, 4, ctx->stream), "memset")) != IBIP_OK) return rc;
     ctx->timer.mark(0, ctx->stream);
-    if ((rc = hip_check(ctx, launch_edt(image, nullptr, 0, 0, dims, g16, tmp, dt2, flag, ctx->stream), "edt launch")) !=
+    if ((rc = hip_check(ctx, launch_edt(image, nullptr, 0, 0, dims, g16, tmp, dt2, flag, ctx->stream, nullptr, nullptr,
+                                         edt_tiles(ctx->tuning)), "edt launch")) !=
         IBIP_OK)
         return rc;
     ctx->timer.mark(1, ctx->stream);
@@ -331,7 +350,8 @@ ibip_status ibip_edt_noalloc(ibip_ctx* ctx, const uint8_t* image, ibip_dims dims
     uint16_t* g16 = (uint16_t*)base;
     uint32_t* tmp = (uint32_t*)(base + align256(sizeof(uint16_t) * (size_t)n));
     hipLaunchKernelGGL(k_clear_word, dim3(1), dim3(1), 0, ctx->stream, solid_flag);
-    return hip_check(ctx, launch_edt(image, nullptr, 0, 0, dims, g16, tmp, dt2, solid_flag, ctx->stream),
+    return hip_check(ctx, launch_edt(image, nullptr, 0, 0, dims, g16, tmp, dt2, solid_flag, ctx->stream, nullptr, nullptr,
+                                      edt_tiles(ctx->tuning)),
                      "edt_noalloc launch");
 }
 

@@ -431,19 +431,20 @@ __global__ __launch_bounds__(256) void edt_pass_z_vec(Feat feat, int64_t rows, i
 // candidate costs one multiply-add (or add) and one min. Lines are at most
 // 512 voxels, so every real sum stays below 3 * 511^2.
 constexpr int kPad = 4;
-constexpr int kTW = 32;                              // z columns per tile
 constexpr uint32_t kSent16 = 0x7FFFu;                // pass y: sentinel distance
 constexpr uint32_t kSentSq = kSent16 * kSent16;      // its square (+ o^2 < 2^31)
 constexpr uint32_t kSent32 = 0x40000000u;            // pass x: sentinel value
 constexpr int kThreadsY = 512, kThreadsX = 1024;
 
+// TW: z columns per tile (32: 64-byte tile rows; 64: whole 128-byte lines)
+template <int TW>
 __global__ __launch_bounds__(kThreadsY) void edt_pass_y_vec(const uint16_t* __restrict__ g, int X, int Y, int Z,
                                                            uint64_t cap, uint32_t* __restrict__ h) {
-    extern __shared__ uint16_t t16[];  // [kPad + Y + kPad][kTW]
-    constexpr int kSegs = kTW / 8, kRows = kThreadsY / kSegs;
-    const int nzc = (Z + kTW - 1) / kTW;
+    extern __shared__ uint16_t t16[];  // [kPad + Y + kPad][TW]
+    constexpr int kSegs = TW / 8, kRows = kThreadsY / kSegs;
+    const int nzc = (Z + TW - 1) / TW;
     const int x = blockIdx.x / nzc;
-    const int z0 = (blockIdx.x - x * nzc) * kTW;
+    const int z0 = (blockIdx.x - x * nzc) * TW;
     const int64_t plane = (int64_t)x * Y * Z;
     {
         const int seg = threadIdx.x % kSegs;
@@ -458,33 +459,33 @@ __global__ __launch_bounds__(kThreadsY) void edt_pass_y_vec(const uint16_t* __re
                 w.z &= 0x7FFF7FFFu;
                 w.w &= 0x7FFF7FFFu;
             }
-            *reinterpret_cast<uint4*>(t16 + (y + kPad) * kTW + seg * 8) = w;
+            *reinterpret_cast<uint4*>(t16 + (y + kPad) * TW + seg * 8) = w;
         }
-        for (int i = threadIdx.x; i < 2 * kPad * kTW; i += kThreadsY) {
-            const int r = i / kTW;
-            t16[(r < kPad ? r : Y + r) * kTW + (i - r * kTW)] = (uint16_t)kSent16;
+        for (int i = threadIdx.x; i < 2 * kPad * TW; i += kThreadsY) {
+            const int r = i / TW;
+            t16[(r < kPad ? r : Y + r) * TW + (i - r * TW)] = (uint16_t)kSent16;
         }
     }
     __syncthreads();
-    const int lz = threadIdx.x % kTW;
+    const int lz = threadIdx.x % TW;
     const int z = z0 + lz;
     if (z >= Z) return;
     const uint32_t capv = (uint32_t)cap;
     const uint32_t lim = min(capv, kSentSq);
-    const uint16_t* col = t16 + kPad * kTW + lz;  // row i at col[i * kTW]
-    for (int y = threadIdx.x / kTW; y < Y; y += kThreadsY / kTW) {
-        const uint32_t f0 = col[y * kTW];
+    const uint16_t* col = t16 + kPad * TW + lz;  // row i at col[i * TW]
+    for (int y = threadIdx.x / TW; y < Y; y += kThreadsY / TW) {
+        const uint32_t f0 = col[y * TW];
         uint32_t best = f0 == kSent16 ? capv : f0 * f0;
         if (best) {
             const int far = max(y, Y - 1 - y);
             for (int o = 1; o <= far; o += 4) {
                 if ((uint32_t)(o * o) >= best) break;
-                const uint16_t* lp = col + (y - o >= 0 ? y - o : -1) * kTW;
-                const uint16_t* rp = col + (y + o < Y ? y + o : Y) * kTW;
+                const uint16_t* lp = col + (y - o >= 0 ? y - o : -1) * TW;
+                const uint16_t* rp = col + (y + o < Y ? y + o : Y) * TW;
 #pragma unroll
                 for (int j = 0; j < 4; j++) {
                     const uint32_t oo = (uint32_t)((o + j) * (o + j));
-                    const uint32_t fl = lp[-j * kTW], fr = rp[j * kTW];
+                    const uint32_t fl = lp[-j * TW], fr = rp[j * TW];
                     best = min(best, fl * fl + oo);
                     best = min(best, fr * fr + oo);
                 }
@@ -494,14 +495,15 @@ __global__ __launch_bounds__(kThreadsY) void edt_pass_y_vec(const uint16_t* __re
     }
 }
 
-template <class Out>
+// TW: z columns per tile (16: 64-byte tile rows; 32: whole 128-byte lines)
+template <class Out, int TW>
 __global__ __launch_bounds__(kThreadsX) void edt_pass_x_vec(const uint32_t* __restrict__ hin, int X, int Y, int Z,
                                                            uint64_t cap, Out outp, uint32_t* count) {
-    extern __shared__ uint32_t t32[];  // [kPad + X + kPad][kTW]
-    constexpr int kSegs = kTW / 4, kRows = kThreadsX / kSegs;
-    const int nzc = (Z + kTW - 1) / kTW;
+    extern __shared__ uint32_t t32[];  // [kPad + X + kPad][TW]
+    constexpr int kSegs = TW / 4, kRows = kThreadsX / kSegs;
+    const int nzc = (Z + TW - 1) / TW;
     const int y = blockIdx.x / nzc;
-    const int z0 = (blockIdx.x - y * nzc) * kTW;
+    const int z0 = (blockIdx.x - y * nzc) * TW;
     const int64_t yz = (int64_t)Y * Z;
     const int64_t col0 = (int64_t)y * Z + z0;
     {
@@ -516,35 +518,35 @@ __global__ __launch_bounds__(kThreadsX) void edt_pass_x_vec(const uint32_t* __re
                 w.z = w.z == kInf32 ? kSent32 : w.z;
                 w.w = w.w == kInf32 ? kSent32 : w.w;
             }
-            *reinterpret_cast<uint4*>(t32 + (x + kPad) * kTW + seg * 4) = w;
+            *reinterpret_cast<uint4*>(t32 + (x + kPad) * TW + seg * 4) = w;
         }
-        for (int i = threadIdx.x; i < 2 * kPad * kTW; i += kThreadsX) {
-            const int r = i / kTW;
-            t32[(r < kPad ? r : X + r) * kTW + (i - r * kTW)] = kSent32;
+        for (int i = threadIdx.x; i < 2 * kPad * TW; i += kThreadsX) {
+            const int r = i / TW;
+            t32[(r < kPad ? r : X + r) * TW + (i - r * TW)] = kSent32;
         }
     }
     __syncthreads();
-    const int lz = threadIdx.x % kTW;
+    const int lz = threadIdx.x % TW;
     const int z = z0 + lz;
     uint32_t hits = 0;
     if (z < Z) {
         const uint32_t capv = (uint32_t)cap;
         const uint32_t lim = min(capv, kSent32);
-        const uint32_t* col = t32 + kPad * kTW + lz;
-        for (int x = threadIdx.x / kTW; x < X; x += kThreadsX / kTW) {
-            const uint32_t f0 = col[x * kTW];
+        const uint32_t* col = t32 + kPad * TW + lz;
+        for (int x = threadIdx.x / TW; x < X; x += kThreadsX / TW) {
+            const uint32_t f0 = col[x * TW];
             uint32_t best = f0 == kSent32 ? capv : f0;
             if (best) {
                 const int far = max(x, X - 1 - x);
                 for (int o = 1; o <= far; o += 4) {
                     if ((uint32_t)(o * o) >= best) break;
-                    const uint32_t* lp = col + (x - o >= 0 ? x - o : -1) * kTW;
-                    const uint32_t* rp = col + (x + o < X ? x + o : X) * kTW;
+                    const uint32_t* lp = col + (x - o >= 0 ? x - o : -1) * TW;
+                    const uint32_t* rp = col + (x + o < X ? x + o : X) * TW;
 #pragma unroll
                     for (int j = 0; j < 4; j++) {
                         const uint32_t oo = (uint32_t)((o + j) * (o + j));
-                        best = min(best, lp[-j * kTW] + oo);
-                        best = min(best, rp[j * kTW] + oo);
+                        best = min(best, lp[-j * TW] + oo);
+                        best = min(best, rp[j * TW] + oo);
                     }
                 }
             }
@@ -576,13 +578,15 @@ size_t max_lds_per_block() {
 
 hipError_t launch_edt(const uint8_t* image, const uint32_t* w, uint32_t thr, uint32_t cap, ibip_dims d,
                       uint16_t* g16, uint32_t* tmp32, uint32_t* out, uint32_t* solid_flag, hipStream_t s,
-                      uint32_t* mio_r2, uint32_t* mio_count) {
+                      uint32_t* mio_r2, uint32_t* mio_count, EdtTiles tiles) {
     // cap == 0: exact everywhere; else exact where dt2 < cap, 0xFFFFFFFF elsewhere
     const uint64_t c64 = cap ? (uint64_t)cap : 0xFFFFFFFFull;
     const int64_t n = nvox(d);
+    // tile widths in z columns: pass y 32 or 64 (uint16), pass x 16 or 32 (uint32)
+    const int ty = tiles.y == 64 ? 64 : 32, tx = tiles.x == 16 ? 16 : 32;
     // vector path: rows of Z % 8 == 0 voxels, lines of at most 512 voxels,
     // aligned inputs; 32-bit sums when they cannot reach 2^31
-    const size_t ly = sizeof(uint16_t) * kTW * (d.Y + 2 * kPad), lx = sizeof(uint32_t) * kTW * (d.X + 2 * kPad);
+    const size_t ly = sizeof(uint16_t) * ty * (d.Y + 2 * kPad), lx = sizeof(uint32_t) * tx * (d.X + 2 * kPad);
     const bool vec = d.Z % 8 == 0 && d.Z <= 512 && d.X <= kMaxTileLine && d.Y <= kMaxTileLine &&
                      (image ? ((uintptr_t)image & 7) == 0 : ((uintptr_t)w & 15) == 0) &&
                      std::max(ly, lx) <= max_lds_per_block();
@@ -596,15 +600,28 @@ hipError_t launch_edt(const uint8_t* image, const uint32_t* w, uint32_t thr, uin
         else
             hipLaunchKernelGGL(edt_pass_z_vec<FeatThreshold8>, dim3(gz), dim3(256), 0, s, FeatThreshold8{w, thr},
                                rows, d.Z, c64, g16, solid_flag);
-        const unsigned nzc = (unsigned)((d.Z + kTW - 1) / kTW);
-        hipLaunchKernelGGL(edt_pass_y_vec, dim3((unsigned)d.X * nzc), dim3(kThreadsY), ly, s, g16, d.X, d.Y, d.Z, c64,
-                           tmp32);
-        if (mio_r2)
-            hipLaunchKernelGGL(edt_pass_x_vec<OutOpening>, dim3((unsigned)d.Y * nzc), dim3(kThreadsX), lx, s, tmp32,
-                               d.X, d.Y, d.Z, c64, OutOpening{mio_r2, cap}, mio_count);
+        const unsigned nzy = (unsigned)((d.Z + ty - 1) / ty), nzx = (unsigned)((d.Z + tx - 1) / tx);
+        if (ty == 64)
+            hipLaunchKernelGGL(edt_pass_y_vec<64>, dim3((unsigned)d.X * nzy), dim3(kThreadsY), ly, s, g16, d.X, d.Y,
+                               d.Z, c64, tmp32);
         else
-            hipLaunchKernelGGL(edt_pass_x_vec<OutPlain>, dim3((unsigned)d.Y * nzc), dim3(kThreadsX), lx, s, tmp32,
-                               d.X, d.Y, d.Z, c64, OutPlain{out}, (uint32_t*)nullptr);
+            hipLaunchKernelGGL(edt_pass_y_vec<32>, dim3((unsigned)d.X * nzy), dim3(kThreadsY), ly, s, g16, d.X, d.Y,
+                               d.Z, c64, tmp32);
+        const dim3 gx((unsigned)d.Y * nzx);
+        if (mio_r2) {
+            if (tx == 16)
+                hipLaunchKernelGGL((edt_pass_x_vec<OutOpening, 16>), gx, dim3(kThreadsX), lx, s, tmp32, d.X, d.Y,
+                                   d.Z, c64, OutOpening{mio_r2, cap}, mio_count);
+            else
+                hipLaunchKernelGGL((edt_pass_x_vec<OutOpening, 32>), gx, dim3(kThreadsX), lx, s, tmp32, d.X, d.Y,
+                                   d.Z, c64, OutOpening{mio_r2, cap}, mio_count);
+        } else if (tx == 16) {
+            hipLaunchKernelGGL((edt_pass_x_vec<OutPlain, 16>), gx, dim3(kThreadsX), lx, s, tmp32, d.X, d.Y, d.Z, c64,
+                               OutPlain{out}, (uint32_t*)nullptr);
+        } else {
+            hipLaunchKernelGGL((edt_pass_x_vec<OutPlain, 32>), gx, dim3(kThreadsX), lx, s, tmp32, d.X, d.Y, d.Z, c64,
+                               OutPlain{out}, (uint32_t*)nullptr);
+        }
         return hipGetLastError();
     }
     const int64_t rows = (int64_t)d.X * d.Y;

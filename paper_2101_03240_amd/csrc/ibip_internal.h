@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <string>
+#include <vector>
 
 #include "../../include/ibip.h"
 
@@ -236,7 +237,9 @@ struct ibip_ctx {
     ibip::Buf buf[ibip::B_NUM];
     void* host_pinned = nullptr;   // pinned mirror of LoopState and small results
     hipEvent_t copy_ev = nullptr;  // the loop state's copy to the host (no timing)
-    // per-job completion records of a batch (3 words each: done, k, err) in
+    std::vector<hipEvent_t> job_ev;  // per batch job: its continued loop's state copy
+    // per-job completion records of a batch (4 words each: done, k, err,
+    // loop status) in
     // coherent pinned host memory that the loop kernel writes directly
     uint32_t* done_host = nullptr;
     uint32_t* done_dev = nullptr;
@@ -247,6 +250,7 @@ struct ibip_ctx {
     int64_t last_n_pore = 0;
     bool have_steps = false;
     uint32_t readings = 0;         // IBIP_READ_* flags for the following calls
+    ibip_tuning tuning = {};       // launch parameters (zero: defaults)
 };
 
 namespace ibip {
@@ -272,9 +276,15 @@ inline int64_t nvox(ibip_dims d) { return (int64_t)d.X * d.Y * d.Z; }
 // With mio_r2 given (opening drainage), the last pass writes no distances:
 // it sets mio_r2[v] = cap where mio_r2[v] == 0 and dt2 < cap, and adds the
 // number of voxels with mio_r2 >= cap to *mio_count.
+// Tile widths (z columns) of the LDS-tiled passes y and x.
+struct EdtTiles {
+    int y = 32;  // 32 or 64
+    int x = 32;  // 16 or 32
+};
 hipError_t launch_edt(const uint8_t* image, const uint32_t* w, uint32_t thr, uint32_t cap, ibip_dims d,
                       uint16_t* g16, uint32_t* tmp32, uint32_t* out, uint32_t* solid_flag,
-                      hipStream_t s, uint32_t* mio_r2 = nullptr, uint32_t* mio_count = nullptr);
+                      hipStream_t s, uint32_t* mio_r2 = nullptr, uint32_t* mio_count = nullptr,
+                      EdtTiles tiles = EdtTiles{});
 
 // *dst = the sum of kCountSlots slot words (see block_add_slots).
 hipError_t launch_sum_slots(const uint32_t* slots, uint32_t* dst, hipStream_t s);
@@ -327,13 +337,33 @@ size_t job_bytes(ibip_dims d, bool own_state, bool want_sat);
 JobBufs carve(uint8_t* base, ibip_dims d, int32_t* caller_state, bool want_sat);
 // EDT, ranks, slices and seeds; loop state initialised on the device
 hipError_t job_setup(const JobBufs& j, LoopState* st, const uint8_t* image, const uint8_t* inlets, ibip_dims d,
-                     int64_t max_steps, int32_t* seq, hipStream_t s);
+                     int64_t max_steps, int32_t* seq, hipStream_t s, EdtTiles tiles = EdtTiles{});
+// EDT tile widths from a tuning (defaults where it holds 0)
+inline EdtTiles edt_tiles(const ibip_tuning& t) {
+    EdtTiles e;
+    if (t.edt_tile_y) e.y = t.edt_tile_y;
+    if (t.edt_tile_x) e.x = t.edt_tile_x;
+    return e;
+}
+// true when the tuning's values are among the accepted ones
+inline bool tuning_ok(const ibip_tuning& t) {
+    return (t.edt_tile_y == 0 || t.edt_tile_y == 32 || t.edt_tile_y == 64) &&
+           (t.edt_tile_x == 0 || t.edt_tile_x == 16 || t.edt_tile_x == 32);
+}
 // post-processing with K read on the device (no host sync)
 hipError_t job_post_devk(const JobBufs& j, LoopState* st, ibip_dims d, int32_t* seq, uint32_t* rad2,
                          uint32_t* M_out, hipStream_t s);
 size_t loop_args_bytes();
 // fills `out` (loop_args_bytes() of host memory) with the loop arguments of a job
-void fill_loop_args(void* out, const JobBufs& j, LoopState* st, ibip_dims d);
+void fill_loop_args(void* out, const JobBufs& j, LoopState* st, ibip_dims d, uint32_t wide);
+// the step-count threshold above which a batch or served job's step runs over
+// the whole GPU, from a tuning value (0: kWideRound; negative: never)
+uint32_t wide_threshold(int64_t tuned);
+// after a job's loop stopped at a wide step (its state on the device says
+// so): that step over the whole GPU, then the job's loop in one workgroup to
+// its next wide step or its end, stream-ordered on s. host_args: the job's
+// loop arguments (fill_loop_args); n: its voxel count.
+hipError_t launch_wide_and_loop_host(const void* host_args, int64_t n, hipStream_t s);
 // one workgroup per job, every step loop to completion
 hipError_t launch_loop_jobs(const void* d_args, int32_t n, hipStream_t s);
 // create the batch streams and events once per context

@@ -844,7 +844,8 @@ __device__ inline void loop_body(const LoopArgs& a, LoopShared& s) {
     }
     if (a.done) {
         // a batch job: tell the host, which starts the job's post-processing
-        // while other jobs' loops still run. The barrier orders every
+        // (or, after a stop at a wide step, runs that step over the whole GPU
+        // and resumes the job's loop) while other jobs' loops still run. The barrier orders every
         // thread's writes before thread 0's fence, which makes them visible
         // before the record; the record's fields precede its flag.
         __syncthreads();
@@ -852,6 +853,7 @@ __device__ inline void loop_body(const LoopArgs& a, LoopShared& s) {
             __threadfence_system();
             a.done[1] = k;
             a.done[2] = a.st->err;
+            a.done[3] = a.st->status;
             __threadfence_system();
             a.done[0] = 1u;
         }
@@ -1333,7 +1335,8 @@ ibip_status run_invade(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlet
     if ((rc = hip_check(ctx, hipMemsetAsync(misc, 0, 4096, s), "memset")) != IBIP_OK) return rc;
     if ((rc = hip_check(ctx, hipMemsetAsync(hist, 0, sizeof(uint32_t) * V, s), "memset")) != IBIP_OK) return rc;
     // a1: distance transform into key[]
-    if ((rc = hip_check(ctx, launch_edt(image, nullptr, 0, 0, d, g16, tmp32, key, solid_flag, s), "edt")) != IBIP_OK)
+    if ((rc = hip_check(ctx, launch_edt(image, nullptr, 0, 0, d, g16, tmp32, key, solid_flag, s, nullptr, nullptr,
+                                        edt_tiles(ctx->tuning)), "edt")) != IBIP_OK)
         return rc;
     tm.mark(1, s);
     // a2: histogram -> ranks and bucket slices
@@ -1557,7 +1560,7 @@ static __global__ void k_sat(const uint32_t* counts, const uint32_t* count_excl,
 }
 
 hipError_t job_setup(const JobBufs& j, LoopState* st, const uint8_t* image, const uint8_t* inlets, ibip_dims d,
-                     int64_t max_steps, int32_t* seq, hipStream_t s) {
+                     int64_t max_steps, int32_t* seq, hipStream_t s, EdtTiles tiles) {
     const int64_t n = nvox(d), V = value_range(d);
     hipError_t e;
     if ((e = hipMemsetAsync(st, 0, sizeof(LoopState), s)) != hipSuccess) return e;
@@ -1565,7 +1568,7 @@ hipError_t job_setup(const JobBufs& j, LoopState* st, const uint8_t* image, cons
     if ((e = hipMemsetAsync(j.head, 0, sizeof(uint32_t) * (kMaxRanks + 2), s)) != hipSuccess) return e;
     if ((e = hipMemsetAsync(j.tail, 0, sizeof(uint32_t) * (kMaxRanks + 2), s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_loopstate_init, dim3(1), dim3(1), 0, s, st, max_steps);
-    if ((e = launch_edt(image, nullptr, 0, 0, d, j.g16, j.tmp32, j.key, &st->solid_seen, s)) != hipSuccess) return e;
+    if ((e = launch_edt(image, nullptr, 0, 0, d, j.g16, j.tmp32, j.key, &st->solid_seen, s, nullptr, nullptr, tiles)) != hipSuccess) return e;
     uint32_t* present = j.hist + V;
     uint32_t* flags = j.hist + 2 * V;
     hipLaunchKernelGGL(k_hist, dim3(std::min<int64_t>(blocks(n), kHistBlocks)), dim3(256), 0, s, j.key, n,
@@ -1638,15 +1641,36 @@ hipError_t launch_loop_jobs(const void* d_args, int32_t n, hipStream_t s) {
     return hipGetLastError();
 }
 
-LoopArgs job_loop_args(const JobBufs& j, LoopState* st, ibip_dims d) {
-    return LoopArgs{st,  j.head, j.tail, j.val, j.bucket, j.state, j.key, j.M, d.X, d.Y, d.Z, 0xFFFFFFFFu,
+// wide: a step with more centres stops the job's loop, to be run over the
+// whole GPU (0xFFFFFFFF: every step inside the job's workgroup)
+LoopArgs job_loop_args(const JobBufs& j, LoopState* st, ibip_dims d, uint32_t wide = 0xFFFFFFFFu) {
+    return LoopArgs{st,  j.head, j.tail, j.val, j.bucket, j.state, j.key, j.M, d.X, d.Y, d.Z, wide,
                     kSmallRound, make_fastdiv((uint32_t)d.Z), make_fastdiv((uint32_t)d.Y)};
+}
+
+uint32_t wide_threshold(int64_t tuned) {
+    return tuned < 0 ? 0xFFFFFFFFu : tuned == 0 ? kWideRound : (uint32_t)std::min<int64_t>(tuned, 0xFFFFFFFEll);
+}
+
+// The wide step a job's loop stopped at, over the whole GPU, then the job's
+// loop again in one workgroup (to its next wide step or its end), on s.
+hipError_t launch_wide_and_loop(const LoopArgs& la, int64_t n, hipStream_t s) {
+    const unsigned gw = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096));
+    hipLaunchKernelGGL(k_wide, dim3(gw), dim3(256), 0, s, la);
+    hipLaunchKernelGGL(k_loop, dim3(1), dim3(kLoopThreads), 0, s, la);
+    return hipGetLastError();
+}
+
+hipError_t launch_wide_and_loop_host(const void* host_args, int64_t n, hipStream_t s) {
+    LoopArgs la = *(const LoopArgs*)host_args;
+    la.done = nullptr;
+    return launch_wide_and_loop(la, n, s);
 }
 
 size_t loop_args_bytes() { return sizeof(LoopArgs); }
 
-void fill_loop_args(void* out, const JobBufs& j, LoopState* st, ibip_dims d) {
-    *(LoopArgs*)out = job_loop_args(j, st, d);
+void fill_loop_args(void* out, const JobBufs& j, LoopState* st, ibip_dims d, uint32_t wide) {
+    *(LoopArgs*)out = job_loop_args(j, st, d, wide);
 }
 
 ibip_status run_invade_batch(ibip_ctx* ctx, ibip_job* jobs, int32_t nj) {
@@ -1668,11 +1692,16 @@ ibip_status run_invade_batch(ibip_ctx* ctx, ibip_job* jobs, int32_t nj) {
     const size_t la_off = total;
     total += align256(sizeof(LoopArgs) * (size_t)nj);
     uint8_t* arena = (uint8_t*)ensure(ctx, B_BATCH, total);
-    LoopState* h_st = (LoopState*)pinned(ctx, std::max<size_t>(4096, sizeof(LoopState) * nj + sizeof(LoopArgs) * nj));
+    // pinned: the states after the launch, the loop arguments, and each
+    // continued job's state after its latest segment
+    LoopState* h_st =
+        (LoopState*)pinned(ctx, std::max<size_t>(4096, (2 * sizeof(LoopState) + sizeof(LoopArgs)) * (size_t)nj));
     if (!arena || !h_st) return fail(ctx, IBIP_ENOMEM, "invade_batch: scratch allocation failed");
     LoopState* states = (LoopState*)(arena + st_off);
     LoopArgs* d_args = (LoopArgs*)(arena + la_off);
     LoopArgs* h_args = (LoopArgs*)(h_st + nj);
+    LoopState* h_cont = (LoopState*)(h_args + nj);
+    const uint32_t wide = wide_threshold(ctx->tuning.batch_wide);
     ibip_status rc;
     if ((rc = batch_streams(ctx)) != IBIP_OK) return rc;
     const int S = kBatchStreams;
@@ -1685,19 +1714,25 @@ ibip_status run_invade_batch(ibip_ctx* ctx, ibip_job* jobs, int32_t nj) {
         ibip_job& jb = jobs[order[q]];
         bufs[q] = carve(arena + offs[q], jb.dims, jb.centre_step, jb.sat != nullptr);
         hipStream_t s = ctx->bstream[q % S];
-        if ((rc = hip_check(ctx, job_setup(bufs[q], states + q, jb.image, jb.inlets, jb.dims, jb.max_steps, jb.seq, s),
+        if ((rc = hip_check(ctx, job_setup(bufs[q], states + q, jb.image, jb.inlets, jb.dims, jb.max_steps, jb.seq, s,
+                                      edt_tiles(ctx->tuning)),
                             "setup")) != IBIP_OK)
             return rc;
         const JobBufs& j = bufs[q];
-        h_args[q] = job_loop_args(j, states + q, jb.dims);
+        h_args[q] = job_loop_args(j, states + q, jb.dims, wide);
     }
     // join, then one launch runs every job's step loop. Each job's workgroup
     // writes a completion record to host memory when its loop ends, and the
     // host starts that job's post-processing on the batch streams while the
     // launch still runs the other (larger) jobs; the jobs left when the
     // launch ends take their results from the state copy.
-    if (!done_records(ctx, 3 * (size_t)nj)) return fail(ctx, IBIP_ENOMEM, "invade_batch: pinned allocation failed");
-    for (int32_t q = 0; q < nj; q++) h_args[q].done = ctx->done_dev + 3 * q;
+    if (!done_records(ctx, 4 * (size_t)nj)) return fail(ctx, IBIP_ENOMEM, "invade_batch: pinned allocation failed");
+    for (int32_t q = 0; q < nj; q++) h_args[q].done = ctx->done_dev + 4 * q;
+    while (ctx->job_ev.size() < (size_t)nj) {
+        hipEvent_t e = nullptr;
+        if ((rc = hip_check(ctx, hipEventCreateWithFlags(&e, hipEventDisableTiming), "event")) != IBIP_OK) return rc;
+        ctx->job_ev.push_back(e);
+    }
     for (int i = 0; i < S; i++) {
         if ((rc = hip_check(ctx, hipEventRecord(ctx->bev[i], ctx->bstream[i]), "event")) != IBIP_OK) return rc;
         if ((rc = hip_check(ctx, hipStreamWaitEvent(s0, ctx->bev[i], 0), "wait")) != IBIP_OK) return rc;
@@ -1734,33 +1769,77 @@ ibip_status run_invade_batch(ibip_ctx* ctx, ibip_job* jobs, int32_t nj) {
         return hip_check(ctx, job_post(bufs[q], states + q, jb.dims, K, jb.seq, jb.rad2, jb.M, jb.sat,
                                        ctx->bstream[q % S]), "post");
     };
-    std::vector<uint8_t> posted(nj, 0);
+    // per job: 0 = in the launch, 1 = continued on its batch stream after a
+    // stop at a wide step, 2 = post-processing queued
+    std::vector<uint8_t> phase(nj, 0);
+    auto cont = [&](int32_t q) -> ibip_status {
+        hipStream_t bs = ctx->bstream[q % S];
+        LoopArgs la = h_args[q];
+        la.done = nullptr;  // the continued loop reports through its state copy
+        ibip_status r;
+        if (tm.on) ctx->timing.wide_launches++;
+        if ((r = hip_check(ctx, launch_wide_and_loop(la, nvox(jobs[order[q]].dims), bs), "wide launch")) != IBIP_OK)
+            return r;
+        if ((r = hip_check(ctx, hipMemcpyAsync(h_cont + q, states + q, sizeof(LoopState), hipMemcpyDeviceToHost, bs),
+                           "copy")) != IBIP_OK)
+            return r;
+        phase[q] = 1;
+        return hip_check(ctx, hipEventRecord(ctx->job_ev[q], bs), "event");
+    };
     int32_t left = nj;
+    bool launch_done = false;
     for (;;) {
         bool progress = false;
         for (int32_t q = 0; q < nj; q++) {
-            if (posted[q] || __atomic_load_n(&ctx->done_host[3 * q], __ATOMIC_ACQUIRE) == 0) continue;
-            if ((rc = post(q, ctx->done_host[3 * q + 1], ctx->done_host[3 * q + 2])) != IBIP_OK) return rc;
-            posted[q] = 1;
-            left--;
-            progress = true;
+            if (phase[q] == 0) {
+                if (__atomic_load_n(&ctx->done_host[4 * q], __ATOMIC_ACQUIRE) == 0) {
+                    if (!launch_done) continue;
+                    // the launch ended without a record: rejected before its loop
+                    if ((rc = post(q, h_st[q].k, h_st[q].err)) != IBIP_OK) return rc;
+                    phase[q] = 2;
+                } else if (ctx->done_host[4 * q + 3] == LS_WIDE && ctx->done_host[4 * q + 2] == 0) {
+                    if ((rc = cont(q)) != IBIP_OK) return rc;
+                    progress = true;
+                    continue;
+                } else {
+                    if ((rc = post(q, ctx->done_host[4 * q + 1], ctx->done_host[4 * q + 2])) != IBIP_OK) return rc;
+                    phase[q] = 2;
+                }
+                left--;
+                progress = true;
+            } else if (phase[q] == 1) {
+                const hipError_t qe = hipEventQuery(ctx->job_ev[q]);
+                if (qe == hipErrorNotReady) continue;
+                if ((rc = hip_check(ctx, qe, "event query")) != IBIP_OK) return rc;
+                progress = true;
+                if (h_cont[q].status == LS_WIDE && h_cont[q].err == 0) {
+                    if ((rc = cont(q)) != IBIP_OK) return rc;
+                    continue;
+                }
+                if ((rc = post(q, h_cont[q].k, h_cont[q].err)) != IBIP_OK) return rc;
+                phase[q] = 2;
+                left--;
+            }
         }
         if (left == 0) break;
-        const hipError_t qe = hipEventQuery(ctx->copy_ev);
-        if (qe == hipSuccess) break;
-        if (qe != hipErrorNotReady) return hip_check(ctx, qe, "event query");
+        if (!launch_done) {
+            const hipError_t qe = hipEventQuery(ctx->copy_ev);
+            if (qe == hipSuccess) {
+                launch_done = true;
+                if (tm.on) {
+                    ctx->timing.loop_kernel_ms += tm.ms(3, 4);
+                    ctx->timing.loop_launches++;
+                }
+                continue;  // a last pass over the records
+            }
+            if (qe != hipErrorNotReady) return hip_check(ctx, qe, "event query");
+        }
         if (!progress) std::this_thread::sleep_for(std::chrono::microseconds(20));
     }
     if ((rc = hip_check(ctx, hipEventSynchronize(ctx->copy_ev), "sync")) != IBIP_OK) return rc;
-    if (tm.on) {
+    if (!launch_done && tm.on) {
         ctx->timing.loop_kernel_ms += tm.ms(3, 4);
         ctx->timing.loop_launches++;
-    }
-    // jobs that wrote no record (rejected before their loop) or were not seen
-    // before the launch ended
-    for (int32_t q = 0; q < nj; q++) {
-        if (posted[q]) continue;
-        if ((rc = post(q, h_st[q].k, h_st[q].err)) != IBIP_OK) return rc;
     }
     for (int i = 0; i < S; i++) {
         if ((rc = hip_check(ctx, hipEventRecord(ctx->bev[i], ctx->bstream[i]), "event")) != IBIP_OK) return rc;

@@ -92,7 +92,8 @@ ibip_status run_mio(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlets, 
     if ((rc = hip_check(ctx, hipMemsetAsync(counts, 0, sizeof(uint32_t) * ncount, s), "memset")) != IBIP_OK)
         return rc;
     if ((rc = hip_check(ctx, hipMemsetAsync(mio_r2, 0, sizeof(uint32_t) * n, s), "memset")) != IBIP_OK) return rc;
-    if ((rc = hip_check(ctx, launch_edt(image, nullptr, 0, 0, d, g16, tmp32, dt2, &flags[0], s), "edt")) != IBIP_OK)
+    if ((rc = hip_check(ctx, launch_edt(image, nullptr, 0, 0, d, g16, tmp32, dt2, &flags[0], s, nullptr, nullptr,
+                                        edt_tiles(ctx->tuning)), "edt")) != IBIP_OK)
         return rc;
     hipLaunchKernelGGL(k_mio_seed, dim3(blocks(n)), dim3(256), 0, s, image, inlets, dt2, d.X, d.Y, d.Z,
                        make_fastdiv((uint32_t)d.Z), make_fastdiv((uint32_t)d.Y), kmap, pore_slots, (ctx->readings & IBIP_READ_MASK_INLETS) != 0);
@@ -110,7 +111,8 @@ ibip_status run_mio(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlets, 
         // distance to the kept centres, capped at T; the last pass writes T
         // into mio_r2 where it is still 0 and the distance is below T
         if ((rc = hip_check(ctx, launch_edt(nullptr, kmap, T[i], T[i], d, g16, tmp32, nullptr, &flags[2], s, mio_r2,
-                                            counts + (size_t)kCountSlots * i), "edt")) != IBIP_OK)
+                                            counts + (size_t)kCountSlots * i, edt_tiles(ctx->tuning)),
+                                 "edt")) != IBIP_OK)
             return rc;
     }
     if ((rc = hip_check(ctx, hipGetLastError(), "mio launch")) != IBIP_OK) return rc;

@@ -85,6 +85,7 @@ struct Slot {
     uint8_t* host_small = nullptr;  // pinned: LoopState copy at 0, loop-argument staging at 512
     int64_t ticket = -1;
     bool broken = false;            // its stream failed; no job is admitted to it again
+    int phase = 0;                  // 1: the job's step loop, 2: its post-processing
 };
 
 }  // namespace
@@ -106,6 +107,7 @@ struct ibip_server {
     std::thread worker;
     bool stop = false;
     std::string err;
+    ibip_tuning tuning{};  // launch parameters of the jobs admitted from now on
     ibip_server_stats stats{};
 };
 
@@ -122,12 +124,14 @@ bool start_job(ibip_server* S, int64_t t, int si) {
     JobBufs b = carve(S->pool_base + J.off, jb.dims, jb.centre_step, false);
     LoopState* st = (LoopState*)sl.dev_small;
     void* dargs = sl.dev_small + 512;
-    hipError_t e = job_setup(b, st, jb.image, jb.inlets, jb.dims, jb.max_steps, jb.seq, sl.stream);
-    fill_loop_args(sl.host_small + 512, b, st, jb.dims);
+    hipError_t e = job_setup(b, st, jb.image, jb.inlets, jb.dims, jb.max_steps, jb.seq, sl.stream,
+                             edt_tiles(S->tuning));
+    // a step with more centres than the threshold stops the loop; the worker
+    // then runs that step over the whole GPU and resumes the loop (advance())
+    fill_loop_args(sl.host_small + 512, b, st, jb.dims, wide_threshold(S->tuning.batch_wide));
     if (e == hipSuccess)
         e = hipMemcpyAsync(dargs, sl.host_small + 512, loop_args_bytes(), hipMemcpyHostToDevice, sl.stream);
     if (e == hipSuccess) e = launch_loop_jobs(dargs, 1, sl.stream);
-    if (e == hipSuccess) e = job_post_devk(b, st, jb.dims, jb.seq, jb.rad2, jb.M, sl.stream);
     if (e == hipSuccess) e = hipMemcpyAsync(sl.host_small, st, sizeof(LoopState), hipMemcpyDeviceToHost, sl.stream);
     if (e == hipSuccess) e = hipEventRecord(sl.done, sl.stream);
     if (e != hipSuccess) {
@@ -144,9 +148,43 @@ bool start_job(ibip_server* S, int64_t t, int si) {
     J.slot = si;
     J.state = J_RUNNING;
     sl.ticket = t;
+    sl.phase = 1;
     S->stats.running++;
     S->stats.pending--;
     if (S->stats.running > S->stats.peak_running) S->stats.peak_running = S->stats.running;
+    return true;
+}
+
+// The slot's queued work ended (mu held). After a loop segment that stopped
+// at a wide step: queue that step over the whole GPU and the next loop
+// segment; after the last segment: queue the post-processing. Returns false
+// when the job is finished (or a launch failed: *e holds the error).
+bool advance(ibip_server* S, int si, hipError_t* e) {
+    Slot& sl = S->slots[si];
+    if (sl.phase != 1 || *e != hipSuccess) return false;
+    Job& J = S->jobs[sl.ticket];
+    const ibip_job& jb = J.job;
+    const LoopState* hs = (const LoopState*)sl.host_small;
+    LoopState* st = (LoopState*)sl.dev_small;
+    hipError_t r = hipSuccess;
+    if (hs->status == LS_WIDE && hs->err == 0) {
+        r = launch_wide_and_loop_host(sl.host_small + 512, (int64_t)jb.dims.X * jb.dims.Y * jb.dims.Z, sl.stream);
+    } else {
+        JobBufs b = carve(S->pool_base + J.off, jb.dims, jb.centre_step, false);
+        r = job_post_devk(b, st, jb.dims, jb.seq, jb.rad2, jb.M, sl.stream);
+        sl.phase = 2;
+    }
+    if (r == hipSuccess) r = hipMemcpyAsync(sl.host_small, st, sizeof(LoopState), hipMemcpyDeviceToHost, sl.stream);
+    if (r == hipSuccess) r = hipEventRecord(sl.done, sl.stream);
+    if (r != hipSuccess) {
+        set_err(S, std::string("server: launch failed: ") + hipGetErrorString(r));
+        if (hipStreamSynchronize(sl.stream) != hipSuccess) {
+            (void)hipGetLastError();
+            sl.broken = true;
+        }
+        *e = r;
+        return false;
+    }
     return true;
 }
 
@@ -181,8 +219,10 @@ void worker_main(ibip_server* S) {
             if (sl.ticket < 0) continue;
             const hipError_t q = hipEventQuery(sl.done);
             if (q == hipErrorNotReady) continue;
-            finish_job(S, (int)si, q == hipSuccess ? hipSuccess : q);
+            hipError_t e = q == hipSuccess ? hipSuccess : q;
             progressed = true;
+            if (advance(S, (int)si, &e)) continue;
+            finish_job(S, (int)si, e);
         }
         if (progressed) S->cv_done.notify_all();
         // admissions: first pending job (within the window) whose scratch fits
@@ -380,6 +420,14 @@ ibip_status ibip_server_stats_get(ibip_server* S, ibip_server_stats* out) {
     if (!S || !out) return IBIP_EINVAL;
     std::lock_guard<std::mutex> g(S->mu);
     *out = S->stats;
+    return IBIP_OK;
+}
+
+ibip_status ibip_server_set_tuning(ibip_server* S, const ibip_tuning* t) {
+    if (!S) return IBIP_EINVAL;
+    if (t && !tuning_ok(*t)) return IBIP_EINVAL;
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->tuning = t ? *t : ibip_tuning{};
     return IBIP_OK;
 }
 

@@ -131,3 +131,59 @@ def test_batch_shared_wide_steps(dev, tuning):
         np.testing.assert_array_equal(b["M"].cpu().numpy().view(np.uint32), r["M"])
     # the context's own tuning is back to what it was
     assert ibip.get_tuning() == {"batch_wide": 0, "batch_workgroups": 0, "batch_chunk_rounds": 0}
+
+
+def _wide_jobs():
+    rng = np.random.default_rng(7)
+    imgs, inls, lims = [], [], []
+    for i in range(9):
+        L = int(rng.integers(40, 90))
+        if i % 2:
+            img = synth.blurred_noise((L, L + 3, L - 5), sigma=3.0, porosity=0.6, seed=50 + i)
+        else:
+            img = synth.overlapping_spheres((L, L - 2, L + 4), r2=16, porosity=0.65, seed=50 + i)
+        imgs.append(img)
+        inls.append(synth.face_mask(img.shape, 0, 0))
+        lims.append(0 if i != 4 else 57)
+    return imgs, inls, lims
+
+
+@pytest.mark.parametrize("tuning", [
+    {"batch_wide": 128},
+    {"batch_wide": 300, "edt_tile_y": 64, "edt_tile_x": 16},
+    {"batch_wide": 2000, "edt_tile_y": 64},
+    {"batch_wide": -1, "edt_tile_x": 16},
+])
+def test_batch_continued_wide_steps(dev, tuning):
+    """A job's step above the threshold stops its loop in the batched launch;
+    the host runs that step over the whole GPU and the job's loop continues
+    in launches of its own, stopping again at every later such step (a low
+    threshold makes that happen hundreds of times per job). Every result
+    equals the oracle; a job without solid fails alone; a step limit holds;
+    the EDT tile widths change nothing."""
+    imgs, inls, lims = _wide_jobs()
+    imgs.append(np.ones((20, 20, 24), np.uint8))  # no solid: ENOSOLID
+    inls.append(synth.face_mask(imgs[-1].shape, 0, 0))
+    lims.append(0)
+    print("batch tuning", tuning, flush=True)
+    out = ibip.invade_batch([_d(a, dev) for a in imgs], [_d(a, dev) for a in inls], max_steps=lims,
+                            raise_on_error=False, tuning=tuning)
+    assert out[-1]["status"] == -3
+    for img, inl, lim, b in zip(imgs[:-1], inls[:-1], lims[:-1], out[:-1]):
+        r = oracle.invade(img, inl, max_steps=lim)
+        assert b["status"] == 0
+        assert b["K"] == r["K"]
+        np.testing.assert_array_equal(b["seq"].cpu().numpy(), r["seq"])
+        np.testing.assert_array_equal(b["rad2"].cpu().numpy().view(np.uint32), r["rad2"])
+        np.testing.assert_array_equal(b["centre_step"].cpu().numpy(), r["centre_step"])
+        np.testing.assert_array_equal(b["M"].cpu().numpy().view(np.uint32), r["M"])
+    # the context's own tuning is back to the defaults
+    assert ibip.get_tuning() == {"edt_tile_y": 0, "edt_tile_x": 0, "batch_wide": 0}
+
+
+def test_tuning_rejects_unknown_tile_widths(dev):
+    with pytest.raises(ibip.IbipError):
+        ibip.set_tuning({"edt_tile_y": 48})
+    with pytest.raises(ibip.IbipError):
+        ibip.set_tuning({"edt_tile_x": 64})
+    assert ibip.get_tuning() == {"edt_tile_y": 0, "edt_tile_x": 0, "batch_wide": 0}

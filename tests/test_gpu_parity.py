@@ -92,6 +92,26 @@ def test_edt_vector_path(dev, shape, p):
     np.testing.assert_array_equal(_u32(ibip.edt(_d(img, dev))), oracle.edt(img))
 
 
+@pytest.mark.parametrize("tiles", [(64, 32), (32, 16), (64, 16)])
+@pytest.mark.parametrize("shape", [(3, 5, 8), (17, 33, 200), (512, 2, 16), (2, 512, 24), (9, 7, 512), (40, 50, 72)])
+def test_edt_tile_widths(dev, shape, tiles):
+    """The other LDS tile widths of passes y and x (whole 128-byte lines in
+    pass y, 64-byte rows in pass x) give the same distances, also for the
+    opening's capped transform."""
+    rng = np.random.default_rng(sum(shape) + tiles[0] + tiles[1])
+    img = (rng.random(shape) < 0.8).astype(np.uint8)
+    img.flat[int(rng.integers(img.size))] = 0
+    ibip.set_tuning({"edt_tile_y": tiles[0], "edt_tile_x": tiles[1]})
+    try:
+        np.testing.assert_array_equal(_u32(ibip.edt(_d(img, dev))), oracle.edt(img))
+        inl = synth.face_mask(shape, 0, 0)
+        T = np.array([9, 4, 2, 1], np.uint32)
+        m = ibip.opening_drainage(_d(img, dev), _d(inl, dev), T.tolist())
+        np.testing.assert_array_equal(_u32(m["mio_r2"]), oracle.mio(img, inl, T)["mio_r2"])
+    finally:
+        ibip.set_tuning(None)
+
+
 def test_edt_unaligned_input(dev):
     rng = np.random.default_rng(3)
     img = (rng.random((16, 24, 64)) < 0.9).astype(np.uint8)

@@ -128,3 +128,27 @@ def test_step_limit(dev):
                                      for (i, m), k in zip(jobs, limits)]]
     for (img, inl), k, r in zip(jobs, limits, res):
         _same(r, ibip.invade(_d(img, dev), _d(inl, dev), max_steps=k))
+
+
+@pytest.mark.parametrize("wide", [128, 1000])
+def test_continued_wide_steps_in_the_mix(dev, wide):
+    """With a low wide-step threshold every served job stops at many steps;
+    the worker runs each over the whole GPU and resumes the job's loop while
+    other jobs run. Every result equals the oracle; a step limit holds."""
+    rng = np.random.default_rng(wide)
+    jobs = []
+    for i in range(10):
+        L = int(rng.integers(30, 80))
+        img = synth.blurred_noise((L, L + 2, L + 5), sigma=3.0, porosity=float(rng.uniform(0.45, 0.65)), seed=300 + i)
+        jobs.append((img, synth.face_mask(img.shape, 0, 0), 0 if i != 3 else 41))
+    with ibip.Server(dev, hbm_budget_bytes=1 << 30, max_inflight=4) as srv:
+        srv.set_tuning({"batch_wide": wide, "edt_tile_y": 64})
+        tickets = [srv.submit(_d(img, dev), _d(inl, dev), max_steps=lim) for img, inl, lim in jobs]
+        res = [srv.wait(t) for t in tickets]
+    for (img, inl, lim), r in zip(jobs, res):
+        o = oracle.invade(img, inl, max_steps=lim)
+        assert r["status"] == 0
+        assert r["K"] == o["K"]
+        np.testing.assert_array_equal(r["seq"].cpu().numpy(), o["seq"])
+        np.testing.assert_array_equal(r["rad2"].cpu().numpy().view(np.uint32), o["rad2"])
+        np.testing.assert_array_equal(r["M"].cpu().numpy().view(np.uint32), o["M"])
