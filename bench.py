@@ -235,8 +235,10 @@ def run_batch(args) -> int:
     d_inls = [torch.from_numpy(synth.face_mask(a.shape, 0, 0)).to(dev) for a in imgs]
     n_vox = int(sum(a.size for a in imgs))
 
+    tuning = json.loads(args.tuning) if args.tuning else None
+
     def batched():
-        return ibip.invade_batch(d_imgs, d_inls)
+        return ibip.invade_batch(d_imgs, d_inls, tuning=tuning)
 
     def plain():
         return [ibip.invade(a, b) for a, b in zip(d_imgs, d_inls)]
@@ -265,7 +267,8 @@ def run_batch(args) -> int:
         "warmup": args.warmup, "ms_per_step": 1e3 * tb, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u32", "data": "synthetic",
         "config": {"workload": "batch96", "description": WORKLOADS["batch96"], "images": len(imgs),
-                   "voxels": n_vox, "invaded_voxels": invaded, "parallelism": "single GPU"},
+                   "voxels": n_vox, "invaded_voxels": invaded, "parallelism": "single GPU",
+                   "tuning": tuning or {}},
         "batched_vs_plain": {"batched_ms": 1e3 * tb, "plain_ms": 1e3 * tp, "speedup": tp / tb,
                              "bit_exact": bool(exact), "plain_value": invaded / tp},
     }
@@ -300,6 +303,8 @@ def run_serve(args) -> int:
     print(f"serve: {len(imgs)} requests generated, {vox.sum() / 1e9:.2f} G voxels", file=sys.stderr, flush=True)
     srv = ibip.Server(dev, hbm_budget_bytes=int(args.serve_budget_gb * (1 << 30)), max_inflight=args.inflight,
                       lookahead=args.lookahead)
+    if args.tuning:
+        srv.set_tuning(json.loads(args.tuning))
     small = np.argsort(vox)[:min(8, len(imgs))]
     for i in small[: args.warmup * 4]:
         srv.wait(srv.submit(imgs[i], inls[i]))
@@ -365,7 +370,8 @@ def run_serve(args) -> int:
         "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
         "config": {"workload": "serve", "description": WORKLOADS["serve"], "requests": len(imgs),
                    "voxels": float(vox.sum()), "max_inflight": args.inflight, "hbm_budget_gb": args.serve_budget_gb,
-                   "closed_loop_depth": args.depth, "parallelism": "single GPU"},
+                   "closed_loop_depth": args.depth, "parallelism": "single GPU",
+                   "tuning": json.loads(args.tuning) if args.tuning else {}},
         "serve": {"capacity_jobs_per_s": len(imgs) / wall_c, "capacity_voxels_per_s": vox.sum() / wall_c,
                   "closed_loop_p50_ms": float(np.percentile(lat_c, 50)),
                   "closed_loop_p99_ms": float(np.percentile(lat_c, 99)),
@@ -404,6 +410,9 @@ def main() -> int:
     ap.add_argument("--depth", type=int, default=32, help="serve: outstanding requests in the closed loop")
     ap.add_argument("--serve-budget-gb", type=float, default=96.0, help="serve: HBM pool for job scratch")
     ap.add_argument("--check-large", type=int, default=0, help="serve: also rerun the largest request alone")
+    ap.add_argument("--tuning", default="",
+                    help="launch parameters as JSON (keys edt_tile_y, edt_tile_x, batch_wide) for the batch, the "
+                         "server or the single-image workloads")
     ap.add_argument("--hw-queues", type=int, default=-1,
                     help="hardware queues per process for the HIP runtime (0: its default)")
     args = ap.parse_args()
@@ -439,6 +448,8 @@ def main() -> int:
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.tuning:
+        ibip.set_tuning(json.loads(args.tuning))
     if args.workload == "edt512":
         e = edt_alone(dev)
         print(json.dumps({

@@ -110,7 +110,8 @@ ibip_status ibip_ctx_set_readings(ibip_ctx* ctx, uint32_t flags);
    edt_tile_x  z columns per LDS tile of the EDT's pass x: 16 or 32 (0: 32)
    batch_wide  a batch job's step with more centres than this leaves the job's
                workgroup: the step runs over the whole GPU and the job's loop
-               resumes in its own launch (0: 8192; negative: never).
+               resumes in its own launch (0: never for ibip_invade_batch, 8192
+               for the server's jobs; negative: never).
    Errors: EINVAL (a tile width not listed). NULL restores the defaults. */
 typedef struct {
     int32_t edt_tile_y;

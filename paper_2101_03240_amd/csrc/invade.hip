@@ -1701,7 +1701,10 @@ ibip_status run_invade_batch(ibip_ctx* ctx, ibip_job* jobs, int32_t nj) {
     LoopArgs* d_args = (LoopArgs*)(arena + la_off);
     LoopArgs* h_args = (LoopArgs*)(h_st + nj);
     LoopState* h_cont = (LoopState*)(h_args + nj);
-    const uint32_t wide = wide_threshold(ctx->tuning.batch_wide);
+    // a job that leaves the batched launch continues in launches of its own
+    // on a batch stream, where it serialises with the other jobs of that
+    // stream: by default every step stays in the job's workgroup
+    const uint32_t wide = ctx->tuning.batch_wide == 0 ? 0xFFFFFFFFu : wide_threshold(ctx->tuning.batch_wide);
     ibip_status rc;
     if ((rc = batch_streams(ctx)) != IBIP_OK) return rc;
     const int S = kBatchStreams;
