@@ -163,6 +163,46 @@ def _torch():
     return torch
 
 
+# Launch parameters from the autotuner's cache (autotune.py), applied per call
+# by the image's size class unless the thread set its own with set_tuning.
+_tuned = {"loaded": False, "doc": None}
+_manual = set()  # context keys whose tuning the caller set
+
+
+def _tuning_doc():
+    if not _tuned["loaded"]:
+        _tuned["loaded"] = True
+        try:
+            from . import autotune
+            torch = _torch()
+            _tuned["doc"] = autotune.load(torch.cuda.get_device_properties(torch.cuda.current_device()).gcnArchName)
+        except Exception:
+            _tuned["doc"] = None
+    return _tuned["doc"]
+
+
+def _auto_tuning(shape, batch: bool = False) -> dict | None:
+    doc = _tuning_doc()
+    if doc is None:
+        return None
+    from .autotune import size_class
+    t = dict(doc.get("edt", {}).get(size_class(shape), {}))
+    t = {k: t[k] for k in ("edt_tile_y", "edt_tile_x") if k in t}
+    if batch and "batch" in doc:
+        t["batch_wide"] = int(doc["batch"]["batch_wide"])
+    return t or None
+
+
+def _apply_auto(ctx, shape):
+    """Set the cached tuning of this shape's size class on the context, unless
+    the calling thread chose its own."""
+    if ctx.value in _manual:
+        return
+    t = _auto_tuning(shape)
+    if t is not None:
+        load_library().ibip_ctx_set_tuning(ctx, ctypes.byref(_tuning_struct(t)))
+
+
 def _context(device) -> ctypes.c_void_p:
     """The calling thread's context on `device` (a context holds scratch
     buffers and is used by one thread at a time, so each host thread gets its
@@ -231,6 +271,7 @@ def edt(image):
     image = _dev_u8(image, "image")
     dims, shape = _dims_of(image)
     ctx = _context(image.device)
+    _apply_auto(ctx, shape)
     out = torch.empty(image.shape, dtype=torch.int32, device=image.device)
     _check(load_library().ibip_edt(ctx, _ptr(image), dims, _ptr(out)), ctx)
     return out
@@ -247,6 +288,7 @@ def edt_noalloc(image, out=None, solid_flag=None):
     image = _dev_u8(image, "image")
     dims, shape = _dims_of(image)
     ctx = _context(image.device)
+    _apply_auto(ctx, shape)
     if out is None:
         out = torch.empty(image.shape, dtype=torch.int32, device=image.device)
     if solid_flag is None:
@@ -273,6 +315,7 @@ def invade(image, inlets, max_steps: int = 0, sigma: float = 1.0, theta_rad: flo
     dev = image.device
     ctx = _context(dev)
     _readings(ctx, integer_ball=integer_ball, mask_inlets=mask_inlets)
+    _apply_auto(ctx, shape)
     lib = load_library()
     seq = torch.empty(image.shape, dtype=torch.int32, device=dev)
     r2 = torch.empty(image.shape, dtype=torch.int32, device=dev) if rad2 else None
@@ -304,6 +347,11 @@ def set_tuning(tuning: dict | None = None, device=None):
     ctx = _context(torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device()))
     t = _tuning_struct(tuning)
     _check(load_library().ibip_ctx_set_tuning(ctx, ctypes.byref(t)), ctx)
+    # None hands the choice back to the autotuner's cache
+    if tuning is None:
+        _manual.discard(ctx.value)
+    else:
+        _manual.add(ctx.value)
 
 
 def get_tuning(device=None) -> dict:
@@ -354,6 +402,8 @@ def invade_batch(images, inlets, max_steps=0, rad2: bool = True, centre_step: bo
             setattr(jobs[i], f, o[f].data_ptr() if o[f] is not None else None)
     lib = load_library()
     saved = None
+    if tuning is None and ctx.value not in _manual:
+        tuning = _auto_tuning(max((tuple(t.shape) for t in imgs), key=lambda sh: max(sh)), batch=True)
     if tuning is not None:
         saved = _Tuning()
         _check(lib.ibip_ctx_get_tuning(ctx, ctypes.byref(saved)), ctx)
@@ -393,6 +443,12 @@ class Server:
         if st != 0:
             raise IbipError(st, "cannot create the server")
         self._live = {}
+        doc = _tuning_doc()
+        if doc is not None and "serve" in doc:
+            t = dict(doc.get("edt", {}).get("large", {}))
+            t = {k: t[k] for k in ("edt_tile_y", "edt_tile_x") if k in t}
+            t["batch_wide"] = int(doc["serve"]["serve_wide"])
+            self.set_tuning(t)
 
     def submit(self, image, inlets, max_steps: int = 0, rad2: bool = True, centre_step: bool = True,
                M: bool = True) -> int:
@@ -558,6 +614,7 @@ def opening_drainage(image, inlets, thresholds, mask_inlets: bool = False):
     dev = image.device
     ctx = _context(dev)
     _readings(ctx, mask_inlets=mask_inlets)
+    _apply_auto(ctx, shape)
     T = [int(t) for t in thresholds]
     arr = (ctypes.c_uint32 * max(len(T), 1))(*T)
     sat = (ctypes.c_double * max(len(T), 1))()

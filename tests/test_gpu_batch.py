@@ -166,6 +166,7 @@ def test_batch_continued_wide_steps(dev, tuning):
     inls.append(synth.face_mask(imgs[-1].shape, 0, 0))
     lims.append(0)
     print("batch tuning", tuning, flush=True)
+    before = ibip.get_tuning()
     out = ibip.invade_batch([_d(a, dev) for a in imgs], [_d(a, dev) for a in inls], max_steps=lims,
                             raise_on_error=False, tuning=tuning)
     assert out[-1]["status"] == -3
@@ -177,13 +178,16 @@ def test_batch_continued_wide_steps(dev, tuning):
         np.testing.assert_array_equal(b["rad2"].cpu().numpy().view(np.uint32), r["rad2"])
         np.testing.assert_array_equal(b["centre_step"].cpu().numpy(), r["centre_step"])
         np.testing.assert_array_equal(b["M"].cpu().numpy().view(np.uint32), r["M"])
-    # the context's own tuning is back to the defaults
-    assert ibip.get_tuning() == {"edt_tile_y": 0, "edt_tile_x": 0, "batch_wide": 0}
+    # the context's own tuning is back to what it was
+    assert ibip.get_tuning() == before
 
 
 def test_tuning_rejects_unknown_tile_widths(dev):
+    ibip.set_tuning({"edt_tile_y": 64, "edt_tile_x": 16, "batch_wide": 5})
     with pytest.raises(ibip.IbipError):
         ibip.set_tuning({"edt_tile_y": 48})
     with pytest.raises(ibip.IbipError):
         ibip.set_tuning({"edt_tile_x": 64})
+    assert ibip.get_tuning() == {"edt_tile_y": 64, "edt_tile_x": 16, "batch_wide": 5}
+    ibip.set_tuning(None)
     assert ibip.get_tuning() == {"edt_tile_y": 0, "edt_tile_x": 0, "batch_wide": 0}
