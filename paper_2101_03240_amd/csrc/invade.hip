@@ -1546,6 +1546,18 @@ JobBufs carve(uint8_t* base, ibip_dims d, int32_t* caller_state, bool want_sat) 
     return j;
 }
 
+// n words of p set to v (a kernel, not a memset: the batch's setup is
+// captured into a graph, where memset nodes are avoided)
+static __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = v;
+}
+
+static hipError_t fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(blocks(n), 1024))),
+                       dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
 static __global__ void k_loopstate_init(LoopState* st, int64_t max_steps) {
     st->k = 1;
     st->status = LS_RUN;
@@ -1563,10 +1575,11 @@ hipError_t job_setup(const JobBufs& j, LoopState* st, const uint8_t* image, cons
                      int64_t max_steps, int32_t* seq, hipStream_t s, EdtTiles tiles) {
     const int64_t n = nvox(d), V = value_range(d);
     hipError_t e;
-    if ((e = hipMemsetAsync(st, 0, sizeof(LoopState), s)) != hipSuccess) return e;
-    if ((e = hipMemsetAsync(j.hist, 0, sizeof(uint32_t) * V, s)) != hipSuccess) return e;
-    if ((e = hipMemsetAsync(j.head, 0, sizeof(uint32_t) * (kMaxRanks + 2), s)) != hipSuccess) return e;
-    if ((e = hipMemsetAsync(j.tail, 0, sizeof(uint32_t) * (kMaxRanks + 2), s)) != hipSuccess) return e;
+    static_assert(sizeof(LoopState) % 4 == 0, "LoopState is cleared as words");
+    if ((e = fill_u32((uint32_t*)st, sizeof(LoopState) / 4, 0u, s)) != hipSuccess) return e;
+    if ((e = fill_u32(j.hist, V, 0u, s)) != hipSuccess) return e;
+    if ((e = fill_u32(j.head, kMaxRanks + 2, 0u, s)) != hipSuccess) return e;
+    if ((e = fill_u32(j.tail, kMaxRanks + 2, 0u, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_loopstate_init, dim3(1), dim3(1), 0, s, st, max_steps);
     if ((e = launch_edt(image, nullptr, 0, 0, d, j.g16, j.tmp32, j.key, &st->solid_seen, s, nullptr, nullptr, tiles)) != hipSuccess) return e;
     uint32_t* present = j.hist + V;
@@ -1709,21 +1722,66 @@ ibip_status run_invade_batch(ibip_ctx* ctx, ibip_job* jobs, int32_t nj) {
     if ((rc = batch_streams(ctx)) != IBIP_OK) return rc;
     const int S = kBatchStreams;
     std::vector<JobBufs> bufs(nj);
-    // fork: every stream waits for the caller's stream (inputs ready)
-    if ((rc = hip_check(ctx, hipEventRecord(ctx->bev[S], s0), "event")) != IBIP_OK) return rc;
-    for (int i = 0; i < S; i++)
-        if ((rc = hip_check(ctx, hipStreamWaitEvent(ctx->bstream[i], ctx->bev[S], 0), "wait")) != IBIP_OK) return rc;
+    const EdtTiles tiles = edt_tiles(ctx->tuning);
+    // the per-job setup (EDT, histogram, ranks, slices, seeds) depends only on
+    // the jobs' buffers, dims and step limits and the arena: it is captured
+    // once into a graph (fork over the batch streams, join back) and replayed
+    // while the same batch comes back
+    std::vector<uint64_t> key = {(uint64_t)nj, (uint64_t)(uintptr_t)arena, (uint64_t)tiles.y, (uint64_t)tiles.x};
     for (int32_t q = 0; q < nj; q++) {
-        ibip_job& jb = jobs[order[q]];
+        const ibip_job& jb = jobs[order[q]];
         bufs[q] = carve(arena + offs[q], jb.dims, jb.centre_step, jb.sat != nullptr);
-        hipStream_t s = ctx->bstream[q % S];
-        if ((rc = hip_check(ctx, job_setup(bufs[q], states + q, jb.image, jb.inlets, jb.dims, jb.max_steps, jb.seq, s,
-                                      edt_tiles(ctx->tuning)),
-                            "setup")) != IBIP_OK)
-            return rc;
-        const JobBufs& j = bufs[q];
-        h_args[q] = job_loop_args(j, states + q, jb.dims, wide);
+        h_args[q] = job_loop_args(bufs[q], states + q, jb.dims, wide);
+        key.insert(key.end(), {(uint64_t)(uintptr_t)jb.image, (uint64_t)(uintptr_t)jb.inlets,
+                               (uint64_t)(uintptr_t)jb.seq, (uint64_t)(uintptr_t)jb.centre_step,
+                               (uint64_t)(uintptr_t)jb.sat, (uint64_t)jb.max_steps, (uint64_t)jb.dims.X,
+                               ((uint64_t)jb.dims.Y << 32) | (uint32_t)jb.dims.Z});
     }
+    if ((rc = batch_graph(ctx)) != IBIP_OK) return rc;
+    if (!ctx->batch_exec || ctx->batch_key != key) {
+        if (ctx->batch_exec) {
+            (void)hipGraphExecDestroy(ctx->batch_exec);
+            ctx->batch_exec = nullptr;
+            ctx->batch_key.clear();
+        }
+        hipStream_t cs = ctx->cap_stream;
+        if ((rc = hip_check(ctx, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "begin capture")) !=
+            IBIP_OK)
+            return rc;
+        hipError_t e = hipEventRecord(ctx->cap_ev[0], cs);
+        for (int i = 0; i < S && e == hipSuccess; i++) e = hipStreamWaitEvent(ctx->bstream[i], ctx->cap_ev[0], 0);
+        for (int32_t q = 0; q < nj && e == hipSuccess; q++) {
+            const ibip_job& jb = jobs[order[q]];
+            e = job_setup(bufs[q], states + q, jb.image, jb.inlets, jb.dims, jb.max_steps, jb.seq, ctx->bstream[q % S],
+                          tiles);
+        }
+        for (int i = 0; i < S && e == hipSuccess; i++) {
+            e = hipEventRecord(ctx->cap_join[i], ctx->bstream[i]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(cs, ctx->cap_join[i], 0);
+        }
+        hipGraph_t graph = nullptr;
+        const hipError_t ee = hipStreamEndCapture(cs, &graph);
+        if (e == hipSuccess) e = ee;
+        if (e == hipSuccess) e = hipGraphInstantiate(&ctx->batch_exec, graph, nullptr, nullptr, 0);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            ctx->batch_exec = nullptr;
+            return hip_check(ctx, e, "setup graph");
+        }
+        ctx->batch_key = key;
+    }
+    // replay after the caller's stream (inputs ready); the caller's stream
+    // then waits for the setup
+    if ((rc = hip_check(ctx, hipEventRecord(ctx->bev[S], s0), "event")) != IBIP_OK) return rc;
+    if ((rc = hip_check(ctx, hipStreamWaitEvent(ctx->cap_stream, ctx->bev[S], 0), "wait")) != IBIP_OK) return rc;
+    if ((rc = hip_check(ctx, hipGraphLaunch(ctx->batch_exec, ctx->cap_stream), "setup graph launch")) != IBIP_OK)
+        return rc;
+    if ((rc = hip_check(ctx, hipEventRecord(ctx->cap_ev[1], ctx->cap_stream), "event")) != IBIP_OK) return rc;
+    if ((rc = hip_check(ctx, hipStreamWaitEvent(s0, ctx->cap_ev[1], 0), "wait")) != IBIP_OK) return rc;
+    // the batch streams' later work (post-processing, continued loops) follows the setup
+    for (int i = 0; i < S; i++)
+        if ((rc = hip_check(ctx, hipStreamWaitEvent(ctx->bstream[i], ctx->cap_ev[1], 0), "wait")) != IBIP_OK)
+            return rc;
     // join, then one launch runs every job's step loop. Each job's workgroup
     // writes a completion record to host memory when its loop ends, and the
     // host starts that job's post-processing on the batch streams while the
@@ -1735,10 +1793,6 @@ ibip_status run_invade_batch(ibip_ctx* ctx, ibip_job* jobs, int32_t nj) {
         hipEvent_t e = nullptr;
         if ((rc = hip_check(ctx, hipEventCreateWithFlags(&e, hipEventDisableTiming), "event")) != IBIP_OK) return rc;
         ctx->job_ev.push_back(e);
-    }
-    for (int i = 0; i < S; i++) {
-        if ((rc = hip_check(ctx, hipEventRecord(ctx->bev[i], ctx->bstream[i]), "event")) != IBIP_OK) return rc;
-        if ((rc = hip_check(ctx, hipStreamWaitEvent(s0, ctx->bev[i], 0), "wait")) != IBIP_OK) return rc;
     }
     Timer& tm = ctx->timer;
     if ((rc = hip_check(ctx, hipMemcpyAsync(d_args, h_args, sizeof(LoopArgs) * nj, hipMemcpyHostToDevice, s0),

@@ -191,3 +191,40 @@ def test_tuning_rejects_unknown_tile_widths(dev):
     assert ibip.get_tuning() == {"edt_tile_y": 64, "edt_tile_x": 16, "batch_wide": 5}
     ibip.set_tuning(None)
     assert ibip.get_tuning() == {"edt_tile_y": 0, "edt_tile_x": 0, "batch_wide": 0}
+
+
+def test_setup_graph_replays(dev):
+    """The batch's setup is captured into a graph for its buffers and
+    replayed while the same batch comes back: A twice (a capture, then a
+    replay), a single-image call, B twice, three rounds, every result equal
+    to the single runs; then new contents in A's input buffers, which a
+    capture and a replay of A must both read."""
+    imgs_a, inls_a = _jobs(11, 9)
+    imgs_b, inls_b = _jobs(12, 5)
+    da = [_d(a, dev) for a in imgs_a]
+    ia = [_d(a, dev) for a in inls_a]
+    db = [_d(a, dev) for a in imgs_b]
+    ib = [_d(a, dev) for a in inls_b]
+    want_a = [ibip.invade(x, y) for x, y in zip(da, ia)]
+    want_b = [ibip.invade(x, y) for x, y in zip(db, ib)]
+
+    def check(out, want):
+        for b, s in zip(out, want):
+            assert b["status"] == 0 and b["K"] == s["K"]
+            assert torch.equal(b["seq"], s["seq"]) and torch.equal(b["rad2"], s["rad2"])
+            assert torch.equal(b["centre_step"], s["centre_step"]) and torch.equal(b["M"], s["M"])
+
+    for rnd in range(3):
+        check(ibip.invade_batch(da, ia), want_a)  # a capture
+        check(ibip.invade_batch(da, ia), want_a)  # a replay
+        ibip.invade(da[0], ia[0])
+        torch.cuda.synchronize()
+        check(ibip.invade_batch(db, ib), want_b)
+        check(ibip.invade_batch(db, ib), want_b)
+    # the same buffers with new contents: the replay reads them
+    flip = [torch.from_numpy(np.flip(a, axis=-1).copy()).to(dev) for a in imgs_a]
+    for x, y in zip(da, flip):
+        x.copy_(y)
+    want_f = [ibip.invade(x, y) for x, y in zip(da, ia)]
+    check(ibip.invade_batch(da, ia), want_f)
+    check(ibip.invade_batch(da, ia), want_f)
