@@ -190,6 +190,31 @@ ibip_status ibip_invade(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inle
                         int32_t* centre_step, int64_t* n_steps);
 
 /*
+ * ibip_invade_resume -- continue an invasion from a checkpoint taken at a
+ * step boundary (Section 2.1; the sequence image holds the whole history of
+ * the invasion, Section 2.2.1). A call of ibip_invade with max_steps = k_done
+ * that returned K = k_done leaves, in its centre_step output, the step at
+ * which every voxel was a centre; that map and k_done are the checkpoint.
+ * The candidates of step k_done + 1 are rebuilt from it (every pore voxel that
+ * is a seed of the inlets, a centre, or a face neighbour of a centre, minus
+ * the centres), and the loop continues from there. The outputs cover the
+ * whole invasion (steps 1..K) and equal those of one uninterrupted
+ * ibip_invade on the same inputs and readings; ibip_get_steps then returns
+ * all K steps.
+ * centre_step_in: int32 DEVICE in, the checkpoint (values 0..k_done); it must
+ *                 not be the same buffer as centre_step.
+ * k_done:         steps taken before the checkpoint (>= 0; 0 = a fresh start).
+ * opts:           as for ibip_invade; max_steps counts every step from step 1
+ *                 and must be 0 or at least k_done.
+ * Other arguments and outputs as for ibip_invade.
+ * Errors: as ibip_invade, and EINVAL for a checkpoint with a value outside
+ * 0..k_done or a centre on solid.
+ */
+ibip_status ibip_invade_resume(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlets, ibip_dims dims,
+                               const ibip_invade_opts* opts, const int32_t* centre_step_in, int64_t k_done,
+                               int32_t* seq, uint32_t* rad2, int32_t* centre_step, int64_t* n_steps);
+
+/*
  * ibip_invade_batch -- ibip_invade (Section 2.1) over many images of uneven
  * size in one call, with the same results as one ibip_invade per image.
  * Each job names its own device buffers, dims and step limit; per-job setup

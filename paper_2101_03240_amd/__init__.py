@@ -22,7 +22,7 @@ import ctypes
 import os
 import threading
 
-__all__ = ["edt", "edt_noalloc", "invade", "invade_batch", "set_tuning", "get_tuning", "Server", "trap", "saturation", "remap_steps", "compare_opening", "opening_drainage",
+__all__ = ["edt", "edt_noalloc", "invade", "invade_resume", "invade_batch", "set_tuning", "get_tuning", "Server", "trap", "saturation", "remap_steps", "compare_opening", "opening_drainage",
            "IbipError", "library_path", "load_library", "enable_timing", "get_timing", "reset_timing",
            "probe_claim_latency"]
 
@@ -113,6 +113,9 @@ def load_library():
         lib.ibip_edt_noalloc.argtypes = [P, P, _Dims, P, P]
         lib.ibip_edt_noalloc.restype = i32
         lib.ibip_invade.argtypes = [P, P, P, _Dims, ctypes.POINTER(_InvadeOpts), P, P, P, ctypes.POINTER(i64)]
+        lib.ibip_invade_resume.argtypes = [P, P, P, _Dims, ctypes.POINTER(_InvadeOpts), P, i64, P, P, P,
+                                           ctypes.POINTER(i64)]
+        lib.ibip_invade_resume.restype = i32
         lib.ibip_get_steps.argtypes = [P, P, P, P, P, i64]
         lib.ibip_trap.argtypes = [P, P, P, _Dims, P, P, ctypes.POINTER(i64)]
         lib.ibip_opening_drainage.argtypes = [P, P, P, _Dims, P, i32, P, P]
@@ -297,9 +300,21 @@ def edt_noalloc(image, out=None, solid_flag=None):
     return out, solid_flag
 
 
+def invade_resume(image, inlets, checkpoint, k_done: int, **kw):
+    """Continue an invasion from a checkpoint (ibip_invade_resume):
+    ``checkpoint`` is the ``centre_step`` of an ``invade(..., max_steps=k_done)``
+    on the same inputs that returned K = k_done. Takes the keyword arguments
+    of ``invade`` (``max_steps`` counts from step 1) and returns the same
+    dict, over the whole invasion."""
+    ck = _dev_i32(checkpoint, "checkpoint")
+    if ck.numel() != image.numel():
+        raise ValueError("the checkpoint must have the image's shape")
+    return invade(image, inlets, _resume=(ck, int(k_done)), **kw)
+
+
 def invade(image, inlets, max_steps: int = 0, sigma: float = 1.0, theta_rad: float = 0.0,
            voxel_size: float = 1.0, rad2: bool = True, centre_step: bool = True, steps: bool = True,
-           integer_ball: bool = False, mask_inlets: bool = False):
+           integer_ball: bool = False, mask_inlets: bool = False, _resume=None):
     """The invasion loop of Section 2.1 with the per-step arrays of Sections
     2.2.1-2.2.2. Returns a dict with ``seq`` (int32: -1 solid, 0 uninvaded,
     k = step), ``rad2``, ``centre_step``, ``K`` and, when ``steps``, the
@@ -322,9 +337,15 @@ def invade(image, inlets, max_steps: int = 0, sigma: float = 1.0, theta_rad: flo
     cs = torch.empty(image.shape, dtype=torch.int32, device=dev) if centre_step else None
     opts = _InvadeOpts(int(max_steps), float(sigma), float(theta_rad), float(voxel_size))
     K = ctypes.c_int64(0)
-    _check(lib.ibip_invade(ctx, _ptr(image), _ptr(inlets), dims, ctypes.byref(opts), _ptr(seq),
-                           _ptr(r2) if r2 is not None else None, _ptr(cs) if cs is not None else None,
-                           ctypes.byref(K)), ctx)
+    if _resume is None:
+        _check(lib.ibip_invade(ctx, _ptr(image), _ptr(inlets), dims, ctypes.byref(opts), _ptr(seq),
+                               _ptr(r2) if r2 is not None else None, _ptr(cs) if cs is not None else None,
+                               ctypes.byref(K)), ctx)
+    else:
+        cs_in, k_done = _resume
+        _check(lib.ibip_invade_resume(ctx, _ptr(image), _ptr(inlets), dims, ctypes.byref(opts), _ptr(cs_in),
+                                      int(k_done), _ptr(seq), _ptr(r2) if r2 is not None else None,
+                                      _ptr(cs) if cs is not None else None, ctypes.byref(K)), ctx)
     out = {"seq": seq, "rad2": r2, "centre_step": cs, "K": int(K.value)}
     if steps:
         k = max(int(K.value), 1)

@@ -388,6 +388,24 @@ ibip_status ibip_invade(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inle
     return run_invade(ctx, image, inlets, dims, opts, seq, rad2, centre_step, n_steps);
 }
 
+ibip_status ibip_invade_resume(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlets, ibip_dims dims,
+                               const ibip_invade_opts* opts, const int32_t* centre_step_in, int64_t k_done,
+                               int32_t* seq, uint32_t* rad2, int32_t* centre_step, int64_t* n_steps) {
+    if (!ctx) return IBIP_EINVAL;
+    if (!image || !inlets || !seq || !centre_step_in) return fail(ctx, IBIP_EINVAL, "invade_resume: null pointer");
+    if (!dims_ok(dims)) return fail(ctx, IBIP_EINVAL, "invade_resume: bad dims");
+    if (k_done < 0) return fail(ctx, IBIP_EINVAL, "invade_resume: k_done < 0");
+    if (centre_step == centre_step_in)
+        return fail(ctx, IBIP_EINVAL, "invade_resume: centre_step must not be the checkpoint's buffer");
+    if (opts && opts->max_steps < 0) return fail(ctx, IBIP_EINVAL, "invade_resume: max_steps < 0");
+    if (opts && opts->max_steps > 0 && opts->max_steps < k_done)
+        return fail(ctx, IBIP_EINVAL, "invade_resume: max_steps below the steps already done");
+    if (opts && (opts->voxel_size < 0.0)) return fail(ctx, IBIP_EINVAL, "invade_resume: voxel_size < 0");
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return fail(ctx, IBIP_EDEVICE, "invade_resume: cannot select device");
+    return run_invade(ctx, image, inlets, dims, opts, seq, rad2, centre_step, n_steps, centre_step_in, k_done);
+}
+
 ibip_status ibip_invade_batch(ibip_ctx* ctx, ibip_job* jobs, int32_t n) {
     if (!ctx) return IBIP_EINVAL;
     if (n < 0 || (n > 0 && !jobs)) return fail(ctx, IBIP_EINVAL, "invade_batch: bad job list");

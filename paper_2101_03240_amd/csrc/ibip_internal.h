@@ -192,7 +192,7 @@ struct LoopState {
     uint32_t err;
     uint32_t big_k;    // step number of the pending wide step
     uint32_t popped;   // centres of the steps the loop kernels ran (wide steps not included)
-    uint32_t pad2;
+    uint32_t pad2;     // resumption: set when the checkpoint is not a valid one
     int64_t max_steps;
 };
 
@@ -314,9 +314,10 @@ hipError_t launch_scan_u32(uint32_t* data, int64_t n, uint32_t* partials, uint32
 ibip_status reconstruct(ibip_ctx* ctx, const int32_t* seq, const uint32_t* cap32, bool conn26, ibip_dims d,
                         uint32_t* w, int* n_iter);
 
+// resume_cs / k_done: a checkpoint (the centres of steps 1..k_done) to resume from, or null
 ibip_status run_invade(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlets, ibip_dims d,
                        const ibip_invade_opts* opts, int32_t* seq, uint32_t* rad2, int32_t* centre_step,
-                       int64_t* n_steps);
+                       int64_t* n_steps, const int32_t* resume_cs = nullptr, int64_t k_done = 0);
 ibip_status run_invade_batch(ibip_ctx* ctx, ibip_job* jobs, int32_t n);
 
 // ---- one job of the batch / server paths (invade.hip) ----

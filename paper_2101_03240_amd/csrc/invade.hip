@@ -238,6 +238,51 @@ __global__ __launch_bounds__(256) void k_seed(const uint8_t* __restrict__ inlets
     }
 }
 
+// Resumption from a checkpoint (ibip_invade_resume): cs_in holds the step at
+// which each voxel was a centre in steps 1..k_done (0 if it was not). Every
+// pore voxel that was a centre, a seed of Q0 or a face neighbour of a centre
+// has been claimed; the claimed voxels that were not centres are the
+// candidates of step k_done + 1 and go into the slices of their ranks (the
+// order inside a slice never matters); the maximum of each earlier step is
+// the rank of its centres. A value outside 0..k_done, or a centre on solid,
+// sets *bad.
+__global__ __launch_bounds__(256) void k_resume_seed(const uint8_t* __restrict__ inlets,
+                                                     const int32_t* __restrict__ cs_in, int64_t k_done, uint32_t* key,
+                                                     int32_t* state, uint32_t* M, int X, int Y, int Z, uint32_t* tail,
+                                                     uint32_t* bucket, bool mask, uint32_t* bad) {
+    const int64_t n = (int64_t)X * Y * Z;
+    const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const bool in = v < n;
+    const uint32_t kv = in ? key[v] : 0u;
+    const uint32_t rk = kv & kRankMask;
+    const bool pore = rk != 0;
+    const int32_t c = in ? cs_in[v] : 0;
+    if (in) {
+        state[v] = c;
+        if (c < 0 || (int64_t)c > k_done || (c > 0 && !pore)) atomicOr(bad, 1u);
+    }
+    const bool popped = pore && c > 0 && (int64_t)c <= k_done;
+    bool seed = false, touched = false;
+    if (pore) {
+        const int64_t yz = (int64_t)Y * Z;
+        const int z = (int)(v % Z), y = (int)((v / Z) % Y), x = (int)(v / yz);
+        seed = inlets[v] != 0;  // v itself is pore
+        const bool inb[6] = {x > 0, x < X - 1, y > 0, y < Y - 1, z > 0, z < Z - 1};
+        const int64_t off[6] = {-yz, yz, -(int64_t)Z, (int64_t)Z, -1, 1};
+#pragma unroll
+        for (int j = 0; j < 6; j++) {
+            if (!inb[j]) continue;
+            const int64_t u = v + off[j];
+            seed |= inlets[u] != 0 && (!mask || (key[u] & kRankMask) != 0);
+            touched |= cs_in[u] > 0;
+        }
+    }
+    const bool claimed = popped || seed || touched;
+    if (claimed) key[v] = kv | kClaim;
+    if (popped) M[c - 1] = rk;  // every centre of a step holds the step's rank
+    push_global(claimed && !popped, (uint32_t)v, rk, tail, bucket);
+}
+
 // ---------------------------------------------------------------------------
 // The step loop: one workgroup.
 // ---------------------------------------------------------------------------
@@ -1306,7 +1351,7 @@ hipError_t launch_finalise(int32_t* seq, int32_t* state, int64_t n, const uint32
 // ---------------------------------------------------------------------------
 ibip_status run_invade(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlets, ibip_dims d,
                        const ibip_invade_opts* opts, int32_t* seq, uint32_t* rad2, int32_t* centre_step,
-                       int64_t* n_steps) {
+                       int64_t* n_steps, const int32_t* resume_cs, int64_t k_done) {
     hipStream_t s = ctx->stream;
     const int64_t n = nvox(d);
     const int64_t V = (int64_t)(d.X - 1) * (d.X - 1) + (int64_t)(d.Y - 1) * (d.Y - 1) +
@@ -1368,11 +1413,17 @@ ibip_status run_invade(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlet
     hipLaunchKernelGGL(k_rank_tables, dim3(blocks(V)), dim3(256), 0, s, hist, present, flags, V, val, off, head, tail);
     hipLaunchKernelGGL(k_convert, dim3(blocks(n)), dim3(256), 0, s, image, key, present, n, (uint32_t)(V - 1), state,
                        seq, d.X, d.Y, d.Z, make_fastdiv((uint32_t)d.Z), make_fastdiv((uint32_t)d.Y));
-    hipLaunchKernelGGL(k_seed, dim3(blocks(n)), dim3(256), 0, s, inlets, key, d.X, d.Y, d.Z, tail, bucket,
-                       (ctx->readings & IBIP_READ_MASK_INLETS) != 0);
+    if (resume_cs) {
+        if (k_done > n_pore) return fail(ctx, IBIP_EINVAL, "invade_resume: more steps done than pore voxels");
+        hipLaunchKernelGGL(k_resume_seed, dim3(blocks(n)), dim3(256), 0, s, inlets, resume_cs, k_done, key, state, M,
+                           d.X, d.Y, d.Z, tail, bucket, (ctx->readings & IBIP_READ_MASK_INLETS) != 0, &st->pad2);
+    } else {
+        hipLaunchKernelGGL(k_seed, dim3(blocks(n)), dim3(256), 0, s, inlets, key, d.X, d.Y, d.Z, tail, bucket,
+                           (ctx->readings & IBIP_READ_MASK_INLETS) != 0);
+    }
     tm.mark(2, s);
     // loop control
-    h_st->k = 1;
+    h_st->k = 1 + (uint32_t)(resume_cs ? k_done : 0);
     h_st->status = LS_RUN;
     h_st->max_steps = opts ? opts->max_steps : 0;
     {
@@ -1384,7 +1435,13 @@ ibip_status run_invade(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlet
         if ((rc = hip_check(ctx, hipMemcpyAsync(&st->max_steps, &init.max_steps, sizeof(int64_t),
                                                 hipMemcpyHostToDevice, s), "copy")) != IBIP_OK)
             return rc;
+        if (resume_cs &&
+            (rc = hip_check(ctx, hipMemcpyAsync(&h_st->pad2, &st->pad2, sizeof(uint32_t), hipMemcpyDeviceToHost, s),
+                            "copy")) != IBIP_OK)
+            return rc;
         if ((rc = hip_check(ctx, hipStreamSynchronize(s), "sync")) != IBIP_OK) return rc;
+        if (resume_cs && h_st->pad2)
+            return fail(ctx, IBIP_EINVAL, "invade_resume: the checkpoint has a step outside 1..k_done or a centre on solid");
     }
     LoopArgs la{st,     head, tail, val, bucket, state, key, M, d.X, d.Y, d.Z, kWideRound, kSmallRound,
                 make_fastdiv((uint32_t)d.Z), make_fastdiv((uint32_t)d.Y)};
