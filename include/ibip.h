@@ -281,8 +281,11 @@ ibip_status ibip_server_poll(ibip_server* s, int64_t ticket, int32_t* done);
    its latency into *latency_ms (either may be NULL), then forget the ticket.
    Returns the job's status. */
 ibip_status ibip_server_wait(ibip_server* s, int64_t ticket, ibip_job* result, double* latency_ms);
-/* Cancel a job that has not started (its status becomes ECANCELLED); EINVAL
-   if it is running, done or unknown. */
+/* Cancel a job. A pending job is dropped at once; a running one stops at the
+   next check of its step loop (every 1024 steps, and between its loop
+   segments) and nothing more is queued for it. Its status becomes ECANCELLED
+   (its outputs are unspecified) unless it had finished before the request
+   took effect. EINVAL if the job is done or unknown. */
 ibip_status ibip_server_cancel(ibip_server* s, int64_t ticket);
 ibip_status ibip_server_stats_get(ibip_server* s, ibip_server_stats* out);
 /* Launch parameters of the jobs admitted from now on (ibip_tuning:

@@ -196,7 +196,7 @@ struct LoopState {
     int64_t max_steps;
 };
 
-enum LoopStatus : uint32_t { LS_RUN = 0, LS_DONE = 1, LS_WIDE = 2, LS_MAXSTEPS = 3 };
+enum LoopStatus : uint32_t { LS_RUN = 0, LS_DONE = 1, LS_WIDE = 2, LS_MAXSTEPS = 3, LS_CANCEL = 4 };
 
 }  // namespace ibip
 
@@ -365,6 +365,9 @@ hipError_t job_post_devk(const JobBufs& j, LoopState* st, ibip_dims d, int32_t* 
 size_t loop_args_bytes();
 // fills `out` (loop_args_bytes() of host memory) with the loop arguments of a job
 void fill_loop_args(void* out, const JobBufs& j, LoopState* st, ibip_dims d, uint32_t wide);
+// the loop of `args` stops with LS_CANCEL when *flag (device-visible host
+// memory) is nonzero at one of its checks (every 1024 steps)
+void set_loop_cancel(void* args, const uint32_t* flag);
 // the step-count threshold above which a batch or served job's step runs over
 // the whole GPU, from a tuning value (0: kWideRound; negative: never)
 uint32_t wide_threshold(int64_t tuned);

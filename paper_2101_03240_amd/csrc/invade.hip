@@ -301,7 +301,15 @@ struct LoopArgs {
     FastDiv divZ, divY;
     // a batch job's completion record in host memory (done, k, err), or null
     uint32_t* done = nullptr;
+    // a served job's cancel flag in host memory, read every 1024 steps, or null
+    const uint32_t* cancel = nullptr;
 };
+
+// true when the job's cancel flag is set (wave-uniform)
+__device__ inline bool cancel_requested(const LoopArgs& a) {
+    return a.cancel && __builtin_amdgcn_readfirstlane(
+                           __hip_atomic_load(a.cancel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) != 0u;
+}
 
 constexpr int kLoopThreads = 1024;
 constexpr int kBitWords = (kMaxRanks >> 5) + 2;
@@ -707,7 +715,8 @@ __device__ inline void loop_body(const LoopArgs& a, LoopShared& s) {
     for (;;) {
         if (wave0) {
             for (;;) {
-                if (r == 0 || k > klim) {
+                const bool cancelled = r != 0 && k <= klim && (k & 1023u) == 0 && cancel_requested(a);
+                if (r == 0 || k > klim || cancelled) {
                     if (r == 0) {
                         a.st->status = LS_DONE;
                     } else if (k > n_pore) {
@@ -715,6 +724,8 @@ __device__ inline void loop_body(const LoopArgs& a, LoopShared& s) {
                         // instead of looping
                         a.st->err = 1;
                         a.st->status = LS_DONE;
+                    } else if (cancelled) {
+                        a.st->status = LS_CANCEL;
                     } else {
                         a.st->status = LS_MAXSTEPS;
                     }
@@ -773,7 +784,9 @@ __device__ inline void loop_body(const LoopArgs& a, LoopShared& s) {
                         prev_r = r;
                         r = rn;
                         k = k + 1;
-                        if (!direct || k > klim) break;
+                        // (a job that can be cancelled returns to the check above
+                        // every 1024 steps)
+                        if (!direct || k > klim || (a.cancel && (k & 1023u) == 0)) break;
                         const uint32_t hh = uni(s.head[r]);
                         tt = uni(s.tail[r]);
                         c1 = tt - hh;
@@ -1738,6 +1751,8 @@ hipError_t launch_wide_and_loop_host(const void* host_args, int64_t n, hipStream
 }
 
 size_t loop_args_bytes() { return sizeof(LoopArgs); }
+
+void set_loop_cancel(void* args, const uint32_t* flag) { ((LoopArgs*)args)->cancel = flag; }
 
 void fill_loop_args(void* out, const JobBufs& j, LoopState* st, ibip_dims d, uint32_t wide) {
     *(LoopArgs*)out = job_loop_args(j, st, d, wide);

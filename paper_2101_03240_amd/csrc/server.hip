@@ -73,6 +73,7 @@ struct Job {
     size_t bytes = 0, off = 0;
     int slot = -1;
     int state = J_PENDING;
+    bool cancel = false;  // cancellation requested while it ran
     Clock::time_point t_submit, t_done;
 };
 
@@ -86,6 +87,8 @@ struct Slot {
     int64_t ticket = -1;
     bool broken = false;            // its stream failed; no job is admitted to it again
     int phase = 0;                  // 1: the job's step loop, 2: its post-processing
+    uint32_t* cancel_host = nullptr;  // coherent pinned word the job's loop reads every 1024 steps
+    uint32_t* cancel_dev = nullptr;   // its device address
 };
 
 }  // namespace
@@ -129,6 +132,8 @@ bool start_job(ibip_server* S, int64_t t, int si) {
     // a step with more centres than the threshold stops the loop; the worker
     // then runs that step over the whole GPU and resumes the loop (advance())
     fill_loop_args(sl.host_small + 512, b, st, jb.dims, wide_threshold(S->tuning.batch_wide));
+    __atomic_store_n(sl.cancel_host, 0u, __ATOMIC_RELEASE);
+    set_loop_cancel(sl.host_small + 512, sl.cancel_dev);
     if (e == hipSuccess)
         e = hipMemcpyAsync(dargs, sl.host_small + 512, loop_args_bytes(), hipMemcpyHostToDevice, sl.stream);
     if (e == hipSuccess) e = launch_loop_jobs(dargs, 1, sl.stream);
@@ -165,6 +170,7 @@ bool advance(ibip_server* S, int si, hipError_t* e) {
     Job& J = S->jobs[sl.ticket];
     const ibip_job& jb = J.job;
     const LoopState* hs = (const LoopState*)sl.host_small;
+    if (J.cancel || hs->status == LS_CANCEL) return false;  // finish_job reports the cancellation
     LoopState* st = (LoopState*)sl.dev_small;
     hipError_t r = hipSuccess;
     if (hs->status == LS_WIDE && hs->err == 0) {
@@ -194,7 +200,9 @@ void finish_job(ibip_server* S, int si, hipError_t e) {
     const LoopState* hs = (const LoopState*)sl.host_small;
     J.job.status = IBIP_OK;
     J.job.n_steps = 0;
+    const bool cancelled = sl.phase == 1 && (J.cancel || hs->status == LS_CANCEL);
     if (e != hipSuccess) J.job.status = IBIP_EDEVICE;
+    else if (cancelled) J.job.status = IBIP_ECANCELLED;
     else if (hs->err == 2) J.job.status = IBIP_ENOSOLID;
     else if (hs->err == 3) J.job.status = IBIP_ECAPACITY;
     else if (hs->err) J.job.status = IBIP_EDEVICE;
@@ -205,6 +213,7 @@ void finish_job(ibip_server* S, int si, hipError_t e) {
     S->stats.bytes_in_use -= (int64_t)J.bytes;
     S->stats.running--;
     S->stats.completed++;
+    if (cancelled && e == hipSuccess) S->stats.cancelled++;
     sl.ticket = -1;
 }
 
@@ -321,7 +330,9 @@ ibip_status ibip_server_create(ibip_server** out, int32_t device, const ibip_ser
         ok = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) == hipSuccess &&
              hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) == hipSuccess &&
              hipMalloc(&sl.dev_small, kSlotSmall) == hipSuccess &&
-             hipHostMalloc(&sl.host_small, kSlotSmall, hipHostMallocDefault) == hipSuccess;
+             hipHostMalloc(&sl.host_small, kSlotSmall, hipHostMallocDefault) == hipSuccess &&
+             hipHostMalloc((void**)&sl.cancel_host, 64, hipHostMallocCoherent | hipHostMallocMapped) == hipSuccess &&
+             hipHostGetDevicePointer((void**)&sl.cancel_dev, sl.cancel_host, 0) == hipSuccess;
     }
     if (prev >= 0) (void)hipSetDevice(prev);
     if (!ok) {
@@ -331,6 +342,7 @@ ibip_status ibip_server_create(ibip_server** out, int32_t device, const ibip_ser
             if (sl.done) (void)hipEventDestroy(sl.done);
             if (sl.dev_small) (void)hipFree(sl.dev_small);
             if (sl.host_small) (void)hipHostFree(sl.host_small);
+            if (sl.cancel_host) (void)hipHostFree(sl.cancel_host);
         }
         if (S->pool_base) (void)hipFree(S->pool_base);
         delete S;
@@ -397,8 +409,16 @@ ibip_status ibip_server_cancel(ibip_server* S, int64_t ticket) {
     if (!S) return IBIP_EINVAL;
     std::lock_guard<std::mutex> g(S->mu);
     auto it = S->jobs.find(ticket);
+    if (it != S->jobs.end() && it->second.state == J_RUNNING) {
+        // a running job: its loop stops at its next check (every 1024 steps)
+        // and the worker queues nothing more for it
+        Job& J = it->second;
+        J.cancel = true;
+        __atomic_store_n(S->slots[J.slot].cancel_host, 1u, __ATOMIC_RELEASE);
+        return IBIP_OK;
+    }
     if (it == S->jobs.end() || it->second.state != J_PENDING) {
-        set_err(S, "server_cancel: the job is not pending");
+        set_err(S, "server_cancel: the job is done or unknown");
         return IBIP_EINVAL;
     }
     for (auto p = S->pending.begin(); p != S->pending.end(); ++p)
@@ -460,6 +480,7 @@ ibip_status ibip_server_destroy(ibip_server* S) {
         (void)hipEventDestroy(sl.done);
         (void)hipFree(sl.dev_small);
         (void)hipHostFree(sl.host_small);
+        (void)hipHostFree(sl.cancel_host);
     }
     (void)hipFree(S->pool_base);
     if (prev >= 0) (void)hipSetDevice(prev);

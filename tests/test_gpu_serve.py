@@ -152,3 +152,32 @@ def test_continued_wide_steps_in_the_mix(dev, wide):
         np.testing.assert_array_equal(r["seq"].cpu().numpy(), o["seq"])
         np.testing.assert_array_equal(r["rad2"].cpu().numpy().view(np.uint32), o["rad2"])
         np.testing.assert_array_equal(r["M"].cpu().numpy().view(np.uint32), o["M"])
+
+
+@pytest.mark.parametrize("wide", [0, 500])
+def test_cancel_running_job(dev, wide):
+    """A running job is stopped at its loop's next check (every 1024 steps) or
+    between its loop segments (wide=500: many segments) and reports
+    ECANCELLED; the server keeps running the other jobs, whose results equal
+    the same jobs alone, and the pool is returned."""
+    import time
+    big = synth.blurred_noise((256, 256, 256), sigma=6.0, porosity=0.55, seed=77)
+    small = [synth.blurred_noise((40, 44, 48), sigma=3.0, porosity=0.6, seed=80 + i) for i in range(3)]
+    with ibip.Server(dev, hbm_budget_bytes=4 << 30, max_inflight=4) as srv:
+        if wide:
+            srv.set_tuning({"batch_wide": wide})
+        tb = srv.submit(_d(big, dev), _d(synth.face_mask(big.shape, 0, 0), dev))
+        t0 = time.time()
+        while srv.stats()["running"] < 1 and time.time() - t0 < 30:
+            time.sleep(0.001)
+        assert srv.cancel(tb)
+        ts = [srv.submit(_d(a, dev), _d(synth.face_mask(a.shape, 0, 0), dev)) for a in small]
+        rb = srv.wait(tb)
+        rs = [srv.wait(t) for t in ts]
+        st = srv.stats()
+    assert rb["status"] == -6
+    assert st["cancelled"] == 1 and st["bytes_in_use"] == 0 and st["running"] == 0
+    for a, r in zip(small, rs):
+        s = ibip.invade(_d(a, dev), _d(synth.face_mask(a.shape, 0, 0), dev))
+        assert r["status"] == 0
+        _same(r, s)
