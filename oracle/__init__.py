@@ -46,13 +46,24 @@ def build(force: bool = True) -> str:
     return _LIB_PATH
 
 
+def build_sanitized(path: str) -> str:
+    """Compile the same source with AddressSanitizer and UndefinedBehaviour-
+    Sanitizer into `path` (loaded through IBIP_ORACLE_LIB with libasan
+    preloaded; used by the tests only)."""
+    subprocess.run(["gcc", "-O1", "-g", "-std=c99", "-fPIC", "-shared", "-Wall", "-fno-omit-frame-pointer",
+                    "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-o", path, _SRC, "-lm"],
+                   check=True)
+    return path
+
+
 def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB_PATH):
+    path = os.environ.get("IBIP_ORACLE_LIB") or _LIB_PATH
+    if path == _LIB_PATH and not os.path.exists(_LIB_PATH):
         build(force=True)
-    lib = ctypes.CDLL(_LIB_PATH)
+    lib = ctypes.CDLL(path)
     P = ctypes.c_void_p
     i32, i64, d = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     lib.ibipref_edt_brute.argtypes = [P, i32, i32, i32, P]
