@@ -268,7 +268,8 @@ def run_batch(args) -> int:
         "vs_baseline": None, "dtype": "u32", "data": "synthetic",
         "config": {"workload": "batch96", "description": WORKLOADS["batch96"], "images": len(imgs),
                    "voxels": n_vox, "invaded_voxels": invaded, "parallelism": "single GPU",
-                   "tuning": tuning or {}},
+                   "tuning": tuning if tuning is not None else
+                   ibip.cached_tuning(max((a.shape for a in imgs), key=max), batch=True)},
         "batched_vs_plain": {"batched_ms": 1e3 * tb, "plain_ms": 1e3 * tp, "speedup": tp / tb,
                              "bit_exact": bool(exact), "plain_value": invaded / tp},
     }
@@ -371,7 +372,7 @@ def run_serve(args) -> int:
         "config": {"workload": "serve", "description": WORKLOADS["serve"], "requests": len(imgs),
                    "voxels": float(vox.sum()), "max_inflight": args.inflight, "hbm_budget_gb": args.serve_budget_gb,
                    "closed_loop_depth": args.depth, "parallelism": "single GPU",
-                   "tuning": json.loads(args.tuning) if args.tuning else {}},
+                   "tuning": srv.tuning},
         "serve": {"capacity_jobs_per_s": len(imgs) / wall_c, "capacity_voxels_per_s": vox.sum() / wall_c,
                   "closed_loop_p50_ms": float(np.percentile(lat_c, 50)),
                   "closed_loop_p99_ms": float(np.percentile(lat_c, 99)),

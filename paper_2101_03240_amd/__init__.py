@@ -22,7 +22,7 @@ import ctypes
 import os
 import threading
 
-__all__ = ["edt", "edt_noalloc", "invade", "invade_resume", "invade_batch", "set_tuning", "get_tuning", "Server", "trap", "saturation", "remap_steps", "compare_opening", "opening_drainage",
+__all__ = ["edt", "edt_noalloc", "invade", "invade_resume", "invade_batch", "set_tuning", "get_tuning", "cached_tuning", "Server", "trap", "saturation", "remap_steps", "compare_opening", "opening_drainage",
            "IbipError", "library_path", "load_library", "enable_timing", "get_timing", "reset_timing",
            "probe_claim_latency"]
 
@@ -194,6 +194,13 @@ def _auto_tuning(shape, batch: bool = False) -> dict | None:
     if batch and "batch" in doc:
         t["batch_wide"] = int(doc["batch"]["batch_wide"])
     return t or None
+
+
+def cached_tuning(shape, batch: bool = False) -> dict:
+    """The launch parameters the autotuner's cache holds for an image of
+    `shape` on the current GPU (with `batch`, also the batch's wide-step
+    threshold); empty when there is no cache for this GPU."""
+    return _auto_tuning(tuple(shape), batch=batch) or {}
 
 
 def _apply_auto(ctx, shape):
@@ -464,6 +471,7 @@ class Server:
         if st != 0:
             raise IbipError(st, "cannot create the server")
         self._live = {}
+        self.tuning = {}  # the launch parameters last set (empty: the library's defaults)
         doc = _tuning_doc()
         if doc is not None and "serve" in doc:
             t = dict(doc.get("edt", {}).get("large", {}))
@@ -509,6 +517,7 @@ class Server:
         st = self._lib.ibip_server_set_tuning(self._h, ctypes.byref(t))
         if st != 0:
             raise IbipError(st, "bad tuning")
+        self.tuning = dict(tuning or {})
 
     def done(self, ticket: int) -> bool:
         d = ctypes.c_int32(0)

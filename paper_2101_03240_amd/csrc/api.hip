@@ -143,20 +143,6 @@ ibip_status batch_streams(ibip_ctx* ctx) {
     return IBIP_OK;
 }
 
-ibip_status batch_graph(ibip_ctx* ctx) {
-    if (ctx->have_cap) return IBIP_OK;
-    if (hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess)
-        return fail(ctx, IBIP_EDEVICE, "cannot create the capture stream");
-    for (auto& e : ctx->cap_ev)
-        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
-            return fail(ctx, IBIP_EDEVICE, "cannot create capture events");
-    for (auto& e : ctx->cap_join)
-        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
-            return fail(ctx, IBIP_EDEVICE, "cannot create capture events");
-    ctx->have_cap = true;
-    return IBIP_OK;
-}
-
 bool dims_ok(ibip_dims d) {
     if (d.X <= 0 || d.Y <= 0 || d.Z <= 0) return false;
     if (d.X > 65535 || d.Y > 65535 || d.Z > 65535) return false;
@@ -244,12 +230,8 @@ ibip_status ibip_ctx_destroy(ibip_ctx* ctx) {
         for (auto& e : ctx->timer.ev) (void)hipEventDestroy(e);
     if (ctx->copy_ev) (void)hipEventDestroy(ctx->copy_ev);
     for (auto& e : ctx->job_ev) (void)hipEventDestroy(e);
-    if (ctx->batch_exec) (void)hipGraphExecDestroy(ctx->batch_exec);
-    if (ctx->have_cap) {
-        (void)hipStreamDestroy(ctx->cap_stream);
-        for (auto& e : ctx->cap_ev) (void)hipEventDestroy(e);
-        for (auto& e : ctx->cap_join) (void)hipEventDestroy(e);
-    }
+    for (auto& g : ctx->batch_exec)
+        if (g) (void)hipGraphExecDestroy(g);
     for (auto& b : ctx->buf)
         if (b.p) (void)hipFree(b.p);
     if (ctx->host_pinned) (void)hipHostFree(ctx->host_pinned);

@@ -229,14 +229,10 @@ struct ibip_ctx {
     ibip::Timer timer;
     hipStream_t bstream[ibip::kBatchStreams] = {};
     hipEvent_t bev[ibip::kBatchStreams + 1] = {};
-    // the batch's captured setup graph, the batch it was captured for, and
-    // the stream and events it is captured on and replayed with
-    hipStream_t cap_stream = nullptr;
-    hipEvent_t cap_ev[2] = {};
-    hipEvent_t cap_join[ibip::kBatchStreams] = {};
-    hipGraphExec_t batch_exec = nullptr;
+    // the batch's setup captured as one graph per batch stream, and the
+    // batch it was captured for
+    hipGraphExec_t batch_exec[ibip::kBatchStreams] = {};
     std::vector<uint64_t> batch_key;
-    bool have_cap = false;
     bool have_bstreams = false;
     ibip_timing timing = {};
     int device = 0;
@@ -376,12 +372,11 @@ uint32_t wide_threshold(int64_t tuned);
 // its next wide step or its end, stream-ordered on s. host_args: the job's
 // loop arguments (fill_loop_args); n: its voxel count.
 hipError_t launch_wide_and_loop_host(const void* host_args, int64_t n, hipStream_t s);
-// one workgroup per job, every step loop to completion
+// one workgroup per job, every step loop to completion (served jobs: each loop
+// checks its cancel flag)
 hipError_t launch_loop_jobs(const void* d_args, int32_t n, hipStream_t s);
 // create the batch streams and events once per context
 ibip_status batch_streams(ibip_ctx* ctx);
-// create the capture stream and events of the batch's setup graph once per context
-ibip_status batch_graph(ibip_ctx* ctx);
 ibip_status run_trap(ibip_ctx* ctx, const int32_t* seq, const uint8_t* outlets, ibip_dims d,
                      uint8_t* trapped, int32_t* seq_trapped, int64_t* n_steps_after);
 ibip_status run_mio(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlets, ibip_dims d,

@@ -673,6 +673,9 @@ __device__ inline uint32_t small_step(uint32_t cnt, uint32_t k, uint32_t r, uint
 // are exactly the previous step's pushes of that rank (the slice was either
 // popped empty by that step or empty before it), so they are read from the
 // LDS push log instead of global memory, if the log did not overflow.
+// kCancel: the loop checks the job's cancel flag every 1024 steps (served
+// jobs only; the check costs the other paths about 3 % of their loop time)
+template <bool kCancel>
 __device__ inline void loop_body(const LoopArgs& a, LoopShared& s) {
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -715,7 +718,7 @@ __device__ inline void loop_body(const LoopArgs& a, LoopShared& s) {
     for (;;) {
         if (wave0) {
             for (;;) {
-                const bool cancelled = r != 0 && k <= klim && (k & 1023u) == 0 && cancel_requested(a);
+                const bool cancelled = kCancel && r != 0 && k <= klim && (k & 1023u) == 0 && cancel_requested(a);
                 if (r == 0 || k > klim || cancelled) {
                     if (r == 0) {
                         a.st->status = LS_DONE;
@@ -786,7 +789,7 @@ __device__ inline void loop_body(const LoopArgs& a, LoopShared& s) {
                         k = k + 1;
                         // (a job that can be cancelled returns to the check above
                         // every 1024 steps)
-                        if (!direct || k > klim || (a.cancel && (k & 1023u) == 0)) break;
+                        if (!direct || k > klim || (kCancel && (k & 1023u) == 0)) break;
                         const uint32_t hh = uni(s.head[r]);
                         tt = uni(s.tail[r]);
                         c1 = tt - hh;
@@ -920,19 +923,21 @@ __device__ inline void loop_body(const LoopArgs& a, LoopShared& s) {
 
 // The host queues each launch before it knows whether the previous one
 // finished the loop: a launch after the end does nothing.
+template <bool kCancel>
 __global__ __launch_bounds__(kLoopThreads) void k_loop(LoopArgs a) {
     __shared__ LoopShared s;
     const uint32_t status = a.st->status;
     if (status != LS_RUN && status != LS_WIDE) return;
-    loop_body(a, s);
+    loop_body<kCancel>(a, s);
 }
 
 // Many images in one launch: workgroup j runs the whole step loop of job j
 // (jobs are ordered largest first, so the longest loops start first).
+template <bool kCancel>
 __global__ __launch_bounds__(kLoopThreads) void k_loop_batch(const LoopArgs* __restrict__ all) {
     __shared__ LoopShared s;
     const LoopArgs a = all[blockIdx.x];
-    loop_body(a, s);
+    loop_body<kCancel>(a, s);
 }
 
 // One step with many centres, spread over the whole GPU. Claims as in the
@@ -1475,7 +1480,7 @@ ibip_status run_invade(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlet
     int p = 0;
     bool wide_ran = false;  // the wide launch read this round ran a wide step
     tm.mark(loop_ev(p, 0), s);
-    hipLaunchKernelGGL(k_loop, dim3(1), dim3(kLoopThreads), 0, s, la);
+    hipLaunchKernelGGL(k_loop<false>, dim3(1), dim3(kLoopThreads), 0, s, la);
     tm.mark(loop_ev(p, 1), s);
     for (;;) {
         if ((rc = hip_check(ctx, hipGetLastError(), "loop launch")) != IBIP_OK) return rc;
@@ -1487,7 +1492,7 @@ ibip_status run_invade(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlet
         hipLaunchKernelGGL(k_wide, dim3(gw), dim3(256), 0, s, la);
         tm.mark(wide_ev(p, 1), s);
         tm.mark(loop_ev(p ^ 1, 0), s);
-        hipLaunchKernelGGL(k_loop, dim3(1), dim3(kLoopThreads), 0, s, la);
+        hipLaunchKernelGGL(k_loop<false>, dim3(1), dim3(kLoopThreads), 0, s, la);
         tm.mark(loop_ev(p ^ 1, 1), s);
         if ((rc = hip_check(ctx, hipGetLastError(), "wide launch")) != IBIP_OK) return rc;
         if ((rc = hip_check(ctx, hipEventSynchronize(ctx->copy_ev), "sync")) != IBIP_OK) return rc;
@@ -1720,7 +1725,7 @@ hipError_t job_post_devk(const JobBufs& j, LoopState* st, ibip_dims d, int32_t* 
 }
 
 hipError_t launch_loop_jobs(const void* d_args, int32_t n, hipStream_t s) {
-    hipLaunchKernelGGL(k_loop_batch, dim3((unsigned)n), dim3(kLoopThreads), 0, s, (const LoopArgs*)d_args);
+    hipLaunchKernelGGL(k_loop_batch<true>, dim3((unsigned)n), dim3(kLoopThreads), 0, s, (const LoopArgs*)d_args);
     return hipGetLastError();
 }
 
@@ -1736,18 +1741,20 @@ uint32_t wide_threshold(int64_t tuned) {
 }
 
 // The wide step a job's loop stopped at, over the whole GPU, then the job's
-// loop again in one workgroup (to its next wide step or its end), on s.
-hipError_t launch_wide_and_loop(const LoopArgs& la, int64_t n, hipStream_t s) {
+// loop again in one workgroup (to its next wide step or its end), on s; with
+// `cancellable` the loop checks the job's cancel flag.
+hipError_t launch_wide_and_loop(const LoopArgs& la, int64_t n, hipStream_t s, bool cancellable = false) {
     const unsigned gw = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096));
     hipLaunchKernelGGL(k_wide, dim3(gw), dim3(256), 0, s, la);
-    hipLaunchKernelGGL(k_loop, dim3(1), dim3(kLoopThreads), 0, s, la);
+    if (cancellable) hipLaunchKernelGGL(k_loop<true>, dim3(1), dim3(kLoopThreads), 0, s, la);
+    else hipLaunchKernelGGL(k_loop<false>, dim3(1), dim3(kLoopThreads), 0, s, la);
     return hipGetLastError();
 }
 
 hipError_t launch_wide_and_loop_host(const void* host_args, int64_t n, hipStream_t s) {
     LoopArgs la = *(const LoopArgs*)host_args;
     la.done = nullptr;
-    return launch_wide_and_loop(la, n, s);
+    return launch_wide_and_loop(la, n, s, true);
 }
 
 size_t loop_args_bytes() { return sizeof(LoopArgs); }
@@ -1796,9 +1803,11 @@ ibip_status run_invade_batch(ibip_ctx* ctx, ibip_job* jobs, int32_t nj) {
     std::vector<JobBufs> bufs(nj);
     const EdtTiles tiles = edt_tiles(ctx->tuning);
     // the per-job setup (EDT, histogram, ranks, slices, seeds) depends only on
-    // the jobs' buffers, dims and step limits and the arena: it is captured
-    // once into a graph (fork over the batch streams, join back) and replayed
-    // while the same batch comes back
+    // the jobs' buffers, dims and step limits and the arena: each batch
+    // stream's share of it is captured once into a graph of its own and
+    // replayed on that stream while the same batch comes back (one graph
+    // for the whole setup would replay its branches without the streams'
+    // concurrency)
     std::vector<uint64_t> key = {(uint64_t)nj, (uint64_t)(uintptr_t)arena, (uint64_t)tiles.y, (uint64_t)tiles.x};
     for (int32_t q = 0; q < nj; q++) {
         const ibip_job& jb = jobs[order[q]];
@@ -1809,51 +1818,46 @@ ibip_status run_invade_batch(ibip_ctx* ctx, ibip_job* jobs, int32_t nj) {
                                (uint64_t)(uintptr_t)jb.sat, (uint64_t)jb.max_steps, (uint64_t)jb.dims.X,
                                ((uint64_t)jb.dims.Y << 32) | (uint32_t)jb.dims.Z});
     }
-    if ((rc = batch_graph(ctx)) != IBIP_OK) return rc;
-    if (!ctx->batch_exec || ctx->batch_key != key) {
-        if (ctx->batch_exec) {
-            (void)hipGraphExecDestroy(ctx->batch_exec);
-            ctx->batch_exec = nullptr;
-            ctx->batch_key.clear();
-        }
-        hipStream_t cs = ctx->cap_stream;
-        if ((rc = hip_check(ctx, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "begin capture")) !=
-            IBIP_OK)
-            return rc;
-        hipError_t e = hipEventRecord(ctx->cap_ev[0], cs);
-        for (int i = 0; i < S && e == hipSuccess; i++) e = hipStreamWaitEvent(ctx->bstream[i], ctx->cap_ev[0], 0);
-        for (int32_t q = 0; q < nj && e == hipSuccess; q++) {
-            const ibip_job& jb = jobs[order[q]];
-            e = job_setup(bufs[q], states + q, jb.image, jb.inlets, jb.dims, jb.max_steps, jb.seq, ctx->bstream[q % S],
-                          tiles);
-        }
-        for (int i = 0; i < S && e == hipSuccess; i++) {
-            e = hipEventRecord(ctx->cap_join[i], ctx->bstream[i]);
-            if (e == hipSuccess) e = hipStreamWaitEvent(cs, ctx->cap_join[i], 0);
-        }
-        hipGraph_t graph = nullptr;
-        const hipError_t ee = hipStreamEndCapture(cs, &graph);
-        if (e == hipSuccess) e = ee;
-        if (e == hipSuccess) e = hipGraphInstantiate(&ctx->batch_exec, graph, nullptr, nullptr, 0);
-        if (graph) (void)hipGraphDestroy(graph);
-        if (e != hipSuccess) {
-            ctx->batch_exec = nullptr;
-            return hip_check(ctx, e, "setup graph");
+    if (ctx->batch_key != key) {
+        for (auto& g : ctx->batch_exec)
+            if (g) {
+                (void)hipGraphExecDestroy(g);
+                g = nullptr;
+            }
+        ctx->batch_key.clear();
+        for (int i = 0; i < S && i < nj; i++) {
+            hipStream_t bs = ctx->bstream[i];
+            if ((rc = hip_check(ctx, hipStreamBeginCapture(bs, hipStreamCaptureModeThreadLocal), "begin capture")) !=
+                IBIP_OK)
+                return rc;
+            hipError_t e = hipSuccess;
+            for (int32_t q = i; q < nj && e == hipSuccess; q += S) {
+                const ibip_job& jb = jobs[order[q]];
+                e = job_setup(bufs[q], states + q, jb.image, jb.inlets, jb.dims, jb.max_steps, jb.seq, bs, tiles);
+            }
+            hipGraph_t graph = nullptr;
+            const hipError_t ee = hipStreamEndCapture(bs, &graph);
+            if (e == hipSuccess) e = ee;
+            if (e == hipSuccess) e = hipGraphInstantiate(&ctx->batch_exec[i], graph, nullptr, nullptr, 0);
+            if (graph) (void)hipGraphDestroy(graph);
+            if (e != hipSuccess) {
+                ctx->batch_exec[i] = nullptr;
+                return hip_check(ctx, e, "setup graph");
+            }
         }
         ctx->batch_key = key;
     }
-    // replay after the caller's stream (inputs ready); the caller's stream
-    // then waits for the setup
+    // fork: every batch stream waits for the caller's stream (inputs ready)
+    // and replays its setup; the caller's stream then waits for all of them
     if ((rc = hip_check(ctx, hipEventRecord(ctx->bev[S], s0), "event")) != IBIP_OK) return rc;
-    if ((rc = hip_check(ctx, hipStreamWaitEvent(ctx->cap_stream, ctx->bev[S], 0), "wait")) != IBIP_OK) return rc;
-    if ((rc = hip_check(ctx, hipGraphLaunch(ctx->batch_exec, ctx->cap_stream), "setup graph launch")) != IBIP_OK)
-        return rc;
-    if ((rc = hip_check(ctx, hipEventRecord(ctx->cap_ev[1], ctx->cap_stream), "event")) != IBIP_OK) return rc;
-    if ((rc = hip_check(ctx, hipStreamWaitEvent(s0, ctx->cap_ev[1], 0), "wait")) != IBIP_OK) return rc;
-    // the batch streams' later work (post-processing, continued loops) follows the setup
-    for (int i = 0; i < S; i++)
-        if ((rc = hip_check(ctx, hipStreamWaitEvent(ctx->bstream[i], ctx->cap_ev[1], 0), "wait")) != IBIP_OK)
+    for (int i = 0; i < S && i < nj; i++) {
+        if ((rc = hip_check(ctx, hipStreamWaitEvent(ctx->bstream[i], ctx->bev[S], 0), "wait")) != IBIP_OK) return rc;
+        if ((rc = hip_check(ctx, hipGraphLaunch(ctx->batch_exec[i], ctx->bstream[i]), "setup graph launch")) !=
+            IBIP_OK)
             return rc;
+        if ((rc = hip_check(ctx, hipEventRecord(ctx->bev[i], ctx->bstream[i]), "event")) != IBIP_OK) return rc;
+        if ((rc = hip_check(ctx, hipStreamWaitEvent(s0, ctx->bev[i], 0), "wait")) != IBIP_OK) return rc;
+    }
     // join, then one launch runs every job's step loop. Each job's workgroup
     // writes a completion record to host memory when its loop ends, and the
     // host starts that job's post-processing on the batch streams while the
@@ -1871,7 +1875,7 @@ ibip_status run_invade_batch(ibip_ctx* ctx, ibip_job* jobs, int32_t nj) {
                         "copy")) != IBIP_OK)
         return rc;
     tm.mark(3, s0);
-    hipLaunchKernelGGL(k_loop_batch, dim3((unsigned)nj), dim3(kLoopThreads), 0, s0, d_args);
+    hipLaunchKernelGGL(k_loop_batch<false>, dim3((unsigned)nj), dim3(kLoopThreads), 0, s0, d_args);
     tm.mark(4, s0);
     if ((rc = hip_check(ctx, hipGetLastError(), "batch loop launch")) != IBIP_OK) return rc;
     if ((rc = hip_check(ctx, hipMemcpyAsync(h_st, states, sizeof(LoopState) * nj, hipMemcpyDeviceToHost, s0),

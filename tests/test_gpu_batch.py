@@ -194,9 +194,10 @@ def test_tuning_rejects_unknown_tile_widths(dev):
 
 
 def test_setup_graph_replays(dev):
-    """The batch's setup is captured into a graph for its buffers and
-    replayed while the same batch comes back: A twice (a capture, then a
-    replay), a single-image call, B twice, three rounds, every result equal
+    """The batch's setup is captured into graphs (one per batch stream) for
+    its buffers and replayed while the same batch comes back: A (9 jobs)
+    twice (a capture, then a replay), a single-image call, B (5 jobs, fewer
+    than the streams) twice, three rounds, every result equal
     to the single runs; then new contents in A's input buffers, which a
     capture and a replay of A must both read."""
     imgs_a, inls_a = _jobs(11, 9)
