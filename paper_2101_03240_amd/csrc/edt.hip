@@ -307,9 +307,9 @@ __global__ __launch_bounds__(256) void edt_pass_x_opening(const uint32_t* __rest
 }
 
 // ---------------------------------------------------------------------------
-// Vectorised passes (rows of Z % 8 == 0 voxels, lines of at most 512 voxels):
-// every global access is an 8- or 16-byte vector per lane and each row or
-// tile is read once. Other shapes take the passes above.
+// Vectorised passes (rows of Z % 8 == 0 voxels, lines of at most 1024
+// voxels): every global access is an 8- or 16-byte vector per lane and each
+// row or tile is read once. Other shapes take the passes above.
 // ---------------------------------------------------------------------------
 struct FeatImage8 {
     const uint8_t* img;
@@ -337,16 +337,18 @@ struct FeatThreshold8 {
     }
 };
 
-// Pass z with the whole row in registers: a lane owns 8 consecutive voxels, a
-// row spans lpr = Z / 8 lanes, a wave holds 64 / lpr rows. The nearest
-// feature before / after each lane's voxels comes from a max / min scan over
-// the row's lanes.
+// Pass z with the whole row in registers: a lane owns P = 8 (rows of at most
+// 512 voxels) or 16 (at most 1024) consecutive voxels, a row spans lpr = Z / P
+// lanes, a wave holds 64 / lpr rows. The nearest feature before / after each
+// lane's voxels comes from a max / min scan over the row's lanes.
 constexpr int kZGroups = 4;  // row groups per wave, their loads issued together
+constexpr int kMaxVecLine = 1024;  // longest row or line of the vectorised passes
 
 // pass z of one row group: lane li of lpr holds feature bits fb of voxels
-// v0..v0+7 of its row; writes their distances along z
+// v0..v0+P-1 of its row; writes their distances along z
+template <int P>
 __device__ inline void pass_z_rows(uint32_t fb, bool act, int64_t v0, int li, int lpr, uint64_t cap, uint16_t* g) {
-    const int zb = li * 8;
+    const int zb = li * P;
     // nearest feature at or before the end of this lane's voxels
     int incl = fb ? zb + 31 - __clz(fb) : -1;
     // nearest feature at or after the start of this lane's voxels
@@ -364,33 +366,38 @@ __device__ inline void pass_z_rows(uint32_t fb, bool act, int64_t v0, int li, in
     int next = __shfl_down(incr, 1, 64);
     if (li == 0) prev = -1;
     if (li == lpr - 1) next = 0x7FFFFFFF;
-    uint32_t d[8];
+    uint32_t d[P];
 #pragma unroll
-    for (int j = 0; j < 8; j++) {
+    for (int j = 0; j < P; j++) {
         if (fb & (1u << j)) prev = zb + j;
         d[j] = prev < 0 ? 0xFFFFFFFFu : (uint32_t)(zb + j - prev);
     }
 #pragma unroll
-    for (int j = 7; j >= 0; j--) {
+    for (int j = P - 1; j >= 0; j--) {
         if (fb & (1u << j)) next = zb + j;
         if (next != 0x7FFFFFFF) d[j] = min(d[j], (uint32_t)(next - zb - j));
     }
-    uint32_t pk[4];
+    uint32_t pk[P / 2];
 #pragma unroll
-    for (int j = 0; j < 4; j++) {
+    for (int j = 0; j < P / 2; j++) {
         const uint32_t lo = (d[2 * j] == 0xFFFFFFFFu || (uint64_t)d[2 * j] * d[2 * j] >= cap) ? kInf16 : d[2 * j];
         const uint32_t hi =
             (d[2 * j + 1] == 0xFFFFFFFFu || (uint64_t)d[2 * j + 1] * d[2 * j + 1] >= cap) ? kInf16 : d[2 * j + 1];
         pk[j] = lo | (hi << 16);
     }
-    if (act) *reinterpret_cast<uint4*>(g + v0) = make_uint4(pk[0], pk[1], pk[2], pk[3]);
+    if (act) {
+#pragma unroll
+        for (int j = 0; j < P / 8; j++)
+            *reinterpret_cast<uint4*>(g + v0 + 8 * j) =
+                make_uint4(pk[4 * j], pk[4 * j + 1], pk[4 * j + 2], pk[4 * j + 3]);
+    }
 }
 
-template <class Feat>
+template <class Feat, int P>
 __global__ __launch_bounds__(256) void edt_pass_z_vec(Feat feat, int64_t rows, int Z, uint64_t cap, uint16_t* g,
                                                       uint32_t* solid_flag) {
     const int lane = threadIdx.x & 63;
-    const int lpr = Z >> 3;
+    const int lpr = Z / P;
     const int rpw = 64 / lpr;
     const int r = lane / lpr;
     const int li = lane - r * lpr;
@@ -404,14 +411,15 @@ __global__ __launch_bounds__(256) void edt_pass_z_vec(Feat feat, int64_t rows, i
         act[q] = r < rpw && row < rows;
         // unconditional load (a lane past the last row reads row 0): a load
         // under a lane condition would be waited for before the next one
-        v0[q] = (act[q] ? row : 0) * Z + li * 8;
-        const uint32_t b = feat.bits8(v0[q]);
+        v0[q] = (act[q] ? row : 0) * Z + li * P;
+        uint32_t b = feat.bits8(v0[q]);
+        if (P == 16) b |= feat.bits8(v0[q] + 8) << 8;
         fb[q] = act[q] ? b : 0u;
     }
     bool any = false;
 #pragma unroll
     for (int q = 0; q < kZGroups; q++) {
-        pass_z_rows(fb[q], act[q], v0[q], li, lpr, cap, g);
+        pass_z_rows<P>(fb[q], act[q], v0[q], li, lpr, cap, g);
         any |= __ballot(fb[q] != 0) != 0;
     }
     if (lane == 0 && any && __hip_atomic_load(solid_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
@@ -429,7 +437,7 @@ __global__ __launch_bounds__(256) void edt_pass_z_vec(Feat feat, int64_t rows, i
 // fixed offsets. The sentinel stands for "no feature": it is larger than any
 // real value and small enough that sentinel + o^2 cannot overflow, so each
 // candidate costs one multiply-add (or add) and one min. Lines are at most
-// 512 voxels, so every real sum stays below 3 * 511^2.
+// 1024 voxels, so every real sum stays below 3 * 1023^2.
 constexpr int kPad = 4;
 constexpr uint32_t kSent16 = 0x7FFFu;                // pass y: sentinel distance
 constexpr uint32_t kSentSq = kSent16 * kSent16;      // its square (+ o^2 < 2^31)
@@ -452,7 +460,7 @@ __global__ __launch_bounds__(kThreadsY) void edt_pass_y_vec(const uint16_t* __re
         for (int y = threadIdx.x / kSegs; y < Y; y += kRows) {
             uint4 w = make_uint4(0x7FFF7FFFu, 0x7FFF7FFFu, 0x7FFF7FFFu, 0x7FFF7FFFu);
             if (zc < Z) {
-                // 0xFFFF (no feature) becomes the sentinel 0x7FFF; distances are < 512
+                // 0xFFFF (no feature) becomes the sentinel 0x7FFF; distances are < 1024
                 w = *reinterpret_cast<const uint4*>(g + plane + (int64_t)y * Z + zc);
                 w.x &= 0x7FFF7FFFu;
                 w.y &= 0x7FFF7FFFu;
@@ -560,7 +568,7 @@ __global__ __launch_bounds__(kThreadsX) void edt_pass_x_vec(const uint32_t* __re
 }
 
 // LDS a workgroup may use on the current device (the pass-x tile of a
-// 512-voxel line takes 66.5 KB).
+// 512-voxel line takes 66.5 KB, of a 1024-voxel line 132 KB).
 size_t max_lds_per_block() {
     static size_t cached[64] = {};
     int dev = 0;
@@ -584,29 +592,62 @@ hipError_t launch_edt(const uint8_t* image, const uint32_t* w, uint32_t thr, uin
     const int64_t n = nvox(d);
     // tile widths in z columns: pass y 32 or 64 (uint16), pass x 16 or 32 (uint32)
     const int ty = tiles.y == 64 ? 64 : 32, tx = tiles.x == 16 ? 16 : 32;
-    // vector path: rows of Z % 8 == 0 voxels, lines of at most 512 voxels,
-    // aligned inputs; 32-bit sums when they cannot reach 2^31
+    // each pass takes its vectorised form where it can: pass z for rows of
+    // Z % 8 == 0 voxels up to 512 (8 per lane) or Z % 16 == 0 up to 1024 (16
+    // per lane) from an aligned input; passes y and x when Z % 8 == 0, every
+    // line the pass has read so far is at most 1024 voxels long (so each
+    // distance along z is below 1024, each h below 2 * 1023^2, and 32-bit sums
+    // with the sentinels cannot reach 2^31) and the tile fits in LDS. The
+    // other forms read and write the same layouts.
     const size_t ly = sizeof(uint16_t) * ty * (d.Y + 2 * kPad), lx = sizeof(uint32_t) * tx * (d.X + 2 * kPad);
-    const bool vec = d.Z % 8 == 0 && d.Z <= 512 && d.X <= kMaxTileLine && d.Y <= kMaxTileLine &&
-                     (image ? ((uintptr_t)image & 7) == 0 : ((uintptr_t)w & 15) == 0) &&
-                     std::max(ly, lx) <= max_lds_per_block();
-    if (vec) {
-        const int64_t rows = (int64_t)d.X * d.Y;
-        const int64_t rows_per_block = 4LL * (64 / (d.Z / 8)) * kZGroups;
+    const size_t lds = max_lds_per_block();
+    const bool in_al = image ? ((uintptr_t)image & 7) == 0 : ((uintptr_t)w & 15) == 0;
+    const int zp = !in_al ? 0 : (d.Z % 8 == 0 && d.Z <= 512) ? 8 : (d.Z % 16 == 0 && d.Z <= kMaxVecLine) ? 16 : 0;
+    const bool yvec = d.Z % 8 == 0 && d.Z <= kMaxVecLine && d.Y <= kMaxVecLine && ly <= lds;
+    const bool xvec = yvec && d.X <= kMaxVecLine && lx <= lds;
+    const int64_t rows = (int64_t)d.X * d.Y;
+    if (zp) {
+        const int64_t rows_per_block = 4LL * (64 / (d.Z / zp)) * kZGroups;
         const unsigned gz = (unsigned)((rows + rows_per_block - 1) / rows_per_block);
-        if (image)
-            hipLaunchKernelGGL(edt_pass_z_vec<FeatImage8>, dim3(gz), dim3(256), 0, s, FeatImage8{image}, rows, d.Z,
-                               c64, g16, solid_flag);
+        if (image && zp == 8)
+            hipLaunchKernelGGL((edt_pass_z_vec<FeatImage8, 8>), dim3(gz), dim3(256), 0, s, FeatImage8{image}, rows,
+                               d.Z, c64, g16, solid_flag);
+        else if (image)
+            hipLaunchKernelGGL((edt_pass_z_vec<FeatImage8, 16>), dim3(gz), dim3(256), 0, s, FeatImage8{image}, rows,
+                               d.Z, c64, g16, solid_flag);
+        else if (zp == 8)
+            hipLaunchKernelGGL((edt_pass_z_vec<FeatThreshold8, 8>), dim3(gz), dim3(256), 0, s,
+                               FeatThreshold8{w, thr}, rows, d.Z, c64, g16, solid_flag);
         else
-            hipLaunchKernelGGL(edt_pass_z_vec<FeatThreshold8>, dim3(gz), dim3(256), 0, s, FeatThreshold8{w, thr},
-                               rows, d.Z, c64, g16, solid_flag);
-        const unsigned nzy = (unsigned)((d.Z + ty - 1) / ty), nzx = (unsigned)((d.Z + tx - 1) / tx);
+            hipLaunchKernelGGL((edt_pass_z_vec<FeatThreshold8, 16>), dim3(gz), dim3(256), 0, s,
+                               FeatThreshold8{w, thr}, rows, d.Z, c64, g16, solid_flag);
+    } else {
+        const unsigned gz = (unsigned)((rows + 3) / 4);
+        if (image)
+            hipLaunchKernelGGL(edt_pass_z<FeatImage>, dim3(gz), dim3(256), 0, s, FeatImage{image}, rows, d.Z, c64,
+                               g16, solid_flag);
+        else
+            hipLaunchKernelGGL(edt_pass_z<FeatThreshold>, dim3(gz), dim3(256), 0, s, FeatThreshold{w, thr}, rows,
+                               d.Z, c64, g16, solid_flag);
+    }
+    const unsigned gv = (unsigned)((n + 255) / 256);
+    if (yvec) {
+        const unsigned nzy = (unsigned)((d.Z + ty - 1) / ty);
         if (ty == 64)
             hipLaunchKernelGGL(edt_pass_y_vec<64>, dim3((unsigned)d.X * nzy), dim3(kThreadsY), ly, s, g16, d.X, d.Y,
                                d.Z, c64, tmp32);
         else
             hipLaunchKernelGGL(edt_pass_y_vec<32>, dim3((unsigned)d.X * nzy), dim3(kThreadsY), ly, s, g16, d.X, d.Y,
                                d.Z, c64, tmp32);
+    } else if (d.Y <= kMaxTileLine) {
+        const int nzc = (d.Z + kW - 1) / kW;
+        hipLaunchKernelGGL(edt_pass_y_tile, dim3((unsigned)(d.X * nzc)), dim3(256), sizeof(uint16_t) * kW * d.Y, s,
+                           g16, d.X, d.Y, d.Z, c64, tmp32);
+    } else {
+        hipLaunchKernelGGL(edt_pass_y, dim3(gv), dim3(256), 0, s, g16, d.X, d.Y, d.Z, c64, tmp32);
+    }
+    if (xvec) {
+        const unsigned nzx = (unsigned)((d.Z + tx - 1) / tx);
         const dim3 gx((unsigned)d.Y * nzx);
         if (mio_r2) {
             if (tx == 16)
@@ -624,22 +665,7 @@ hipError_t launch_edt(const uint8_t* image, const uint32_t* w, uint32_t thr, uin
         }
         return hipGetLastError();
     }
-    const int64_t rows = (int64_t)d.X * d.Y;
-    const unsigned gz = (unsigned)((rows + 3) / 4);
-    if (image)
-        hipLaunchKernelGGL(edt_pass_z<FeatImage>, dim3(gz), dim3(256), 0, s, FeatImage{image}, rows, d.Z,
-                           c64, g16, solid_flag);
-    else
-        hipLaunchKernelGGL(edt_pass_z<FeatThreshold>, dim3(gz), dim3(256), 0, s, FeatThreshold{w, thr},
-                           rows, d.Z, c64, g16, solid_flag);
-    const unsigned gv = (unsigned)((n + 255) / 256);
-    const int nzc = (d.Z + kW - 1) / kW;
     const int nzcx = (d.Z + kWx - 1) / kWx;
-    if (d.Y <= kMaxTileLine)
-        hipLaunchKernelGGL(edt_pass_y_tile, dim3((unsigned)(d.X * nzc)), dim3(256), sizeof(uint16_t) * kW * d.Y, s,
-                           g16, d.X, d.Y, d.Z, c64, tmp32);
-    else
-        hipLaunchKernelGGL(edt_pass_y, dim3(gv), dim3(256), 0, s, g16, d.X, d.Y, d.Z, c64, tmp32);
     const bool tile_x = d.X <= kMaxTileLine;
     if (mio_r2) {
         OutOpening o{mio_r2, cap};
@@ -658,5 +684,6 @@ hipError_t launch_edt(const uint8_t* image, const uint32_t* w, uint32_t thr, uin
     }
     return hipGetLastError();
 }
+
 
 }  // namespace ibip

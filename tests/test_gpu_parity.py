@@ -71,13 +71,38 @@ def test_edt_random_shapes(dev, seed):
     np.testing.assert_array_equal(_u32(ibip.edt(_d(img, dev))), oracle.edt(img))
 
 
-@pytest.mark.parametrize("shape", [(600, 3, 5), (2, 700, 9), (1, 900, 40), (520, 1, 70)])
+@pytest.mark.parametrize("shape", [(600, 3, 5), (2, 700, 9), (1, 900, 40), (520, 1, 70), (1100, 2, 3), (2, 1030, 5)])
 def test_edt_long_lines(dev, shape):
-    """Lines longer than an LDS tile take the untiled passes."""
+    """Rows that are not a multiple of 8 voxels take the scalar pass z and the
+    LDS tiles of at most 512 voxels or the untiled passes."""
     rng = np.random.default_rng(sum(shape))
     img = (rng.random(shape) < 0.97).astype(np.uint8)
     img.flat[int(rng.integers(img.size))] = 0
     np.testing.assert_array_equal(_u32(ibip.edt(_d(img, dev))), oracle.edt(img))
+
+
+@pytest.mark.parametrize("shape", [(600, 3, 8), (2, 700, 16), (1, 9, 768), (3, 5, 1000), (1024, 2, 8),
+                                   (2, 1024, 24), (1, 3, 1024), (40, 30, 640), (1030, 2, 8), (2, 1100, 8),
+                                   (1, 2, 1040), (3, 1, 1032)])
+@pytest.mark.parametrize("tiles", [None, (64, 16)])
+def test_edt_vector_path_long_lines(dev, shape, tiles):
+    """Lines of 513-1024 voxels take the vectorised passes (rows of a multiple
+    of 16 voxels up to 1024: 16 per lane in pass z; a multiple of 8 that is not
+    one of 16: the scalar pass z, then the vectorised y and x); longer lines
+    the untiled passes. Also the opening's capped transform."""
+    rng = np.random.default_rng(sum(shape) + (0 if tiles is None else 7))
+    img = (rng.random(shape) < 0.97).astype(np.uint8)
+    img.flat[int(rng.integers(img.size))] = 0
+    if tiles is not None:
+        ibip.set_tuning({"edt_tile_y": tiles[0], "edt_tile_x": tiles[1]})
+    try:
+        np.testing.assert_array_equal(_u32(ibip.edt(_d(img, dev))), oracle.edt(img))
+        inl = synth.face_mask(shape, 0, 0)
+        T = np.array([40, 9, 2], np.uint32)
+        m = ibip.opening_drainage(_d(img, dev), _d(inl, dev), T.tolist())
+        np.testing.assert_array_equal(_u32(m["mio_r2"]), oracle.mio(img, inl, T)["mio_r2"])
+    finally:
+        ibip.set_tuning(None)
 
 
 @pytest.mark.parametrize("shape", [(3, 5, 8), (1, 40, 64), (17, 33, 200), (512, 2, 16), (2, 512, 24), (9, 7, 512),
