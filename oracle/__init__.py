@@ -164,24 +164,28 @@ def _flags(integer_ball: bool, mask_inlets: bool) -> int:
 
 
 def invade(img, inlets, max_steps: int = 0, literal: bool = False, integer_ball: bool = False,
-           mask_inlets: bool = False) -> dict:
+           mask_inlets: bool = False, paint: bool = True) -> dict:
     """Returns dict(seq int32, rad2 uint32, centre_step int32, M uint32[K], K).
     integer_ball / mask_inlets select the variant readings of the sphere rule
-    and of the seeds."""
+    and of the seeds. paint=False runs the selection alone (the candidate-set
+    loop; seq and rad2 are None): sphere insertion never feeds back into which
+    voxels are centres (Section 2.1), so centre_step and M are the same."""
     img = _u8(img)
     inl = _u8(inlets)
     if inl.shape != img.shape:
         raise ValueError("inlets shape")
     X, Y, Z = _dims(img)
     N = img.size
-    seq = np.empty(img.shape, dtype=np.int32)
-    rad2 = np.empty(img.shape, dtype=np.uint32)
+    if not paint and literal:
+        raise ValueError("the literal loop always paints")
+    seq = np.empty(img.shape, dtype=np.int32) if paint else None
+    rad2 = np.empty(img.shape, dtype=np.uint32) if paint else None
     cs = np.empty(img.shape, dtype=np.int32)
     cap = int(N) + 1
     M = np.zeros(cap, dtype=np.uint32)
     fn = _load().ibipref_invade_literal_v if literal else _load().ibipref_invade_v
-    K = _check(fn(_p(img), _p(inl), X, Y, Z, int(max_steps), _flags(integer_ball, mask_inlets), _p(seq), _p(rad2),
-                  _p(cs), _p(M), cap), "invade")
+    K = _check(fn(_p(img), _p(inl), X, Y, Z, int(max_steps), _flags(integer_ball, mask_inlets),
+                  _p(seq) if paint else None, _p(rad2) if paint else None, _p(cs), _p(M), cap), "invade")
     return {"seq": seq, "rad2": rad2, "centre_step": cs, "M": M[:K].copy(), "K": int(K)}
 
 

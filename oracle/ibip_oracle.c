@@ -22,7 +22,9 @@
  *                         centres to the inlets image and zero dt there; the
  *                         whole image is rescanned every step.
  *   ibipref_invade        the same loop with the dilated inlets image kept as
- *                         an explicit candidate set grouped by dt value.
+ *                         an explicit candidate set grouped by dt value (with
+ *                         seq NULL: the selection alone, centres and M, no
+ *                         spheres inserted).
  *   ibipref_steps         Sections 2.2.1-2.2.2: per-step newly invaded counts,
  *                         saturation and Washburn capillary pressure.
  *   ibipref_satmap        Section 2.2.1, Figure 5 (left): each invaded voxel
@@ -276,7 +278,7 @@ static void insert_sphere(int X, int Y, int Z, int64_t c, uint32_t m, int32_t st
 
 static void init_seq(const uint8_t* img, int64_t N, int32_t* seq, uint32_t* rad2, int32_t* cs) {
     for (int64_t i = 0; i < N; i++) {
-        seq[i] = img[i] ? 0 : -1;
+        if (seq) seq[i] = img[i] ? 0 : -1;
         if (rad2) rad2[i] = 0;
         if (cs) cs[i] = 0;
     }
@@ -365,7 +367,8 @@ static int vlist_push(vlist* l, int64_t v) {
 int64_t ibipref_invade_v(const uint8_t* img, const uint8_t* inlets, int X, int Y, int Z,
                          int64_t max_steps, int flags, int32_t* seq, uint32_t* rad2,
                          int32_t* centre_step, uint32_t* M_out, int64_t M_cap) {
-    if (!img || !inlets || !seq || !dims_ok(X, Y, Z)) return REF_EINVAL;
+    /* seq may be NULL: the selection alone (painting never feeds back into it) */
+    if (!img || !inlets || !dims_ok(X, Y, Z)) return REF_EINVAL;
     int64_t N = (int64_t)X * Y * Z;
     uint32_t* dt = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)N);
     uint8_t* seen = (uint8_t*)calloc((size_t)N, 1);
@@ -408,7 +411,7 @@ int64_t ibipref_invade_v(const uint8_t* img, const uint8_t* inlets, int X, int Y
         for (int64_t i = 0; i < cur.n; i++) {
             int64_t c = cur.v[i];
             if (centre_step) centre_step[c] = (int32_t)step;
-            insert_sphere(X, Y, Z, c, M, (int32_t)step, seq, rad2, flags & IBIPREF_INTEGER_BALL);
+            if (seq) insert_sphere(X, Y, Z, c, M, (int32_t)step, seq, rad2, flags & IBIPREF_INTEGER_BALL);
         }
         for (int64_t i = 0; i < cur.n; i++) {
             int64_t nb[6]; int n = neighbours6(X, Y, Z, cur.v[i], nb);

@@ -174,6 +174,7 @@ enum BufId {
     B_BATCH,       // arena of a batch of jobs
     B_SATW,        // counts and scan of ibip_saturation
     B_MIOCNT,      // per-level counts of the opening (kept apart from B_M, which ibip_get_steps reads)
+    B_GBITS,       // occupancy bitmap of the global-memory step loop (more ranks than LDS holds)
     B_NUM
 };
 

@@ -136,13 +136,15 @@ __global__ void k_present(const uint32_t* hist, uint32_t* present, int64_t V) {
 }
 
 // After the scans: offv[v] = bucket offset of value v, rk[v] = rank - 1 of v.
+// rcap: the largest rank the tables hold (a job of a batch or of the server
+// has room for kMaxRanks; beyond that its loop rejects the image).
 __global__ void k_rank_tables(const uint32_t* cnt_scanned, const uint32_t* present_scanned,
                               const uint32_t* hist_raw_flag, int64_t V, uint32_t* val, uint32_t* off,
-                              uint32_t* head, uint32_t* tail) {
+                              uint32_t* head, uint32_t* tail, uint32_t rcap) {
     int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (v >= V || v == 0 || !hist_raw_flag[v]) return;
     uint32_t r = present_scanned[v] + 1;
-    if (r > (uint32_t)kMaxRanks + 1) return;  // too many ranks: the loop rejects the image
+    if (r > rcap + 1) return;  // too many ranks: the loop rejects the image
     val[r] = (uint32_t)v;
     off[r] = cnt_scanned[v];
     head[r] = cnt_scanned[v];
@@ -154,7 +156,7 @@ __global__ void k_rank_tables(const uint32_t* cnt_scanned, const uint32_t* prese
 __global__ __launch_bounds__(256) void k_convert(const uint8_t* __restrict__ img, uint32_t* key,
                                                  const uint32_t* __restrict__ present_scanned, int64_t n,
                                                  uint32_t vlimit, int32_t* state, int32_t* seq, int X, int Y, int Z,
-                                                 FastDiv divZ, FastDiv divY) {
+                                                 FastDiv divZ, FastDiv divY, uint32_t rcap) {
     int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (v >= n) return;
     state[v] = 0;
@@ -164,7 +166,7 @@ __global__ __launch_bounds__(256) void k_convert(const uint8_t* __restrict__ img
         const uint32_t rk = d < vlimit ? present_scanned[d] + 1 : 0u;
         const uint32_t t = fdiv((uint32_t)v, divZ), xx = fdiv(t, divY);
         const uint32_t nb = nb_bits(xx, t - xx * (uint32_t)Y, (uint32_t)v - t * (uint32_t)Z, X, Y, Z);
-        key[v] = rk > (uint32_t)kMaxRanks ? 0u : rk | (nb << kNbShift);
+        key[v] = rk > rcap ? 0u : rk | (nb << kNbShift);
         seq[v] = INT_MAX;
     } else {
         key[v] = 0;
@@ -209,7 +211,7 @@ __device__ inline void push_global(bool active, uint32_t u, uint32_t rr, uint32_
 // Seeds: Q0 = (inlets U their face neighbours) restricted to pore.
 // mask: a solid inlet voxel (rank 0) seeds nothing (the masked reading).
 __global__ __launch_bounds__(256) void k_seed(const uint8_t* __restrict__ inlets, uint32_t* key, int X, int Y,
-                                              int Z, uint32_t* tail, uint32_t* bucket, bool mask) {
+                                              int Z, uint32_t* tail, uint32_t* bucket, bool mask, uint32_t rcap) {
     const int64_t n = (int64_t)X * Y * Z;
     const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const bool inl = v < n && inlets[v] != 0 && (!mask || (key[v] & kRankMask) != 0);
@@ -232,7 +234,7 @@ __global__ __launch_bounds__(256) void k_seed(const uint8_t* __restrict__ inlets
         if (ok && key[u] < kClaim) {
             const uint32_t old = atomicOr(&key[u], kClaim);
             rr = old & kRankMask;
-            won = !(old & kClaim) && rr != 0 && rr <= (uint32_t)kMaxRanks;
+            won = !(old & kClaim) && rr != 0 && rr <= rcap;
         }
         push_global(won, (uint32_t)u, rr, tail, bucket);
     }
@@ -303,6 +305,8 @@ struct LoopArgs {
     uint32_t* done = nullptr;
     // a served job's cancel flag in host memory, read every 1024 steps, or null
     const uint32_t* cancel = nullptr;
+    // the occupancy bitmap of k_loop_global (more ranks than LDS holds), or null
+    uint32_t* gbits = nullptr;
 };
 
 // true when the job's cancel flag is set (wave-uniform)
@@ -940,6 +944,168 @@ __global__ __launch_bounds__(kLoopThreads) void k_loop_batch(const LoopArgs* __r
     loop_body<kCancel>(a, s);
 }
 
+// ---------------------------------------------------------------------------
+// The step loop for images with more distinct distance values than the LDS
+// tables hold (R > kMaxRanks). The same steps on the slice tables in global
+// memory, with a two-level occupancy bitmap there (bits: rank r non-empty;
+// sum: bits word w non-zero), rebuilt from the tables at every launch: every
+// step is run by all waves between barriers, thread 0 takes the decisions.
+// Slices and the bitmap are updated with atomics and read with device-scope
+// loads; each pop is followed by a barrier before its slice grows again.
+// ---------------------------------------------------------------------------
+struct GlobalLoopShared {
+    uint32_t exit, r, k, h, t, up, refill;
+};
+
+__device__ inline uint32_t gload(const uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline void gbits_set(uint32_t* bits, uint32_t* sum, uint32_t r) {
+    atomicOr(&bits[r >> 5], 1u << (r & 31));
+    atomicOr(&sum[r >> 10], 1u << ((r >> 5) & 31));
+}
+
+// highest set rank strictly below r (0 = none); a summary bit whose word
+// reads zero is dropped on the way (thread 0 only)
+__device__ inline uint32_t gbits_highest_below(uint32_t* bits, uint32_t* sum, uint32_t r) {
+    uint32_t w = r >> 5;
+    const uint32_t m = gload(&bits[w]) & ((1u << (r & 31)) - 1u);
+    if (m) return (w << 5) + 31 - __clz(m);
+    uint32_t sw = w >> 5;
+    uint32_t ms = gload(&sum[sw]) & ((1u << (w & 31)) - 1u);
+    for (;;) {
+        while (ms) {
+            const uint32_t wb = 31 - __clz(ms);
+            const uint32_t ww = (sw << 5) + wb;
+            const uint32_t bw = gload(&bits[ww]);
+            if (bw) return (ww << 5) + 31 - __clz(bw);
+            ms &= ~(1u << wb);
+            atomicAnd(&sum[sw], ~(1u << wb));
+        }
+        if (sw == 0) return 0;
+        sw--;
+        ms = gload(&sum[sw]);
+    }
+}
+
+template <bool kCancel>
+__global__ __launch_bounds__(kLoopThreads) void k_loop_global(LoopArgs a) {
+    __shared__ GlobalLoopShared s;
+    const int tid = threadIdx.x;
+    const uint32_t status0 = a.st->status;
+    if (status0 != LS_RUN && status0 != LS_WIDE) return;
+    const uint32_t R = a.st->R;
+    uint32_t* bits = a.gbits;
+    const uint32_t nbw = (R >> 5) + 2;
+    uint32_t* sum = a.gbits + nbw;
+    const uint32_t nsw = (nbw >> 5) + 2;
+    for (uint32_t w = tid; w < nbw; w += kLoopThreads) bits[w] = 0;
+    for (uint32_t w = tid; w < nsw; w += kLoopThreads) sum[w] = 0;
+    __syncthreads();
+    for (uint32_t q = 1 + tid; q <= R; q += kLoopThreads)
+        if (gload(&a.tail[q]) > a.head[q]) gbits_set(bits, sum, q);
+    __syncthreads();
+    const int64_t max_steps = a.st->max_steps;
+    const uint32_t n_pore = a.st->n_pore;
+    const uint32_t klim = max_steps > 0 && max_steps < (int64_t)n_pore ? (uint32_t)max_steps : n_pore;
+    uint32_t npop = 0;  // thread 0
+    // thread 0: start step k at rank r, or stop (exit set)
+    auto decide = [&](uint32_t r, uint32_t k) {
+        const bool cancelled = kCancel && r != 0 && k <= klim && (k & 1023u) == 0 && cancel_requested(a);
+        s.exit = 1;
+        s.k = k;
+        if (r == 0 || k > klim || cancelled) {
+            if (r == 0) {
+                a.st->status = LS_DONE;
+            } else if (k > n_pore) {
+                a.st->err = 1;
+                a.st->status = LS_DONE;
+            } else {
+                a.st->status = cancelled ? LS_CANCEL : LS_MAXSTEPS;
+            }
+            return;
+        }
+        const uint32_t h = a.head[r], t = gload(&a.tail[r]);
+        a.head[r] = t;
+        a.M[k - 1] = r;  // rank; k_rank_to_value turns it into dt2 after the loop
+        if (t - h > a.wide) {  // its centres are counted by the host
+            a.st->big_r = r;
+            a.st->big_h = h;
+            a.st->big_t = t;
+            a.st->big_k = k;
+            a.st->status = LS_WIDE;
+            s.k = k + 1;
+            return;
+        }
+        npop += t - h;
+        s.r = r;
+        s.h = h;
+        s.t = t;
+        s.up = 0;
+        s.refill = 0;
+        s.exit = 0;
+    };
+    if (tid == 0) decide(gbits_highest_below(bits, sum, R + 1), a.st->k);
+    __syncthreads();
+    const int64_t yz = (int64_t)a.Y * a.Z;
+    while (!uni(s.exit)) {
+        const uint32_t r = uni(s.r), k = uni(s.k), h = uni(s.h), cnt = uni(s.t) - h;
+        for (uint32_t i = tid; i < cnt; i += kLoopThreads) {
+            const uint32_t c = a.bucket[h + i];
+            a.state[c] = (int32_t)k;
+            const uint32_t tt = fdiv(c, a.divZ);
+            const int z = (int)(c - tt * (uint32_t)a.Z);
+            const int x = (int)fdiv(tt, a.divY);
+            const int y = (int)(tt - (uint32_t)x * (uint32_t)a.Y);
+            const int64_t uu[6] = {(int64_t)c - yz, (int64_t)c + yz, (int64_t)c - a.Z, (int64_t)c + a.Z,
+                                   (int64_t)c - 1, (int64_t)c + 1};
+            const bool okd[6] = {x > 0, x < a.X - 1, y > 0, y < a.Y - 1, z > 0, z < a.Z - 1};
+            uint32_t old[6];
+#pragma unroll
+            for (int j = 0; j < 6; j++) old[j] = okd[j] ? atomicOr(&a.key[uu[j]], kClaim) : kClaim;
+#pragma unroll
+            for (int j = 0; j < 6; j++) {
+                const uint32_t rr = won_rank(old[j]);
+                if (!rr) continue;
+                const uint32_t pos = atomicAdd(&a.tail[rr], 1u);
+                a.bucket[pos] = (uint32_t)uu[j];
+                // the push that finds its slice empty marks it non-empty
+                // (slice heads other than r's do not move during the step)
+                if (pos == a.head[rr]) gbits_set(bits, sum, rr);
+                if (rr > r) atomicMax(&s.up, rr);
+                else if (rr == r) s.refill = 1;
+            }
+        }
+        __syncthreads();
+        if (tid == 0) {
+            // every rank above r was empty when the step began: a push above r
+            // makes its largest rank the maximum; else r if its slice refilled,
+            // else the highest non-empty rank below r
+            if (!s.refill) atomicAnd(&bits[r >> 5], ~(1u << (r & 31)));  // slice r stayed empty
+            const uint32_t rn = s.up > r ? s.up : s.refill ? r : gbits_highest_below(bits, sum, r);
+            decide(rn, k + 1);
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        a.st->k = s.k;
+        a.st->popped = a.st->popped + npop;
+    }
+    if (a.done) {
+        // a batch job's completion record, as in loop_body
+        __syncthreads();
+        if (tid == 0) {
+            __threadfence_system();
+            a.done[1] = s.k;
+            a.done[2] = a.st->err;
+            a.done[3] = a.st->status;
+            __threadfence_system();
+            a.done[0] = 1u;
+        }
+    }
+}
+
 // One step with many centres, spread over the whole GPU. Claims as in the
 // loop (filtered by a read of the key first). The pushes of a block are
 // counted per rank in LDS, each rank then takes one slice-tail atomic per
@@ -948,17 +1114,22 @@ __global__ __launch_bounds__(kLoopThreads) void k_loop_batch(const LoopArgs* __r
 // queued thousands of atomics on each of them.
 // It is queued after every loop launch and does nothing unless that launch
 // stopped at a wide step.
+// With more ranks than its LDS counts hold, a block pushes with one slice-tail
+// atomic per wave and distinct rank instead.
 __global__ __launch_bounds__(256) void k_wide(LoopArgs a) {
     __shared__ uint32_t lcnt[kMaxRanks + 1];  // per rank: the block's pushes, then their base
     if (a.st->status != LS_WIDE) return;
     const uint32_t h = a.st->big_h, t = a.st->big_t, k = a.st->big_k, R = a.st->R;
+    const bool lds = R <= (uint32_t)kMaxRanks;
     const uint32_t cnt = t - h;
     const uint32_t stride = gridDim.x * 256;
     const uint32_t ntrip = (cnt + stride - 1) / stride;
     const int64_t yz = (int64_t)a.Y * a.Z;
     for (uint32_t it = 0; it < ntrip; it++) {
-        for (uint32_t q = threadIdx.x; q <= R; q += 256) lcnt[q] = 0;
-        __syncthreads();
+        if (lds) {
+            for (uint32_t q = threadIdx.x; q <= R; q += 256) lcnt[q] = 0;
+            __syncthreads();
+        }
         const uint32_t i = it * stride + blockIdx.x * 256 + threadIdx.x;
         const bool have = i < cnt;
         const uint32_t c = have ? a.bucket[h + i] : 0u;
@@ -981,6 +1152,11 @@ __global__ __launch_bounds__(256) void k_wide(LoopArgs a) {
         for (int j = 0; j < 6; j++) {
             rr[j] = old[j] & kRankMask;
             if ((old[j] & kClaim) || rr[j] > R) rr[j] = 0;  // 0: no push (ranks above R do not occur)
+        }
+        if (!lds) {
+#pragma unroll
+            for (int j = 0; j < 6; j++) push_global(rr[j] != 0, (uint32_t)uu[j], rr[j], a.tail, a.bucket);
+            continue;
         }
 #pragma unroll
         for (int j = 0; j < 6; j++) off[j] = rr[j] ? atomicAdd(&lcnt[rr[j]], 1u) : 0u;
@@ -1415,8 +1591,10 @@ ibip_status run_invade(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlet
     if ((rc = hip_check(ctx, hipStreamSynchronize(s), "sync")) != IBIP_OK) return rc;
     if (!h_st->solid_seen) return fail(ctx, IBIP_ENOSOLID, "invade: image holds no solid voxel");
     const uint32_t R = h_st->R;
-    if (R > (uint32_t)kMaxRanks)
-        return fail(ctx, IBIP_ECAPACITY, "invade: more than 8192 distinct distance values in the pore space");
+    if (R > kRankMask)
+        return fail(ctx, IBIP_ECAPACITY, "invade: more distinct distance values than the 24-bit rank field holds");
+    // more ranks than the LDS tables of k_loop hold: the global-memory loop
+    const bool big = R > (uint32_t)kMaxRanks;
     const int64_t n_pore = h_st->n_pore;
     uint32_t* val = (uint32_t*)ensure(ctx, B_VAL, sizeof(uint32_t) * (R + 2));
     uint32_t* off = (uint32_t*)ensure(ctx, B_OFF, sizeof(uint32_t) * (R + 2));
@@ -1424,20 +1602,23 @@ ibip_status run_invade(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlet
     uint32_t* tail = (uint32_t*)ensure(ctx, B_TAIL, sizeof(uint32_t) * (R + 2));
     uint32_t* M = (uint32_t*)ensure(ctx, B_M, sizeof(uint32_t) * (n_pore + 1));
     uint32_t* full = (uint32_t*)ensure(ctx, B_FULL, sizeof(uint32_t) * (n_pore + 1));
-    if (!val || !off || !head || !tail || !M || !full)
+    uint32_t* gbits =
+        big ? (uint32_t*)ensure(ctx, B_GBITS, sizeof(uint32_t) * (((size_t)R >> 5) + ((size_t)R >> 10) + 8)) : nullptr;
+    if (!val || !off || !head || !tail || !M || !full || (big && !gbits))
         return fail(ctx, IBIP_ENOMEM, "invade: scratch allocation failed");
     if ((rc = hip_check(ctx, hipMemsetAsync(head, 0, sizeof(uint32_t) * (R + 2), s), "memset")) != IBIP_OK) return rc;
     if ((rc = hip_check(ctx, hipMemsetAsync(tail, 0, sizeof(uint32_t) * (R + 2), s), "memset")) != IBIP_OK) return rc;
-    hipLaunchKernelGGL(k_rank_tables, dim3(blocks(V)), dim3(256), 0, s, hist, present, flags, V, val, off, head, tail);
+    hipLaunchKernelGGL(k_rank_tables, dim3(blocks(V)), dim3(256), 0, s, hist, present, flags, V, val, off, head, tail,
+                       R);
     hipLaunchKernelGGL(k_convert, dim3(blocks(n)), dim3(256), 0, s, image, key, present, n, (uint32_t)(V - 1), state,
-                       seq, d.X, d.Y, d.Z, make_fastdiv((uint32_t)d.Z), make_fastdiv((uint32_t)d.Y));
+                       seq, d.X, d.Y, d.Z, make_fastdiv((uint32_t)d.Z), make_fastdiv((uint32_t)d.Y), R);
     if (resume_cs) {
         if (k_done > n_pore) return fail(ctx, IBIP_EINVAL, "invade_resume: more steps done than pore voxels");
         hipLaunchKernelGGL(k_resume_seed, dim3(blocks(n)), dim3(256), 0, s, inlets, resume_cs, k_done, key, state, M,
                            d.X, d.Y, d.Z, tail, bucket, (ctx->readings & IBIP_READ_MASK_INLETS) != 0, &st->pad2);
     } else {
         hipLaunchKernelGGL(k_seed, dim3(blocks(n)), dim3(256), 0, s, inlets, key, d.X, d.Y, d.Z, tail, bucket,
-                           (ctx->readings & IBIP_READ_MASK_INLETS) != 0);
+                           (ctx->readings & IBIP_READ_MASK_INLETS) != 0, R);
     }
     tm.mark(2, s);
     // loop control
@@ -1463,6 +1644,11 @@ ibip_status run_invade(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlet
     }
     LoopArgs la{st,     head, tail, val, bucket, state, key, M, d.X, d.Y, d.Z, kWideRound, kSmallRound,
                 make_fastdiv((uint32_t)d.Z), make_fastdiv((uint32_t)d.Y)};
+    la.gbits = gbits;
+    auto launch_loop = [&]() {
+        if (big) hipLaunchKernelGGL(k_loop_global<false>, dim3(1), dim3(kLoopThreads), 0, s, la);
+        else hipLaunchKernelGGL(k_loop<false>, dim3(1), dim3(kLoopThreads), 0, s, la);
+    };
     // The loop kernel stops at each wide step; the host reads the loop state
     // after each stop. The wide step and the next loop segment are queued
     // before that read (each does nothing if the loop had ended), so the GPU
@@ -1480,7 +1666,7 @@ ibip_status run_invade(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlet
     int p = 0;
     bool wide_ran = false;  // the wide launch read this round ran a wide step
     tm.mark(loop_ev(p, 0), s);
-    hipLaunchKernelGGL(k_loop<false>, dim3(1), dim3(kLoopThreads), 0, s, la);
+    launch_loop();
     tm.mark(loop_ev(p, 1), s);
     for (;;) {
         if ((rc = hip_check(ctx, hipGetLastError(), "loop launch")) != IBIP_OK) return rc;
@@ -1492,7 +1678,7 @@ ibip_status run_invade(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlet
         hipLaunchKernelGGL(k_wide, dim3(gw), dim3(256), 0, s, la);
         tm.mark(wide_ev(p, 1), s);
         tm.mark(loop_ev(p ^ 1, 0), s);
-        hipLaunchKernelGGL(k_loop<false>, dim3(1), dim3(kLoopThreads), 0, s, la);
+        launch_loop();
         tm.mark(loop_ev(p ^ 1, 1), s);
         if ((rc = hip_check(ctx, hipGetLastError(), "wide launch")) != IBIP_OK) return rc;
         if ((rc = hip_check(ctx, hipEventSynchronize(ctx->copy_ev), "sync")) != IBIP_OK) return rc;
@@ -1665,12 +1851,14 @@ hipError_t job_setup(const JobBufs& j, LoopState* st, const uint8_t* image, cons
     hipLaunchKernelGGL(k_copy_u32, dim3(blocks(V)), dim3(256), 0, s, present, flags, V);
     if ((e = launch_scan_u32(j.hist, V, j.partials, j.scan_total, s)) != hipSuccess) return e;
     if ((e = launch_scan_u32(present, V, j.partials, &st->R, s)) != hipSuccess) return e;
+    // a job's tables hold kMaxRanks ranks; its loop rejects an image with more
     hipLaunchKernelGGL(k_rank_tables, dim3(blocks(V)), dim3(256), 0, s, j.hist, present, flags, V, j.val, j.off,
-                       j.head, j.tail);
+                       j.head, j.tail, (uint32_t)kMaxRanks);
     hipLaunchKernelGGL(k_convert, dim3(blocks(n)), dim3(256), 0, s, image, j.key, present, n, (uint32_t)(V - 1),
-                       j.state, seq, d.X, d.Y, d.Z, make_fastdiv((uint32_t)d.Z), make_fastdiv((uint32_t)d.Y));
+                       j.state, seq, d.X, d.Y, d.Z, make_fastdiv((uint32_t)d.Z), make_fastdiv((uint32_t)d.Y),
+                       (uint32_t)kMaxRanks);
     hipLaunchKernelGGL(k_seed, dim3(blocks(n)), dim3(256), 0, s, inlets, j.key, d.X, d.Y, d.Z, j.tail, j.bucket,
-                       false);
+                       false, (uint32_t)kMaxRanks);
     return hipGetLastError();
 }
 

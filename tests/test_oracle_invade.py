@@ -133,6 +133,25 @@ def test_random_3d_literal_equals_candidate_set(seed):
         np.testing.assert_array_equal(a[k], b[k])
 
 
+@settings(max_examples=40, deadline=None)
+@given(st.integers(0, 2**31 - 1))
+def test_random_3d_selection_alone_equals_full_loop(seed):
+    """The candidate-set loop without sphere insertion selects the same
+    centres with the same M (insertion never feeds back into selection)."""
+    rng = np.random.default_rng(seed)
+    img, inl = _random_case(rng)
+    a = oracle.invade(img, inl)
+    b = oracle.invade(img, inl, paint=False)
+    assert a["K"] == b["K"] and b["seq"] is None
+    np.testing.assert_array_equal(a["centre_step"], b["centre_step"])
+    np.testing.assert_array_equal(a["M"], b["M"])
+    # and on a literal-loop run truncated by max_steps
+    c = oracle.invade(img, inl, max_steps=3, literal=True)
+    d = oracle.invade(img, inl, max_steps=3, paint=False)
+    assert c["K"] == d["K"]
+    np.testing.assert_array_equal(c["centre_step"], d["centre_step"])
+
+
 def _paint_by_definition(shape, cs, M):
     """seq[v] = min over popped c with |v - c|^2 < M[step(c)] of step(c)."""
     seq = np.zeros(shape, np.int64)
