@@ -182,8 +182,12 @@ ibip_status ibip_edt_noalloc(ibip_ctx* ctx, const uint8_t* image, ibip_dims dims
  * n_steps: host out, the number of steps K.
  * The per-step arrays of this call stay in the context until the next
  * ibip_invade on it; read them with ibip_get_steps.
- * Errors: EINVAL, ENOSOLID, ENOMEM, EDEVICE, ECAPACITY (more than 8192
- * distinct distance values in the pore space).
+ * An image with more than 8192 distinct distance values in its pore space
+ * (a pore whose largest inscribed ball has a radius near 100 voxels or more)
+ * runs a slower form of the step loop whose per-rank tables live in device
+ * memory instead of LDS; the results are the same.
+ * Errors: EINVAL, ENOSOLID, ENOMEM, EDEVICE, ECAPACITY (more than 2^24 - 1
+ * distinct distance values).
  */
 ibip_status ibip_invade(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlets, ibip_dims dims,
                         const ibip_invade_opts* opts, int32_t* seq, uint32_t* rad2,
@@ -225,6 +229,11 @@ ibip_status ibip_invade_resume(ibip_ctx* ctx, const uint8_t* image, const uint8_
  * EDEVICE) and n_steps its K. M (uint32) and sat (double) are optional DEVICE
  * outputs of the per-step squared radius and saturation, each with capacity
  * for at least as many entries as the image has pore voxels.
+ * A job whose image has more than 8192 distinct distance values in its pore
+ * space (more than a job's rank tables hold) runs after the batched launch,
+ * alone, through the path of ibip_invade on the context's stream (same
+ * results); that call replaces the context's per-step arrays, so
+ * ibip_get_steps afterwards reports EINVAL until the next ibip_invade.
  * Returns IBIP_OK when every job succeeded, else the first failing job's code.
  */
 typedef struct {

@@ -2074,6 +2074,9 @@ ibip_status run_invade_batch(ibip_ctx* ctx, ibip_job* jobs, int32_t nj) {
         return rc;
     if ((rc = hip_check(ctx, hipEventRecord(ctx->copy_ev, s0), "event")) != IBIP_OK) return rc;
     ibip_status first = IBIP_OK;
+    // jobs with more distinct distance values than a job's rank tables hold
+    // (their loop stopped before its first step): run alone afterwards
+    std::vector<int32_t> alone;
     auto post = [&](int32_t q, uint32_t k, uint32_t err) -> ibip_status {
         ibip_job& jb = jobs[order[q]];
         jb.status = IBIP_OK;
@@ -2081,6 +2084,10 @@ ibip_status run_invade_batch(ibip_ctx* ctx, ibip_job* jobs, int32_t nj) {
         if (err == 2) jb.status = IBIP_ENOSOLID;
         else if (err == 3) jb.status = IBIP_ECAPACITY;
         else if (err) jb.status = IBIP_EDEVICE;
+        if (err == 3) {
+            alone.push_back(q);
+            return IBIP_OK;
+        }
         if (jb.status != IBIP_OK) {
             if (first == IBIP_OK) first = (ibip_status)jb.status;
             return IBIP_OK;
@@ -2167,6 +2174,33 @@ ibip_status run_invade_batch(ibip_ctx* ctx, ibip_job* jobs, int32_t nj) {
         if ((rc = hip_check(ctx, hipStreamWaitEvent(s0, ctx->bev[i], 0), "wait")) != IBIP_OK) return rc;
     }
     if ((rc = hip_check(ctx, hipStreamSynchronize(s0), "sync")) != IBIP_OK) return rc;
+    // the jobs with too many ranks for the batch's tables take the
+    // single-image path (its global-memory loop), one after another on the
+    // context's stream, with the batch's readings (none); that replaces the
+    // context's per-step arrays, so ibip_get_steps then refers to no call
+    if (!alone.empty()) {
+        const uint32_t readings = ctx->readings;
+        ctx->readings = 0;
+        for (int32_t q : alone) {
+            ibip_job& jb = jobs[order[q]];
+            ibip_invade_opts o{};
+            o.max_steps = jb.max_steps;
+            int64_t K = 0;
+            ibip_status r = run_invade(ctx, jb.image, jb.inlets, jb.dims, &o, jb.seq, jb.rad2, jb.centre_step, &K);
+            if (r == IBIP_OK && K > 0 && jb.M)
+                r = hip_check(ctx, hipMemcpyAsync(jb.M, ctx->buf[B_M].p, sizeof(uint32_t) * K,
+                                                  hipMemcpyDeviceToDevice, s0), "copy");
+            if (r == IBIP_OK && K > 0 && jb.sat)
+                r = hip_check(ctx, hipMemcpyAsync(jb.sat, ctx->buf[B_SAT].p, sizeof(double) * K,
+                                                  hipMemcpyDeviceToDevice, s0), "copy");
+            if (r == IBIP_OK) r = hip_check(ctx, hipStreamSynchronize(s0), "sync");
+            jb.status = r;
+            jb.n_steps = r == IBIP_OK ? K : 0;
+            if (r != IBIP_OK && first == IBIP_OK) first = r;
+        }
+        ctx->readings = readings;
+        ctx->have_steps = false;
+    }
     if (first != IBIP_OK) return fail(ctx, first, "invade_batch: at least one job failed (see its status)");
     return IBIP_OK;
 }

@@ -250,8 +250,10 @@ def test_invade_more_distance_values_than_lds_ranks(dev):
     through a channel along x: ibip_invade runs the global-memory step loop.
     Its centres and M equal the oracle's selection exactly; sphere insertion
     is checked at sampled voxels against the minimum over covering balls, and
-    the per-step counts against the sequence. In a batch that job fails with
-    ECAPACITY (a job's tables hold 8,192 ranks) and the other job runs."""
+    the per-step counts against the sequence. In a batch that job (more
+    ranks than a job's tables hold) runs alone through the same path after
+    the batched launch, with the same results, and the other job runs in the
+    launch."""
     L, c, r = 264, 132, 130
     v = np.indices((L, L, L), dtype=np.int16)
     pore = ((v[0] - c).astype(np.int32) ** 2 + (v[1] - c).astype(np.int32) ** 2
@@ -288,14 +290,25 @@ def test_invade_more_distance_values_than_lds_ranks(dev):
         assert seq.flat[vi] == want, (tuple(p), int(seq.flat[vi]), want)
     cnt = np.bincount(seq[inv], minlength=g["K"] + 1)[1:]
     np.testing.assert_array_equal(g["n_new"].cpu().numpy(), cnt)
-    # in a batch only that job fails; the other one runs
+    # in a batch, with a job that runs in the launch before and after it
     small = synth.overlapping_spheres((24, 20, 28), r2=9, porosity=0.6, seed=3)
     sinl = synth.face_mask(small.shape, 0, 0)
-    out = ibip.invade_batch([img_d, _d(small, dev)], [_d(inl, dev), _d(sinl, dev)], raise_on_error=False)
-    assert out[0]["status"] == -5 and out[1]["status"] == 0
+    out = ibip.invade_batch([_d(small, dev), img_d, _d(small, dev)], [_d(sinl, dev), _d(inl, dev), _d(sinl, dev)],
+                            sat=True)
+    assert [o["status"] for o in out] == [0, 0, 0]
+    b = out[1]
+    assert b["K"] == g["K"]
+    for key in ("seq", "rad2", "centre_step"):
+        assert torch.equal(b[key], g[key]), key
+    np.testing.assert_array_equal(_u32(b["M"]), M)
+    np.testing.assert_array_equal(b["sat"].cpu().numpy(), g["sat"].cpu().numpy())
     rs = oracle.invade(small, sinl)
-    assert out[1]["K"] == rs["K"]
-    np.testing.assert_array_equal(out[1]["seq"].cpu().numpy(), rs["seq"])
+    for o in (out[0], out[2]):
+        assert o["K"] == rs["K"]
+        np.testing.assert_array_equal(o["seq"].cpu().numpy(), rs["seq"])
+    # the batch replaced the context's per-step arrays: no call to report
+    lib = ibip.load_library()
+    assert lib.ibip_get_steps(ibip._context(dev), None, None, None, None, 1 << 30) != 0
 
 
 @pytest.mark.parametrize("shape", [(12, 10, 16), (1, 9, 14)])
