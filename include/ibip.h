@@ -282,7 +282,10 @@ typedef struct {
 
 ibip_status ibip_server_create(ibip_server** out, int32_t device, const ibip_server_opts* opts);
 /* Queue a job (copied); *ticket identifies it. ECAPACITY if its scratch
-   exceeds the whole pool, EINVAL for a bad job. */
+   exceeds the whole pool, EINVAL for a bad job. A job whose image has more
+   than 8192 distinct distance values in its pore space completes with status
+   ECAPACITY (a served job's rank tables hold 8192 ranks; ibip_invade takes
+   such images). */
 ibip_status ibip_server_submit(ibip_server* s, const ibip_job* job, int64_t* ticket);
 /* *done = 1 once the job completed (or was cancelled). */
 ibip_status ibip_server_poll(ibip_server* s, int64_t ticket, int32_t* done);
