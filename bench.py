@@ -110,6 +110,54 @@ def cpu_baseline(img, with_mio: bool) -> dict:
                       f"outlets x={L - 1}: {what} in {dt:.1f} s, {invaded} invaded voxels, one thread"}
 
 
+CPU_PARALLEL_CHILD = r"""
+import json, sys, time
+sys.path.insert(0, sys.argv[1])
+import numpy as np
+import oracle
+from paper_2101_03240_amd import synth
+sl = np.load(sys.argv[2])
+inl = synth.face_mask(sl.shape, 0, 0)
+out = synth.face_mask(sl.shape, 0, sl.shape[0] - 1)
+t0 = time.perf_counter()
+r = oracle.invade(sl, inl)
+oracle.trap(r["seq"], out)
+dt = time.perf_counter() - t0
+print(json.dumps({"s": dt, "invaded": int((r["seq"] > 0).sum()), "threads": oracle.threads()}))
+"""
+
+
+def cpu_parallel_baseline(img) -> dict:
+    """The same oracle source built with OpenMP (its distance transform's
+    lines and the x-planes of large spheres split over the host's threads;
+    the selection loop and trapping stay serial), on the same slab as
+    cpu_baseline, in a child process that loads that build."""
+    import subprocess
+    import tempfile
+
+    import numpy as np
+
+    import oracle
+
+    lib = oracle.OPENMP_LIB if os.path.exists(oracle.OPENMP_LIB) else oracle.build_openmp()
+    X = img.shape[0]
+    L = min(X, 128 if img.shape[1] * img.shape[2] <= 200 * 200 else 48)
+    with tempfile.TemporaryDirectory() as tmp:
+        path = os.path.join(tmp, "slab.npy")
+        np.save(path, np.ascontiguousarray(img[:L]))
+        p = subprocess.run([sys.executable, "-c", CPU_PARALLEL_CHILD, ROOT, path], capture_output=True, text=True,
+                           env=dict(os.environ, IBIP_ORACLE_LIB=lib), timeout=600)
+    if p.returncode != 0:
+        raise RuntimeError("cpu parallel baseline failed: " + p.stderr[-2000:])
+    r = json.loads(p.stdout.strip().splitlines()[-1])
+    return {"value": r["invaded"] / r["s"], "unit": "invaded voxels/s", "threads": r["threads"],
+            "kind": "oracle built with OpenMP", "cpu": cpu_model(),
+            "sample": f"slab x<{L} of the same image ({L}x{img.shape[1]}x{img.shape[2]}), inlets x=0, "
+                      f"outlets x={L - 1}: invade + trap in {r['s']:.1f} s, {r['invaded']} invaded voxels, "
+                      f"EDT lines and the x-planes of spheres of radius >= 8 on {r['threads']} threads, the "
+                      f"selection loop and trapping serial"}
+
+
 def edt_alone(dev, L: int = 512, reps: int = 20) -> dict:
     """The exact EDT alone (passes z, y, x) on an L^3 blurred-noise image
     (sigma 6, porosity 0.55, seed 0, generated on the device), kernel time
@@ -608,6 +656,9 @@ def main() -> int:
     if not args.no_cpu_baseline:
         print("bench: cpu baseline (oracle on a slab)", file=sys.stderr, flush=True)
         res["cpu_baseline"] = cpu_baseline(img, with_mio)
+        print("bench: cpu data-parallel baseline (OpenMP build of the oracle on the slab)", file=sys.stderr,
+              flush=True)
+        res["cpu_parallel_baseline"] = cpu_parallel_baseline(img)
     print(json.dumps(res), flush=True)
     del np
     return 0

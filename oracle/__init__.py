@@ -1,7 +1,10 @@
 """CPU oracle for the IBIP hot path -- TEST INFRASTRUCTURE ONLY.
 
 Plain, slow, single-threaded C (``ibip_oracle.c``) behind ctypes, with numpy
-arrays in and out. Only the test suite, the smoke check and the benchmark's
+arrays in and out. The same source built with OpenMP (``build_openmp``; the
+distance transform's lines and the x-planes of large spheres split over the
+host's threads, nothing else changed) is the benchmark's data-parallel CPU
+baseline, loaded in a child process through ``IBIP_ORACLE_LIB``. Only the test suite, the smoke check and the benchmark's
 CPU-baseline leg may import this package; the product path never does, and the
 two share no code.
 
@@ -40,7 +43,7 @@ def build(force: bool = True) -> str:
     if not force and os.path.exists(_LIB_PATH) and os.path.getmtime(_LIB_PATH) >= os.path.getmtime(_SRC):
         return _LIB_PATH
     tmp = _LIB_PATH + f".tmp{os.getpid()}"
-    subprocess.run(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-Wall", "-o", tmp, _SRC, "-lm"],
+    subprocess.run(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-Wall", "-Wno-unknown-pragmas", "-o", tmp, _SRC, "-lm"],
                    check=True)
     os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
@@ -50,10 +53,27 @@ def build_sanitized(path: str) -> str:
     """Compile the same source with AddressSanitizer and UndefinedBehaviour-
     Sanitizer into `path` (loaded through IBIP_ORACLE_LIB with libasan
     preloaded; used by the tests only)."""
-    subprocess.run(["gcc", "-O1", "-g", "-std=c99", "-fPIC", "-shared", "-Wall", "-fno-omit-frame-pointer",
+    subprocess.run(["gcc", "-O1", "-g", "-std=c99", "-fPIC", "-shared", "-Wall", "-Wno-unknown-pragmas", "-fno-omit-frame-pointer",
                     "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-o", path, _SRC, "-lm"],
                    check=True)
     return path
+
+
+OPENMP_LIB = os.path.join(_HERE, "libibip_oracle_omp.so")
+
+
+def build_openmp(path: str = OPENMP_LIB) -> str:
+    """Compile the same source with OpenMP into `path`."""
+    tmp = path + f".tmp{os.getpid()}"
+    subprocess.run(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-Wall", "-fopenmp", "-o", tmp, _SRC, "-lm"],
+                   check=True)
+    os.replace(tmp, path)
+    return path
+
+
+def threads() -> int:
+    """Threads the loaded build uses (1 unless it is the OpenMP build)."""
+    return int(_load().ibipref_threads())
 
 
 def _load():
@@ -66,6 +86,8 @@ def _load():
     lib = ctypes.CDLL(path)
     P = ctypes.c_void_p
     i32, i64, d = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    lib.ibipref_threads.argtypes = []
+    lib.ibipref_threads.restype = i32
     lib.ibipref_edt_brute.argtypes = [P, i32, i32, i32, P]
     lib.ibipref_edt_brute.restype = i32
     lib.ibipref_edt.argtypes = [P, i32, i32, i32, P]

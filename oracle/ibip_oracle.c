@@ -67,6 +67,9 @@
 #include <stdlib.h>
 #include <string.h>
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define REF_OK 0
 #define REF_EINVAL (-1)
@@ -173,10 +176,12 @@ int ibipref_edt(const uint8_t* img, int X, int Y, int Z, uint32_t* dt2) {
     if (ns == 0) return REF_ENOSOLID;
     uint64_t* a = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)N);
     uint64_t* b = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)N);
-    int L = X > Y ? X : Y; if (Z > L) L = Z;
-    uint64_t* line = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)L);
-    if (!a || !b || !line) { free(a); free(b); free(line); return REF_ENOMEM; }
+    if (!a || !b) { free(a); free(b); return REF_ENOMEM; }
+    /* Lines are independent: built with OpenMP (the CPU data-parallel
+       baseline), each pass splits its lines over the threads; the plain build
+       ignores the pragmas. */
     /* along z: nearest solid in the same row */
+#pragma omp parallel for schedule(static)
     for (int64_t r = 0; r < (int64_t)X * Y; r++) {
         const uint8_t* row = img + r * Z;
         for (int z = 0; z < Z; z++) {
@@ -190,35 +195,44 @@ int ibipref_edt(const uint8_t* img, int X, int Y, int Z, uint32_t* dt2) {
         }
     }
     /* along y */
-    for (int x = 0; x < X; x++)
-        for (int z = 0; z < Z; z++) {
-            for (int y = 0; y < Y; y++) line[y] = a[((int64_t)x * Y + y) * Z + z];
-            for (int y = 0; y < Y; y++) {
-                uint64_t best = REF_INF;
-                for (int yp = 0; yp < Y; yp++) {
-                    if (line[yp] >= REF_INF) continue;
-                    uint64_t d = line[yp] + (uint64_t)((int64_t)(y - yp) * (y - yp));
-                    if (d < best) best = d;
-                }
-                b[((int64_t)x * Y + y) * Z + z] = best;
+    int fail = 0;
+#pragma omp parallel for schedule(static) reduction(| : fail)
+    for (int64_t xz = 0; xz < (int64_t)X * Z; xz++) {
+        const int x = (int)(xz / Z), z = (int)(xz % Z);
+        uint64_t* line = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)Y);
+        if (!line) { fail = 1; continue; }
+        for (int y = 0; y < Y; y++) line[y] = a[((int64_t)x * Y + y) * Z + z];
+        for (int y = 0; y < Y; y++) {
+            uint64_t best = REF_INF;
+            for (int yp = 0; yp < Y; yp++) {
+                if (line[yp] >= REF_INF) continue;
+                uint64_t d = line[yp] + (uint64_t)((int64_t)(y - yp) * (y - yp));
+                if (d < best) best = d;
             }
+            b[((int64_t)x * Y + y) * Z + z] = best;
         }
+        free(line);
+    }
     /* along x */
-    for (int y = 0; y < Y; y++)
-        for (int z = 0; z < Z; z++) {
-            for (int x = 0; x < X; x++) line[x] = b[((int64_t)x * Y + y) * Z + z];
-            for (int x = 0; x < X; x++) {
-                uint64_t best = REF_INF;
-                for (int xp = 0; xp < X; xp++) {
-                    if (line[xp] >= REF_INF) continue;
-                    uint64_t d = line[xp] + (uint64_t)((int64_t)(x - xp) * (x - xp));
-                    if (d < best) best = d;
-                }
-                dt2[((int64_t)x * Y + y) * Z + z] = (uint32_t)best;
+#pragma omp parallel for schedule(static) reduction(| : fail)
+    for (int64_t yz = 0; yz < (int64_t)Y * Z; yz++) {
+        const int y = (int)(yz / Z), z = (int)(yz % Z);
+        uint64_t* line = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)X);
+        if (!line) { fail = 1; continue; }
+        for (int x = 0; x < X; x++) line[x] = b[((int64_t)x * Y + y) * Z + z];
+        for (int x = 0; x < X; x++) {
+            uint64_t best = REF_INF;
+            for (int xp = 0; xp < X; xp++) {
+                if (line[xp] >= REF_INF) continue;
+                uint64_t d = line[xp] + (uint64_t)((int64_t)(x - xp) * (x - xp));
+                if (d < best) best = d;
             }
+            dt2[((int64_t)x * Y + y) * Z + z] = (uint32_t)best;
         }
-    free(a); free(b); free(line);
-    return REF_OK;
+        free(line);
+    }
+    free(a); free(b);
+    return fail ? REF_ENOMEM : REF_OK;
 }
 
 /*
@@ -227,6 +241,15 @@ int ibipref_edt(const uint8_t* img, int X, int Y, int Z, uint32_t* dt2) {
  * outside the searched cube is at squared distance > h*h. Returns -1 if the
  * image holds no solid voxel.
  */
+/* threads the OpenMP build uses (1 for the plain build) */
+int ibipref_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 int64_t ibipref_edt_at(const uint8_t* img, int X, int Y, int Z, int x, int y, int z) {
     int64_t best = INT64_MAX;
     int Lmax = X > Y ? X : Y; if (Z > Lmax) Lmax = Z;
@@ -262,6 +285,9 @@ static void insert_sphere(int X, int Y, int Z, int64_t c, uint32_t m, int32_t st
     int cz = (int)(c % Z), cy = (int)((c / Z) % Y), cx = (int)(c / ((int64_t)Y * Z));
     int64_t R = integer_ball ? isqrt64((int64_t)m) : isqrt64((int64_t)m - 1);
     int64_t lim = integer_ball ? R * R + 1 : (int64_t)m; /* ball = {d^2 < lim} */
+    /* under OpenMP the x-planes of a large sphere go to different threads
+       (they write disjoint voxels); the plain build ignores the pragma */
+#pragma omp parallel for schedule(static) if (R >= 8)
     for (int64_t dx = -R; dx <= R; dx++) {
         int64_t x = cx + dx; if (x < 0 || x >= X) continue;
         for (int64_t dy = -R; dy <= R; dy++) {
