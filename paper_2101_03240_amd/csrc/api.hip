@@ -229,6 +229,8 @@ ibip_status ibip_ctx_destroy(ibip_ctx* ctx) {
     if (ctx->timer.made)
         for (auto& e : ctx->timer.ev) (void)hipEventDestroy(e);
     if (ctx->copy_ev) (void)hipEventDestroy(ctx->copy_ev);
+    if (ctx->paint_ev) (void)hipEventDestroy(ctx->paint_ev);
+    if (ctx->paint_stream) (void)hipStreamDestroy(ctx->paint_stream);
     for (auto& e : ctx->job_ev) (void)hipEventDestroy(e);
     for (auto& g : ctx->batch_exec)
         if (g) (void)hipGraphExecDestroy(g);

@@ -195,6 +195,8 @@ struct LoopState {
     uint32_t popped;   // centres of the steps the loop kernels ran (wide steps not included)
     uint32_t pad2;     // resumption: set when the checkpoint is not a valid one
     int64_t max_steps;
+    uint32_t full_done;  // full-ball list entries painted by earlier insertion passes
+    uint32_t pad3;
 };
 
 enum LoopStatus : uint32_t { LS_RUN = 0, LS_DONE = 1, LS_WIDE = 2, LS_MAXSTEPS = 3, LS_CANCEL = 4 };
@@ -242,6 +244,9 @@ struct ibip_ctx {
     ibip::Buf buf[ibip::B_NUM];
     void* host_pinned = nullptr;   // pinned mirror of LoopState and small results
     hipEvent_t copy_ev = nullptr;  // the loop state's copy to the host (no timing)
+    // sphere insertion of finished steps while the step loop runs (ibip_invade)
+    hipStream_t paint_stream = nullptr;
+    hipEvent_t paint_ev = nullptr;
     std::vector<hipEvent_t> job_ev;  // per batch job: its continued loop's state copy
     // per-job completion records of a batch (4 words each: done, k, err,
     // loop status) in

@@ -1186,6 +1186,10 @@ struct PaintArgs {
     int X, Y, Z;
     bool integer_ball;  // footnote 1's integer sphere instead of the strict ball
     FastDiv divZ, divY;  // voxel index -> coordinates (indices fit 31 bits)
+    // the centres of steps k_lo..k_hi only (insertion is order-free, so the
+    // steps can be inserted in passes); the full-ball list from *full_lo on
+    int32_t k_lo = 1, k_hi = INT_MAX;
+    const uint32_t* full_lo = nullptr;
 };
 
 // Coordinates of voxel c (c < 2^31) by two multiplicative divisions.
@@ -1364,6 +1368,7 @@ __global__ __launch_bounds__(256) void k_paint_shell(PaintArgs a) {
     uint32_t mp[6] = {0u, 0u, 0u, 0u, 0u, 0u};
     int x = 0, y = 0, z = 0;
     if (c < n) k = a.state[c];
+    if (k < a.k_lo || k > a.k_hi) k = 0;
     if (k > 0) {
         const uint32_t rc = a.key[c] & kRankMask;
         m = ball_m(a, a.val[rc]);
@@ -1425,8 +1430,9 @@ __global__ __launch_bounds__(256) void k_paint_shell(PaintArgs a) {
 __global__ __launch_bounds__(256) void k_paint_full(PaintArgs a) {
     const int lane = threadIdx.x & 63;
     const uint32_t nf = *a.n_full;
+    const uint32_t f0 = a.full_lo ? *a.full_lo : 0u;
     const int64_t yz = (int64_t)a.Y * a.Z;
-    for (uint32_t i = blockIdx.x * 4 + (threadIdx.x >> 6); i < nf; i += gridDim.x * 4) {
+    for (uint32_t i = f0 + blockIdx.x * 4 + (threadIdx.x >> 6); i < nf; i += gridDim.x * 4) {
         const int64_t c = a.full[i];
         const int32_t k = a.state[c];
         const uint32_t m = ball_m(a, a.val[a.key[c] & kRankMask]);
@@ -1463,6 +1469,9 @@ __global__ __launch_bounds__(256) void k_paint_full(PaintArgs a) {
 // Finalise and per-step accounting
 // ---------------------------------------------------------------------------
 // M held ranks during the loop; turn them into squared radii.
+// After an insertion pass: the full-ball list entries so far are painted.
+__global__ void k_full_mark(uint32_t* full_done, const uint32_t* n_full) { *full_done = *n_full; }
+
 __global__ void k_rank_to_value(uint32_t* M, int64_t K, const uint32_t* val) {
     const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (k < K) M[k] = val[M[k]];
@@ -1663,6 +1672,31 @@ ibip_status run_invade(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlet
     auto loop_ev = [](int p, int e) { return p ? 12 + e : 3 + e; };  // e = 0 start, 1 end
     auto wide_ev = [](int p, int e) { return p ? 14 + e : 5 + e; };
     int64_t segments = 0, wide_centres = 0;
+    // a5, in passes: insertion is order-free and selection never reads it,
+    // so the steps finished so far are inserted on a second stream while the
+    // loop runs, a pass each time an eighth of the pore voxels have become
+    // centres since the last one; the rest after the loop
+    PaintArgs pa{state, key, val, seq, full, &st->n_full, d.X, d.Y, d.Z,
+                 (ctx->readings & IBIP_READ_INTEGER_BALL) != 0, make_fastdiv((uint32_t)d.Z),
+                 make_fastdiv((uint32_t)d.Y)};
+    pa.full_lo = &st->full_done;
+    auto paint_pass = [&](hipStream_t ps, int32_t lo, int32_t hi) {
+        pa.k_lo = lo;
+        pa.k_hi = hi;
+        hipLaunchKernelGGL(k_paint_shell, dim3(blocks(n)), dim3(256), 0, ps, pa);
+        hipLaunchKernelGGL(k_paint_full, dim3(2048), dim3(256), 0, ps, pa);
+        hipLaunchKernelGGL(k_full_mark, dim3(1), dim3(1), 0, ps, &st->full_done, (const uint32_t*)&st->n_full);
+    };
+    int32_t painted = 0;  // steps 1..painted inserted by passes on the second stream
+    int64_t painted_centres = 0;
+    const int64_t pass_centres = std::max<int64_t>(n_pore / 8, 1);
+    // an early return leaves no pass running on buffers the next call reuses
+    struct PaintJoin {
+        hipStream_t ps = nullptr;
+        ~PaintJoin() {
+            if (ps) (void)hipStreamSynchronize(ps);
+        }
+    } pjoin;
     int p = 0;
     bool wide_ran = false;  // the wide launch read this round ran a wide step
     tm.mark(loop_ev(p, 0), s);
@@ -1692,6 +1726,25 @@ ibip_status run_invade(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlet
         }
         if (++segments > n_pore + 2) return fail(ctx, IBIP_EDEVICE, "invade: too many loop segments");
         if (h_st->status != LS_WIDE) break;
+        {
+            // steps before the pending wide step are finished; their centres:
+            // the loop kernels' and the earlier wide steps'
+            const int32_t done = (int32_t)h_st->big_k - 1;
+            const int64_t centres = (int64_t)h_st->popped + wide_centres;
+            if (centres - painted_centres >= pass_centres && done > painted) {
+                if (!ctx->paint_stream &&
+                    (rc = hip_check(ctx, hipStreamCreateWithFlags(&ctx->paint_stream, hipStreamNonBlocking),
+                                    "stream")) != IBIP_OK)
+                    return rc;
+                if ((rc = hip_check(ctx, hipStreamWaitEvent(ctx->paint_stream, ctx->copy_ev, 0), "wait")) != IBIP_OK)
+                    return rc;
+                pjoin.ps = ctx->paint_stream;
+                paint_pass(ctx->paint_stream, painted + 1, done);
+                if ((rc = hip_check(ctx, hipGetLastError(), "paint launch")) != IBIP_OK) return rc;
+                painted = done;
+                painted_centres = centres;
+            }
+        }
         const uint32_t cnt = h_st->big_t - h_st->big_h;
         wide_centres += cnt;
         if (tm.on) ctx->timing.wide_centres += cnt;
@@ -1702,12 +1755,15 @@ ibip_status run_invade(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlet
     const int64_t K = (int64_t)h_st->k - 1;
     tm.mark(7, s);
     if (K > 0) hipLaunchKernelGGL(k_rank_to_value, dim3(blocks(K)), dim3(256), 0, s, M, K, val);
-    // a5: sphere insertion
-    PaintArgs pa{state, key, val, seq, full, &st->n_full, d.X, d.Y, d.Z,
-                 (ctx->readings & IBIP_READ_INTEGER_BALL) != 0, make_fastdiv((uint32_t)d.Z),
-                 make_fastdiv((uint32_t)d.Y)};
-    hipLaunchKernelGGL(k_paint_shell, dim3(blocks(n)), dim3(256), 0, s, pa);
-    hipLaunchKernelGGL(k_paint_full, dim3(2048), dim3(256), 0, s, pa);
+    // a5: the steps not inserted yet, after the passes on the second stream
+    if (pjoin.ps) {
+        if (!ctx->paint_ev &&
+            (rc = hip_check(ctx, hipEventCreateWithFlags(&ctx->paint_ev, hipEventDisableTiming), "event")) != IBIP_OK)
+            return rc;
+        if ((rc = hip_check(ctx, hipEventRecord(ctx->paint_ev, ctx->paint_stream), "event")) != IBIP_OK) return rc;
+        if ((rc = hip_check(ctx, hipStreamWaitEvent(s, ctx->paint_ev, 0), "wait")) != IBIP_OK) return rc;
+    }
+    paint_pass(s, painted + 1, INT_MAX);
     tm.mark(8, s);
     // a6: finalise and per-step arrays
     int64_t* n_new = (int64_t*)ensure(ctx, B_NNEW, sizeof(int64_t) * (K + 1));
