@@ -307,8 +307,9 @@ __global__ __launch_bounds__(256) void edt_pass_x_opening(const uint32_t* __rest
 }
 
 // ---------------------------------------------------------------------------
-// Vectorised passes (rows of Z % 8 == 0 voxels, lines of at most 1024
-// voxels): every global access is an 8- or 16-byte vector per lane and each
+// Vectorised passes (lines of at most 1024 voxels): pass z for rows of a
+// multiple of 8 voxels, with 8- and 16-byte vectors per lane; passes y and x
+// from LDS tiles, loaded with 16-byte vectors when the rows allow it. Each
 // row or tile is read once. Other shapes take the passes above.
 // ---------------------------------------------------------------------------
 struct FeatImage8 {
@@ -444,8 +445,10 @@ constexpr uint32_t kSentSq = kSent16 * kSent16;      // its square (+ o^2 < 2^31
 constexpr uint32_t kSent32 = 0x40000000u;            // pass x: sentinel value
 constexpr int kThreadsY = 512, kThreadsX = 1024;
 
-// TW: z columns per tile (32: 64-byte tile rows; 64: whole 128-byte lines)
-template <int TW>
+// TW: z columns per tile (32: 64-byte tile rows; 64: whole 128-byte lines).
+// V: rows of Z % 8 == 0 voxels, loaded with 16-byte vectors; otherwise the
+// tile is loaded element by element (consecutive threads, consecutive z).
+template <int TW, bool V>
 __global__ __launch_bounds__(kThreadsY) void edt_pass_y_vec(const uint16_t* __restrict__ g, int X, int Y, int Z,
                                                            uint64_t cap, uint32_t* __restrict__ h) {
     extern __shared__ uint16_t t16[];  // [kPad + Y + kPad][TW]
@@ -454,7 +457,13 @@ __global__ __launch_bounds__(kThreadsY) void edt_pass_y_vec(const uint16_t* __re
     const int x = blockIdx.x / nzc;
     const int z0 = (blockIdx.x - x * nzc) * TW;
     const int64_t plane = (int64_t)x * Y * Z;
-    {
+    if (!V) {
+        for (int i = threadIdx.x; i < Y * TW; i += kThreadsY) {
+            const int y = i / TW, lz = i - y * TW, zc = z0 + lz;
+            // 0xFFFF (no feature) becomes the sentinel 0x7FFF; distances are < 1024
+            t16[(y + kPad) * TW + lz] = zc < Z ? (uint16_t)(g[plane + (int64_t)y * Z + zc] & 0x7FFFu) : (uint16_t)kSent16;
+        }
+    } else {
         const int seg = threadIdx.x % kSegs;
         const int zc = z0 + seg * 8;
         for (int y = threadIdx.x / kSegs; y < Y; y += kRows) {
@@ -469,10 +478,10 @@ __global__ __launch_bounds__(kThreadsY) void edt_pass_y_vec(const uint16_t* __re
             }
             *reinterpret_cast<uint4*>(t16 + (y + kPad) * TW + seg * 8) = w;
         }
-        for (int i = threadIdx.x; i < 2 * kPad * TW; i += kThreadsY) {
-            const int r = i / TW;
-            t16[(r < kPad ? r : Y + r) * TW + (i - r * TW)] = (uint16_t)kSent16;
-        }
+    }
+    for (int i = threadIdx.x; i < 2 * kPad * TW; i += kThreadsY) {
+        const int r = i / TW;
+        t16[(r < kPad ? r : Y + r) * TW + (i - r * TW)] = (uint16_t)kSent16;
     }
     __syncthreads();
     const int lz = threadIdx.x % TW;
@@ -503,8 +512,10 @@ __global__ __launch_bounds__(kThreadsY) void edt_pass_y_vec(const uint16_t* __re
     }
 }
 
-// TW: z columns per tile (16: 64-byte tile rows; 32: whole 128-byte lines)
-template <class Out, int TW>
+// TW: z columns per tile (16: 64-byte tile rows; 32: whole 128-byte lines).
+// V: rows of Z % 4 == 0 voxels, loaded with 16-byte vectors; otherwise the
+// tile is loaded element by element.
+template <class Out, int TW, bool V>
 __global__ __launch_bounds__(kThreadsX) void edt_pass_x_vec(const uint32_t* __restrict__ hin, int X, int Y, int Z,
                                                            uint64_t cap, Out outp, uint32_t* count) {
     extern __shared__ uint32_t t32[];  // [kPad + X + kPad][TW]
@@ -514,7 +525,17 @@ __global__ __launch_bounds__(kThreadsX) void edt_pass_x_vec(const uint32_t* __re
     const int z0 = (blockIdx.x - y * nzc) * TW;
     const int64_t yz = (int64_t)Y * Z;
     const int64_t col0 = (int64_t)y * Z + z0;
-    {
+    if (!V) {
+        for (int i = threadIdx.x; i < X * TW; i += kThreadsX) {
+            const int x = i / TW, lz = i - x * TW;
+            uint32_t w = kSent32;
+            if (z0 + lz < Z) {
+                w = hin[x * yz + col0 + lz];
+                w = w == kInf32 ? kSent32 : w;
+            }
+            t32[(x + kPad) * TW + lz] = w;
+        }
+    } else {
         const int seg = threadIdx.x % kSegs;
         const int zc = z0 + seg * 4;
         for (int x = threadIdx.x / kSegs; x < X; x += kRows) {
@@ -528,10 +549,10 @@ __global__ __launch_bounds__(kThreadsX) void edt_pass_x_vec(const uint32_t* __re
             }
             *reinterpret_cast<uint4*>(t32 + (x + kPad) * TW + seg * 4) = w;
         }
-        for (int i = threadIdx.x; i < 2 * kPad * TW; i += kThreadsX) {
-            const int r = i / TW;
-            t32[(r < kPad ? r : X + r) * TW + (i - r * TW)] = kSent32;
-        }
+    }
+    for (int i = threadIdx.x; i < 2 * kPad * TW; i += kThreadsX) {
+        const int r = i / TW;
+        t32[(r < kPad ? r : X + r) * TW + (i - r * TW)] = kSent32;
     }
     __syncthreads();
     const int lz = threadIdx.x % TW;
@@ -594,17 +615,19 @@ hipError_t launch_edt(const uint8_t* image, const uint32_t* w, uint32_t thr, uin
     const int ty = tiles.y == 64 ? 64 : 32, tx = tiles.x == 16 ? 16 : 32;
     // each pass takes its vectorised form where it can: pass z for rows of
     // Z % 8 == 0 voxels up to 512 (8 per lane) or Z % 16 == 0 up to 1024 (16
-    // per lane) from an aligned input; passes y and x when Z % 8 == 0, every
+    // per lane) from an aligned input; the LDS-tiled passes y and x when every
     // line the pass has read so far is at most 1024 voxels long (so each
     // distance along z is below 1024, each h below 2 * 1023^2, and 32-bit sums
-    // with the sentinels cannot reach 2^31) and the tile fits in LDS. The
-    // other forms read and write the same layouts.
+    // with the sentinels cannot reach 2^31) and the tile fits in LDS, loading
+    // their tiles with 16-byte vectors when the rows allow it. The other forms
+    // read and write the same layouts.
     const size_t ly = sizeof(uint16_t) * ty * (d.Y + 2 * kPad), lx = sizeof(uint32_t) * tx * (d.X + 2 * kPad);
     const size_t lds = max_lds_per_block();
     const bool in_al = image ? ((uintptr_t)image & 7) == 0 : ((uintptr_t)w & 15) == 0;
     const int zp = !in_al ? 0 : (d.Z % 8 == 0 && d.Z <= 512) ? 8 : (d.Z % 16 == 0 && d.Z <= kMaxVecLine) ? 16 : 0;
-    const bool yvec = d.Z % 8 == 0 && d.Z <= kMaxVecLine && d.Y <= kMaxVecLine && ly <= lds;
+    const bool yvec = d.Z <= kMaxVecLine && d.Y <= kMaxVecLine && ly <= lds;
     const bool xvec = yvec && d.X <= kMaxVecLine && lx <= lds;
+    const bool yv = d.Z % 8 == 0, xv = d.Z % 4 == 0;  // rows that 16-byte loads can take
     const int64_t rows = (int64_t)d.X * d.Y;
     if (zp) {
         const int64_t rows_per_block = 4LL * (64 / (d.Z / zp)) * kZGroups;
@@ -633,12 +656,15 @@ hipError_t launch_edt(const uint8_t* image, const uint32_t* w, uint32_t thr, uin
     const unsigned gv = (unsigned)((n + 255) / 256);
     if (yvec) {
         const unsigned nzy = (unsigned)((d.Z + ty - 1) / ty);
-        if (ty == 64)
-            hipLaunchKernelGGL(edt_pass_y_vec<64>, dim3((unsigned)d.X * nzy), dim3(kThreadsY), ly, s, g16, d.X, d.Y,
-                               d.Z, c64, tmp32);
+        const dim3 gy((unsigned)d.X * nzy);
+        if (ty == 64 && yv)
+            hipLaunchKernelGGL((edt_pass_y_vec<64, true>), gy, dim3(kThreadsY), ly, s, g16, d.X, d.Y, d.Z, c64, tmp32);
+        else if (ty == 64)
+            hipLaunchKernelGGL((edt_pass_y_vec<64, false>), gy, dim3(kThreadsY), ly, s, g16, d.X, d.Y, d.Z, c64, tmp32);
+        else if (yv)
+            hipLaunchKernelGGL((edt_pass_y_vec<32, true>), gy, dim3(kThreadsY), ly, s, g16, d.X, d.Y, d.Z, c64, tmp32);
         else
-            hipLaunchKernelGGL(edt_pass_y_vec<32>, dim3((unsigned)d.X * nzy), dim3(kThreadsY), ly, s, g16, d.X, d.Y,
-                               d.Z, c64, tmp32);
+            hipLaunchKernelGGL((edt_pass_y_vec<32, false>), gy, dim3(kThreadsY), ly, s, g16, d.X, d.Y, d.Z, c64, tmp32);
     } else if (d.Y <= kMaxTileLine) {
         const int nzc = (d.Z + kW - 1) / kW;
         hipLaunchKernelGGL(edt_pass_y_tile, dim3((unsigned)(d.X * nzc)), dim3(256), sizeof(uint16_t) * kW * d.Y, s,
@@ -649,19 +675,43 @@ hipError_t launch_edt(const uint8_t* image, const uint32_t* w, uint32_t thr, uin
     if (xvec) {
         const unsigned nzx = (unsigned)((d.Z + tx - 1) / tx);
         const dim3 gx((unsigned)d.Y * nzx);
-        if (mio_r2) {
-            if (tx == 16)
-                hipLaunchKernelGGL((edt_pass_x_vec<OutOpening, 16>), gx, dim3(kThreadsX), lx, s, tmp32, d.X, d.Y,
-                                   d.Z, c64, OutOpening{mio_r2, cap}, mio_count);
-            else
-                hipLaunchKernelGGL((edt_pass_x_vec<OutOpening, 32>), gx, dim3(kThreadsX), lx, s, tmp32, d.X, d.Y,
-                                   d.Z, c64, OutOpening{mio_r2, cap}, mio_count);
-        } else if (tx == 16) {
-            hipLaunchKernelGGL((edt_pass_x_vec<OutPlain, 16>), gx, dim3(kThreadsX), lx, s, tmp32, d.X, d.Y, d.Z, c64,
-                               OutPlain{out}, (uint32_t*)nullptr);
-        } else {
-            hipLaunchKernelGGL((edt_pass_x_vec<OutPlain, 32>), gx, dim3(kThreadsX), lx, s, tmp32, d.X, d.Y, d.Z, c64,
-                               OutPlain{out}, (uint32_t*)nullptr);
+        const OutOpening oo{mio_r2, cap};
+        const OutPlain op{out};
+        uint32_t* const nocount = nullptr;
+        const int form = (mio_r2 ? 4 : 0) + (tx == 16 ? 2 : 0) + (xv ? 1 : 0);
+        switch (form) {
+            case 7:
+                hipLaunchKernelGGL((edt_pass_x_vec<OutOpening, 16, true>), gx, dim3(kThreadsX), lx, s, tmp32,
+                                   d.X, d.Y, d.Z, c64, oo, mio_count);
+                break;
+            case 6:
+                hipLaunchKernelGGL((edt_pass_x_vec<OutOpening, 16, false>), gx, dim3(kThreadsX), lx, s, tmp32,
+                                   d.X, d.Y, d.Z, c64, oo, mio_count);
+                break;
+            case 5:
+                hipLaunchKernelGGL((edt_pass_x_vec<OutOpening, 32, true>), gx, dim3(kThreadsX), lx, s, tmp32,
+                                   d.X, d.Y, d.Z, c64, oo, mio_count);
+                break;
+            case 4:
+                hipLaunchKernelGGL((edt_pass_x_vec<OutOpening, 32, false>), gx, dim3(kThreadsX), lx, s, tmp32,
+                                   d.X, d.Y, d.Z, c64, oo, mio_count);
+                break;
+            case 3:
+                hipLaunchKernelGGL((edt_pass_x_vec<OutPlain, 16, true>), gx, dim3(kThreadsX), lx, s, tmp32,
+                                   d.X, d.Y, d.Z, c64, op, nocount);
+                break;
+            case 2:
+                hipLaunchKernelGGL((edt_pass_x_vec<OutPlain, 16, false>), gx, dim3(kThreadsX), lx, s, tmp32,
+                                   d.X, d.Y, d.Z, c64, op, nocount);
+                break;
+            case 1:
+                hipLaunchKernelGGL((edt_pass_x_vec<OutPlain, 32, true>), gx, dim3(kThreadsX), lx, s, tmp32,
+                                   d.X, d.Y, d.Z, c64, op, nocount);
+                break;
+            default:
+                hipLaunchKernelGGL((edt_pass_x_vec<OutPlain, 32, false>), gx, dim3(kThreadsX), lx, s, tmp32,
+                                   d.X, d.Y, d.Z, c64, op, nocount);
+                break;
         }
         return hipGetLastError();
     }

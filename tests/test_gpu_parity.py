@@ -73,8 +73,9 @@ def test_edt_random_shapes(dev, seed):
 
 @pytest.mark.parametrize("shape", [(600, 3, 5), (2, 700, 9), (1, 900, 40), (520, 1, 70), (1100, 2, 3), (2, 1030, 5)])
 def test_edt_long_lines(dev, shape):
-    """Rows that are not a multiple of 8 voxels take the scalar pass z and the
-    LDS tiles of at most 512 voxels or the untiled passes."""
+    """Rows that are not a multiple of 8 voxels take the scalar pass z, then
+    the LDS-tiled passes with element-wise tile loads (lines up to 1024
+    voxels) or the untiled passes (longer lines)."""
     rng = np.random.default_rng(sum(shape))
     img = (rng.random(shape) < 0.97).astype(np.uint8)
     img.flat[int(rng.integers(img.size))] = 0
@@ -83,13 +84,16 @@ def test_edt_long_lines(dev, shape):
 
 @pytest.mark.parametrize("shape", [(600, 3, 8), (2, 700, 16), (1, 9, 768), (3, 5, 1000), (1024, 2, 8),
                                    (2, 1024, 24), (1, 3, 1024), (40, 30, 640), (1030, 2, 8), (2, 1100, 8),
-                                   (1, 2, 1040), (3, 1, 1032)])
+                                   (1, 2, 1040), (3, 1, 1032), (600, 3, 7), (3, 700, 13), (2, 5, 1001),
+                                   (3, 4, 1020), (1023, 3, 6), (37, 41, 645)])
 @pytest.mark.parametrize("tiles", [None, (64, 16)])
 def test_edt_vector_path_long_lines(dev, shape, tiles):
     """Lines of 513-1024 voxels take the vectorised passes (rows of a multiple
     of 16 voxels up to 1024: 16 per lane in pass z; a multiple of 8 that is not
-    one of 16: the scalar pass z, then the vectorised y and x); longer lines
-    the untiled passes. Also the opening's capped transform."""
+    one of 16: the scalar pass z, then the tiled y and x; rows of other lengths:
+    element-wise tile loads, 16-byte ones in pass x when the row is a multiple
+    of 4); longer lines the untiled passes. Also the opening's capped
+    transform."""
     rng = np.random.default_rng(sum(shape) + (0 if tiles is None else 7))
     img = (rng.random(shape) < 0.97).astype(np.uint8)
     img.flat[int(rng.integers(img.size))] = 0
