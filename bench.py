@@ -44,6 +44,9 @@ WORKLOADS = {
                   "inlets x=0, outlets x=199; invade + trap + MIO at 25 radii",
     "noise512": "512^3 Gaussian-blurred noise (sigma 6, porosity 0.55, seed 0); inlets x=0, outlets x=511; "
                 "invade + trap",
+    "opening512": "the opening drainage alone (Section 2.4.1: erosion at T, trim to the inlet-connected part, "
+                  "ball dilation) on the 512^3 blurred-noise image at one squared radius T = the median of dt2 over "
+                  "the pore; library time over 5 calls",
     "edt768": "the exact squared EDT alone (passes z, y, x; lines of 768 voxels) on 768^3 Gaussian-blurred noise "
               "(sigma 6, porosity 0.55, seed 0, generated on the device), kernel time over 20 calls",
     "edt512": "the exact squared EDT alone (passes z, y, x) on 512^3 Gaussian-blurred noise (sigma 6, porosity "
@@ -56,6 +59,7 @@ WORKLOADS = {
                "invade of every image in one batched call vs one call per image",
 }
 
+OPENING_BYTES_PER_VOXEL = 25  # the survey's ball dilation: 17 B (three EDT passes) + 8 B (threshold read, output)
 # Algorithmic bytes per unit of work for each phase.
 EDT_BYTES_PER_VOXEL = 5          # read 1 B image, write 4 B dt2 (the floor)
 EDT_BUDGET_BYTES_PER_VOXEL = 17  # three passes: 1+2, 2+4, 4+4
@@ -191,6 +195,41 @@ def edt_alone(dev, L: int = 512, reps: int = 20) -> dict:
             "traffic": traffic, "avg_launch_ms": ms, "budget_gbps": budget, "budget_frac": budget / HBM_PEAK_GBPS,
             "measured_gbps": traffic / (ms * 1e-3) / 1e9 if traffic else None,
             "measured_frac": traffic / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS if traffic else None}
+
+
+def opening_alone(dev, reps: int = 5) -> dict:
+    """The opening drainage alone on the 512^3 blurred-noise image at one
+    squared radius (the median of dt2 over the pore), library time (HIP
+    events on its stream) per call, against HBM at the survey's 25 B per
+    voxel for the ball dilation."""
+    import torch
+
+    import paper_2101_03240_amd as ibip
+    from paper_2101_03240_amd import synth
+
+    img = make_image("noise512")
+    img_d = torch.from_numpy(img).to(dev)
+    inl_d = torch.from_numpy(synth.face_mask(img.shape, 0, 0)).to(dev)
+    d = ibip.edt(img_d)
+    T = int(torch.median(d[d > 0].to(torch.int64)).item())
+    for _ in range(2):
+        ibip.opening_drainage(img_d, inl_d, [T])
+    torch.cuda.synchronize()
+    ibip.reset_timing()
+    ibip.enable_timing(True)
+    for _ in range(reps):
+        m = ibip.opening_drainage(img_d, inl_d, [T])
+    torch.cuda.synchronize()
+    ibip.enable_timing(False)
+    ms = ibip.get_timing()["mio_ms"] / reps
+    ibip.reset_timing()
+    n = img.size
+    gbps = OPENING_BYTES_PER_VOXEL * n / (ms * 1e-3) / 1e9
+    traffic = measured_traffic("opening", "opening512")
+    return {"bound": "hbm", "kernel": "opening drainage at one radius (K-map, capped EDT, first-write epilogue)",
+            "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": gbps / HBM_PEAK_GBPS,
+            "traffic": traffic, "avg_launch_ms": ms, "T": T, "mio_sat": m["mio_sat"][0],
+            "measured_gbps": traffic / (ms * 1e-3) / 1e9 if traffic else None}
 
 
 def eqsat_report(dev) -> dict:
@@ -501,6 +540,16 @@ def main() -> int:
         del src, dst
     if args.tuning:
         ibip.set_tuning(json.loads(args.tuning))
+    if args.workload == "opening512":
+        e = opening_alone(dev)
+        print(json.dumps({
+            "metric": METRIC, "value": e["achieved"], "unit": "GB/s", "n_gpus": 1, "steps": 5, "warmup": 2,
+            "ms_per_step": e["avg_launch_ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "u32", "data": "synthetic",
+            "config": {"workload": "opening512", "description": WORKLOADS["opening512"], "shape": [512, 512, 512],
+                       "parallelism": "single GPU"},
+            "roofline": e}), flush=True)
+        return 0
     if args.workload in ("edt512", "edt768"):
         L = int(args.workload[3:])
         e = edt_alone(dev, L)

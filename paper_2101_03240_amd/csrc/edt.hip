@@ -307,10 +307,10 @@ __global__ __launch_bounds__(256) void edt_pass_x_opening(const uint32_t* __rest
 }
 
 // ---------------------------------------------------------------------------
-// Vectorised passes (lines of at most 1024 voxels): pass z for rows of a
-// multiple of 8 voxels, with 8- and 16-byte vectors per lane; passes y and x
-// from LDS tiles, loaded with 16-byte vectors when the rows allow it. Each
-// row or tile is read once. Other shapes take the passes above.
+// Vectorised passes (lines of at most 1024 voxels): pass z with each row in
+// registers, loaded and stored with vectors when the rows are aligned;
+// passes y and x from LDS tiles, loaded with 16-byte vectors when the rows
+// allow it. Each row or tile is read once. Longer lines take the passes above.
 // ---------------------------------------------------------------------------
 struct FeatImage8 {
     const uint8_t* img;
@@ -325,6 +325,7 @@ struct FeatImage8 {
         }
         return b;
     }
+    __device__ bool bit(int64_t v) const { return img[v] == 0; }
 };
 struct FeatThreshold8 {
     const uint32_t* w;
@@ -336,6 +337,7 @@ struct FeatThreshold8 {
                (c.x >= thr ? 16u : 0u) | (c.y >= thr ? 32u : 0u) | (c.z >= thr ? 64u : 0u) |
                (c.w >= thr ? 128u : 0u);
     }
+    __device__ bool bit(int64_t v) const { return w[v] >= thr; }
 };
 
 // Pass z with the whole row in registers: a lane owns P = 8 (rows of at most
@@ -346,9 +348,11 @@ constexpr int kZGroups = 4;  // row groups per wave, their loads issued together
 constexpr int kMaxVecLine = 1024;  // longest row or line of the vectorised passes
 
 // pass z of one row group: lane li of lpr holds feature bits fb of voxels
-// v0..v0+P-1 of its row; writes their distances along z
-template <int P>
-__device__ inline void pass_z_rows(uint32_t fb, bool act, int64_t v0, int li, int lpr, uint64_t cap, uint16_t* g) {
+// v0..v0+P-1 of its row (the first nv of them inside the row); writes their
+// distances along z, with 16-byte stores when the rows are aligned (Al)
+template <int P, bool Al>
+__device__ inline void pass_z_rows(uint32_t fb, bool act, int64_t v0, int li, int lpr, int nv, uint64_t cap,
+                                   uint16_t* g) {
     const int zb = li * P;
     // nearest feature at or before the end of this lane's voxels
     int incl = fb ? zb + 31 - __clz(fb) : -1;
@@ -386,23 +390,33 @@ __device__ inline void pass_z_rows(uint32_t fb, bool act, int64_t v0, int li, in
             (d[2 * j + 1] == 0xFFFFFFFFu || (uint64_t)d[2 * j + 1] * d[2 * j + 1] >= cap) ? kInf16 : d[2 * j + 1];
         pk[j] = lo | (hi << 16);
     }
-    if (act) {
+    if (act && Al) {
 #pragma unroll
         for (int j = 0; j < P / 8; j++)
             *reinterpret_cast<uint4*>(g + v0 + 8 * j) =
                 make_uint4(pk[4 * j], pk[4 * j + 1], pk[4 * j + 2], pk[4 * j + 3]);
+    } else if (act) {
+#pragma unroll
+        for (int j = 0; j < P; j++)
+            if (j < nv) g[v0 + j] = (uint16_t)(pk[j >> 1] >> (16 * (j & 1)));
     }
 }
 
-template <class Feat, int P>
+// Al: rows of a multiple of P voxels from an aligned input, loaded and
+// stored with vectors; otherwise (rows of any length up to 64 * P) voxel by
+// voxel, the last lane of a row holding fewer than P.
+template <class Feat, int P, bool Al>
 __global__ __launch_bounds__(256) void edt_pass_z_vec(Feat feat, int64_t rows, int Z, uint64_t cap, uint16_t* g,
                                                       uint32_t* solid_flag) {
     const int lane = threadIdx.x & 63;
-    const int lpr = Z / P;
+    const int lpr = (Z + P - 1) / P;
     const int rpw = 64 / lpr;
     const int r = lane / lpr;
     const int li = lane - r * lpr;
     const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    // voxels of this lane inside its row (a lane of the partial row group
+    // past the last whole row computes a phantom row and stores nothing)
+    const int nv = min(P, Z - li * P);
     uint32_t fb[kZGroups];
     bool act[kZGroups];
     int64_t v0[kZGroups];
@@ -410,17 +424,24 @@ __global__ __launch_bounds__(256) void edt_pass_z_vec(Feat feat, int64_t rows, i
     for (int q = 0; q < kZGroups; q++) {
         const int64_t row = (wave * kZGroups + q) * rpw + r;
         act[q] = r < rpw && row < rows;
-        // unconditional load (a lane past the last row reads row 0): a load
-        // under a lane condition would be waited for before the next one
+        // unconditional loads (a lane past the last row reads row 0, a voxel
+        // past its row's end rereads the row's last voxel): a load under a
+        // lane condition would be waited for before the next one
         v0[q] = (act[q] ? row : 0) * Z + li * P;
-        uint32_t b = feat.bits8(v0[q]);
-        if (P == 16) b |= feat.bits8(v0[q] + 8) << 8;
+        uint32_t b = 0;
+        if (Al) {
+            b = feat.bits8(v0[q]);
+            if (P == 16) b |= feat.bits8(v0[q] + 8) << 8;
+        } else {
+#pragma unroll
+            for (int j = 0; j < P; j++) b |= (feat.bit(v0[q] + min(j, nv - 1)) && j < nv ? 1u : 0u) << j;
+        }
         fb[q] = act[q] ? b : 0u;
     }
     bool any = false;
 #pragma unroll
     for (int q = 0; q < kZGroups; q++) {
-        pass_z_rows<P>(fb[q], act[q], v0[q], li, lpr, cap, g);
+        pass_z_rows<P, Al>(fb[q], act[q], v0[q], li, lpr, nv, cap, g);
         any |= __ballot(fb[q] != 0) != 0;
     }
     if (lane == 0 && any && __hip_atomic_load(solid_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
@@ -613,9 +634,8 @@ hipError_t launch_edt(const uint8_t* image, const uint32_t* w, uint32_t thr, uin
     const int64_t n = nvox(d);
     // tile widths in z columns: pass y 32 or 64 (uint16), pass x 16 or 32 (uint32)
     const int ty = tiles.y == 64 ? 64 : 32, tx = tiles.x == 16 ? 16 : 32;
-    // each pass takes its vectorised form where it can: pass z for rows of
-    // Z % 8 == 0 voxels up to 512 (8 per lane) or Z % 16 == 0 up to 1024 (16
-    // per lane) from an aligned input; the LDS-tiled passes y and x when every
+    // each pass takes its vectorised form where it can: pass z with the row in
+    // registers for rows up to 1024 voxels; the LDS-tiled passes y and x when every
     // line the pass has read so far is at most 1024 voxels long (so each
     // distance along z is below 1024, each h below 2 * 1023^2, and 32-bit sums
     // with the sentinels cannot reach 2^31) and the tile fits in LDS, loading
@@ -624,26 +644,55 @@ hipError_t launch_edt(const uint8_t* image, const uint32_t* w, uint32_t thr, uin
     const size_t ly = sizeof(uint16_t) * ty * (d.Y + 2 * kPad), lx = sizeof(uint32_t) * tx * (d.X + 2 * kPad);
     const size_t lds = max_lds_per_block();
     const bool in_al = image ? ((uintptr_t)image & 7) == 0 : ((uintptr_t)w & 15) == 0;
-    const int zp = !in_al ? 0 : (d.Z % 8 == 0 && d.Z <= 512) ? 8 : (d.Z % 16 == 0 && d.Z <= kMaxVecLine) ? 16 : 0;
+    // pass z: P voxels per lane (8 for rows up to 512, else 16), vectors when
+    // the rows are a multiple of P and the input is aligned
+    const int zp = d.Z <= 512 ? 8 : d.Z <= kMaxVecLine ? 16 : 0;
+    const bool zal = zp && in_al && d.Z % zp == 0;
     const bool yvec = d.Z <= kMaxVecLine && d.Y <= kMaxVecLine && ly <= lds;
     const bool xvec = yvec && d.X <= kMaxVecLine && lx <= lds;
     const bool yv = d.Z % 8 == 0, xv = d.Z % 4 == 0;  // rows that 16-byte loads can take
     const int64_t rows = (int64_t)d.X * d.Y;
     if (zp) {
-        const int64_t rows_per_block = 4LL * (64 / (d.Z / zp)) * kZGroups;
+        const int64_t rows_per_block = 4LL * (64 / ((d.Z + zp - 1) / zp)) * kZGroups;
         const unsigned gz = (unsigned)((rows + rows_per_block - 1) / rows_per_block);
-        if (image && zp == 8)
-            hipLaunchKernelGGL((edt_pass_z_vec<FeatImage8, 8>), dim3(gz), dim3(256), 0, s, FeatImage8{image}, rows,
-                               d.Z, c64, g16, solid_flag);
-        else if (image)
-            hipLaunchKernelGGL((edt_pass_z_vec<FeatImage8, 16>), dim3(gz), dim3(256), 0, s, FeatImage8{image}, rows,
-                               d.Z, c64, g16, solid_flag);
-        else if (zp == 8)
-            hipLaunchKernelGGL((edt_pass_z_vec<FeatThreshold8, 8>), dim3(gz), dim3(256), 0, s,
-                               FeatThreshold8{w, thr}, rows, d.Z, c64, g16, solid_flag);
-        else
-            hipLaunchKernelGGL((edt_pass_z_vec<FeatThreshold8, 16>), dim3(gz), dim3(256), 0, s,
-                               FeatThreshold8{w, thr}, rows, d.Z, c64, g16, solid_flag);
+        const dim3 gzd(gz);
+        const int form = (image ? 4 : 0) + (zp == 16 ? 2 : 0) + (zal ? 1 : 0);
+        const FeatImage8 fi{image};
+        const FeatThreshold8 ft{w, thr};
+        switch (form) {
+            case 7:
+                hipLaunchKernelGGL((edt_pass_z_vec<FeatImage8, 16, true>), gzd, dim3(256), 0, s, fi, rows, d.Z,
+                                   c64, g16, solid_flag);
+                break;
+            case 6:
+                hipLaunchKernelGGL((edt_pass_z_vec<FeatImage8, 16, false>), gzd, dim3(256), 0, s, fi, rows, d.Z,
+                                   c64, g16, solid_flag);
+                break;
+            case 5:
+                hipLaunchKernelGGL((edt_pass_z_vec<FeatImage8, 8, true>), gzd, dim3(256), 0, s, fi, rows, d.Z,
+                                   c64, g16, solid_flag);
+                break;
+            case 4:
+                hipLaunchKernelGGL((edt_pass_z_vec<FeatImage8, 8, false>), gzd, dim3(256), 0, s, fi, rows, d.Z,
+                                   c64, g16, solid_flag);
+                break;
+            case 3:
+                hipLaunchKernelGGL((edt_pass_z_vec<FeatThreshold8, 16, true>), gzd, dim3(256), 0, s, ft, rows, d.Z,
+                                   c64, g16, solid_flag);
+                break;
+            case 2:
+                hipLaunchKernelGGL((edt_pass_z_vec<FeatThreshold8, 16, false>), gzd, dim3(256), 0, s, ft, rows,
+                                   d.Z, c64, g16, solid_flag);
+                break;
+            case 1:
+                hipLaunchKernelGGL((edt_pass_z_vec<FeatThreshold8, 8, true>), gzd, dim3(256), 0, s, ft, rows, d.Z,
+                                   c64, g16, solid_flag);
+                break;
+            default:
+                hipLaunchKernelGGL((edt_pass_z_vec<FeatThreshold8, 8, false>), gzd, dim3(256), 0, s, ft, rows,
+                                   d.Z, c64, g16, solid_flag);
+                break;
+        }
     } else {
         const unsigned gz = (unsigned)((rows + 3) / 4);
         if (image)
