@@ -139,6 +139,11 @@ ibip_status batch_streams(ibip_ctx* ctx) {
     for (auto& e : ctx->bev)
         if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
             return fail(ctx, IBIP_EDEVICE, "cannot create batch events");
+    for (auto& e : ctx->bev_first)
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+            return fail(ctx, IBIP_EDEVICE, "cannot create batch events");
+    if (hipStreamCreateWithFlags(&ctx->bfirst, hipStreamNonBlocking) != hipSuccess)
+        return fail(ctx, IBIP_EDEVICE, "cannot create batch streams");
     ctx->have_bstreams = true;
     return IBIP_OK;
 }
@@ -225,6 +230,8 @@ ibip_status ibip_ctx_destroy(ibip_ctx* ctx) {
     if (ctx->have_bstreams) {
         for (auto& st : ctx->bstream) (void)hipStreamDestroy(st);
         for (auto& e : ctx->bev) (void)hipEventDestroy(e);
+        for (auto& e : ctx->bev_first) (void)hipEventDestroy(e);
+        if (ctx->bfirst) (void)hipStreamDestroy(ctx->bfirst);
     }
     if (ctx->timer.made)
         for (auto& e : ctx->timer.ev) (void)hipEventDestroy(e);

@@ -232,9 +232,13 @@ struct ibip_ctx {
     ibip::Timer timer;
     hipStream_t bstream[ibip::kBatchStreams] = {};
     hipEvent_t bev[ibip::kBatchStreams + 1] = {};
+    // the batch's first jobs (one per batch stream, the largest) start their
+    // loops on their own stream as soon as their setups are done
+    hipStream_t bfirst = nullptr;
+    hipEvent_t bev_first[ibip::kBatchStreams + 2] = {};
     // the batch's setup captured as one graph per batch stream, and the
     // batch it was captured for
-    hipGraphExec_t batch_exec[ibip::kBatchStreams] = {};
+    hipGraphExec_t batch_exec[ibip::kBatchStreams] = {};  // each stream's setups after its first job's
     std::vector<uint64_t> batch_key;
     bool have_bstreams = false;
     ibip_timing timing = {};

@@ -2062,20 +2062,25 @@ ibip_status run_invade_batch(ibip_ctx* ctx, ibip_job* jobs, int32_t nj) {
                                (uint64_t)(uintptr_t)jb.sat, (uint64_t)jb.max_steps, (uint64_t)jb.dims.X,
                                ((uint64_t)jb.dims.Y << 32) | (uint32_t)jb.dims.Z});
     }
+    // The first job of each stream (the S largest jobs) is set up by direct
+    // launches, so that those jobs' loops can start while the other setups
+    // run: replays of the graphs below do not overlap each other (measured:
+    // the 8 streams' replays ran one after another), while direct launches on
+    // the streams do. The other jobs' setups are captured per stream.
     if (ctx->batch_key != key) {
-        for (auto& g : ctx->batch_exec)
-            if (g) {
-                (void)hipGraphExecDestroy(g);
-                g = nullptr;
+        for (int i = 0; i < S; i++)
+            if (ctx->batch_exec[i]) {
+                (void)hipGraphExecDestroy(ctx->batch_exec[i]);
+                ctx->batch_exec[i] = nullptr;
             }
         ctx->batch_key.clear();
-        for (int i = 0; i < S && i < nj; i++) {
+        for (int i = 0; i < S && i + S < nj; i++) {
             hipStream_t bs = ctx->bstream[i];
             if ((rc = hip_check(ctx, hipStreamBeginCapture(bs, hipStreamCaptureModeThreadLocal), "begin capture")) !=
                 IBIP_OK)
                 return rc;
             hipError_t e = hipSuccess;
-            for (int32_t q = i; q < nj && e == hipSuccess; q += S) {
+            for (int32_t q = i + S; q < nj && e == hipSuccess; q += S) {
                 const ibip_job& jb = jobs[order[q]];
                 e = job_setup(bufs[q], states + q, jb.image, jb.inlets, jb.dims, jb.max_steps, jb.seq, bs, tiles);
             }
@@ -2091,22 +2096,11 @@ ibip_status run_invade_batch(ibip_ctx* ctx, ibip_job* jobs, int32_t nj) {
         }
         ctx->batch_key = key;
     }
-    // fork: every batch stream waits for the caller's stream (inputs ready)
-    // and replays its setup; the caller's stream then waits for all of them
-    if ((rc = hip_check(ctx, hipEventRecord(ctx->bev[S], s0), "event")) != IBIP_OK) return rc;
-    for (int i = 0; i < S && i < nj; i++) {
-        if ((rc = hip_check(ctx, hipStreamWaitEvent(ctx->bstream[i], ctx->bev[S], 0), "wait")) != IBIP_OK) return rc;
-        if ((rc = hip_check(ctx, hipGraphLaunch(ctx->batch_exec[i], ctx->bstream[i]), "setup graph launch")) !=
-            IBIP_OK)
-            return rc;
-        if ((rc = hip_check(ctx, hipEventRecord(ctx->bev[i], ctx->bstream[i]), "event")) != IBIP_OK) return rc;
-        if ((rc = hip_check(ctx, hipStreamWaitEvent(s0, ctx->bev[i], 0), "wait")) != IBIP_OK) return rc;
-    }
-    // join, then one launch runs every job's step loop. Each job's workgroup
-    // writes a completion record to host memory when its loop ends, and the
-    // host starts that job's post-processing on the batch streams while the
-    // launch still runs the other (larger) jobs; the jobs left when the
-    // launch ends take their results from the state copy.
+    const int32_t G = std::min<int32_t>(nj, S);  // jobs of the early launch
+    // Each job's workgroup writes a completion record to host memory when its
+    // loop ends, and the host starts that job's post-processing on the batch
+    // streams while the launches still run the other (larger) jobs; the jobs
+    // left when the launches end take their results from the state copy.
     if (!done_records(ctx, 4 * (size_t)nj)) return fail(ctx, IBIP_ENOMEM, "invade_batch: pinned allocation failed");
     for (int32_t q = 0; q < nj; q++) h_args[q].done = ctx->done_dev + 4 * q;
     while (ctx->job_ev.size() < (size_t)nj) {
@@ -2115,11 +2109,45 @@ ibip_status run_invade_batch(ibip_ctx* ctx, ibip_job* jobs, int32_t nj) {
         ctx->job_ev.push_back(e);
     }
     Timer& tm = ctx->timer;
-    if ((rc = hip_check(ctx, hipMemcpyAsync(d_args, h_args, sizeof(LoopArgs) * nj, hipMemcpyHostToDevice, s0),
+    hipStream_t sf = ctx->bfirst;
+    // fork: every batch stream and the early-launch stream wait for the
+    // caller's stream (inputs ready); the loop arguments go over first
+    if ((rc = hip_check(ctx, hipEventRecord(ctx->bev[S], s0), "event")) != IBIP_OK) return rc;
+    if ((rc = hip_check(ctx, hipStreamWaitEvent(sf, ctx->bev[S], 0), "wait")) != IBIP_OK) return rc;
+    if ((rc = hip_check(ctx, hipMemcpyAsync(d_args, h_args, sizeof(LoopArgs) * nj, hipMemcpyHostToDevice, sf),
                         "copy")) != IBIP_OK)
         return rc;
-    tm.mark(3, s0);
-    hipLaunchKernelGGL(k_loop_batch<false>, dim3((unsigned)nj), dim3(kLoopThreads), 0, s0, d_args);
+    if ((rc = hip_check(ctx, hipEventRecord(ctx->bev_first[S], sf), "event")) != IBIP_OK) return rc;
+    // the first job of each stream (the S largest), set up directly; their
+    // loops start on the early-launch stream as soon as those setups end
+    for (int i = 0; i < G; i++) {
+        hipStream_t bs = ctx->bstream[i];
+        const ibip_job& jb = jobs[order[i]];
+        if ((rc = hip_check(ctx, hipStreamWaitEvent(bs, ctx->bev[S], 0), "wait")) != IBIP_OK) return rc;
+        if ((rc = hip_check(ctx, job_setup(bufs[i], states + i, jb.image, jb.inlets, jb.dims, jb.max_steps, jb.seq,
+                                           bs, tiles), "setup")) != IBIP_OK)
+            return rc;
+        if ((rc = hip_check(ctx, hipEventRecord(ctx->bev_first[i], bs), "event")) != IBIP_OK) return rc;
+        if ((rc = hip_check(ctx, hipStreamWaitEvent(sf, ctx->bev_first[i], 0), "wait")) != IBIP_OK) return rc;
+    }
+    tm.mark(3, sf);
+    hipLaunchKernelGGL(k_loop_batch<false>, dim3((unsigned)G), dim3(kLoopThreads), 0, sf, d_args);
+    if ((rc = hip_check(ctx, hipGetLastError(), "batch loop launch")) != IBIP_OK) return rc;
+    if ((rc = hip_check(ctx, hipEventRecord(ctx->bev_first[S + 1], sf), "event")) != IBIP_OK) return rc;
+    // the other jobs' setups (graph replays, after the first job's on each
+    // stream), then their loops in a second launch; the state copy follows both
+    for (int i = 0; i < G; i++) {
+        hipStream_t bs = ctx->bstream[i];
+        if (ctx->batch_exec[i] &&
+            (rc = hip_check(ctx, hipGraphLaunch(ctx->batch_exec[i], bs), "setup graph launch")) != IBIP_OK)
+            return rc;
+        if ((rc = hip_check(ctx, hipEventRecord(ctx->bev[i], bs), "event")) != IBIP_OK) return rc;
+        if ((rc = hip_check(ctx, hipStreamWaitEvent(s0, ctx->bev[i], 0), "wait")) != IBIP_OK) return rc;
+    }
+    if ((rc = hip_check(ctx, hipStreamWaitEvent(s0, ctx->bev_first[S], 0), "wait")) != IBIP_OK) return rc;
+    if (nj > G)
+        hipLaunchKernelGGL(k_loop_batch<false>, dim3((unsigned)(nj - G)), dim3(kLoopThreads), 0, s0, d_args + G);
+    if ((rc = hip_check(ctx, hipStreamWaitEvent(s0, ctx->bev_first[S + 1], 0), "wait")) != IBIP_OK) return rc;
     tm.mark(4, s0);
     if ((rc = hip_check(ctx, hipGetLastError(), "batch loop launch")) != IBIP_OK) return rc;
     if ((rc = hip_check(ctx, hipMemcpyAsync(h_st, states, sizeof(LoopState) * nj, hipMemcpyDeviceToHost, s0),
