@@ -1190,7 +1190,23 @@ struct PaintArgs {
     // steps can be inserted in passes); the full-ball list from *full_lo on
     int32_t k_lo = 1, k_hi = INT_MAX;
     const uint32_t* full_lo = nullptr;
+    // leave the first XCD to the step loop: workgroups b with b % 8 == 0 (the
+    // ones dispatched to XCD 0) return at once and the others take all the
+    // work (a pass run while the loop's single workgroup, on XCD 0, runs)
+    bool skip_xcd0 = false;
 };
+
+// The workgroup's index among those that take work (all of them, or the ones
+// outside XCD 0), and their number; -1 for a workgroup that takes none.
+__device__ inline int64_t paint_block(const PaintArgs& a, int64_t& nblocks) {
+    if (!a.skip_xcd0) {
+        nblocks = gridDim.x;
+        return blockIdx.x;
+    }
+    nblocks = (int64_t)(gridDim.x >> 3) * 7;
+    if ((blockIdx.x & 7u) == 0) return -1;
+    return (int64_t)(blockIdx.x >> 3) * 7 + (blockIdx.x & 7u) - 1;
+}
 
 // Coordinates of voxel c (c < 2^31) by two multiplicative divisions.
 __device__ inline void coords(uint32_t c, const PaintArgs& a, int& x, int& y, int& z) {
@@ -1361,7 +1377,10 @@ constexpr int kSmallCap = 2;
 __global__ __launch_bounds__(256) void k_paint_shell(PaintArgs a) {
     const int64_t yz = (int64_t)a.Y * a.Z;
     const int64_t n = (int64_t)a.X * yz;
-    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    int64_t nb_unused;
+    const int64_t b = paint_block(a, nb_unused);
+    if (b < 0) return;
+    const int64_t c = b * 256 + threadIdx.x;
     const int lane = threadIdx.x & 63;
     int32_t k = 0;
     uint32_t m = 0, qmask = 0;
@@ -1432,7 +1451,10 @@ __global__ __launch_bounds__(256) void k_paint_full(PaintArgs a) {
     const uint32_t nf = *a.n_full;
     const uint32_t f0 = a.full_lo ? *a.full_lo : 0u;
     const int64_t yz = (int64_t)a.Y * a.Z;
-    for (uint32_t i = f0 + blockIdx.x * 4 + (threadIdx.x >> 6); i < nf; i += gridDim.x * 4) {
+    int64_t nblocks;
+    const int64_t b = paint_block(a, nblocks);
+    if (b < 0) return;
+    for (uint32_t i = f0 + (uint32_t)b * 4 + (threadIdx.x >> 6); i < nf; i += (uint32_t)nblocks * 4) {
         const int64_t c = a.full[i];
         const int32_t k = a.state[c];
         const uint32_t m = ball_m(a, a.val[a.key[c] & kRankMask]);
@@ -1683,8 +1705,11 @@ ibip_status run_invade(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlet
     auto paint_pass = [&](hipStream_t ps, int32_t lo, int32_t hi) {
         pa.k_lo = lo;
         pa.k_hi = hi;
-        hipLaunchKernelGGL(k_paint_shell, dim3(blocks(n)), dim3(256), 0, ps, pa);
-        hipLaunchKernelGGL(k_paint_full, dim3(2048), dim3(256), 0, ps, pa);
+        // a pass under the loop keeps off XCD 0: 8 workgroups for every 7
+        pa.skip_xcd0 = ps != s;
+        const int64_t gb = pa.skip_xcd0 ? (blocks(n) + 6) / 7 * 8 : blocks(n);
+        hipLaunchKernelGGL(k_paint_shell, dim3((unsigned)gb), dim3(256), 0, ps, pa);
+        hipLaunchKernelGGL(k_paint_full, dim3(pa.skip_xcd0 ? 2048 / 7 * 8 : 2048), dim3(256), 0, ps, pa);
         hipLaunchKernelGGL(k_full_mark, dim3(1), dim3(1), 0, ps, &st->full_done, (const uint32_t*)&st->n_full);
     };
     int32_t painted = 0;  // steps 1..painted inserted by passes on the second stream
