@@ -1696,8 +1696,9 @@ ibip_status run_invade(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlet
     int64_t segments = 0, wide_centres = 0;
     // a5, in passes: insertion is order-free and selection never reads it,
     // so the steps finished so far are inserted on a second stream while the
-    // loop runs, a pass each time an eighth of the pore voxels have become
-    // centres since the last one; the rest after the loop
+    // loop runs: at a wide-step stop, a pass once the previous one has ended
+    // and a 32nd of the pore voxels (at least 2^21) have become centres since
+    // it; the rest after the loop
     PaintArgs pa{state, key, val, seq, full, &st->n_full, d.X, d.Y, d.Z,
                  (ctx->readings & IBIP_READ_INTEGER_BALL) != 0, make_fastdiv((uint32_t)d.Z),
                  make_fastdiv((uint32_t)d.Y)};
@@ -1714,7 +1715,7 @@ ibip_status run_invade(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlet
     };
     int32_t painted = 0;  // steps 1..painted inserted by passes on the second stream
     int64_t painted_centres = 0;
-    const int64_t pass_centres = std::max<int64_t>(n_pore / 8, 1);
+    const int64_t pass_centres = std::max<int64_t>(n_pore / 32, (int64_t)1 << 21);
     // an early return leaves no pass running on buffers the next call reuses
     struct PaintJoin {
         hipStream_t ps = nullptr;
@@ -1756,7 +1757,13 @@ ibip_status run_invade(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlet
             // the loop kernels' and the earlier wide steps'
             const int32_t done = (int32_t)h_st->big_k - 1;
             const int64_t centres = (int64_t)h_st->popped + wide_centres;
-            if (centres - painted_centres >= pass_centres && done > painted) {
+            bool idle = true;  // no pass yet, or the last one has ended
+            if (pjoin.ps) {
+                const hipError_t qe = hipEventQuery(ctx->paint_ev);
+                if (qe != hipSuccess && qe != hipErrorNotReady) return hip_check(ctx, qe, "event query");
+                idle = qe == hipSuccess;
+            }
+            if (idle && centres - painted_centres >= pass_centres && done > painted) {
                 if (!ctx->paint_stream &&
                     (rc = hip_check(ctx, hipStreamCreateWithFlags(&ctx->paint_stream, hipStreamNonBlocking),
                                     "stream")) != IBIP_OK)
@@ -1766,6 +1773,12 @@ ibip_status run_invade(ibip_ctx* ctx, const uint8_t* image, const uint8_t* inlet
                 pjoin.ps = ctx->paint_stream;
                 paint_pass(ctx->paint_stream, painted + 1, done);
                 if ((rc = hip_check(ctx, hipGetLastError(), "paint launch")) != IBIP_OK) return rc;
+                if (!ctx->paint_ev &&
+                    (rc = hip_check(ctx, hipEventCreateWithFlags(&ctx->paint_ev, hipEventDisableTiming), "event")) !=
+                        IBIP_OK)
+                    return rc;
+                if ((rc = hip_check(ctx, hipEventRecord(ctx->paint_ev, ctx->paint_stream), "event")) != IBIP_OK)
+                    return rc;
                 painted = done;
                 painted_centres = centres;
             }
