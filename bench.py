@@ -289,9 +289,11 @@ def measured_traffic(kernel: str, workload: str):
         t = json.load(f).get("kernels", {}).get(kernel)
     if not t:
         return None
-    with open(os.path.join(ROOT, t["source"]), "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest() != t["source_sha256"]:
-            return None
+    srcs = t.get("sources") or {t["source"]: t["source_sha256"]}
+    for src, digest in srcs.items():
+        with open(os.path.join(ROOT, src), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != digest:
+                return None
     return float(t["traffic_bytes_per_launch"])
 
 
