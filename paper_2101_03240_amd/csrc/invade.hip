@@ -319,6 +319,7 @@ constexpr int kLoopThreads = 1024;
 constexpr int kBitWords = (kMaxRanks >> 5) + 2;
 constexpr int kSumWords = (kBitWords >> 5) + 1;
 constexpr uint32_t kLog = 2048;  // entries of the per-step push log
+constexpr uint32_t kRunCentres = 21;  // steps of at most two passes of 64 (centre, direction) pairs
 
 struct LoopShared {
     uint32_t head[kMaxRanks + 1];
@@ -549,8 +550,11 @@ __device__ inline void claim_pair(uint32_t p, uint32_t np, uint32_t k, const Loo
     u = up ? c + stride : c - stride;
     old = kClaim;
     if (ok) old = atomicOr(&a.key[u], kClaim);
-    // stores go after the claims: a wait for the claims then leaves them in flight
-    if (act && dir == 0) a.state[c] = (int32_t)k;
+    // stores go after the claims: a wait for the claims then leaves them in
+    // flight. Every lane stores (the lanes of one centre the same value; an
+    // idle lane that of centre 0, also a centre of this step), so the number
+    // of memory operations after the claims is fixed.
+    a.state[c] = (int32_t)k;
 }
 
 // Rank of a won claim (0 if the claim lost or hit solid).
@@ -559,14 +563,43 @@ __device__ inline uint32_t won_rank(uint32_t old) {
     return !(old & kClaim) && rr != 0 ? rr : 0u;
 }
 
+// Entries of the slice a step may pop next, read ahead. When a small step
+// pushes nothing at or above the highest non-empty rank below its own
+// (`below`), that rank is the next maximum and its centres come from the
+// bucket in HBM: a global round trip ahead of the next claims. Reading them
+// while the current step's claims are in flight takes it off the chain. The
+// entries of a slice between its head and tail never change, so the next
+// step takes them if its rank, head and tail are the ones read here.
+struct SliceAhead {
+    uint32_t r = 0, h = 0, t = 0;  // wave-uniform; r = 0: nothing read
+    uint32_t c = 0;                // entry h + lane, clamped into the slice
+};
+
+// The load is issued in every case (entry 0 of the bucket when there is
+// nothing to read): with a fixed number of memory operations after the claims,
+// the wait for the claims leaves it in flight.
+__device__ inline void read_ahead(const LoopArgs& a, const LoopShared& s, uint32_t below, SliceAhead& ah) {
+    const uint32_t h = uni(s.head[below]), t = uni(s.tail[below]);
+    const bool ok = below != 0 && t != h && t - h <= 64u;
+    ah.r = ok ? below : 0u;
+    ah.h = h;
+    ah.t = t;
+    ah.c = a.bucket[ok ? h + min((uint32_t)(threadIdx.x & 63), t - h - 1u) : 0u];
+}
+
 // Push the voxel of a won claim into the LDS slice of its rank and (kLogged)
 // the push log; a push of rank rn (the next step's rank, when every live
 // entry of its slice comes from this step) is also listed in s.cl for the
 // next step. A step of at most two passes needs no log: the step after it
 // either takes the list in s.cl or pops an older slice, from the bucket.
+// The bucket store is issued by every lane: one without a push writes the
+// step's rank r into M[k - 1], which holds it anyway. (A store under a lane
+// condition leaves the number of memory operations in flight unknown to the
+// compiler, which then waits for all of them wherever it needs a load's
+// result, as the next step's centres read ahead.)
 template <bool kLogged>
 __device__ inline void push_pair(uint32_t old, uint32_t u, const LoopArgs& a, LoopShared& s, uint32_t sel,
-                                 uint32_t& logn, uint32_t rn, uint32_t& dn) {
+                                 uint32_t& logn, uint32_t rn, uint32_t& dn, uint32_t k, uint32_t r) {
     const uint32_t rr = won_rank(old);
     const bool won = rr != 0;
     uint32_t pos, hd;
@@ -582,8 +615,8 @@ __device__ inline void push_pair(uint32_t old, uint32_t u, const LoopArgs& a, Lo
     const uint64_t mn = __ballot(nx);
     const uint32_t di = dn + (uint32_t)__popcll(mn & lt);
     dn += (uint32_t)__popcll(mn);
+    *(won ? &a.bucket[pos] : &a.M[k - 1]) = won ? u : r;
     if (won) {
-        a.bucket[pos] = u;
         if (pos == hd) lds_set(s, rr);
         if (kLogged && li < kLog) {
             s.logu[sel][li] = u;
@@ -596,41 +629,49 @@ __device__ inline void push_pair(uint32_t old, uint32_t u, const LoopArgs& a, Lo
     }
 }
 
-// One small step; returns the next maximum rank. The next maximum is the
-// highest pushed rank if above r (every rank above r was empty), else r if
-// its slice refilled, else the larger of the highest pushed rank and the
-// highest non-empty rank below r (`below`, read while the claims are in
-// flight). With at most two passes it is known once the claims return, before
-// the pushes: if every live entry of its slice is a push of this step (it is
-// not `below`), the pushes list them in s.cl and `direct` is set, so the next
-// step gathers nothing.
+// Push of one (centre, direction) pair of a step of the run below, from the
+// won rank w (0: nothing to push) and the neighbour bits nb of the claimed
+// voxel u; a push of rank rd is also listed in s.cl for the next step. The
+// bucket store is issued by every lane, as in push_pair.
+__device__ inline void push_won(uint32_t w, uint32_t u, uint32_t nb, const LoopArgs& a, LoopShared& s,
+                                uint32_t rd, uint32_t& dn, uint32_t k, uint32_t r) {
+    const bool won = w != 0;
+    uint32_t pos, hd;
+    slice_pos(s, won, w, pos, hd);
+    const bool nx = won && w == rd;
+    const uint64_t mn = __ballot(nx);
+    const uint32_t di = dn + (uint32_t)__popcll(mn & lanemask_lt());
+    dn += (uint32_t)__popcll(mn);
+    *(won ? &a.bucket[pos] : &a.M[k - 1]) = won ? u : r;
+    if (won) {
+        if (pos == hd) lds_set(s, w);
+        if (nx && di < kSmallRound) {
+            s.cl[di] = u;
+            s.clb[di] = (uint8_t)nb;
+        }
+    }
+}
+
+// One small step of more than kRunCentres centres (3 to 12 passes), wave 0
+// alone; returns the next maximum rank: the highest pushed rank if above r
+// (every rank above r was empty), else r if its slice refilled, else the
+// larger of the highest pushed rank and the highest non-empty rank below r
+// (`below`, read while the claims are in flight). The claims of passes 2-5
+// join those of passes 0 and 1 before the first wait, and passes 6-11 go in
+// flight together. The pushes are logged for the next step.
 __device__ inline uint32_t small_step(uint32_t cnt, uint32_t k, uint32_t r, uint32_t t, const LoopArgs& a,
-                                      LoopShared& s, uint32_t sel, uint32_t& logn, bool& direct) {
+                                      LoopShared& s, uint32_t sel, uint32_t& logn, SliceAhead& ah) {
     const uint32_t np = 6 * cnt;
     const uint32_t passes = (np + 63) >> 6;
     uint32_t o0, u0, o1 = kClaim, u1 = 0, dn = 0;
     claim_pair(0, np, k, a, s, o0, u0);
-    if (passes > 1) claim_pair(1, np, k, a, s, o1, u1);
+    claim_pair(1, np, k, a, s, o1, u1);
     // pop slice r (its head moves to tail t) once the claims are out: only the
     // pushes read it, and LDS operations complete in order, so a write ahead of
     // the centre reads would delay them
     s.head[r] = t;
     const uint32_t below = lds_highest_below_uni(s, r);
-    if (passes <= 2) {
-        const uint32_t w0 = won_rank(o0), w1 = won_rank(o1);
-        const uint32_t pmax = wave_max_u32(max(w0, w1));
-        const bool refilled = __ballot(w0 == r || w1 == r) != 0;
-        if (!refilled) atomicAnd(&s.bits[r >> 5], ~(1u << (r & 31)));
-        const uint32_t rn = pmax > r ? pmax : refilled ? r : max(below, pmax);
-        direct = rn != 0 && rn != below;
-        const uint32_t rd = direct ? rn : 0u;  // rank 0 matches no push
-        push_pair<false>(o0, u0, a, s, sel, logn, rd, dn);
-        if (passes > 1) push_pair<false>(o1, u1, a, s, sel, logn, rd, dn);
-        logn = kLog + 1;  // no log of this step: the next one never reads it
-        return rn;
-    }
-    // more passes (up to 12): the claims of passes 2-5 join those of passes
-    // 0 and 1 before the first wait, and passes 6-11 go in flight together
+    read_ahead(a, s, below, ah);
     uint32_t lm = 0;
     bool same = false;
     for (uint32_t p = 2; p < passes; p += 4) {
@@ -647,21 +688,20 @@ __device__ inline uint32_t small_step(uint32_t cnt, uint32_t k, uint32_t r, uint
             const uint32_t w0 = won_rank(o0), w1 = won_rank(o1);
             lm = max(w0, w1);
             same = w0 == r || w1 == r;
-            push_pair<true>(o0, u0, a, s, sel, logn, 0u, dn);
-            push_pair<true>(o1, u1, a, s, sel, logn, 0u, dn);
+            push_pair<true>(o0, u0, a, s, sel, logn, 0u, dn, k, r);
+            push_pair<true>(o1, u1, a, s, sel, logn, 0u, dn, k, r);
         }
         const uint32_t x0 = won_rank(q0), x1 = won_rank(q1), x2 = won_rank(q2), x3 = won_rank(q3);
         lm = max(lm, max(max(x0, x1), max(x2, x3)));
         same |= x0 == r || x1 == r || x2 == r || x3 == r;
-        push_pair<true>(q0, v0, a, s, sel, logn, 0u, dn);
-        if (p + 1 < passes) push_pair<true>(q1, v1, a, s, sel, logn, 0u, dn);
-        if (p + 2 < passes) push_pair<true>(q2, v2, a, s, sel, logn, 0u, dn);
-        if (p + 3 < passes) push_pair<true>(q3, v3, a, s, sel, logn, 0u, dn);
+        push_pair<true>(q0, v0, a, s, sel, logn, 0u, dn, k, r);
+        if (p + 1 < passes) push_pair<true>(q1, v1, a, s, sel, logn, 0u, dn, k, r);
+        if (p + 2 < passes) push_pair<true>(q2, v2, a, s, sel, logn, 0u, dn, k, r);
+        if (p + 3 < passes) push_pair<true>(q3, v3, a, s, sel, logn, 0u, dn, k, r);
     }
     const uint32_t pmax = wave_max_u32(lm);
     const bool refilled = __ballot(same) != 0;
     if (!refilled) atomicAnd(&s.bits[r >> 5], ~(1u << (r & 31)));
-    direct = false;
     return pmax > r ? pmax : refilled ? r : max(below, pmax);
 }
 
@@ -715,6 +755,7 @@ __device__ inline void loop_body(const LoopArgs& a, LoopShared& s) {
     // driver state, live in wave 0
     uint32_t r = 0, k = 0, prev_r = 0, sel = 0, nlog = 0, npop = 0;
     bool log_ok = false, direct = false;
+    SliceAhead ah;
     if (wave0) {
         r = lds_highest_below_uni(s, R + 1);
         k = uni(a.st->k);
@@ -769,41 +810,6 @@ __device__ inline void loop_body(const LoopArgs& a, LoopShared& s) {
                     break;
                 }
                 npop += cnt;
-                if (direct && cnt <= 10) {
-                    // A run of one-pass steps whose centres the previous step
-                    // listed: a loop of its own, without the gathers, the
-                    // push log and the longer forms, until a step lists no
-                    // centres for the next one or the next has more than 10.
-                    uint32_t tt = t, c1 = cnt;
-                    for (;;) {
-                        uint32_t o0, u0, dn = 0, unused = 0;
-                        claim_pair(0, 6 * c1, k, a, s, o0, u0);
-                        s.head[r] = tt;
-                        const uint32_t below = lds_highest_below_uni(s, r);
-                        const uint32_t w0 = won_rank(o0);
-                        const uint32_t pmax = wave_max_u32(w0);
-                        const bool refilled = __ballot(w0 == r) != 0;
-                        if (!refilled) atomicAnd(&s.bits[r >> 5], ~(1u << (r & 31)));
-                        const uint32_t rn = pmax > r ? pmax : refilled ? r : max(below, pmax);
-                        direct = rn != 0 && rn != below;
-                        push_pair<false>(o0, u0, a, s, sel, unused, direct ? rn : 0u, dn);
-                        a.M[k - 1] = r;
-                        prev_r = r;
-                        r = rn;
-                        k = k + 1;
-                        // (a job that can be cancelled returns to the check above
-                        // every 1024 steps)
-                        if (!direct || k > klim || (kCancel && (k & 1023u) == 0)) break;
-                        const uint32_t hh = uni(s.head[r]);
-                        tt = uni(s.tail[r]);
-                        c1 = tt - hh;
-                        if (c1 > 10) break;
-                        npop += c1;
-                    }
-                    log_ok = false;  // no push log was written
-                    nlog = kLog + 1;
-                    continue;
-                }
                 const uint32_t nsel = sel ^ 1u;
                 // a small step, wave 0 alone: its centres are listed in s.cl by the
                 // previous step, or gathered there from the log or the bucket
@@ -832,7 +838,10 @@ __device__ inline void loop_body(const LoopArgs& a, LoopShared& s) {
                     // outstanding store before the claims.
                     // (the bucket holds voxel indices only: their neighbour bits
                     // come from their coordinates)
-                    const uint32_t c0 = a.bucket[h + min((uint32_t)lane, cnt - 1u)];
+                    // (the entries read ahead by the previous step, if they are
+                    // this slice's: same rank, head and tail)
+                    uint32_t c0 = ah.c;
+                    if (!(ah.r == r && ah.h == h && ah.t == t)) c0 = a.bucket[h + min((uint32_t)lane, cnt - 1u)];
                     s.cl[lane] = c0;
                     s.clb[lane] = (uint8_t)nb_of(c0, a);
                     if (cnt > 64) {
@@ -841,12 +850,108 @@ __device__ inline void loop_body(const LoopArgs& a, LoopShared& s) {
                         s.clb[lane + 64] = (uint8_t)nb_of(c1, a);
                     }
                 }
-                bool dnext = false;
-                const uint32_t rn = small_step(cnt, k, r, t, a, s, nsel, ln, dnext);
+                if (cnt <= kRunCentres) {
+                    // A run of steps of at most kRunCentres centres (at most
+                    // two passes of 64 pairs). Once a step's claims return and
+                    // the next maximum is decided, the next step's centres are
+                    // often known already: this step's pushes of that rank
+                    // (`direct`: they are every live entry of its slice), or
+                    // the entries of the slice below, read ahead while the
+                    // claims were in flight, if this step pushed none of that
+                    // rank. The run then lists them in s.cl and issues the
+                    // next step's claims at once; this step's pushes (LDS
+                    // slices, bucket) follow while those claims are in flight.
+                    // The run ends at a step whose successor is not known that
+                    // way or has more centres, at the step limit, or (a job
+                    // that can be cancelled) every 1024 steps; the last step
+                    // lists its direct pushes in s.cl for the general path.
+                    // (the second pass is issued in every step, with no lane
+                    // active in a step of at most 10 centres: its claim words
+                    // then stay in the same registers from step to step)
+                    uint32_t tt = t, c1 = cnt;
+                    uint32_t o0, u0, o1, u1;
+                    claim_pair(0, 6 * c1, k, a, s, o0, u0);
+                    claim_pair(1, 6 * c1, k, a, s, o1, u1);
+                    for (;;) {
+                        s.head[r] = tt;
+                        const uint32_t below = lds_highest_below_uni(s, r);
+                        read_ahead(a, s, below, ah);
+                        // the claim words are not used past this point: the empty
+                        // asm makes the compiler take their ranks and neighbour
+                        // bits here, so the next step's claims can reuse their
+                        // registers (a copy into them would wait for those claims)
+                        uint32_t w0 = won_rank(o0), w1 = won_rank(o1);
+                        uint32_t b0 = o0 >> kNbShift, b1 = o1 >> kNbShift;
+                        asm volatile("" : "+v"(w0), "+v"(w1), "+v"(b0), "+v"(b1));
+                        const uint32_t pmax = wave_max_u32(max(w0, w1));
+                        const bool refilled = __ballot(w0 == r || w1 == r) != 0;
+                        if (!refilled) atomicAnd(&s.bits[r >> 5], ~(1u << (r & 31)));
+                        const uint32_t rn = pmax > r ? pmax : refilled ? r : max(below, pmax);
+                        const bool dir = rn != 0 && rn != below;
+                        // won pushes of rank rn (a lane that won nothing has w = 0)
+                        const uint64_t m0 = __ballot(rn != 0 && w0 == rn), m1 = __ballot(rn != 0 && w1 == rn);
+                        const uint32_t n0 = (uint32_t)__popcll(m0);
+                        const uint32_t nrn = n0 + (uint32_t)__popcll(m1);
+                        const bool hit = !dir && rn != 0 && rn == ah.r && nrn == 0;
+                        const uint32_t cn = dir ? nrn : hit ? ah.t - ah.h : 0u;
+                        const bool go = cn != 0 && cn <= kRunCentres && k + 1 <= klim &&
+                                        !(kCancel && ((k + 1) & 1023u) == 0);
+                        uint32_t dn = 0;
+                        if (go) {
+                            const uint64_t lt = lanemask_lt();
+                            if (dir) {
+                                if ((m0 >> lane) & 1u) {
+                                    const uint32_t i = (uint32_t)__popcll(m0 & lt);
+                                    s.cl[i] = u0;
+                                    s.clb[i] = (uint8_t)b0;
+                                }
+                                if ((m1 >> lane) & 1u) {
+                                    const uint32_t i = n0 + (uint32_t)__popcll(m1 & lt);
+                                    s.cl[i] = u1;
+                                    s.clb[i] = (uint8_t)b1;
+                                }
+                            } else if ((uint32_t)lane < cn) {
+                                s.cl[lane] = ah.c;
+                                s.clb[lane] = (uint8_t)nb_of(ah.c, a);
+                            }
+                            uint32_t p0, v0, p1, v1;
+                            claim_pair(0, 6 * cn, k + 1, a, s, p0, v0);
+                            claim_pair(1, 6 * cn, k + 1, a, s, p1, v1);
+                            push_won(w0, u0, b0, a, s, 0u, dn, k, r);
+                            if (c1 > 10) push_won(w1, u1, b1, a, s, 0u, dn, k, r);
+                            a.M[k - 1] = r;
+                            prev_r = r;
+                            r = rn;
+                            k = k + 1;
+                            // pop point of the next step: the tail after this step's pushes
+                            tt = dir ? uni(s.tail[rn]) : ah.t;
+                            npop += cn;
+                            c1 = cn;
+                            o0 = p0;
+                            u0 = v0;
+                            o1 = p1;
+                            u1 = v1;
+                            continue;
+                        }
+                        const uint32_t rd = dir ? rn : 0u;
+                        push_won(w0, u0, b0, a, s, rd, dn, k, r);
+                        if (c1 > 10) push_won(w1, u1, b1, a, s, rd, dn, k, r);
+                        a.M[k - 1] = r;
+                        prev_r = r;
+                        r = rn;
+                        k = k + 1;
+                        direct = dir;
+                        break;
+                    }
+                    log_ok = false;  // no push log was written
+                    nlog = kLog + 1;
+                    continue;
+                }
+                const uint32_t rn = small_step(cnt, k, r, t, a, s, nsel, ln, ah);
                 a.M[k - 1] = r;
                 prev_r = r;
                 r = rn;
-                direct = dnext;
+                direct = false;
                 k = k + 1;
                 sel = nsel;
                 log_ok = ln <= kLog;
