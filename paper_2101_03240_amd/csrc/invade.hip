@@ -557,6 +557,50 @@ __device__ inline void claim_pair(uint32_t p, uint32_t np, uint32_t k, const Loo
     a.state[c] = (int32_t)k;
 }
 
+// Pairs of a step of the run below, fixed per lane: pass p takes pair
+// 64p + lane, that is centre (64p + lane) / 6 of the step's list and
+// direction (64p + lane) % 6, its neighbour bit and its signed index offset.
+struct RunLane {
+    uint32_t ci[2], bit[2];
+    int32_t off[2];
+};
+
+__device__ inline RunLane run_lanes(const LoopArgs& a) {
+    RunLane L;
+#pragma unroll
+    for (int p = 0; p < 2; p++) {
+        const uint32_t i = (uint32_t)(p * 64) + (threadIdx.x & 63);
+        const uint32_t d = i % 6u;
+        const int32_t stride = d < 2 ? a.Y * a.Z : d < 4 ? a.Z : 1;
+        L.ci[p] = i / 6u;
+        L.bit[p] = 1u << d;
+        L.off[p] = d & 1u ? stride : -stride;
+    }
+    return L;
+}
+
+// The claims of both passes of a run step of np / 6 centres listed in s.cl,
+// as claim_pair with the pairs' constants from L: the four list reads are
+// issued together (unconditionally: an idle lane reads slot 0), then the
+// claims, then the state stores.
+__device__ inline void claim_run(uint32_t np, uint32_t k, const LoopArgs& a, const LoopShared& s, const RunLane& L,
+                                 uint32_t& o0, uint32_t& u0, uint32_t& o1, uint32_t& u1) {
+    const uint32_t lane = threadIdx.x & 63;
+    const bool act0 = lane < np, act1 = lane + 64u < np;
+    const uint32_t ci0 = act0 ? L.ci[0] : 0u, ci1 = act1 ? L.ci[1] : 0u;
+    const uint32_t c0 = s.cl[ci0], c1 = s.cl[ci1];
+    const uint32_t nb0 = s.clb[ci0], nb1 = s.clb[ci1];
+    const bool ok0 = act0 & ((nb0 & L.bit[0]) != 0u), ok1 = act1 & ((nb1 & L.bit[1]) != 0u);
+    u0 = c0 + (uint32_t)L.off[0];
+    u1 = c1 + (uint32_t)L.off[1];
+    o0 = kClaim;
+    o1 = kClaim;
+    if (ok0) o0 = atomicOr(&a.key[u0], kClaim);
+    if (ok1) o1 = atomicOr(&a.key[u1], kClaim);
+    a.state[c0] = (int32_t)k;
+    a.state[c1] = (int32_t)k;
+}
+
 // Rank of a won claim (0 if the claim lost or hit solid).
 __device__ inline uint32_t won_rank(uint32_t old) {
     const uint32_t rr = old & kRankMask;
@@ -756,6 +800,7 @@ __device__ inline void loop_body(const LoopArgs& a, LoopShared& s) {
     uint32_t r = 0, k = 0, prev_r = 0, sel = 0, nlog = 0, npop = 0;
     bool log_ok = false, direct = false;
     SliceAhead ah;
+    const RunLane L = run_lanes(a);
     if (wave0) {
         r = lds_highest_below_uni(s, R + 1);
         k = uni(a.st->k);
@@ -859,23 +904,24 @@ __device__ inline void loop_body(const LoopArgs& a, LoopShared& s) {
                     // the entries of the slice below, read ahead while the
                     // claims were in flight, if this step pushed none of that
                     // rank. The run then lists them in s.cl and issues the
-                    // next step's claims at once; this step's pushes (LDS
-                    // slices, bucket) follow while those claims are in flight.
-                    // The run ends at a step whose successor is not known that
+                    // next step's claims at once; while they are in flight it
+                    // does this step's pushes, pops the next slice, finds the
+                    // rank below it and reads that slice's entries ahead. The
+                    // run ends at a step whose successor is not known that
                     // way or has more centres, at the step limit, or (a job
                     // that can be cancelled) every 1024 steps; the last step
-                    // lists its direct pushes in s.cl for the general path.
+                    // pushes as a step of the general path and lists its
+                    // direct pushes in s.cl for it.
                     // (the second pass is issued in every step, with no lane
                     // active in a step of at most 10 centres: its claim words
                     // then stay in the same registers from step to step)
-                    uint32_t tt = t, c1 = cnt;
+                    uint32_t c1 = cnt;
                     uint32_t o0, u0, o1, u1;
-                    claim_pair(0, 6 * c1, k, a, s, o0, u0);
-                    claim_pair(1, 6 * c1, k, a, s, o1, u1);
+                    claim_run(6 * c1, k, a, s, L, o0, u0, o1, u1);
+                    s.head[r] = t;
+                    uint32_t below = lds_highest_below_uni(s, r);
+                    read_ahead(a, s, below, ah);
                     for (;;) {
-                        s.head[r] = tt;
-                        const uint32_t below = lds_highest_below_uni(s, r);
-                        read_ahead(a, s, below, ah);
                         // the claim words are not used past this point: the empty
                         // asm makes the compiler take their ranks and neighbour
                         // bits here, so the next step's claims can reuse their
@@ -896,7 +942,6 @@ __device__ inline void loop_body(const LoopArgs& a, LoopShared& s) {
                         const uint32_t cn = dir ? nrn : hit ? ah.t - ah.h : 0u;
                         const bool go = cn != 0 && cn <= kRunCentres && k + 1 <= klim &&
                                         !(kCancel && ((k + 1) & 1023u) == 0);
-                        uint32_t dn = 0;
                         if (go) {
                             const uint64_t lt = lanemask_lt();
                             if (dir) {
@@ -915,16 +960,31 @@ __device__ inline void loop_body(const LoopArgs& a, LoopShared& s) {
                                 s.clb[lane] = (uint8_t)nb_of(ah.c, a);
                             }
                             uint32_t p0, v0, p1, v1;
-                            claim_pair(0, 6 * cn, k + 1, a, s, p0, v0);
-                            claim_pair(1, 6 * cn, k + 1, a, s, p1, v1);
-                            push_won(w0, u0, b0, a, s, 0u, dn, k, r);
-                            if (c1 > 10) push_won(w1, u1, b1, a, s, 0u, dn, k, r);
+                            claim_run(6 * cn, k + 1, a, s, L, p0, v0, p1, v1);
+                            // This step's pushes: slice positions, and the
+                            // occupancy bit of every pushed rank (a step pushes
+                            // few voxels, so few same-address atomics), which
+                            // the search for the rank below the next one reads;
+                            // the bucket stores once the positions are back,
+                            // ahead of the read-ahead, which may read them.
+                            const bool g0 = w0 != 0, g1 = w1 != 0;
+                            uint32_t q0, h0, q1, h1;
+                            slice_pos(s, g0, w0, q0, h0);
+                            slice_pos(s, g1, w1, q1, h1);
+                            const uint32_t hrn = s.head[rn];  // (the next slice was empty: its tail is hrn + nrn)
+                            if (g0) lds_set(s, w0);
+                            if (g1) lds_set(s, w1);
+                            const uint32_t nbelow = lds_highest_below_uni(s, rn);
+                            const uint32_t t_next = dir ? hrn + nrn : ah.t;
+                            *(g0 ? &a.bucket[q0] : &a.M[k - 1]) = g0 ? u0 : r;
+                            *(g1 ? &a.bucket[q1] : &a.M[k - 1]) = g1 ? u1 : r;
                             a.M[k - 1] = r;
+                            read_ahead(a, s, nbelow, ah);
+                            s.head[rn] = t_next;  // the pop of the next step
                             prev_r = r;
                             r = rn;
+                            below = nbelow;
                             k = k + 1;
-                            // pop point of the next step: the tail after this step's pushes
-                            tt = dir ? uni(s.tail[rn]) : ah.t;
                             npop += cn;
                             c1 = cn;
                             o0 = p0;
@@ -933,6 +993,7 @@ __device__ inline void loop_body(const LoopArgs& a, LoopShared& s) {
                             u1 = v1;
                             continue;
                         }
+                        uint32_t dn = 0;
                         const uint32_t rd = dir ? rn : 0u;
                         push_won(w0, u0, b0, a, s, rd, dn, k, r);
                         if (c1 > 10) push_won(w1, u1, b1, a, s, rd, dn, k, r);
