@@ -557,18 +557,20 @@ __device__ inline void claim_pair(uint32_t p, uint32_t np, uint32_t k, const Loo
     a.state[c] = (int32_t)k;
 }
 
-// Pairs of a step of the run below, fixed per lane: pass p takes pair
-// 64p + lane, that is centre (64p + lane) / 6 of the step's list and
-// direction (64p + lane) % 6, its neighbour bit and its signed index offset.
+// Pairs of a wave-0 step, fixed per lane: pass p takes pair 64p + lane,
+// that is centre (64p + lane) / 6 of the step's list and direction
+// (64p + lane) % 6, with its neighbour bit and signed index offset. Three
+// passes are 192 pairs, 32 whole centres: pass p + 3 takes the direction of
+// pass p and the centre 32 further.
 struct RunLane {
-    uint32_t ci[2], bit[2];
-    int32_t off[2];
+    uint32_t ci[3], bit[3];
+    int32_t off[3];
 };
 
 __device__ inline RunLane run_lanes(const LoopArgs& a) {
     RunLane L;
 #pragma unroll
-    for (int p = 0; p < 2; p++) {
+    for (int p = 0; p < 3; p++) {
         const uint32_t i = (uint32_t)(p * 64) + (threadIdx.x & 63);
         const uint32_t d = i % 6u;
         const int32_t stride = d < 2 ? a.Y * a.Z : d < 4 ? a.Z : 1;
@@ -631,52 +633,16 @@ __device__ inline void read_ahead(const LoopArgs& a, const LoopShared& s, uint32
     ah.c = a.bucket[ok ? h + min((uint32_t)(threadIdx.x & 63), t - h - 1u) : 0u];
 }
 
-// Push the voxel of a won claim into the LDS slice of its rank and (kLogged)
-// the push log; a push of rank rn (the next step's rank, when every live
-// entry of its slice comes from this step) is also listed in s.cl for the
-// next step. A step of at most two passes needs no log: the step after it
-// either takes the list in s.cl or pops an older slice, from the bucket.
-// The bucket store is issued by every lane: one without a push writes the
-// step's rank r into M[k - 1], which holds it anyway. (A store under a lane
-// condition leaves the number of memory operations in flight unknown to the
-// compiler, which then waits for all of them wherever it needs a load's
-// result, as the next step's centres read ahead.)
-template <bool kLogged>
-__device__ inline void push_pair(uint32_t old, uint32_t u, const LoopArgs& a, LoopShared& s, uint32_t sel,
-                                 uint32_t& logn, uint32_t rn, uint32_t& dn, uint32_t k, uint32_t r) {
-    const uint32_t rr = won_rank(old);
-    const bool won = rr != 0;
-    uint32_t pos, hd;
-    slice_pos(s, won, rr, pos, hd);
-    const uint64_t lt = lanemask_lt();
-    uint32_t li = 0;
-    if (kLogged) {
-        const uint64_t m = __ballot(won);
-        li = logn + (uint32_t)__popcll(m & lt);
-        logn += (uint32_t)__popcll(m);
-    }
-    const bool nx = won && rr == rn;
-    const uint64_t mn = __ballot(nx);
-    const uint32_t di = dn + (uint32_t)__popcll(mn & lt);
-    dn += (uint32_t)__popcll(mn);
-    *(won ? &a.bucket[pos] : &a.M[k - 1]) = won ? u : r;
-    if (won) {
-        if (pos == hd) lds_set(s, rr);
-        if (kLogged && li < kLog) {
-            s.logu[sel][li] = u;
-            s.logr[sel][li] = old & ~kClaim;  // rank and in-image neighbour bits
-        }
-        if (nx && di < kSmallRound) {
-            s.cl[di] = u;
-            s.clb[di] = (uint8_t)(old >> kNbShift);
-        }
-    }
-}
-
 // Push of one (centre, direction) pair of a step of the run below, from the
 // won rank w (0: nothing to push) and the neighbour bits nb of the claimed
-// voxel u; a push of rank rd is also listed in s.cl for the next step. The
-// bucket store is issued by every lane, as in push_pair.
+// voxel u, into the LDS slice of its rank; a push of rank rd (the next
+// step's rank, when every live entry of its slice comes from this step) is
+// also listed in s.cl for the next step. The bucket store is issued by every
+// lane: one without a push writes the step's rank r into M[k - 1], which
+// holds it anyway. (A store under a lane condition leaves the number of
+// memory operations in flight unknown to the compiler, which then waits for
+// all of them wherever it needs a load's result, as the next step's centres
+// read ahead.)
 __device__ inline void push_won(uint32_t w, uint32_t u, uint32_t nb, const LoopArgs& a, LoopShared& s,
                                 uint32_t rd, uint32_t& dn, uint32_t k, uint32_t r) {
     const bool won = w != 0;
@@ -700,48 +666,81 @@ __device__ inline void push_won(uint32_t w, uint32_t u, uint32_t nb, const LoopA
 // alone; returns the next maximum rank: the highest pushed rank if above r
 // (every rank above r was empty), else r if its slice refilled, else the
 // larger of the highest pushed rank and the highest non-empty rank below r
-// (`below`, read while the claims are in flight). The claims of passes 2-5
-// join those of passes 0 and 1 before the first wait, and passes 6-11 go in
-// flight together. The pushes are logged for the next step.
+// (`below`, found while the claims are in flight). Every pass's claims are
+// issued first, four passes at a time with their list reads together; once
+// they are all back the pushes go four passes at a time, their slice-tail
+// atomics together, and are logged for the next step.
 __device__ inline uint32_t small_step(uint32_t cnt, uint32_t k, uint32_t r, uint32_t t, const LoopArgs& a,
-                                      LoopShared& s, uint32_t sel, uint32_t& logn, SliceAhead& ah) {
+                                      LoopShared& s, uint32_t sel, uint32_t& logn, SliceAhead& ah,
+                                      const RunLane& L) {
+    constexpr int kMaxPasses = (6 * kSmallRound + 63) / 64;  // 12
     const uint32_t np = 6 * cnt;
     const uint32_t passes = (np + 63) >> 6;
-    uint32_t o0, u0, o1 = kClaim, u1 = 0, dn = 0;
-    claim_pair(0, np, k, a, s, o0, u0);
-    claim_pair(1, np, k, a, s, o1, u1);
-    // pop slice r (its head moves to tail t) once the claims are out: only the
-    // pushes read it, and LDS operations complete in order, so a write ahead of
-    // the centre reads would delay them
+    const uint32_t lane = threadIdx.x & 63;
+    uint32_t o[kMaxPasses], u[kMaxPasses];
+#pragma unroll
+    for (int g = 0; g < kMaxPasses; g += 4) {
+        o[g] = o[g + 1] = o[g + 2] = o[g + 3] = kClaim;
+        u[g] = u[g + 1] = u[g + 2] = u[g + 3] = 0;
+        if ((uint32_t)g < passes) {
+            uint32_t cc[4], nbv[4];
+            bool act[4];
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const int p = g + j;
+                act[j] = (uint32_t)(64 * p) + lane < np;
+                const uint32_t ci = act[j] ? L.ci[p % 3] + 32u * (uint32_t)(p / 3) : 0u;
+                cc[j] = s.cl[ci];
+                nbv[j] = s.clb[ci];
+            }
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const int p = g + j;
+                const bool ok = act[j] & ((nbv[j] & L.bit[p % 3]) != 0u);
+                u[p] = cc[j] + (uint32_t)L.off[p % 3];
+                if (ok) o[p] = atomicOr(&a.key[u[p]], kClaim);
+            }
+            // (every lane stores: an idle lane that of centre 0)
+#pragma unroll
+            for (int j = 0; j < 4; j++) a.state[cc[j]] = (int32_t)k;
+        }
+    }
+    // pop slice r (its head moves to tail t) once the claims are out
     s.head[r] = t;
     const uint32_t below = lds_highest_below_uni(s, r);
     read_ahead(a, s, below, ah);
     uint32_t lm = 0;
     bool same = false;
-    for (uint32_t p = 2; p < passes; p += 4) {
-        uint32_t q0, v0, q1 = kClaim, v1 = 0, q2 = kClaim, v2 = 0, q3 = kClaim, v3 = 0;
-        claim_pair(p, np, k, a, s, q0, v0);
-        if (p + 1 < passes) claim_pair(p + 1, np, k, a, s, q1, v1);
-        if (p + 2 < passes) claim_pair(p + 2, np, k, a, s, q2, v2);
-        if (p + 3 < passes) claim_pair(p + 3, np, k, a, s, q3, v3);
-        if (p == 2) {
-            // (an empty asm that takes o0 and o1 keeps the compiler from
-            // computing their ranks, and so waiting for them, before the
-            // claims of passes 2-5 are issued)
-            asm volatile("" : "+v"(o0), "+v"(o1));
-            const uint32_t w0 = won_rank(o0), w1 = won_rank(o1);
-            lm = max(w0, w1);
-            same = w0 == r || w1 == r;
-            push_pair<true>(o0, u0, a, s, sel, logn, 0u, dn, k, r);
-            push_pair<true>(o1, u1, a, s, sel, logn, 0u, dn, k, r);
+    const uint64_t lt = lanemask_lt();
+#pragma unroll
+    for (int g = 0; g < kMaxPasses; g += 4) {
+        if ((uint32_t)g < passes) {
+            uint32_t w[4], pos[4], hd[4];
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                w[j] = won_rank(o[g + j]);
+                lm = max(lm, w[j]);
+                same |= w[j] == r;
+            }
+#pragma unroll
+            for (int j = 0; j < 4; j++) slice_pos(s, w[j] != 0, w[j], pos[j], hd[j]);
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const bool won = w[j] != 0;
+                const uint64_t m = __ballot(won);
+                const uint32_t li = logn + (uint32_t)__popcll(m & lt);
+                logn += (uint32_t)__popcll(m);
+                // (every lane stores, as in push_won)
+                *(won ? &a.bucket[pos[j]] : &a.M[k - 1]) = won ? u[g + j] : r;
+                if (won) {
+                    if (pos[j] == hd[j]) lds_set(s, w[j]);
+                    if (li < kLog) {
+                        s.logu[sel][li] = u[g + j];
+                        s.logr[sel][li] = o[g + j] & ~kClaim;  // rank and in-image neighbour bits
+                    }
+                }
+            }
         }
-        const uint32_t x0 = won_rank(q0), x1 = won_rank(q1), x2 = won_rank(q2), x3 = won_rank(q3);
-        lm = max(lm, max(max(x0, x1), max(x2, x3)));
-        same |= x0 == r || x1 == r || x2 == r || x3 == r;
-        push_pair<true>(q0, v0, a, s, sel, logn, 0u, dn, k, r);
-        if (p + 1 < passes) push_pair<true>(q1, v1, a, s, sel, logn, 0u, dn, k, r);
-        if (p + 2 < passes) push_pair<true>(q2, v2, a, s, sel, logn, 0u, dn, k, r);
-        if (p + 3 < passes) push_pair<true>(q3, v3, a, s, sel, logn, 0u, dn, k, r);
     }
     const uint32_t pmax = wave_max_u32(lm);
     const bool refilled = __ballot(same) != 0;
@@ -1008,7 +1007,7 @@ __device__ inline void loop_body(const LoopArgs& a, LoopShared& s) {
                     nlog = kLog + 1;
                     continue;
                 }
-                const uint32_t rn = small_step(cnt, k, r, t, a, s, nsel, ln, ah);
+                const uint32_t rn = small_step(cnt, k, r, t, a, s, nsel, ln, ah, L);
                 a.M[k - 1] = r;
                 prev_r = r;
                 r = rn;
@@ -1616,7 +1615,6 @@ __global__ __launch_bounds__(256) void k_paint_full(PaintArgs a) {
     const int lane = threadIdx.x & 63;
     const uint32_t nf = *a.n_full;
     const uint32_t f0 = a.full_lo ? *a.full_lo : 0u;
-    const int64_t yz = (int64_t)a.Y * a.Z;
     int64_t nblocks;
     const int64_t b = paint_block(a, nblocks);
     if (b < 0) return;
