@@ -78,6 +78,11 @@ __device__ inline uint32_t nb_bits(uint32_t x, uint32_t y, uint32_t z, int X, in
            (y + 1 < (uint32_t)Y ? 8u : 0u) | (z > 0 ? 16u : 0u) | (z + 1 < (uint32_t)Z ? 32u : 0u);
 }
 
+// number of set bits of m in the lanes below this one
+__device__ inline uint32_t lanes_below(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
 __device__ inline uint64_t lanemask_lt() {
     const int lane = threadIdx.x & 63;
     return lane == 0 ? 0ull : (~0ull >> (64 - lane));
@@ -650,7 +655,7 @@ __device__ inline void push_won(uint32_t w, uint32_t u, uint32_t nb, const LoopA
     slice_pos(s, won, w, pos, hd);
     const bool nx = won && w == rd;
     const uint64_t mn = __ballot(nx);
-    const uint32_t di = dn + (uint32_t)__popcll(mn & lanemask_lt());
+    const uint32_t di = dn + lanes_below(mn);
     dn += (uint32_t)__popcll(mn);
     *(won ? &a.bucket[pos] : &a.M[k - 1]) = won ? u : r;
     if (won) {
@@ -934,7 +939,8 @@ __device__ inline void loop_body(const LoopArgs& a, LoopShared& s) {
                         const uint32_t rn = pmax > r ? pmax : refilled ? r : max(below, pmax);
                         const bool dir = rn != 0 && rn != below;
                         // won pushes of rank rn (a lane that won nothing has w = 0)
-                        const uint64_t m0 = __ballot(rn != 0 && w0 == rn), m1 = __ballot(rn != 0 && w1 == rn);
+                        const bool x0 = rn != 0 && w0 == rn, x1 = rn != 0 && w1 == rn;
+                        const uint64_t m0 = __ballot(x0), m1 = __ballot(x1);
                         const uint32_t n0 = (uint32_t)__popcll(m0);
                         const uint32_t nrn = n0 + (uint32_t)__popcll(m1);
                         const bool hit = !dir && rn != 0 && rn == ah.r && nrn == 0;
@@ -942,15 +948,14 @@ __device__ inline void loop_body(const LoopArgs& a, LoopShared& s) {
                         const bool go = cn != 0 && cn <= kRunCentres && k + 1 <= klim &&
                                         !(kCancel && ((k + 1) & 1023u) == 0);
                         if (go) {
-                            const uint64_t lt = lanemask_lt();
                             if (dir) {
-                                if ((m0 >> lane) & 1u) {
-                                    const uint32_t i = (uint32_t)__popcll(m0 & lt);
+                                if (x0) {
+                                    const uint32_t i = lanes_below(m0);
                                     s.cl[i] = u0;
                                     s.clb[i] = (uint8_t)b0;
                                 }
-                                if ((m1 >> lane) & 1u) {
-                                    const uint32_t i = n0 + (uint32_t)__popcll(m1 & lt);
+                                if (x1) {
+                                    const uint32_t i = n0 + lanes_below(m1);
                                     s.cl[i] = u1;
                                     s.clb[i] = (uint8_t)b1;
                                 }
