@@ -10,7 +10,10 @@
 // o^2 >= best (every farther i adds at least o^2), which is exact; its cost is
 // O(distance) per voxel, small in porous media.
 // Threads of a wave own consecutive z, so every global access of the y and x
-// passes is a contiguous 64-element segment.
+// passes is a contiguous segment. Pass y, and pass x on lines long enough
+// that its 32-bit tile would leave a compute unit a single workgroup, run in
+// packed 16-bit arithmetic with two columns per lane: exact for results
+// below 65535, searched again exactly from HBM above.
 #include "ibip_internal.h"
 
 namespace ibip {
@@ -533,6 +536,122 @@ __global__ __launch_bounds__(kThreadsY) void edt_pass_y_vec(const uint16_t* __re
     }
 }
 
+// Pass y in packed 16-bit arithmetic, two columns per lane. The tile holds
+// min(g^2, 65535) (g < 256 squares exactly; a larger g and the sentinel
+// become 65535), so one 32-bit LDS read gives a lane both of its columns and
+// each candidate costs one saturating packed add (v_pk_add_u16 with clamp)
+// and one packed min for two voxels. A result below 65535 is exact: the
+// minimum's candidate is then below 65535 itself, and every candidate that
+// saturated is at least 65535. A result of 65535 where the cap allows more is
+// searched again exactly, from the distances in HBM (a 2D distance of 256
+// voxels or more; none on the workloads here). The search of a pair of
+// columns goes on until both are settled, and at most to offset 256 (every
+// candidate farther out is at least 65536).
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+__device__ inline u16x2 as_u16x2(uint32_t v) { return __builtin_bit_cast(u16x2, v); }
+__device__ inline uint32_t as_u32(u16x2 v) { return __builtin_bit_cast(uint32_t, v); }
+
+// min(g^2, 65535) of a distance along z (0x7FFF = no feature)
+__device__ inline uint32_t sq16(uint32_t gv) { return gv < 256u ? gv * gv : 65535u; }
+
+// the exact search of pass y for one voxel, reading the distances in HBM
+__device__ inline uint32_t pass_y_exact(const uint16_t* g, int64_t v, int y, int Y, int Z, uint64_t cap) {
+    const uint16_t f = g[v];
+    uint64_t best = f == kInf16 ? cap : (uint64_t)f * f;
+    const int far = max(y, Y - 1 - y);
+    for (int o = 1; o <= far; o++) {
+        const uint64_t oo = (uint64_t)o * o;
+        if (oo >= best) break;
+        if (y - o >= 0) {
+            const uint16_t fl = g[v - (int64_t)o * Z];
+            if (fl != kInf16) best = min(best, (uint64_t)fl * fl + oo);
+        }
+        if (y + o < Y) {
+            const uint16_t fr = g[v + (int64_t)o * Z];
+            if (fr != kInf16) best = min(best, (uint64_t)fr * fr + oo);
+        }
+    }
+    return (uint32_t)min(best, (uint64_t)0xFFFFFFFFu);
+}
+
+template <int TW, bool V>
+__global__ __launch_bounds__(kThreadsY) void edt_pass_y_pk(const uint16_t* __restrict__ g, int X, int Y, int Z,
+                                                          uint64_t cap, uint32_t* __restrict__ h) {
+    extern __shared__ uint16_t t16[];  // [kPad + Y + kPad][TW]: min(g^2, 65535)
+    constexpr int kSegs = TW / 8, kRows = kThreadsY / kSegs;
+    const int nzc = (Z + TW - 1) / TW;
+    const int x = blockIdx.x / nzc;
+    const int z0 = (blockIdx.x - x * nzc) * TW;
+    const int64_t plane = (int64_t)x * Y * Z;
+    if (!V) {
+        for (int i = threadIdx.x; i < Y * TW; i += kThreadsY) {
+            const int y = i / TW, lz = i - y * TW, zc = z0 + lz;
+            t16[(y + kPad) * TW + lz] =
+                (uint16_t)(zc < Z ? sq16(g[plane + (int64_t)y * Z + zc] & 0x7FFFu) : 65535u);
+        }
+    } else {
+        const int seg = threadIdx.x % kSegs;
+        const int zc = z0 + seg * 8;
+        for (int y = threadIdx.x / kSegs; y < Y; y += kRows) {
+            uint4 w = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
+            if (zc < Z) {
+                const uint4 r = *reinterpret_cast<const uint4*>(g + plane + (int64_t)y * Z + zc);
+                w.x = sq16(r.x & 0x7FFFu) | sq16((r.x >> 16) & 0x7FFFu) << 16;
+                w.y = sq16(r.y & 0x7FFFu) | sq16((r.y >> 16) & 0x7FFFu) << 16;
+                w.z = sq16(r.z & 0x7FFFu) | sq16((r.z >> 16) & 0x7FFFu) << 16;
+                w.w = sq16(r.w & 0x7FFFu) | sq16((r.w >> 16) & 0x7FFFu) << 16;
+            }
+            *reinterpret_cast<uint4*>(t16 + (y + kPad) * TW + seg * 8) = w;
+        }
+    }
+    for (int i = threadIdx.x; i < 2 * kPad * TW; i += kThreadsY) {
+        const int r = i / TW;
+        t16[(r < kPad ? r : Y + r) * TW + (i - r * TW)] = (uint16_t)65535u;
+    }
+    __syncthreads();
+    constexpr int LC = TW / 2;             // lanes per tile row
+    constexpr int RPI = kThreadsY / LC;    // rows per round
+    const int lc = threadIdx.x % LC;
+    const int z = z0 + 2 * lc;
+    if (z >= Z) return;
+    const uint32_t capv = (uint32_t)cap;
+    const uint32_t lim = min(capv, kSentSq);
+    const uint32_t c16 = min(capv, 65535u);
+    const u16x2 capp = as_u16x2(c16 | c16 << 16);
+    const uint32_t* col = reinterpret_cast<const uint32_t*>(t16 + kPad * TW) + lc;  // row i at col[i * LC]
+    for (int y = threadIdx.x / LC; y < Y; y += RPI) {
+        u16x2 best = __builtin_elementwise_min(as_u16x2(col[y * LC]), capp);
+        uint32_t bb = as_u32(best);
+        uint32_t bmax = max(bb & 0xFFFFu, bb >> 16);
+        if (bmax > 1) {
+            const int far = min(max(y, Y - 1 - y), 256);
+            for (int o = 1; o <= far && (uint32_t)(o * o) < bmax; o += 4) {
+                const uint32_t* lp = col + (y - o >= 0 ? y - o : -1) * LC;
+                const uint32_t* rp = col + (y + o < Y ? y + o : Y) * LC;
+#pragma unroll
+                for (int j = 0; j < 4; j++) {
+                    const uint32_t oo = min((uint32_t)((o + j) * (o + j)), 65535u);
+                    const u16x2 oop = as_u16x2(oo | oo << 16);
+                    best = __builtin_elementwise_min(best, __builtin_elementwise_add_sat(as_u16x2(lp[-j * LC]), oop));
+                    best = __builtin_elementwise_min(best, __builtin_elementwise_add_sat(as_u16x2(rp[j * LC]), oop));
+                }
+                bb = as_u32(best);
+                bmax = max(bb & 0xFFFFu, bb >> 16);
+            }
+        }
+        bb = as_u32(best);
+#pragma unroll
+        for (int e = 0; e < 2; e++) {
+            if (z + e >= Z) break;
+            const int64_t v = plane + (int64_t)y * Z + z + e;
+            uint32_t r = e ? bb >> 16 : bb & 0xFFFFu;
+            if (r == 65535u && capv > 65535u) r = pass_y_exact(g, v, y, Y, Z, cap);
+            h[v] = r >= lim ? kInf32 : r;
+        }
+    }
+}
+
 // TW: z columns per tile (16: 64-byte tile rows; 32: whole 128-byte lines).
 // V: rows of Z % 4 == 0 voxels, loaded with 16-byte vectors; otherwise the
 // tile is loaded element by element.
@@ -609,6 +728,111 @@ __global__ __launch_bounds__(kThreadsX) void edt_pass_x_vec(const uint32_t* __re
     if (count) block_add_slots(count, hits);
 }
 
+// Pass x in packed 16-bit arithmetic, as pass y above: the tile holds
+// min(h, 65535) (h = 0xFFFFFFFF, no feature in the plane, becomes 65535),
+// two columns per lane; a result of 65535 where the cap allows more is
+// searched again exactly from h in HBM.
+__device__ inline uint32_t pass_x_exact(const uint32_t* hin, int64_t v, int x, int X, int64_t yz, uint64_t cap) {
+    const uint32_t f = hin[v];
+    uint64_t best = f == kInf32 ? cap : (uint64_t)f;
+    const int far = max(x, X - 1 - x);
+    for (int o = 1; o <= far; o++) {
+        const uint64_t oo = (uint64_t)o * o;
+        if (oo >= best) break;
+        if (x - o >= 0) {
+            const uint32_t fl = hin[v - (int64_t)o * yz];
+            if (fl != kInf32) best = min(best, (uint64_t)fl + oo);
+        }
+        if (x + o < X) {
+            const uint32_t fr = hin[v + (int64_t)o * yz];
+            if (fr != kInf32) best = min(best, (uint64_t)fr + oo);
+        }
+    }
+    return (uint32_t)min(best, (uint64_t)0xFFFFFFFFu);
+}
+
+template <class Out, int TW, bool V>
+__global__ __launch_bounds__(kThreadsX) void edt_pass_x_pk(const uint32_t* __restrict__ hin, int X, int Y, int Z,
+                                                          uint64_t cap, Out outp, uint32_t* count) {
+    extern __shared__ uint16_t t16[];  // [kPad + X + kPad][TW]: min(h, 65535)
+    constexpr int kSegs = TW / 4, kRows = kThreadsX / kSegs;
+    const int nzc = (Z + TW - 1) / TW;
+    const int y = blockIdx.x / nzc;
+    const int z0 = (blockIdx.x - y * nzc) * TW;
+    const int64_t yz = (int64_t)Y * Z;
+    const int64_t col0 = (int64_t)y * Z + z0;
+    if (!V) {
+        for (int i = threadIdx.x; i < X * TW; i += kThreadsX) {
+            const int x = i / TW, lz = i - x * TW;
+            t16[(x + kPad) * TW + lz] = (uint16_t)(z0 + lz < Z ? min(hin[x * yz + col0 + lz], 65535u) : 65535u);
+        }
+    } else {
+        const int seg = threadIdx.x % kSegs;
+        const int zc = z0 + seg * 4;
+        for (int x = threadIdx.x / kSegs; x < X; x += kRows) {
+            uint2 w = make_uint2(0xFFFFFFFFu, 0xFFFFFFFFu);
+            if (zc < Z) {
+                const uint4 r = *reinterpret_cast<const uint4*>(hin + x * yz + col0 + seg * 4);
+                w.x = min(r.x, 65535u) | min(r.y, 65535u) << 16;
+                w.y = min(r.z, 65535u) | min(r.w, 65535u) << 16;
+            }
+            *reinterpret_cast<uint2*>(t16 + (x + kPad) * TW + seg * 4) = w;
+        }
+    }
+    for (int i = threadIdx.x; i < 2 * kPad * TW; i += kThreadsX) {
+        const int r = i / TW;
+        t16[(r < kPad ? r : X + r) * TW + (i - r * TW)] = (uint16_t)65535u;
+    }
+    __syncthreads();
+    constexpr int LC = TW / 2;             // lanes per tile row
+    constexpr int RPI = kThreadsX / LC;    // rows per round
+    const int lc = threadIdx.x % LC;
+    const int z = z0 + 2 * lc;
+    uint32_t hits = 0;
+    if (z < Z) {
+        const uint32_t capv = (uint32_t)cap;
+        const uint32_t lim = min(capv, kSent32);
+        const uint32_t c16 = min(capv, 65535u);
+        const u16x2 capp = as_u16x2(c16 | c16 << 16);
+        const uint32_t* col = reinterpret_cast<const uint32_t*>(t16 + kPad * TW) + lc;  // row i at col[i * LC]
+        for (int x = threadIdx.x / LC; x < X; x += RPI) {
+            u16x2 best = __builtin_elementwise_min(as_u16x2(col[x * LC]), capp);
+            uint32_t bb = as_u32(best);
+            uint32_t bmax = max(bb & 0xFFFFu, bb >> 16);
+            if (bmax > 1) {
+                const int far = min(max(x, X - 1 - x), 256);
+                for (int o = 1; o <= far && (uint32_t)(o * o) < bmax; o += 4) {
+                    const uint32_t* lp = col + (x - o >= 0 ? x - o : -1) * LC;
+                    const uint32_t* rp = col + (x + o < X ? x + o : X) * LC;
+#pragma unroll
+                    for (int j = 0; j < 4; j++) {
+                        const uint32_t oo = min((uint32_t)((o + j) * (o + j)), 65535u);
+                        const u16x2 oop = as_u16x2(oo | oo << 16);
+                        best = __builtin_elementwise_min(best,
+                                                         __builtin_elementwise_add_sat(as_u16x2(lp[-j * LC]), oop));
+                        best = __builtin_elementwise_min(best,
+                                                         __builtin_elementwise_add_sat(as_u16x2(rp[j * LC]), oop));
+                    }
+                    bb = as_u32(best);
+                    bmax = max(bb & 0xFFFFu, bb >> 16);
+                }
+            }
+            bb = as_u32(best);
+#pragma unroll
+            for (int e = 0; e < 2; e++) {
+                if (z + e >= Z) break;
+                const int64_t v = x * yz + col0 + 2 * lc + e;
+                uint32_t r = e ? bb >> 16 : bb & 0xFFFFu;
+                if (r == 65535u && capv > 65535u) r = pass_x_exact(hin, v, x, X, yz, cap);
+                const uint64_t b = r >= lim ? (uint64_t)cap : (uint64_t)r;
+                outp.put(v, b, cap);
+                hits += outp.hit(v, b);
+            }
+        }
+    }
+    if (count) block_add_slots(count, hits);
+}
+
 // LDS a workgroup may use on the current device (the pass-x tile of a
 // 512-voxel line takes 66.5 KB, of a 1024-voxel line 132 KB).
 size_t max_lds_per_block() {
@@ -622,6 +846,31 @@ size_t max_lds_per_block() {
         cached[dev] = (size_t)v;
     }
     return cached[dev];
+}
+
+// Pass x in the tiled form: the packed 16-bit kernel (pk) or the 32-bit one,
+// with tiles of tx z columns and 16-byte loads (xv) or not.
+template <class Out>
+void launch_pass_x(bool pk, int tx, bool xv, dim3 gx, size_t lds_bytes, hipStream_t s, const uint32_t* in,
+                   ibip_dims d, uint64_t c64, Out o, uint32_t* count) {
+    const dim3 b(kThreadsX);
+    if (pk) {
+        if (tx == 16) {
+            if (xv) hipLaunchKernelGGL((edt_pass_x_pk<Out, 16, true>), gx, b, lds_bytes, s, in, d.X, d.Y, d.Z, c64, o, count);
+            else hipLaunchKernelGGL((edt_pass_x_pk<Out, 16, false>), gx, b, lds_bytes, s, in, d.X, d.Y, d.Z, c64, o, count);
+        } else {
+            if (xv) hipLaunchKernelGGL((edt_pass_x_pk<Out, 32, true>), gx, b, lds_bytes, s, in, d.X, d.Y, d.Z, c64, o, count);
+            else hipLaunchKernelGGL((edt_pass_x_pk<Out, 32, false>), gx, b, lds_bytes, s, in, d.X, d.Y, d.Z, c64, o, count);
+        }
+    } else {
+        if (tx == 16) {
+            if (xv) hipLaunchKernelGGL((edt_pass_x_vec<Out, 16, true>), gx, b, lds_bytes, s, in, d.X, d.Y, d.Z, c64, o, count);
+            else hipLaunchKernelGGL((edt_pass_x_vec<Out, 16, false>), gx, b, lds_bytes, s, in, d.X, d.Y, d.Z, c64, o, count);
+        } else {
+            if (xv) hipLaunchKernelGGL((edt_pass_x_vec<Out, 32, true>), gx, b, lds_bytes, s, in, d.X, d.Y, d.Z, c64, o, count);
+            else hipLaunchKernelGGL((edt_pass_x_vec<Out, 32, false>), gx, b, lds_bytes, s, in, d.X, d.Y, d.Z, c64, o, count);
+        }
+    }
 }
 
 }  // namespace
@@ -641,7 +890,8 @@ hipError_t launch_edt(const uint8_t* image, const uint32_t* w, uint32_t thr, uin
     // with the sentinels cannot reach 2^31) and the tile fits in LDS, loading
     // their tiles with 16-byte vectors when the rows allow it. The other forms
     // read and write the same layouts.
-    const size_t ly = sizeof(uint16_t) * ty * (d.Y + 2 * kPad), lx = sizeof(uint32_t) * tx * (d.X + 2 * kPad);
+    const size_t ly = sizeof(uint16_t) * ty * (d.Y + 2 * kPad), lx32 = sizeof(uint32_t) * tx * (d.X + 2 * kPad),
+                 lx16 = sizeof(uint16_t) * tx * (d.X + 2 * kPad);
     const size_t lds = max_lds_per_block();
     const bool in_al = image ? ((uintptr_t)image & 7) == 0 : ((uintptr_t)w & 15) == 0;
     // pass z: P voxels per lane (8 for rows up to 512, else 16), vectors when
@@ -649,6 +899,12 @@ hipError_t launch_edt(const uint8_t* image, const uint32_t* w, uint32_t thr, uin
     const int zp = d.Z <= 512 ? 8 : d.Z <= kMaxVecLine ? 16 : 0;
     const bool zal = zp && in_al && d.Z % zp == 0;
     const bool yvec = d.Z <= kMaxVecLine && d.Y <= kMaxVecLine && ly <= lds;
+    // pass x packed (16-bit tile) when two 1024-thread workgroups' 32-bit tiles
+    // would not fit in a compute unit's LDS: on 512-voxel lines the 32-bit
+    // kernel is faster (two columns per lane search as long as the longer of
+    // the two), on 768 the packed one (twice the workgroups per unit)
+    const bool xpk = 2 * lx32 > lds;
+    const size_t lx = xpk ? lx16 : lx32;
     const bool xvec = yvec && d.X <= kMaxVecLine && lx <= lds;
     const bool yv = d.Z % 8 == 0, xv = d.Z % 4 == 0;  // rows that 16-byte loads can take
     const int64_t rows = (int64_t)d.X * d.Y;
@@ -707,13 +963,13 @@ hipError_t launch_edt(const uint8_t* image, const uint32_t* w, uint32_t thr, uin
         const unsigned nzy = (unsigned)((d.Z + ty - 1) / ty);
         const dim3 gy((unsigned)d.X * nzy);
         if (ty == 64 && yv)
-            hipLaunchKernelGGL((edt_pass_y_vec<64, true>), gy, dim3(kThreadsY), ly, s, g16, d.X, d.Y, d.Z, c64, tmp32);
+            hipLaunchKernelGGL((edt_pass_y_pk<64, true>), gy, dim3(kThreadsY), ly, s, g16, d.X, d.Y, d.Z, c64, tmp32);
         else if (ty == 64)
-            hipLaunchKernelGGL((edt_pass_y_vec<64, false>), gy, dim3(kThreadsY), ly, s, g16, d.X, d.Y, d.Z, c64, tmp32);
+            hipLaunchKernelGGL((edt_pass_y_pk<64, false>), gy, dim3(kThreadsY), ly, s, g16, d.X, d.Y, d.Z, c64, tmp32);
         else if (yv)
-            hipLaunchKernelGGL((edt_pass_y_vec<32, true>), gy, dim3(kThreadsY), ly, s, g16, d.X, d.Y, d.Z, c64, tmp32);
+            hipLaunchKernelGGL((edt_pass_y_pk<32, true>), gy, dim3(kThreadsY), ly, s, g16, d.X, d.Y, d.Z, c64, tmp32);
         else
-            hipLaunchKernelGGL((edt_pass_y_vec<32, false>), gy, dim3(kThreadsY), ly, s, g16, d.X, d.Y, d.Z, c64, tmp32);
+            hipLaunchKernelGGL((edt_pass_y_pk<32, false>), gy, dim3(kThreadsY), ly, s, g16, d.X, d.Y, d.Z, c64, tmp32);
     } else if (d.Y <= kMaxTileLine) {
         const int nzc = (d.Z + kW - 1) / kW;
         hipLaunchKernelGGL(edt_pass_y_tile, dim3((unsigned)(d.X * nzc)), dim3(256), sizeof(uint16_t) * kW * d.Y, s,
@@ -727,41 +983,10 @@ hipError_t launch_edt(const uint8_t* image, const uint32_t* w, uint32_t thr, uin
         const OutOpening oo{mio_r2, cap};
         const OutPlain op{out};
         uint32_t* const nocount = nullptr;
-        const int form = (mio_r2 ? 4 : 0) + (tx == 16 ? 2 : 0) + (xv ? 1 : 0);
-        switch (form) {
-            case 7:
-                hipLaunchKernelGGL((edt_pass_x_vec<OutOpening, 16, true>), gx, dim3(kThreadsX), lx, s, tmp32,
-                                   d.X, d.Y, d.Z, c64, oo, mio_count);
-                break;
-            case 6:
-                hipLaunchKernelGGL((edt_pass_x_vec<OutOpening, 16, false>), gx, dim3(kThreadsX), lx, s, tmp32,
-                                   d.X, d.Y, d.Z, c64, oo, mio_count);
-                break;
-            case 5:
-                hipLaunchKernelGGL((edt_pass_x_vec<OutOpening, 32, true>), gx, dim3(kThreadsX), lx, s, tmp32,
-                                   d.X, d.Y, d.Z, c64, oo, mio_count);
-                break;
-            case 4:
-                hipLaunchKernelGGL((edt_pass_x_vec<OutOpening, 32, false>), gx, dim3(kThreadsX), lx, s, tmp32,
-                                   d.X, d.Y, d.Z, c64, oo, mio_count);
-                break;
-            case 3:
-                hipLaunchKernelGGL((edt_pass_x_vec<OutPlain, 16, true>), gx, dim3(kThreadsX), lx, s, tmp32,
-                                   d.X, d.Y, d.Z, c64, op, nocount);
-                break;
-            case 2:
-                hipLaunchKernelGGL((edt_pass_x_vec<OutPlain, 16, false>), gx, dim3(kThreadsX), lx, s, tmp32,
-                                   d.X, d.Y, d.Z, c64, op, nocount);
-                break;
-            case 1:
-                hipLaunchKernelGGL((edt_pass_x_vec<OutPlain, 32, true>), gx, dim3(kThreadsX), lx, s, tmp32,
-                                   d.X, d.Y, d.Z, c64, op, nocount);
-                break;
-            default:
-                hipLaunchKernelGGL((edt_pass_x_vec<OutPlain, 32, false>), gx, dim3(kThreadsX), lx, s, tmp32,
-                                   d.X, d.Y, d.Z, c64, op, nocount);
-                break;
-        }
+        if (mio_r2)
+            launch_pass_x(xpk, tx, xv, gx, lx, s, tmp32, d, c64, oo, mio_count);
+        else
+            launch_pass_x(xpk, tx, xv, gx, lx, s, tmp32, d, c64, op, nocount);
         return hipGetLastError();
     }
     const int nzcx = (d.Z + kWx - 1) / kWx;
