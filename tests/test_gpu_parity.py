@@ -109,6 +109,30 @@ def test_edt_vector_path_long_lines(dev, shape, tiles):
         ibip.set_tuning(None)
 
 
+@pytest.mark.parametrize("shape", [(1, 600, 16), (2, 800, 24), (3, 1000, 8), (700, 2, 8), (768, 3, 16), (1000, 1, 8)])
+@pytest.mark.parametrize("tiles", [None, (64, 32)])
+def test_edt_packed_saturation(dev, shape, tiles):
+    """One solid voxel in a corner: distances past 256 voxels, so the packed
+    16-bit passes (pass y; pass x on lines above about 600 voxels) saturate at
+    65535 and search those voxels again exactly; values around 65535 on both
+    sides. Also the opening's capped transform with caps around 65535."""
+    img = np.ones(shape, np.uint8)
+    img[0, 0, 0] = 0
+    if tiles is not None:
+        ibip.set_tuning({"edt_tile_y": tiles[0], "edt_tile_x": tiles[1]})
+    try:
+        r = oracle.edt(img)
+        assert int((r >= 65535).sum()) > 0 and int(((r > 60000) & (r < 65535)).sum()) > 0
+        np.testing.assert_array_equal(_u32(ibip.edt(_d(img, dev))), r)
+        if shape[0] <= 3:
+            inl = synth.face_mask(shape, 1, 0)
+            T = np.array([70000, 65536, 65535, 100], np.uint32)
+            m = ibip.opening_drainage(_d(img, dev), _d(inl, dev), T.tolist())
+            np.testing.assert_array_equal(_u32(m["mio_r2"]), oracle.mio(img, inl, T)["mio_r2"])
+    finally:
+        ibip.set_tuning(None)
+
+
 @pytest.mark.parametrize("shape", [(3, 5, 8), (1, 40, 64), (17, 33, 200), (512, 2, 16), (2, 512, 24), (9, 7, 512),
                                    (5, 3, 96), (1, 1, 8)])
 @pytest.mark.parametrize("p", [0.6, 0.995])
