@@ -14,6 +14,8 @@
 // that its 32-bit tile would leave a compute unit a single workgroup, run in
 // packed 16-bit arithmetic with two columns per lane: exact for results
 // below 65535, searched again exactly from HBM above.
+#include <cmath>
+
 #include "ibip_internal.h"
 
 namespace ibip {
@@ -329,6 +331,9 @@ struct FeatImage8 {
         return b;
     }
     __device__ bool bit(int64_t v) const { return img[v] == 0; }
+    // the bytes of voxels v..v+7 (v % 8 == 0)
+    __device__ uint2 bytes8(int64_t v) const { return *reinterpret_cast<const uint2*>(img + v); }
+    static constexpr bool kBytes = true;
 };
 struct FeatThreshold8 {
     const uint32_t* w;
@@ -341,57 +346,172 @@ struct FeatThreshold8 {
                (c.w >= thr ? 128u : 0u);
     }
     __device__ bool bit(int64_t v) const { return w[v] >= thr; }
+    __device__ uint2 bytes8(int64_t) const { return make_uint2(0u, 0u); }
+    static constexpr bool kBytes = false;
 };
 
 // Pass z with the whole row in registers: a lane owns P = 8 (rows of at most
 // 512 voxels) or 16 (at most 1024) consecutive voxels, a row spans lpr = Z / P
 // lanes, a wave holds 64 / lpr rows. The nearest feature before / after each
-// lane's voxels comes from a max / min scan over the row's lanes.
+// lane's voxels comes from a max / min scan over the row's lanes (DPP moves
+// when the row fills the wave, lane shuffles otherwise); within the lane, the
+// distances to them run as two packed 16-bit chains. Everything a voxel needs
+// is 16-bit (distances below 1024, 65535 for none), so no 32- or 64-bit
+// product is formed: the cap d^2 >= cap becomes d >= dcap, the least such d.
 constexpr int kZGroups = 4;  // row groups per wave, their loads issued together
 constexpr int kMaxVecLine = 1024;  // longest row or line of the vectorised passes
 
-// pass z of one row group: lane li of lpr holds feature bits fb of voxels
-// v0..v0+P-1 of its row (the first nv of them inside the row); writes their
-// distances along z, with 16-byte stores when the rows are aligned (Al)
-template <int P, bool Al>
-__device__ inline void pass_z_rows(uint32_t fb, bool act, int64_t v0, int li, int lpr, int nv, uint64_t cap,
-                                   uint16_t* g) {
-    const int zb = li * P;
-    // nearest feature at or before the end of this lane's voxels
-    int incl = fb ? zb + 31 - __clz(fb) : -1;
-    // nearest feature at or after the start of this lane's voxels
-    int incr = fb ? zb + __ffs(fb) - 1 : 0x7FFFFFFF;
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+__device__ inline u16x2 as_u16x2(uint32_t v) { return __builtin_bit_cast(u16x2, v); }
+__device__ inline uint32_t as_u32(u16x2 v) { return __builtin_bit_cast(uint32_t, v); }
+
+// DPP moves within the wave: a lane without a source keeps `idle`
+template <int kCtrl, int kRowMask = 0xf>
+__device__ inline int dpp_or(int idle, int v) {
+    return __builtin_amdgcn_update_dpp(idle, v, kCtrl, kRowMask, 0xf, false);
+}
+
+// Over a wave holding one row (64 lanes): the maximum of v over the lanes at
+// or below this one (row shifts within rows of 16, then the last lane of a
+// row broadcast to the rows above), and the minimum of w over the lanes at or
+// above this one (row shifts the other way, then the first lanes of the rows
+// above, read as scalars). A lane without a source takes the operation's
+// identity, so each move folds into the max or min that takes it.
+__device__ inline void wave_scans(int& v, int& w) {
+    constexpr int kLo = INT_MIN, kHi = INT_MAX;
+    v = max(v, dpp_or<0x111>(kLo, v));  // row_shr:1
+    w = min(w, dpp_or<0x101>(kHi, w));  // row_shl:1
+    v = max(v, dpp_or<0x112>(kLo, v));
+    w = min(w, dpp_or<0x102>(kHi, w));
+    v = max(v, dpp_or<0x114>(kLo, v));
+    w = min(w, dpp_or<0x104>(kHi, w));
+    v = max(v, dpp_or<0x118>(kLo, v));
+    w = min(w, dpp_or<0x108>(kHi, w));
+    v = max(v, dpp_or<0x142, 0xa>(kLo, v));  // row_bcast:15 into rows 1 and 3
+    v = max(v, dpp_or<0x143, 0xc>(kLo, v));  // row_bcast:31 into rows 2 and 3
+    const int m3 = __builtin_amdgcn_readlane(w, 48), m2 = min(__builtin_amdgcn_readlane(w, 32), m3),
+              m1 = min(__builtin_amdgcn_readlane(w, 16), m2);
+    const int lane = threadIdx.x & 63;
+    int t = lane < 48 ? m3 : kHi;
+    t = lane < 32 ? m2 : t;
+    t = lane < 16 ? m1 : t;
+    w = min(w, t);
+}
+
+// The chains' step factors from the lane's P image bytes (nonzero: not a
+// feature), without going through single bits: tj[j] holds 1 in its low half
+// where voxel j is not a feature and 1 in its high half where voxel P-1-j is
+// not, 0 elsewhere; fb gets the feature bits.
+template <int P>
+__device__ inline void byte_factors(const uint32_t (&raw)[P / 4], uint32_t (&tj)[P], uint32_t& fb) {
+    // nz[2q + e]: voxels 4q + e and 4q + e + 2 (the bytes e and e + 2 of raw[q])
+    uint32_t nz[P / 2];
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int a = __shfl_up(incl, o, 64);
-        const int b = __shfl_down(incr, o, 64);
-        if (o < lpr) {
-            if (li >= o) incl = max(incl, a);
-            if (li + o < lpr) incr = min(incr, b);
-        }
+    for (int q = 0; q < P / 4; q++) {
+        // bit 7 of each byte of y: that byte is nonzero (no carry crosses a byte)
+        const uint32_t y = ((raw[q] & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | raw[q];
+        nz[2 * q] = y >> 7 & 0x00010001u;
+        nz[2 * q + 1] = y >> 15 & 0x00010001u;
     }
-    int prev = __shfl_up(incl, 1, 64);
-    int next = __shfl_down(incr, 1, 64);
-    if (li == 0) prev = -1;
-    if (li == lpr - 1) next = 0x7FFFFFFF;
-    uint32_t d[P];
 #pragma unroll
     for (int j = 0; j < P; j++) {
-        if (fb & (1u << j)) prev = zb + j;
-        d[j] = prev < 0 ? 0xFFFFFFFFu : (uint32_t)(zb + j - prev);
+        const int k = P - 1 - j;
+        // byte 0 or 2 of voxel j's word into byte 0, of voxel k's word into byte 2
+        const uint32_t sel = (uint32_t)(2 * ((j >> 1) & 1)) | 0x0C00u | (uint32_t)(4 + 2 * ((k >> 1) & 1)) << 16 |
+                             0x0C000000u;
+        tj[j] = __builtin_amdgcn_perm(nz[2 * (k >> 2) + (k & 1)], nz[2 * (j >> 2) + (j & 1)], sel);
     }
+    // voxels 4q, 4q+1 to bits 4q, 4q+1 and voxels 4q+2, 4q+3 to bits 4q+16,
+    // 4q+17, folded down by 14
+    uint32_t c = 0;
 #pragma unroll
-    for (int j = P - 1; j >= 0; j--) {
-        if (fb & (1u << j)) next = zb + j;
-        if (next != 0x7FFFFFFF) d[j] = min(d[j], (uint32_t)(next - zb - j));
+    for (int q = 0; q < P / 4; q++) c |= (nz[2 * q] | nz[2 * q + 1] << 1) << (4 * q);
+    fb = ~(c | c >> 14) & ((1u << P) - 1u);
+}
+
+// pass z of one row group: lane li of lpr holds feature bits fb of voxels
+// v0..v0+P-1 of its row (the first nv of them inside the row); writes their
+// distances along z, kInf16 for a distance of dcap or more (capped when
+// dcap < Z), with 16-byte stores when the rows are aligned (Al). The distances
+// to the nearest feature before and after each voxel run as two chains in
+// the halves of one packed 16-bit word: the first forward from the lane's
+// first voxel, the second backward from its last, each step adding one
+// (saturating at 65535 where no feature lies on that side) and resetting to
+// zero at a feature.
+template <int P, bool Al, bool Bytes>
+__device__ inline uint32_t pass_z_rows(uint32_t fb, const uint32_t (&raw)[P / 4], bool act, int64_t v0, int li,
+                                       int lpr, int nv, uint32_t dcap, int Z, uint16_t* g) {
+    constexpr int kNone = 0x10000;  // a feature position that no row reaches
+    const int zb = li * P;
+    uint32_t tj[P];
+    if (Bytes) {
+        byte_factors<P>(raw, tj, fb);
+    } else {
+        // step j's factors from the feature bits: bit j of the not-feature
+        // bits in the low half, bit P-1-j in the high one
+        const uint32_t nf = ~fb & ((1u << P) - 1u);
+        const uint32_t nfr = nf | (__builtin_bitreverse32(nf) >> (16 - P));
+#pragma unroll
+        for (int j = 0; j < P; j++) tj[j] = (nfr >> j) & 0x00010001u;
+    }
+    // nearest feature at or before the end of this lane's voxels
+    int incl = fb ? zb + 31 - __clz(fb) : -kNone;
+    // nearest feature at or after the start of this lane's voxels
+    int incr = fb ? zb + __ffs(fb) - 1 : 2 * kNone;
+    int prev, next;
+    if (lpr == 64) {
+        // one row per wave: scans and the one-lane shifts by DPP
+        wave_scans(incl, incr);
+        prev = dpp_or<0x138>(-kNone, incl);     // wave_shr:1
+        next = dpp_or<0x130>(2 * kNone, incr);  // wave_shl:1
+    } else {
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int a = __shfl_up(incl, o, 64);
+            const int b = __shfl_down(incr, o, 64);
+            if (o < lpr) {
+                if (li >= o) incl = max(incl, a);
+                if (li + o < lpr) incr = min(incr, b);
+            }
+        }
+        prev = __shfl_up(incl, 1, 64);
+        next = __shfl_down(incr, 1, 64);
+    }
+    if (li == 0) prev = -kNone;
+    if (li == lpr - 1) next = 2 * kNone;
+    // the chains' values one voxel before this lane's first and one after its last
+    const uint32_t l0 = (uint32_t)min(zb - 1 - prev, 0xFFFF), r0 = (uint32_t)min(next - zb - P, 0xFFFF);
+    u16x2 st = as_u16x2(l0 | r0 << 16);
+    u16x2 ch[P];
+#pragma unroll
+    for (int j = 0; j < P; j++) {
+        st = __builtin_elementwise_add_sat(st, as_u16x2(0x00010001u)) * as_u16x2(tj[j]);
+        ch[j] = st;
+    }
+    // ch[j] holds (before-distance of voxel j, after-distance of voxel P-1-j):
+    // the minimum with ch[P-1-j] swapped gives (d_j, d_{P-1-j})
+    uint32_t dp[P / 2];
+#pragma unroll
+    for (int j = 0; j < P / 2; j++) {
+        const uint32_t o = as_u32(ch[P - 1 - j]);
+        dp[j] = as_u32(__builtin_elementwise_min(ch[j], as_u16x2(o >> 16 | o << 16)));
     }
     uint32_t pk[P / 2];
 #pragma unroll
-    for (int j = 0; j < P / 2; j++) {
-        const uint32_t lo = (d[2 * j] == 0xFFFFFFFFu || (uint64_t)d[2 * j] * d[2 * j] >= cap) ? kInf16 : d[2 * j];
-        const uint32_t hi =
-            (d[2 * j + 1] == 0xFFFFFFFFu || (uint64_t)d[2 * j + 1] * d[2 * j + 1] >= cap) ? kInf16 : d[2 * j + 1];
-        pk[j] = lo | (hi << 16);
+    for (int i = 0; i < P / 4; i++) {
+        pk[i] = (dp[2 * i] & 0xFFFFu) | dp[2 * i + 1] << 16;
+        pk[P / 4 + i] = dp[P / 2 - 1 - 2 * i] >> 16 | (dp[P / 2 - 2 - 2 * i] & 0xFFFF0000u);
+    }
+    if (dcap < (uint32_t)Z) {
+        // kInf16 where d >= dcap: (dcap - d) saturates to 0 there
+        const u16x2 dc = as_u16x2(dcap | dcap << 16);
+#pragma unroll
+        for (int i = 0; i < P / 2; i++) {
+            const u16x2 keep = __builtin_elementwise_sub_sat(dc, as_u16x2(pk[i]));
+            const u16x2 over = __builtin_elementwise_sub_sat(as_u16x2(0x00010001u), keep);
+            pk[i] |= as_u32(over * as_u16x2(0xFFFFFFFFu));
+        }
     }
     if (act && Al) {
 #pragma unroll
@@ -403,13 +523,14 @@ __device__ inline void pass_z_rows(uint32_t fb, bool act, int64_t v0, int li, in
         for (int j = 0; j < P; j++)
             if (j < nv) g[v0 + j] = (uint16_t)(pk[j >> 1] >> (16 * (j & 1)));
     }
+    return fb;
 }
 
 // Al: rows of a multiple of P voxels from an aligned input, loaded and
 // stored with vectors; otherwise (rows of any length up to 64 * P) voxel by
 // voxel, the last lane of a row holding fewer than P.
 template <class Feat, int P, bool Al>
-__global__ __launch_bounds__(256) void edt_pass_z_vec(Feat feat, int64_t rows, int Z, uint64_t cap, uint16_t* g,
+__global__ __launch_bounds__(256) void edt_pass_z_vec(Feat feat, int64_t rows, int Z, uint32_t dcap, uint16_t* g,
                                                       uint32_t* solid_flag) {
     const int lane = threadIdx.x & 63;
     const int lpr = (Z + P - 1) / P;
@@ -420,7 +541,10 @@ __global__ __launch_bounds__(256) void edt_pass_z_vec(Feat feat, int64_t rows, i
     // voxels of this lane inside its row (a lane of the partial row group
     // past the last whole row computes a phantom row and stores nothing)
     const int nv = min(P, Z - li * P);
+    // the image's bytes go to the chains directly; other inputs through bits
+    constexpr bool Bytes = Al && Feat::kBytes;
     uint32_t fb[kZGroups];
+    uint32_t raw[kZGroups][P / 4];
     bool act[kZGroups];
     int64_t v0[kZGroups];
 #pragma unroll
@@ -432,20 +556,27 @@ __global__ __launch_bounds__(256) void edt_pass_z_vec(Feat feat, int64_t rows, i
         // lane condition would be waited for before the next one
         v0[q] = (act[q] ? row : 0) * Z + li * P;
         uint32_t b = 0;
-        if (Al) {
+        if (Bytes) {
+#pragma unroll
+            for (int k = 0; k < P / 8; k++) {
+                const uint2 x = feat.bytes8(v0[q] + 8 * k);
+                raw[q][2 * k] = x.x;
+                raw[q][2 * k + 1] = x.y;
+            }
+        } else if (Al) {
             b = feat.bits8(v0[q]);
             if (P == 16) b |= feat.bits8(v0[q] + 8) << 8;
         } else {
 #pragma unroll
             for (int j = 0; j < P; j++) b |= (feat.bit(v0[q] + min(j, nv - 1)) && j < nv ? 1u : 0u) << j;
         }
-        fb[q] = act[q] ? b : 0u;
+        fb[q] = b;
     }
     bool any = false;
 #pragma unroll
     for (int q = 0; q < kZGroups; q++) {
-        pass_z_rows<P, Al>(fb[q], act[q], v0[q], li, lpr, nv, cap, g);
-        any |= __ballot(fb[q] != 0) != 0;
+        const uint32_t f = pass_z_rows<P, Al, Bytes>(fb[q], raw[q], act[q], v0[q], li, lpr, nv, dcap, Z, g);
+        any |= __ballot(act[q] && f != 0) != 0;
     }
     if (lane == 0 && any && __hip_atomic_load(solid_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
         atomicOr(solid_flag, 1u);
@@ -546,11 +677,8 @@ __global__ __launch_bounds__(kThreadsY) void edt_pass_y_vec(const uint16_t* __re
 // searched again exactly, from the distances in HBM (a 2D distance of 256
 // voxels or more; none on the workloads here). The search of a pair of
 // columns goes on until both are settled, and at most to offset 256 (every
-// candidate farther out is at least 65536).
-typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
-
-__device__ inline u16x2 as_u16x2(uint32_t v) { return __builtin_bit_cast(u16x2, v); }
-__device__ inline uint32_t as_u32(u16x2 v) { return __builtin_bit_cast(uint32_t, v); }
+// candidate farther out is at least 65536). The packed type and its casts
+// are the ones of pass z.
 
 // min(g^2, 65535) of a distance along z (0x7FFF = no feature)
 __device__ inline uint32_t sq16(uint32_t gv) { return gv < 256u ? gv * gv : 65535u; }
@@ -909,6 +1037,11 @@ hipError_t launch_edt(const uint8_t* image, const uint32_t* w, uint32_t thr, uin
     const bool yv = d.Z % 8 == 0, xv = d.Z % 4 == 0;  // rows that 16-byte loads can take
     const int64_t rows = (int64_t)d.X * d.Y;
     if (zp) {
+        // the distance cap of pass z: the least d with d^2 >= cap
+        uint64_t dz64 = (uint64_t)std::sqrt((double)c64);
+        while (dz64 * dz64 < c64) dz64++;
+        while (dz64 > 0 && (dz64 - 1) * (dz64 - 1) >= c64) dz64--;
+        const uint32_t dz = (uint32_t)std::min<uint64_t>(dz64, 0xFFFFu);
         const int64_t rows_per_block = 4LL * (64 / ((d.Z + zp - 1) / zp)) * kZGroups;
         const unsigned gz = (unsigned)((rows + rows_per_block - 1) / rows_per_block);
         const dim3 gzd(gz);
@@ -918,35 +1051,35 @@ hipError_t launch_edt(const uint8_t* image, const uint32_t* w, uint32_t thr, uin
         switch (form) {
             case 7:
                 hipLaunchKernelGGL((edt_pass_z_vec<FeatImage8, 16, true>), gzd, dim3(256), 0, s, fi, rows, d.Z,
-                                   c64, g16, solid_flag);
+                                   dz, g16, solid_flag);
                 break;
             case 6:
                 hipLaunchKernelGGL((edt_pass_z_vec<FeatImage8, 16, false>), gzd, dim3(256), 0, s, fi, rows, d.Z,
-                                   c64, g16, solid_flag);
+                                   dz, g16, solid_flag);
                 break;
             case 5:
                 hipLaunchKernelGGL((edt_pass_z_vec<FeatImage8, 8, true>), gzd, dim3(256), 0, s, fi, rows, d.Z,
-                                   c64, g16, solid_flag);
+                                   dz, g16, solid_flag);
                 break;
             case 4:
                 hipLaunchKernelGGL((edt_pass_z_vec<FeatImage8, 8, false>), gzd, dim3(256), 0, s, fi, rows, d.Z,
-                                   c64, g16, solid_flag);
+                                   dz, g16, solid_flag);
                 break;
             case 3:
                 hipLaunchKernelGGL((edt_pass_z_vec<FeatThreshold8, 16, true>), gzd, dim3(256), 0, s, ft, rows, d.Z,
-                                   c64, g16, solid_flag);
+                                   dz, g16, solid_flag);
                 break;
             case 2:
                 hipLaunchKernelGGL((edt_pass_z_vec<FeatThreshold8, 16, false>), gzd, dim3(256), 0, s, ft, rows,
-                                   d.Z, c64, g16, solid_flag);
+                                   d.Z, dz, g16, solid_flag);
                 break;
             case 1:
                 hipLaunchKernelGGL((edt_pass_z_vec<FeatThreshold8, 8, true>), gzd, dim3(256), 0, s, ft, rows, d.Z,
-                                   c64, g16, solid_flag);
+                                   dz, g16, solid_flag);
                 break;
             default:
                 hipLaunchKernelGGL((edt_pass_z_vec<FeatThreshold8, 8, false>), gzd, dim3(256), 0, s, ft, rows,
-                                   d.Z, c64, g16, solid_flag);
+                                   d.Z, dz, g16, solid_flag);
                 break;
         }
     } else {

@@ -109,6 +109,30 @@ def test_edt_vector_path_long_lines(dev, shape, tiles):
         ibip.set_tuning(None)
 
 
+@pytest.mark.parametrize("Z", [505, 509, 512, 1009, 1016, 1020, 1024])
+def test_edt_rows_of_one_wave(dev, Z):
+    """Rows that fill a whole wave in pass z (64 lanes of 8 or 16 voxels):
+    the lone feature of a row at either end, on either side of the 16-lane
+    row boundaries and in the last lane; rows with none (their distances come
+    from the other passes); random rows. Also the opening's capped transform,
+    whose cap also limits the distances along z."""
+    P = 8 if Z <= 512 else 16
+    marks = [[0], [Z - 1], [16 * P - 1], [16 * P], [32 * P - 1, 48 * P], [], [47 * P + P - 1], [63 * P],
+             [31 * P, 32 * P], [15 * P + 3, 49 * P + 1], [], [Z // 2]]
+    rng = np.random.default_rng(Z)
+    img = np.ones((2, len(marks) + 4, Z), np.uint8)
+    for y, ms in enumerate(marks):
+        for z in ms:
+            img[0, y, min(z, Z - 1)] = 0
+    img[1] = (rng.random((len(marks) + 4, Z)) < 0.995).astype(np.uint8)
+    img[1, :4] = 1
+    np.testing.assert_array_equal(_u32(ibip.edt(_d(img, dev))), oracle.edt(img))
+    inl = synth.face_mask(img.shape, 1, 0)
+    T = np.array([300, 90, 17, 2], np.uint32)
+    m = ibip.opening_drainage(_d(img, dev), _d(inl, dev), T.tolist())
+    np.testing.assert_array_equal(_u32(m["mio_r2"]), oracle.mio(img, inl, T)["mio_r2"])
+
+
 @pytest.mark.parametrize("shape", [(1, 600, 16), (2, 800, 24), (3, 1000, 8), (700, 2, 8), (768, 3, 16), (1000, 1, 8)])
 @pytest.mark.parametrize("tiles", [None, (64, 32)])
 def test_edt_packed_saturation(dev, shape, tiles):
