@@ -591,81 +591,24 @@ __global__ __launch_bounds__(256) void edt_pass_z_vec(Feat feat, int64_t rows, i
 // of a sentinel above and below the line, and a side that has run past its
 // end reads the sentinel rows, so a group is eight unconditional LDS reads at
 // fixed offsets. The sentinel stands for "no feature": it is larger than any
-// real value and small enough that sentinel + o^2 cannot overflow, so each
-// candidate costs one multiply-add (or add) and one min. Lines are at most
-// 1024 voxels, so every real sum stays below 3 * 1023^2.
+// real value and small enough that sentinel + o^2 cannot overflow. The two
+// sides at one offset share o^2, so a candidate pair costs a min of the two
+// tile values, one add and one min. Lines are at most 1024 voxels, so every
+// real sum stays below 3 * 1023^2.
+//
+// Between the passes, h (pass y's result) is either one 32-bit word per voxel
+// (HPlain) or, where pass x runs its 32-bit tiles and a 32-bit output array is
+// there, split (HSplit): min(h, 65535) as 16 bits per voxel, and the exact h
+// of the voxels at 65535 or above (no feature in the plane included) in the
+// output array at the voxel's own index. Pass x reads those while loading its
+// tile, before any of its workgroups writes the output of its columns, which
+// are the only voxels whose exact h it reads. 2 bytes per voxel are written
+// and read instead of 4 (plus 4 per voxel at a 2D distance of 256 or more).
 constexpr int kPad = 4;
 constexpr uint32_t kSent16 = 0x7FFFu;                // pass y: sentinel distance
 constexpr uint32_t kSentSq = kSent16 * kSent16;      // its square (+ o^2 < 2^31)
 constexpr uint32_t kSent32 = 0x40000000u;            // pass x: sentinel value
 constexpr int kThreadsY = 512, kThreadsX = 1024;
-
-// TW: z columns per tile (32: 64-byte tile rows; 64: whole 128-byte lines).
-// V: rows of Z % 8 == 0 voxels, loaded with 16-byte vectors; otherwise the
-// tile is loaded element by element (consecutive threads, consecutive z).
-template <int TW, bool V>
-__global__ __launch_bounds__(kThreadsY) void edt_pass_y_vec(const uint16_t* __restrict__ g, int X, int Y, int Z,
-                                                           uint64_t cap, uint32_t* __restrict__ h) {
-    extern __shared__ uint16_t t16[];  // [kPad + Y + kPad][TW]
-    constexpr int kSegs = TW / 8, kRows = kThreadsY / kSegs;
-    const int nzc = (Z + TW - 1) / TW;
-    const int x = blockIdx.x / nzc;
-    const int z0 = (blockIdx.x - x * nzc) * TW;
-    const int64_t plane = (int64_t)x * Y * Z;
-    if (!V) {
-        for (int i = threadIdx.x; i < Y * TW; i += kThreadsY) {
-            const int y = i / TW, lz = i - y * TW, zc = z0 + lz;
-            // 0xFFFF (no feature) becomes the sentinel 0x7FFF; distances are < 1024
-            t16[(y + kPad) * TW + lz] = zc < Z ? (uint16_t)(g[plane + (int64_t)y * Z + zc] & 0x7FFFu) : (uint16_t)kSent16;
-        }
-    } else {
-        const int seg = threadIdx.x % kSegs;
-        const int zc = z0 + seg * 8;
-        for (int y = threadIdx.x / kSegs; y < Y; y += kRows) {
-            uint4 w = make_uint4(0x7FFF7FFFu, 0x7FFF7FFFu, 0x7FFF7FFFu, 0x7FFF7FFFu);
-            if (zc < Z) {
-                // 0xFFFF (no feature) becomes the sentinel 0x7FFF; distances are < 1024
-                w = *reinterpret_cast<const uint4*>(g + plane + (int64_t)y * Z + zc);
-                w.x &= 0x7FFF7FFFu;
-                w.y &= 0x7FFF7FFFu;
-                w.z &= 0x7FFF7FFFu;
-                w.w &= 0x7FFF7FFFu;
-            }
-            *reinterpret_cast<uint4*>(t16 + (y + kPad) * TW + seg * 8) = w;
-        }
-    }
-    for (int i = threadIdx.x; i < 2 * kPad * TW; i += kThreadsY) {
-        const int r = i / TW;
-        t16[(r < kPad ? r : Y + r) * TW + (i - r * TW)] = (uint16_t)kSent16;
-    }
-    __syncthreads();
-    const int lz = threadIdx.x % TW;
-    const int z = z0 + lz;
-    if (z >= Z) return;
-    const uint32_t capv = (uint32_t)cap;
-    const uint32_t lim = min(capv, kSentSq);
-    const uint16_t* col = t16 + kPad * TW + lz;  // row i at col[i * TW]
-    for (int y = threadIdx.x / TW; y < Y; y += kThreadsY / TW) {
-        const uint32_t f0 = col[y * TW];
-        uint32_t best = f0 == kSent16 ? capv : f0 * f0;
-        if (best) {
-            const int far = max(y, Y - 1 - y);
-            for (int o = 1; o <= far; o += 4) {
-                if ((uint32_t)(o * o) >= best) break;
-                const uint16_t* lp = col + (y - o >= 0 ? y - o : -1) * TW;
-                const uint16_t* rp = col + (y + o < Y ? y + o : Y) * TW;
-#pragma unroll
-                for (int j = 0; j < 4; j++) {
-                    const uint32_t oo = (uint32_t)((o + j) * (o + j));
-                    const uint32_t fl = lp[-j * TW], fr = rp[j * TW];
-                    best = min(best, fl * fl + oo);
-                    best = min(best, fr * fr + oo);
-                }
-            }
-        }
-        h[plane + (int64_t)y * Z + z] = best >= lim ? kInf32 : best;
-    }
-}
 
 // Pass y in packed 16-bit arithmetic, two columns per lane. The tile holds
 // min(g^2, 65535) (g < 256 squares exactly; a larger g and the sentinel
@@ -679,6 +622,51 @@ __global__ __launch_bounds__(kThreadsY) void edt_pass_y_vec(const uint16_t* __re
 // columns goes on until both are settled, and at most to offset 256 (every
 // candidate farther out is at least 65536). The packed type and its casts
 // are the ones of pass z.
+
+// pass y's result h: one 32-bit word per voxel
+struct HPlain {
+    static constexpr bool kSplit = false;
+    uint32_t* h;
+    __device__ void put(int64_t v, uint32_t val) const { h[v] = val; }
+    // voxels v and v+1 (v even: one 32-bit store in the split form)
+    __device__ void put2(int64_t v, uint32_t a, uint32_t b) const {
+        h[v] = a;
+        h[v + 1] = b;
+    }
+    __device__ uint32_t get(int64_t v) const { return h[v]; }
+    __device__ uint4 get4(int64_t v) const { return *reinterpret_cast<const uint4*>(h + v); }
+};
+
+// pass y's result h split: min(h, 65535) in h16, the exact h of the voxels at
+// 65535 or above in hx
+struct HSplit {
+    static constexpr bool kSplit = true;
+    uint16_t* h16;
+    uint32_t* hx;
+    __device__ void put(int64_t v, uint32_t val) const {
+        h16[v] = (uint16_t)min(val, 65535u);
+        if (val >= 65535u) hx[v] = val;
+    }
+    __device__ void put2(int64_t v, uint32_t a, uint32_t b) const {
+        *reinterpret_cast<uint32_t*>(h16 + v) = min(a, 65535u) | min(b, 65535u) << 16;
+        if (a >= 65535u) hx[v] = a;
+        if (b >= 65535u) hx[v + 1] = b;
+    }
+    __device__ uint32_t get(int64_t v) const {
+        const uint32_t u = h16[v];
+        return u < 65535u ? u : hx[v];
+    }
+    // voxels v..v+3 (v % 4 == 0)
+    __device__ uint4 get4(int64_t v) const {
+        const uint2 r = *reinterpret_cast<const uint2*>(h16 + v);
+        uint4 w = make_uint4(r.x & 0xFFFFu, r.x >> 16, r.y & 0xFFFFu, r.y >> 16);
+        if (w.x == 65535u) w.x = hx[v];
+        if (w.y == 65535u) w.y = hx[v + 1];
+        if (w.z == 65535u) w.z = hx[v + 2];
+        if (w.w == 65535u) w.w = hx[v + 3];
+        return w;
+    }
+};
 
 // min(g^2, 65535) of a distance along z (0x7FFF = no feature)
 __device__ inline uint32_t sq16(uint32_t gv) { return gv < 256u ? gv * gv : 65535u; }
@@ -703,9 +691,9 @@ __device__ inline uint32_t pass_y_exact(const uint16_t* g, int64_t v, int y, int
     return (uint32_t)min(best, (uint64_t)0xFFFFFFFFu);
 }
 
-template <int TW, bool V>
+template <int TW, bool V, class H>
 __global__ __launch_bounds__(kThreadsY) void edt_pass_y_pk(const uint16_t* __restrict__ g, int X, int Y, int Z,
-                                                          uint64_t cap, uint32_t* __restrict__ h) {
+                                                          uint64_t cap, H h) {
     extern __shared__ uint16_t t16[];  // [kPad + Y + kPad][TW]: min(g^2, 65535)
     constexpr int kSegs = TW / 8, kRows = kThreadsY / kSegs;
     const int nzc = (Z + TW - 1) / TW;
@@ -761,21 +749,29 @@ __global__ __launch_bounds__(kThreadsY) void edt_pass_y_pk(const uint16_t* __res
                 for (int j = 0; j < 4; j++) {
                     const uint32_t oo = min((uint32_t)((o + j) * (o + j)), 65535u);
                     const u16x2 oop = as_u16x2(oo | oo << 16);
-                    best = __builtin_elementwise_min(best, __builtin_elementwise_add_sat(as_u16x2(lp[-j * LC]), oop));
-                    best = __builtin_elementwise_min(best, __builtin_elementwise_add_sat(as_u16x2(rp[j * LC]), oop));
+                    best = __builtin_elementwise_min(
+                        best, __builtin_elementwise_add_sat(
+                                  __builtin_elementwise_min(as_u16x2(lp[-j * LC]), as_u16x2(rp[j * LC])), oop));
                 }
                 bb = as_u32(best);
                 bmax = max(bb & 0xFFFFu, bb >> 16);
             }
         }
         bb = as_u32(best);
-#pragma unroll
-        for (int e = 0; e < 2; e++) {
-            if (z + e >= Z) break;
-            const int64_t v = plane + (int64_t)y * Z + z + e;
-            uint32_t r = e ? bb >> 16 : bb & 0xFFFFu;
-            if (r == 65535u && capv > 65535u) r = pass_y_exact(g, v, y, Y, Z, cap);
-            h[v] = r >= lim ? kInf32 : r;
+        const int64_t v = plane + (int64_t)y * Z + z;
+        uint32_t r0 = bb & 0xFFFFu, r1 = bb >> 16;
+        if (r0 == 65535u && capv > 65535u) r0 = pass_y_exact(g, v, y, Y, Z, cap);
+        r0 = r0 >= lim ? kInf32 : r0;
+        if (z + 1 < Z) {
+            if (r1 == 65535u && capv > 65535u) r1 = pass_y_exact(g, v + 1, y, Y, Z, cap);
+            r1 = r1 >= lim ? kInf32 : r1;
+            if (V) h.put2(v, r0, r1);
+            else {
+                h.put(v, r0);
+                h.put(v + 1, r1);
+            }
+        } else {
+            h.put(v, r0);
         }
     }
 }
@@ -783,9 +779,9 @@ __global__ __launch_bounds__(kThreadsY) void edt_pass_y_pk(const uint16_t* __res
 // TW: z columns per tile (16: 64-byte tile rows; 32: whole 128-byte lines).
 // V: rows of Z % 4 == 0 voxels, loaded with 16-byte vectors; otherwise the
 // tile is loaded element by element.
-template <class Out, int TW, bool V>
-__global__ __launch_bounds__(kThreadsX) void edt_pass_x_vec(const uint32_t* __restrict__ hin, int X, int Y, int Z,
-                                                           uint64_t cap, Out outp, uint32_t* count) {
+template <class Out, int TW, bool V, class H>
+__global__ __launch_bounds__(kThreadsX) void edt_pass_x_vec(H hin, int X, int Y, int Z, uint64_t cap, Out outp,
+                                                           uint32_t* count) {
     extern __shared__ uint32_t t32[];  // [kPad + X + kPad][TW]
     constexpr int kSegs = TW / 4, kRows = kThreadsX / kSegs;
     const int nzc = (Z + TW - 1) / TW;
@@ -798,7 +794,7 @@ __global__ __launch_bounds__(kThreadsX) void edt_pass_x_vec(const uint32_t* __re
             const int x = i / TW, lz = i - x * TW;
             uint32_t w = kSent32;
             if (z0 + lz < Z) {
-                w = hin[x * yz + col0 + lz];
+                w = hin.get(x * yz + col0 + lz);
                 w = w == kInf32 ? kSent32 : w;
             }
             t32[(x + kPad) * TW + lz] = w;
@@ -809,7 +805,7 @@ __global__ __launch_bounds__(kThreadsX) void edt_pass_x_vec(const uint32_t* __re
         for (int x = threadIdx.x / kSegs; x < X; x += kRows) {
             uint4 w = make_uint4(kSent32, kSent32, kSent32, kSent32);
             if (zc < Z) {
-                w = *reinterpret_cast<const uint4*>(hin + x * yz + col0 + seg * 4);
+                w = hin.get4(x * yz + col0 + seg * 4);
                 w.x = w.x == kInf32 ? kSent32 : w.x;
                 w.y = w.y == kInf32 ? kSent32 : w.y;
                 w.z = w.z == kInf32 ? kSent32 : w.z;
@@ -842,8 +838,7 @@ __global__ __launch_bounds__(kThreadsX) void edt_pass_x_vec(const uint32_t* __re
 #pragma unroll
                     for (int j = 0; j < 4; j++) {
                         const uint32_t oo = (uint32_t)((o + j) * (o + j));
-                        best = min(best, lp[-j * TW] + oo);
-                        best = min(best, rp[j * TW] + oo);
+                        best = min(best, min(lp[-j * TW], rp[j * TW]) + oo);
                     }
                 }
             }
@@ -936,10 +931,9 @@ __global__ __launch_bounds__(kThreadsX) void edt_pass_x_pk(const uint32_t* __res
                     for (int j = 0; j < 4; j++) {
                         const uint32_t oo = min((uint32_t)((o + j) * (o + j)), 65535u);
                         const u16x2 oop = as_u16x2(oo | oo << 16);
-                        best = __builtin_elementwise_min(best,
-                                                         __builtin_elementwise_add_sat(as_u16x2(lp[-j * LC]), oop));
-                        best = __builtin_elementwise_min(best,
-                                                         __builtin_elementwise_add_sat(as_u16x2(rp[j * LC]), oop));
+                        best = __builtin_elementwise_min(
+                            best, __builtin_elementwise_add_sat(
+                                      __builtin_elementwise_min(as_u16x2(lp[-j * LC]), as_u16x2(rp[j * LC])), oop));
                     }
                     bb = as_u32(best);
                     bmax = max(bb & 0xFFFFu, bb >> 16);
@@ -976,29 +970,48 @@ size_t max_lds_per_block() {
     return cached[dev];
 }
 
-// Pass x in the tiled form: the packed 16-bit kernel (pk) or the 32-bit one,
-// with tiles of tx z columns and 16-byte loads (xv) or not.
+// the packed pass x with tiles of tx z columns and 16-byte loads (xv) or not
 template <class Out>
-void launch_pass_x(bool pk, int tx, bool xv, dim3 gx, size_t lds_bytes, hipStream_t s, const uint32_t* in,
-                   ibip_dims d, uint64_t c64, Out o, uint32_t* count) {
+void launch_pass_x_pk(int tx, bool xv, dim3 gx, size_t lds_bytes, hipStream_t s, const uint32_t* h, ibip_dims d,
+                      uint64_t c64, Out o, uint32_t* count) {
     const dim3 b(kThreadsX);
-    if (pk) {
-        if (tx == 16) {
-            if (xv) hipLaunchKernelGGL((edt_pass_x_pk<Out, 16, true>), gx, b, lds_bytes, s, in, d.X, d.Y, d.Z, c64, o, count);
-            else hipLaunchKernelGGL((edt_pass_x_pk<Out, 16, false>), gx, b, lds_bytes, s, in, d.X, d.Y, d.Z, c64, o, count);
-        } else {
-            if (xv) hipLaunchKernelGGL((edt_pass_x_pk<Out, 32, true>), gx, b, lds_bytes, s, in, d.X, d.Y, d.Z, c64, o, count);
-            else hipLaunchKernelGGL((edt_pass_x_pk<Out, 32, false>), gx, b, lds_bytes, s, in, d.X, d.Y, d.Z, c64, o, count);
-        }
+    if (tx == 16) {
+        if (xv) hipLaunchKernelGGL((edt_pass_x_pk<Out, 16, true>), gx, b, lds_bytes, s, h, d.X, d.Y, d.Z, c64, o, count);
+        else hipLaunchKernelGGL((edt_pass_x_pk<Out, 16, false>), gx, b, lds_bytes, s, h, d.X, d.Y, d.Z, c64, o, count);
     } else {
-        if (tx == 16) {
-            if (xv) hipLaunchKernelGGL((edt_pass_x_vec<Out, 16, true>), gx, b, lds_bytes, s, in, d.X, d.Y, d.Z, c64, o, count);
-            else hipLaunchKernelGGL((edt_pass_x_vec<Out, 16, false>), gx, b, lds_bytes, s, in, d.X, d.Y, d.Z, c64, o, count);
-        } else {
-            if (xv) hipLaunchKernelGGL((edt_pass_x_vec<Out, 32, true>), gx, b, lds_bytes, s, in, d.X, d.Y, d.Z, c64, o, count);
-            else hipLaunchKernelGGL((edt_pass_x_vec<Out, 32, false>), gx, b, lds_bytes, s, in, d.X, d.Y, d.Z, c64, o, count);
-        }
+        if (xv) hipLaunchKernelGGL((edt_pass_x_pk<Out, 32, true>), gx, b, lds_bytes, s, h, d.X, d.Y, d.Z, c64, o, count);
+        else hipLaunchKernelGGL((edt_pass_x_pk<Out, 32, false>), gx, b, lds_bytes, s, h, d.X, d.Y, d.Z, c64, o, count);
     }
+}
+
+// Pass x: packed (pk) or 32-bit tiles of tx z columns, 16-byte loads (xv) or
+// not. The packed kernels read h as one word per voxel (their exact search
+// reads it in HBM), so the split form only ever comes with the 32-bit ones.
+template <class Out, class H>
+void launch_pass_x(bool pk, int tx, bool xv, dim3 gx, size_t lds_bytes, hipStream_t s, H in, ibip_dims d,
+                   uint64_t c64, Out o, uint32_t* count) {
+    if constexpr (!H::kSplit) {
+        if (pk) return launch_pass_x_pk(tx, xv, gx, lds_bytes, s, in.h, d, c64, o, count);
+    }
+    const dim3 b(kThreadsX);
+    if (tx == 16) {
+        if (xv) hipLaunchKernelGGL((edt_pass_x_vec<Out, 16, true, H>), gx, b, lds_bytes, s, in, d.X, d.Y, d.Z, c64, o, count);
+        else hipLaunchKernelGGL((edt_pass_x_vec<Out, 16, false, H>), gx, b, lds_bytes, s, in, d.X, d.Y, d.Z, c64, o, count);
+    } else {
+        if (xv) hipLaunchKernelGGL((edt_pass_x_vec<Out, 32, true, H>), gx, b, lds_bytes, s, in, d.X, d.Y, d.Z, c64, o, count);
+        else hipLaunchKernelGGL((edt_pass_x_vec<Out, 32, false, H>), gx, b, lds_bytes, s, in, d.X, d.Y, d.Z, c64, o, count);
+    }
+}
+
+// pass y with tiles of ty z columns and 16-byte loads (yv) or not
+template <class H>
+void launch_pass_y(int ty, bool yv, dim3 gy, size_t lds_bytes, hipStream_t s, const uint16_t* g16, ibip_dims d,
+                   uint64_t c64, H h) {
+    const dim3 b(kThreadsY);
+    if (ty == 64 && yv) hipLaunchKernelGGL((edt_pass_y_pk<64, true, H>), gy, b, lds_bytes, s, g16, d.X, d.Y, d.Z, c64, h);
+    else if (ty == 64) hipLaunchKernelGGL((edt_pass_y_pk<64, false, H>), gy, b, lds_bytes, s, g16, d.X, d.Y, d.Z, c64, h);
+    else if (yv) hipLaunchKernelGGL((edt_pass_y_pk<32, true, H>), gy, b, lds_bytes, s, g16, d.X, d.Y, d.Z, c64, h);
+    else hipLaunchKernelGGL((edt_pass_y_pk<32, false, H>), gy, b, lds_bytes, s, g16, d.X, d.Y, d.Z, c64, h);
 }
 
 }  // namespace
@@ -1036,6 +1049,12 @@ hipError_t launch_edt(const uint8_t* image, const uint32_t* w, uint32_t thr, uin
     const bool xvec = yvec && d.X <= kMaxVecLine && lx <= lds;
     const bool yv = d.Z % 8 == 0, xv = d.Z % 4 == 0;  // rows that 16-byte loads can take
     const int64_t rows = (int64_t)d.X * d.Y;
+    // h between passes y and x split in two (16 bits per voxel, the exact
+    // values at 65535 and above in the output array) where pass x runs its
+    // 32-bit tiles, which read all of it while loading, and writes an output
+    const bool split = yvec && xvec && !xpk && out != nullptr && mio_r2 == nullptr;
+    const HPlain hp{tmp32};
+    const HSplit hs{reinterpret_cast<uint16_t*>(tmp32), out};
     if (zp) {
         // the distance cap of pass z: the least d with d^2 >= cap
         uint64_t dz64 = (uint64_t)std::sqrt((double)c64);
@@ -1095,14 +1114,8 @@ hipError_t launch_edt(const uint8_t* image, const uint32_t* w, uint32_t thr, uin
     if (yvec) {
         const unsigned nzy = (unsigned)((d.Z + ty - 1) / ty);
         const dim3 gy((unsigned)d.X * nzy);
-        if (ty == 64 && yv)
-            hipLaunchKernelGGL((edt_pass_y_pk<64, true>), gy, dim3(kThreadsY), ly, s, g16, d.X, d.Y, d.Z, c64, tmp32);
-        else if (ty == 64)
-            hipLaunchKernelGGL((edt_pass_y_pk<64, false>), gy, dim3(kThreadsY), ly, s, g16, d.X, d.Y, d.Z, c64, tmp32);
-        else if (yv)
-            hipLaunchKernelGGL((edt_pass_y_pk<32, true>), gy, dim3(kThreadsY), ly, s, g16, d.X, d.Y, d.Z, c64, tmp32);
-        else
-            hipLaunchKernelGGL((edt_pass_y_pk<32, false>), gy, dim3(kThreadsY), ly, s, g16, d.X, d.Y, d.Z, c64, tmp32);
+        if (split) launch_pass_y(ty, yv, gy, ly, s, g16, d, c64, hs);
+        else launch_pass_y(ty, yv, gy, ly, s, g16, d, c64, hp);
     } else if (d.Y <= kMaxTileLine) {
         const int nzc = (d.Z + kW - 1) / kW;
         hipLaunchKernelGGL(edt_pass_y_tile, dim3((unsigned)(d.X * nzc)), dim3(256), sizeof(uint16_t) * kW * d.Y, s,
@@ -1116,10 +1129,9 @@ hipError_t launch_edt(const uint8_t* image, const uint32_t* w, uint32_t thr, uin
         const OutOpening oo{mio_r2, cap};
         const OutPlain op{out};
         uint32_t* const nocount = nullptr;
-        if (mio_r2)
-            launch_pass_x(xpk, tx, xv, gx, lx, s, tmp32, d, c64, oo, mio_count);
-        else
-            launch_pass_x(xpk, tx, xv, gx, lx, s, tmp32, d, c64, op, nocount);
+        if (mio_r2) launch_pass_x(xpk, tx, xv, gx, lx, s, hp, d, c64, oo, mio_count);
+        else if (split) launch_pass_x(xpk, tx, xv, gx, lx, s, hs, d, c64, op, nocount);
+        else launch_pass_x(xpk, tx, xv, gx, lx, s, hp, d, c64, op, nocount);
         return hipGetLastError();
     }
     const int nzcx = (d.Z + kWx - 1) / kWx;
