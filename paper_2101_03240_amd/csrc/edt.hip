@@ -227,6 +227,11 @@ struct OutPlain {
         out[v] = best >= cap ? kInf32 : (uint32_t)best;
     }
     __device__ uint32_t hit(int64_t, uint64_t) const { return 0; }
+    // r: the result, kInf32 at or above the cap
+    __device__ uint32_t put_hit(int64_t v, uint32_t r) const {
+        out[v] = r;
+        return 0;
+    }
 };
 struct OutOpening {
     uint32_t* mio_r2;
@@ -240,6 +245,7 @@ struct OutOpening {
         }
         return r >= T ? 1u : 0u;
     }
+    __device__ uint32_t put_hit(int64_t v, uint32_t r) const { return hit(v, r); }
 };
 
 template <class Out>
@@ -736,7 +742,9 @@ __global__ __launch_bounds__(kThreadsY) void edt_pass_y_pk(const uint16_t* __res
     const uint32_t c16 = min(capv, 65535u);
     const u16x2 capp = as_u16x2(c16 | c16 << 16);
     const uint32_t* col = reinterpret_cast<const uint32_t*>(t16 + kPad * TW) + lc;  // row i at col[i * LC]
-    for (int y = threadIdx.x / LC; y < Y; y += RPI) {
+    // the voxel's index runs with y (no 64-bit product per voxel)
+    int64_t v = plane + (int64_t)(threadIdx.x / LC) * Z + z;
+    for (int y = threadIdx.x / LC; y < Y; y += RPI, v += (int64_t)RPI * Z) {
         u16x2 best = __builtin_elementwise_min(as_u16x2(col[y * LC]), capp);
         uint32_t bb = as_u32(best);
         uint32_t bmax = max(bb & 0xFFFFu, bb >> 16);
@@ -758,7 +766,6 @@ __global__ __launch_bounds__(kThreadsY) void edt_pass_y_pk(const uint16_t* __res
             }
         }
         bb = as_u32(best);
-        const int64_t v = plane + (int64_t)y * Z + z;
         uint32_t r0 = bb & 0xFFFFu, r1 = bb >> 16;
         if (r0 == 65535u && capv > 65535u) r0 = pass_y_exact(g, v, y, Y, Z, cap);
         r0 = r0 >= lim ? kInf32 : r0;
@@ -826,7 +833,10 @@ __global__ __launch_bounds__(kThreadsX) void edt_pass_x_vec(H hin, int X, int Y,
         const uint32_t capv = (uint32_t)cap;
         const uint32_t lim = min(capv, kSent32);
         const uint32_t* col = t32 + kPad * TW + lz;
-        for (int x = threadIdx.x / TW; x < X; x += kThreadsX / TW) {
+        // the voxel's index runs with x (no 64-bit product per voxel)
+        int64_t v = (int64_t)(threadIdx.x / TW) * yz + col0 + lz;
+        const int64_t dv = (int64_t)(kThreadsX / TW) * yz;
+        for (int x = threadIdx.x / TW; x < X; x += kThreadsX / TW, v += dv) {
             const uint32_t f0 = col[x * TW];
             uint32_t best = f0 == kSent32 ? capv : f0;
             if (best) {
@@ -842,10 +852,7 @@ __global__ __launch_bounds__(kThreadsX) void edt_pass_x_vec(H hin, int X, int Y,
                     }
                 }
             }
-            const int64_t v = x * yz + col0 + lz;
-            const uint64_t b = best >= lim ? (uint64_t)cap : (uint64_t)best;
-            outp.put(v, b, cap);
-            hits += outp.hit(v, b);
+            hits += outp.put_hit(v, best >= lim ? kInf32 : best);
         }
     }
     if (count) block_add_slots(count, hits);

@@ -109,6 +109,26 @@ def test_edt_vector_path_long_lines(dev, shape, tiles):
         ibip.set_tuning(None)
 
 
+@pytest.mark.parametrize("shape", [(5, 40, 64), (7, 3, 8), (4, 600, 16), (9, 33, 100)])
+def test_edt_planes_without_features(dev, shape):
+    """Solid voxels only in plane x = 0 (and one in the last plane of some
+    shapes): pass y finds no feature in the planes between, so their h is
+    'none' for every voxel, handed to pass x through the exact values kept
+    for h >= 65535; on the 600-voxel lines the last plane's h also exceeds
+    65535 for real. The no-allocation entry point takes the same path."""
+    rng = np.random.default_rng(sum(shape))
+    img = np.ones(shape, np.uint8)
+    img[0] = (rng.random(shape[1:]) < 0.9).astype(np.uint8)
+    img[0, 0, 0] = 0
+    if shape[0] > 5:
+        img[-1, shape[1] // 2, shape[2] // 2] = 0
+    if shape[1] >= 600:
+        img[-1, 0, 0] = 0  # pass y's h in the last plane reaches 599^2
+    r = oracle.edt(img)
+    np.testing.assert_array_equal(_u32(ibip.edt(_d(img, dev))), r)
+    np.testing.assert_array_equal(_u32(ibip.edt_noalloc(_d(img, dev))[0]), r)
+
+
 @pytest.mark.parametrize("Z", [505, 509, 512, 1009, 1016, 1020, 1024])
 def test_edt_rows_of_one_wave(dev, Z):
     """Rows that fill a whole wave in pass z (64 lanes of 8 or 16 voxels):
