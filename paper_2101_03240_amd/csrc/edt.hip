@@ -596,7 +596,10 @@ __global__ __launch_bounds__(256) void edt_pass_z_vec(Feat feat, int64_t rows, i
 // only adds candidates, so the result is exact). The tile carries kPad rows
 // of a sentinel above and below the line, and a side that has run past its
 // end reads the sentinel rows, so a group is eight unconditional LDS reads at
-// fixed offsets. The sentinel stands for "no feature": it is larger than any
+// fixed offsets. Each side keeps a pointer to its group's lowest row, moved
+// by four rows and held at the pad rows in one add and one unsigned min/max;
+// with 8 pad rows the held pointer lies at least one move above LDS address
+// 0, so the move never wraps. The sentinel stands for "no feature": it is larger than any
 // real value and small enough that sentinel + o^2 cannot overflow. The two
 // sides at one offset share o^2, so a candidate pair costs a min of the two
 // tile values, one add and one min. Lines are at most 1024 voxels, so every
@@ -610,7 +613,7 @@ __global__ __launch_bounds__(256) void edt_pass_z_vec(Feat feat, int64_t rows, i
 // tile, before any of its workgroups writes the output of its columns, which
 // are the only voxels whose exact h it reads. 2 bytes per voxel are written
 // and read instead of 4 (plus 4 per voxel at a 2D distance of 256 or more).
-constexpr int kPad = 4;
+constexpr int kPad = 8;
 constexpr uint32_t kSent16 = 0x7FFFu;                // pass y: sentinel distance
 constexpr uint32_t kSentSq = kSent16 * kSent16;      // its square (+ o^2 < 2^31)
 constexpr uint32_t kSent32 = 0x40000000u;            // pass x: sentinel value
@@ -750,16 +753,22 @@ __global__ __launch_bounds__(kThreadsY) void edt_pass_y_pk(const uint16_t* __res
         uint32_t bmax = max(bb & 0xFFFFu, bb >> 16);
         if (bmax > 1) {
             const int far = min(max(y, Y - 1 - y), 256);
-            for (int o = 1; o <= far && (uint32_t)(o * o) < bmax; o += 4) {
-                const uint32_t* lp = col + (y - o >= 0 ? y - o : -1) * LC;
-                const uint32_t* rp = col + (y + o < Y ? y + o : Y) * LC;
+            // rows y - o - 3 (the lowest of the group on the left, so that
+            // every read has a positive offset) and y + o, each stepped and
+            // held at the pad rows in one move, so neither leaves the tile
+            const uint32_t* const ltop = col - 4 * LC;
+            const uint32_t* const rbot = col + Y * LC;
+            const uint32_t* lp = col + (y - 4) * LC;
+            const uint32_t* rp = col + (y + 1) * LC;
+            for (int o = 1; o <= far && (uint32_t)(o * o) < bmax;
+                 o += 4, lp = lp - 4 * LC < ltop ? ltop : lp - 4 * LC, rp = rp + 4 * LC > rbot ? rbot : rp + 4 * LC) {
 #pragma unroll
                 for (int j = 0; j < 4; j++) {
                     const uint32_t oo = min((uint32_t)((o + j) * (o + j)), 65535u);
                     const u16x2 oop = as_u16x2(oo | oo << 16);
                     best = __builtin_elementwise_min(
                         best, __builtin_elementwise_add_sat(
-                                  __builtin_elementwise_min(as_u16x2(lp[-j * LC]), as_u16x2(rp[j * LC])), oop));
+                                  __builtin_elementwise_min(as_u16x2(lp[(3 - j) * LC]), as_u16x2(rp[j * LC])), oop));
                 }
                 bb = as_u32(best);
                 bmax = max(bb & 0xFFFFu, bb >> 16);
@@ -841,14 +850,20 @@ __global__ __launch_bounds__(kThreadsX) void edt_pass_x_vec(H hin, int X, int Y,
             uint32_t best = f0 == kSent32 ? capv : f0;
             if (best) {
                 const int far = max(x, X - 1 - x);
-                for (int o = 1; o <= far; o += 4) {
+                // rows x - o - 3 (the lowest of the group on the left, so that
+                // every read has a positive offset) and x + o, each stepped and
+                // held at the pad rows in one move, so neither leaves the tile
+                const uint32_t* const ltop = col - 4 * TW;
+                const uint32_t* const rbot = col + X * TW;
+                const uint32_t* lp = col + (x - 4) * TW;
+                const uint32_t* rp = col + (x + 1) * TW;
+                for (int o = 1; o <= far;
+                     o += 4, lp = lp - 4 * TW < ltop ? ltop : lp - 4 * TW, rp = rp + 4 * TW > rbot ? rbot : rp + 4 * TW) {
                     if ((uint32_t)(o * o) >= best) break;
-                    const uint32_t* lp = col + (x - o >= 0 ? x - o : -1) * TW;
-                    const uint32_t* rp = col + (x + o < X ? x + o : X) * TW;
 #pragma unroll
                     for (int j = 0; j < 4; j++) {
                         const uint32_t oo = (uint32_t)((o + j) * (o + j));
-                        best = min(best, min(lp[-j * TW], rp[j * TW]) + oo);
+                        best = min(best, min(lp[(3 - j) * TW], rp[j * TW]) + oo);
                     }
                 }
             }
@@ -931,16 +946,21 @@ __global__ __launch_bounds__(kThreadsX) void edt_pass_x_pk(const uint32_t* __res
             uint32_t bmax = max(bb & 0xFFFFu, bb >> 16);
             if (bmax > 1) {
                 const int far = min(max(x, X - 1 - x), 256);
-                for (int o = 1; o <= far && (uint32_t)(o * o) < bmax; o += 4) {
-                    const uint32_t* lp = col + (x - o >= 0 ? x - o : -1) * LC;
-                    const uint32_t* rp = col + (x + o < X ? x + o : X) * LC;
+                // rows x - o - 3 and x + o, stepped and held at the pad rows
+                // in one move each (as in pass y)
+                const uint32_t* const ltop = col - 4 * LC;
+                const uint32_t* const rbot = col + X * LC;
+                const uint32_t* lp = col + (x - 4) * LC;
+                const uint32_t* rp = col + (x + 1) * LC;
+                for (int o = 1; o <= far && (uint32_t)(o * o) < bmax;
+                     o += 4, lp = lp - 4 * LC < ltop ? ltop : lp - 4 * LC, rp = rp + 4 * LC > rbot ? rbot : rp + 4 * LC) {
 #pragma unroll
                     for (int j = 0; j < 4; j++) {
                         const uint32_t oo = min((uint32_t)((o + j) * (o + j)), 65535u);
                         const u16x2 oop = as_u16x2(oo | oo << 16);
                         best = __builtin_elementwise_min(
                             best, __builtin_elementwise_add_sat(
-                                      __builtin_elementwise_min(as_u16x2(lp[-j * LC]), as_u16x2(rp[j * LC])), oop));
+                                      __builtin_elementwise_min(as_u16x2(lp[(3 - j) * LC]), as_u16x2(rp[j * LC])), oop));
                     }
                     bb = as_u32(best);
                     bmax = max(bb & 0xFFFFu, bb >> 16);
