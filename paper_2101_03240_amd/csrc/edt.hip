@@ -13,7 +13,10 @@
 // passes is a contiguous segment. Pass y, and pass x on lines long enough
 // that its 32-bit tile would leave a compute unit a single workgroup, run in
 // packed 16-bit arithmetic with two columns per lane: exact for results
-// below 65535, searched again exactly from HBM above.
+// below 65535, searched again exactly from HBM above. Pass z works in 16-bit
+// halves too (its two distance chains in one packed word). Where pass x runs
+// its 32-bit tiles, h travels between passes y and x as 16 bits per voxel,
+// the exact values at 65535 and above kept aside in the output array.
 #include <cmath>
 
 #include "ibip_internal.h"
