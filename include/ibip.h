@@ -139,6 +139,10 @@ ibip_status ibip_probe_claim_latency(ibip_ctx* ctx, int64_t span_bytes, int32_t 
  * ibip_edt -- distance transform of the pore space (Section 2.1, Figure 2(b)).
  * dt2[v] = min over solid voxels s of |v - s|^2 (exact, integer), 0 on solid.
  * Only voxels inside the image count as solid; the border is not solid.
+ * dt2 (caller-owned DEVICE buffer, one uint32 per voxel) also holds
+ * intermediate values while the call's kernels run (pass y's exact values at
+ * 65535 and above, read back by pass x), so it is meaningful only once they
+ * have finished on the context's stream.
  * Errors: EINVAL, ENOSOLID (checked on device, reported after a sync).
  */
 ibip_status ibip_edt(ibip_ctx* ctx, const uint8_t* image, ibip_dims dims, uint32_t* dt2);
