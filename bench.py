@@ -59,7 +59,7 @@ WORKLOADS = {
                "invade of every image in one batched call vs one call per image",
 }
 
-OPENING_BYTES_PER_VOXEL = 25  # the survey's ball dilation: 17 B (three EDT passes) + 8 B (threshold read, output)
+OPENING_BYTES_PER_VOXEL = 25  # the ball dilation: 17 B (three EDT passes) + 8 B (threshold read, output)
 # Algorithmic bytes per unit of work for each phase.
 EDT_BYTES_PER_VOXEL = 5          # read 1 B image, write 4 B dt2 (the floor)
 EDT_BUDGET_BYTES_PER_VOXEL = 17  # three passes: 1+2, 2+4, 4+4
@@ -200,8 +200,8 @@ def edt_alone(dev, L: int = 512, reps: int = 20) -> dict:
 def opening_alone(dev, reps: int = 5) -> dict:
     """The opening drainage alone on the 512^3 blurred-noise image at one
     squared radius (the median of dt2 over the pore), library time (HIP
-    events on its stream) per call, against HBM at the survey's 25 B per
-    voxel for the ball dilation."""
+    events on its stream) per call, against HBM at 25 B per voxel for the
+    ball dilation (three EDT passes, the threshold read and the output)."""
     import torch
 
     import paper_2101_03240_amd as ibip

@@ -23,7 +23,7 @@ IBIP_eq = {0 < seq <= k_eq}, and k*(T) the first step with M_k < T. Then:
   and 2 pixels per unit: max a from 0.38 % to 0.16 % of the pore pixels; at
   1, 2 and 4 pixels per unit on a 500-unit box 0.23 %, 0.13 %, 0.08 %).
 
-The survey's soft bound of 0.5 % of the pore space applies to a, the part
+The soft bound of 0.5 % of the pore space applies to a, the part
 that depends on the method: both 500 x 500 images stay below it (0.37 % and
 0.27 %); the symmetric difference counts each such voxel twice and adds the
 step granularity gap.
