@@ -516,7 +516,7 @@ def main() -> int:
         os.environ["GPU_MAX_HW_QUEUES"] = str(min(args.hw_queues, 32))
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(independent images would shard one per GPU)", file=sys.stderr)
         return 2
 
